@@ -1,0 +1,48 @@
+"""QPD coefficient tensors, as data.
+
+These are the classical tensors (CTs) of the h-TN.  They are inputs to the
+contraction, so they live with the input generators; tests check them
+against the channel identities they encode.
+
+* Pauli-basis wire cut, rho = 1/2 sum_P Tr(P rho) P: a dim-4 index over
+  (I, Z, X, Y) carried by both sides, with weight 1/2 per term.  All four
+  terms have equal weight, the property Sec. 4.3 relies on when it exempts
+  the wire tensor from QPD sampling.
+* CutQC-form wire tensor c_w (Sec. 4.1, Eq. wire-tensor): a 4x4 matrix over
+  upstream measurements A = (I, Z, X, Y) (rows) and downstream preparations
+  B = (|0>, |1>, |+>, |i>) (columns).
+* CZ gate cut (Sec. 2.1, gate QPD; six single-qubit instances): the paper
+  takes the decomposition from an external library and never prints the
+  weights.  The weights below follow from writing CZ = (S (x) S) exp(i pi/4
+  Z(x)Z) up to phase and expanding the ZZ rotation channel into local
+  operations; the instance order is
+      (S^dag, S^dag; +1/2), (S, S; +1/2), (M_Z, I; +1/2), (M_Z, Z; -1/2),
+      (I, M_Z; +1/2), (Z, M_Z; -1/2)
+  where M_Z is the signed Z measurement sigma -> P0 sigma P0 - P1 sigma P1.
+  sum c = 1 and gamma = sum |c| = 3.
+"""
+
+import numpy as np
+
+WIRE_PAULI = np.array([0.5, 0.5, 0.5, 0.5])
+
+CW = 0.5 * np.array([[1.0, 1.0, 0.0, 0.0],
+                     [1.0, -1.0, 0.0, 0.0],
+                     [-1.0, -1.0, 2.0, 0.0],
+                     [-1.0, -1.0, 0.0, 2.0]])
+CW_ROWS = ("I", "Z", "X", "Y")
+CW_COLS = ("0", "1", "+", "+i")
+
+CZ_COEFFS = np.array([0.5, 0.5, 0.5, -0.5, 0.5, -0.5])
+# (op on first qubit, op on second qubit) per instance.
+CZ_INSTANCES = (("Sdg", "Sdg"), ("S", "S"), ("MZ", "I"), ("MZ", "Z"), ("I", "MZ"), ("Z", "MZ"))
+
+# Downstream side of a Pauli-basis wire cut: the Pauli operator injected in
+# place of the cut qubit's state, written as signed preparations.
+PAULI_AS_PREPS = {
+    "I": (("0", 1.0), ("1", 1.0)),
+    "Z": (("0", 1.0), ("1", -1.0)),
+    "X": (("+", 1.0), ("-", -1.0)),
+    "Y": (("+i", 1.0), ("-i", -1.0)),
+}
+PAULI_ORDER = ("I", "Z", "X", "Y")
