@@ -1,0 +1,233 @@
+/*
+ * htn.h — contraction of hybrid tensor networks (h-TNs) on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * What is computed.  Circuit knitting reconstructs an expectation value as
+ * the sum, over every combination of QPD terms of every cut, of the
+ * coefficient product times the product of the subcircuit results
+ * (Sec. 2.1, Eq. knitting).  Writing the subcircuit results as quantum
+ * tensors (QTs) and the QPD coefficients as classical tensors (CTs) joined
+ * by shared indices turns that sum into the contraction of one tensor
+ * network (Sec. 4.1, hybrid circuit contraction); contracting it pairwise
+ * along a good order gives the same value at a far lower cost (Sec. 4.2).
+ * With open output labels the same contraction yields a marginal
+ * distribution.  This library performs that contraction (the runtime's
+ * Step 4, Sec. 6.1) with hand-written HIP kernels.
+ *
+ * Index semantics (Sec. 2.2, tensor networks with hyper-indices).  Every
+ * tensor mode carries an integer label in [0, n_labels).  A label carried
+ * by several tensors is ONE index, summed exactly once (a hyperedge: a CT
+ * and the two QTs it joins).  A label that is not an output label is summed;
+ * it is summed in the first pairwise step after which no remaining tensor
+ * carries it.  All tensors are dense, row-major, last mode fastest.
+ *
+ * Cost unit.  A pairwise step costs one multiplication per element of the
+ * joint index space of its two operands (the product of the extents of the
+ * union of their labels), the paper's postprocessing FLOP count
+ * (Sec. 2.1, Sec. 4.2).  GFLOP/s figures count 2 flops per multiplication.
+ *
+ * Conventions for every function below:
+ *   - Every call returns an htn_status; HTN_OK is 0.  On failure no state
+ *     changes and htn_last_error() returns a message for the calling thread.
+ *   - Structural errors (labels, shapes, paths) are detected on the host
+ *     before anything is enqueued.  Faults raised by device work surface as
+ *     HTN_E_DEVICE at a later call or at stream synchronisation.
+ *   - NaN and Inf inputs propagate into the result; they are not errors.
+ *   - A net is not thread-safe; distinct nets are independent.
+ *   - hip_stream arguments are hipStream_t values passed as void*; NULL
+ *     means the default stream of the current device.
+ */
+#ifndef HTN_H
+#define HTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct htn_net *htn_net_t;
+typedef struct htn_batch *htn_batch_t;
+
+typedef enum {
+    HTN_OK = 0,
+    HTN_E_ARG = 1,         /* NULL pointer, bad count, bad enum value      */
+    HTN_E_LABEL = 2,       /* label out of range, repeated in one tensor,
+                              output label carried by no tensor          */
+    HTN_E_SHAPE = 3,       /* non-positive extent, size overflow         */
+    HTN_E_PATH = 4,        /* SSA path malformed or not a full contraction */
+    HTN_E_OOM = 5,         /* host/device allocation failed, or a peak
+                              intermediate above the configured cap      */
+    HTN_E_DEVICE = 6,      /* HIP runtime error                          */
+    HTN_E_UNSUPPORTED = 7, /* valid request this build does not support  */
+    HTN_E_STATE = 8        /* call out of order (e.g. no device data)    */
+} htn_status;
+
+/* Element types.  HTN_F64/HTN_F32 are IEEE binary64/binary32; HTN_BF16 is
+ * bfloat16 (the upper 16 bits of a binary32), rounded to nearest-even.    */
+typedef enum { HTN_F64 = 0, HTN_F32 = 1, HTN_BF16 = 2 } htn_dtype;
+
+/* How the final contraction step accumulates.
+ *   HTN_SUM_PLAIN        in the compute accumulator (FP64 for HTN_F64,
+ *                        FP32 otherwise); output dtype = intermediate dtype
+ *                        (FP64 for HTN_F64, FP32 for HTN_F32/HTN_BF16).
+ *   HTN_SUM_FP64         products and sums of the last step in FP64;
+ *                        output FP64.
+ *   HTN_SUM_COMPENSATED  as HTN_SUM_FP64 with Neumaier-compensated sums and
+ *                        TwoSum combination of partial sums; output FP64.
+ * The final signed sum over QPD terms (weights +-1/2, gamma = 3 per CZ cut)
+ * is where cancellation concentrates, so it may run in FP64 even when
+ * every earlier step ran in FP32 or BF16.                                  */
+typedef enum { HTN_SUM_PLAIN = 0, HTN_SUM_FP64 = 1, HTN_SUM_COMPENSATED = 2 } htn_final_sum;
+
+/* Execution strategy for htn_contract.
+ *   HTN_EXEC_AUTO   fused when the whole network fits on chip, else steps.
+ *   HTN_EXEC_STEPS  one kernel launch per pairwise step (plus one launch
+ *                   that applies absorbed coefficient vectors), every
+ *                   intermediate in device memory.
+ *   HTN_EXEC_FUSED  one workgroup contracts the whole network with every
+ *                   operand in LDS; HTN_E_UNSUPPORTED if it does not fit.  */
+typedef enum { HTN_EXEC_AUTO = 0, HTN_EXEC_STEPS = 1, HTN_EXEC_FUSED = 2 } htn_exec_mode;
+
+/* Path selectors for htn_set_path's n_steps argument. */
+#define HTN_PATH_GREEDY (-1)
+#define HTN_PATH_LEARNED (-2)
+
+/* ---------------------------------------------------------------------
+ * htn_create — build a net from tensors and labels.
+ *
+ *   out           receives the handle (set to NULL on failure).
+ *   n_tensors     >= 1.
+ *   ranks         [n_tensors], each >= 1.
+ *   labels        concatenation of ranks[i] labels per tensor, each in
+ *                 [0, n_labels), no label twice in one tensor.
+ *   n_labels      number of label ids; label_dims[n_labels] extents >= 1.
+ *   data          [n_tensors] pointers to row-major tensors of dtype
+ *                 `storage`.  data_on_device = 0: host memory, copied into
+ *                 net-owned device memory at the first contraction (the
+ *                 caller may free it when htn_create returns).
+ *                 data_on_device = 1: device memory on the current device,
+ *                 borrowed — it must stay valid and unchanged in layout for
+ *                 the life of the net; when `storage` differs from the
+ *                 compute element type a converted device copy is made.
+ *   n_out, out_labels  ordered output labels (n_out = 0: scalar).  Each
+ *                 must be carried by at least one tensor.
+ *   storage       dtype of `data` (HTN_F64, HTN_F32 or HTN_BF16).
+ *   compute       HTN_F64: FP64 inputs, intermediates, accumulation.
+ *                 HTN_F32: FP32 inputs, intermediates, accumulation.
+ *                 HTN_BF16: BF16 inputs (round-to-nearest-even from
+ *                 `storage`), FP32 intermediates and accumulation; operands
+ *                 of matrix-core steps enter as BF16.
+ *   final_sum     see htn_final_sum.
+ * The default path is FLOP-greedy (as after htn_set_path(net, -1, NULL)).
+ * ------------------------------------------------------------------- */
+htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks,
+                      const int32_t *labels, int32_t n_labels, const int64_t *label_dims,
+                      const void *const *data, int32_t data_on_device, int32_t n_out,
+                      const int32_t *out_labels, htn_dtype storage, htn_dtype compute,
+                      htn_final_sum final_sum);
+
+/* ---------------------------------------------------------------------
+ * htn_set_path — choose the pairwise contraction order (Sec. 4.2: the cost
+ * depends heavily on the order; Sec. 6.1 Step 3).
+ *
+ *   n_steps >= 0  explicit SSA path: ssa_pairs[2*t], ssa_pairs[2*t+1] are
+ *                 the ids contracted by step t; inputs are ids
+ *                 0..n_tensors-1 and step t creates id n_tensors+t.  Every
+ *                 id is consumed exactly once and the last step's result
+ *                 is the network's value, so n_steps == n_tensors - 1.
+ *                 Pairs without a shared label are outer products.
+ *   HTN_PATH_GREEDY   FLOP-greedy: repeatedly contract the pair, among
+ *                 pairs sharing a label, with the fewest multiplications;
+ *                 ties go to the smaller result, then to the lower ids;
+ *                 disconnected parts are joined last, smallest first.
+ *   HTN_PATH_LEARNED  path proposed by the installed cost model
+ *                 (htn_model_set); falls back to FLOP-greedy when no model
+ *                 is installed or when the model does not predict the
+ *                 candidate to be faster than the greedy path.
+ * Errors: HTN_E_PATH for a malformed path; HTN_E_OOM if an intermediate
+ * exceeds the size cap (htn_set_option HTN_OPT_MAX_INTERMEDIATE).
+ * ------------------------------------------------------------------- */
+htn_status htn_set_path(htn_net_t net, int32_t n_steps, const int32_t *ssa_pairs);
+
+/* htn_get_path — the current path.  *n_steps receives its length; if
+ * ssa_pairs is non-NULL, min(capacity, n_steps) pairs are written.  If
+ * mults is non-NULL it receives the path's multiplication count.        */
+htn_status htn_get_path(htn_net_t net, int32_t *n_steps, int32_t *ssa_pairs, int32_t capacity,
+                        double *mults);
+
+/* Options (htn_set_option). */
+typedef enum {
+    HTN_OPT_EXEC = 0,              /* htn_exec_mode                            */
+    HTN_OPT_MAX_INTERMEDIATE = 1,  /* cap on intermediate elements (default 2^31-1) */
+    HTN_OPT_FUSED_LDS_BYTES = 2,   /* LDS budget of the fused kernel (default 65536) */
+    HTN_OPT_MFMA = 3               /* 1: allow matrix-core steps (default), 0: VALU only */
+} htn_option;
+
+htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value);
+
+/* Summary of a planned net. */
+typedef struct {
+    int64_t out_elements;   /* elements of the result                        */
+    int32_t out_dtype;      /* htn_dtype of the result                       */
+    int32_t n_steps;        /* path length                                   */
+    int32_t n_kernel_steps; /* steps executed as kernels (not absorbed)      */
+    int32_t n_absorbed;     /* coefficient tensors folded into operand loads */
+    int32_t fused_ok;       /* 1 if the whole net fits the fused kernel      */
+    int32_t fused_lds_bytes;/* LDS the fused kernel needs                    */
+    double mults;           /* multiplications along the path                */
+    double peak_elements;   /* largest intermediate                          */
+    int64_t workspace_bytes;/* device workspace of the per-step executor     */
+    int64_t input_bytes;    /* bytes of the inputs in compute storage        */
+} htn_info;
+
+htn_status htn_get_info(htn_net_t net, htn_info *info);
+
+/* ---------------------------------------------------------------------
+ * htn_contract — contract the net into out_device (caller-owned device
+ * memory of info.out_elements elements of info.out_dtype, laid out
+ * row-major over out_labels).  Asynchronous on hip_stream.  The first call
+ * uploads host data and allocates the net's workspace (synchronously).
+ * ------------------------------------------------------------------- */
+htn_status htn_contract(htn_net_t net, void *out_device, void *hip_stream);
+
+/* htn_contract_batch — contract n independent nets, outs[i] receiving net
+ * i's result, with as few launches as possible: every net that fits the
+ * fused kernel runs in one launch (one workgroup per net, heaviest first);
+ * the others run step by step on the same stream.  Equivalent to
+ * htn_batch_create + htn_batch_run + htn_batch_destroy.                  */
+htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream);
+
+/* Reusable batch: plans the combined launch once.  The nets must outlive
+ * the batch and keep their paths.  htn_batch_run may capture its launches
+ * in a HIP graph (htn_batch_set_graph) and replay it on later calls with
+ * the same outs.                                                          */
+htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets);
+htn_status htn_batch_set_graph(htn_batch_t batch, int32_t use_graph);
+htn_status htn_batch_run(htn_batch_t batch, void *const *outs, void *hip_stream);
+/* Per-net completion times of the last run, in ticks of the device's
+ * constant 100 MHz clock after the launch's first workgroup started
+ * (fused nets only; -1 for nets run step by step).                        */
+htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
+void htn_batch_destroy(htn_batch_t batch);
+
+/* htn_update_data — replace the tensor values (same structure and path).
+ * Same data / data_on_device semantics as htn_create.                     */
+htn_status htn_update_data(htn_net_t net, const void *const *data, int32_t data_on_device);
+
+void htn_destroy(htn_net_t net);
+
+const char *htn_status_string(htn_status s);
+const char *htn_last_error(void);
+
+/* htn_plan_json — a JSON description of the current plan (steps, labels,
+ * kernel classes, sizes) for tests and tools.  Writes at most `capacity`
+ * bytes including the terminating NUL; *needed receives the full length
+ * plus one.                                                               */
+htn_status htn_plan_json(htn_net_t net, char *buf, int64_t capacity, int64_t *needed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTN_H */

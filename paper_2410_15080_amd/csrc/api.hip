@@ -1,0 +1,767 @@
+// C ABI of the h-TN library: handles, device state, executors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "htn.h"
+#include "htn_core.hpp"
+#include "kernels.hpp"
+
+using namespace htn;
+
+static thread_local std::string g_err;
+
+static htn_status fail(htn_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+#define HIP_TRY(x)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) throw Error{HTN_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                                                  \
+    }                                                                  \
+    catch (const Error &e) {                                           \
+        return fail(e.st, e.msg);                                      \
+    }                                                                  \
+    catch (const std::bad_alloc &) {                                   \
+        return fail(HTN_E_OOM, "host allocation failed");              \
+    }                                                                  \
+    catch (...) {                                                      \
+        return fail(HTN_E_ARG, "unexpected internal error");           \
+    }
+
+namespace htn {
+struct DeviceState {
+    int device = -1;
+    std::vector<void *> in;  // per tensor, compute input dtype
+    std::vector<char> own;
+    void **d_inptrs = nullptr;
+    int32_t *d_prog = nullptr;
+    int2 *d_tab = nullptr;
+    void *d_ws = nullptr;
+    int64_t ws_cap = 0;
+    kern::PrepDesc *d_prep = nullptr;
+    int n_prep = 0, prep_max = 0;
+    kern::FusedDesc *d_fdesc = nullptr;
+    int plan_uploaded = -1;
+};
+}  // namespace htn
+
+struct htn_net : public Net {};
+
+struct htn_batch {
+    struct Group {
+        int compute = 0, fm = 0, lds = 0;
+        std::vector<int> idx;  // net indices, heaviest first
+        int32_t *d_order = nullptr;
+    };
+    std::vector<htn_net *> nets;
+    std::vector<int> versions;
+    std::vector<Group> groups;
+    std::vector<int> step_nets;
+    kern::FusedDesc *d_desc = nullptr;
+    void **d_outs = nullptr;
+    int64_t *d_stamps = nullptr;
+    std::vector<void *> outs_uploaded;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    std::vector<void *> graph_outs;
+};
+
+// ------------------------------------------------------------- helpers
+
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+static T *dalloc(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw Error{HTN_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    return (T *)p;
+}
+
+static float bf16_bits_to_f32(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+static uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Host conversion of n elements from dtype `from` to dtype `to`.
+// BF16 results are rounded from FP32 (an FP64 source is first rounded to
+// FP32), both steps to nearest-even.
+static void host_convert(const void *src, htn_dtype from, void *dst, htn_dtype to, int64_t n) {
+    if (from == to) {
+        std::memcpy(dst, src, (size_t)n * dtype_size(from));
+        return;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double v;
+        if (from == HTN_F64)
+            v = ((const double *)src)[i];
+        else if (from == HTN_F32)
+            v = ((const float *)src)[i];
+        else
+            v = bf16_bits_to_f32(((const uint16_t *)src)[i]);
+        if (to == HTN_F64)
+            ((double *)dst)[i] = v;
+        else if (to == HTN_F32)
+            ((float *)dst)[i] = (float)v;
+        else
+            ((uint16_t *)dst)[i] = f32_to_bf16_bits((float)v);
+    }
+}
+
+static void release_inputs(Net &n) {
+    if (!n.dev) return;
+    for (size_t i = 0; i < n.dev->in.size(); ++i)
+        if (n.dev->own[i]) dfree(n.dev->in[i]);
+    n.dev->in.clear();
+    n.dev->own.clear();
+}
+
+static void release_device(Net &n) {
+    if (!n.dev) return;
+    release_inputs(n);
+    DeviceState &D = *n.dev;
+    dfree(D.d_inptrs);
+    dfree(D.d_prog);
+    dfree(D.d_tab);
+    dfree(D.d_ws);
+    dfree(D.d_prep);
+    dfree(D.d_fdesc);
+    delete n.dev;
+    n.dev = nullptr;
+}
+
+static void set_data(Net &n, const void *const *data, int on_device) {
+    if (!data) throw Error{HTN_E_ARG, "data is NULL"};
+    for (int i = 0; i < n.n_t; ++i)
+        if (!data[i]) throw Error{HTN_E_ARG, "data[" + std::to_string(i) + "] is NULL"};
+    n.data_on_device = on_device != 0;
+    n.user_ptrs.assign(n.n_t, nullptr);
+    n.host.assign(n.n_t, {});
+    const htn_dtype tin = input_dtype(n.compute);
+    for (int i = 0; i < n.n_t; ++i) {
+        if (n.data_on_device) {
+            n.user_ptrs[i] = data[i];
+        } else {
+            n.host[i].resize((size_t)n.sizes[i] * dtype_size(tin));
+            host_convert(data[i], n.storage, n.host[i].data(), tin, n.sizes[i]);
+        }
+    }
+    n.data_dirty = true;
+}
+
+static void upload_inputs(Net &n) {
+    DeviceState &D = *n.dev;
+    const htn_dtype tin = input_dtype(n.compute);
+    release_inputs(n);
+    D.in.assign(n.n_t, nullptr);
+    D.own.assign(n.n_t, 0);
+    for (int i = 0; i < n.n_t; ++i) {
+        const size_t bytes = (size_t)n.sizes[i] * dtype_size(tin);
+        if (n.data_on_device && n.storage == tin) {
+            D.in[i] = const_cast<void *>(n.user_ptrs[i]);
+            continue;
+        }
+        D.in[i] = dalloc<unsigned char>(bytes);
+        D.own[i] = 1;
+        if (n.data_on_device) {
+            HIP_TRY(kern::launch_convert(n.user_ptrs[i], n.storage, D.in[i], tin, n.sizes[i], 0));
+        } else {
+            HIP_TRY(hipMemcpy(D.in[i], n.host[i].data(), bytes, hipMemcpyHostToDevice));
+            std::vector<unsigned char>().swap(n.host[i]);
+        }
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    dfree(D.d_inptrs);
+    D.d_inptrs = dalloc<void *>(n.n_t);
+    HIP_TRY(hipMemcpy(D.d_inptrs, D.in.data(), sizeof(void *) * n.n_t, hipMemcpyHostToDevice));
+    n.data_dirty = false;
+    D.plan_uploaded = -1;  // prep descriptors hold input pointers
+}
+
+static void upload_plan(Net &n) {
+    DeviceState &D = *n.dev;
+    Plan &P = n.plan;
+    dfree(D.d_prog);
+    D.d_prog = dalloc<int32_t>(P.program.size());
+    HIP_TRY(hipMemcpy(D.d_prog, P.program.data(), P.program.size() * 4, hipMemcpyHostToDevice));
+    dfree(D.d_tab);
+    D.d_tab = dalloc<int2>(P.tables.size() / 2);
+    HIP_TRY(hipMemcpy(D.d_tab, P.tables.data(), P.tables.size() * 4, hipMemcpyHostToDevice));
+    const int64_t ws_need = std::max<int64_t>(P.ws_bytes, P.fused_scratch_bytes);
+    if (ws_need > D.ws_cap) {
+        dfree(D.d_ws);
+        D.d_ws = nullptr;
+        D.d_ws = dalloc<unsigned char>((size_t)ws_need);
+        D.ws_cap = ws_need;
+    }
+    std::vector<kern::PrepDesc> prep;
+    int pmax = 0;
+    for (const LoadPlan &lp : P.loads) {
+        if (lp.scales.empty()) continue;
+        kern::PrepDesc q;
+        std::memset(&q, 0, sizeof(q));
+        q.src = D.in[lp.base];
+        q.dst = (unsigned char *)D.d_ws + P.ws_off[lp.value];
+        q.size = (int32_t)lp.size;
+        q.ns = (int32_t)lp.scales.size();
+        for (int k = 0; k < q.ns; ++k) {
+            q.sp[k] = D.in[lp.scales[k].tensor];
+            q.thi[k] = (int32_t)lp.scales[k].t_hi;
+            q.tlo[k] = (int32_t)lp.scales[k].t_lo;
+            q.nlo[k] = (int32_t)lp.scales[k].n_lo;
+        }
+        pmax = std::max<int>(pmax, q.size);
+        prep.push_back(q);
+    }
+    dfree(D.d_prep);
+    D.d_prep = nullptr;
+    D.n_prep = (int)prep.size();
+    D.prep_max = pmax;
+    if (!prep.empty()) {
+        D.d_prep = dalloc<kern::PrepDesc>(prep.size());
+        HIP_TRY(hipMemcpy(D.d_prep, prep.data(), prep.size() * sizeof(kern::PrepDesc), hipMemcpyHostToDevice));
+    }
+    kern::FusedDesc fd{D.d_prog, D.d_tab, (const void *const *)D.d_inptrs, D.d_ws};
+    dfree(D.d_fdesc);
+    D.d_fdesc = dalloc<kern::FusedDesc>(1);
+    HIP_TRY(hipMemcpy(D.d_fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
+    D.plan_uploaded = n.plan_version;
+}
+
+static void ensure_device(Net &n) {
+    if (!n.dev) {
+        n.dev = new DeviceState;
+        HIP_TRY(hipGetDevice(&n.dev->device));
+    } else {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != n.dev->device) throw Error{HTN_E_STATE, "net was first used on another device"};
+    }
+    if (n.data_dirty) upload_inputs(n);
+    if (n.dev->plan_uploaded != n.plan_version) upload_plan(n);
+}
+
+static int final_mode(const Net &n) {
+    if (n.final_sum == HTN_SUM_COMPENSATED) return kern::FM_COMP;
+    if (n.final_sum == HTN_SUM_FP64) return kern::FM_F64;
+    return kern::FM_INTER;
+}
+
+static bool use_fused(const Net &n) {
+    if (n.exec == HTN_EXEC_STEPS) return false;
+    if (n.exec == HTN_EXEC_FUSED) return true;  // spills to global scratch if needed
+    return n.plan.fused_ok;
+}
+
+static void run_fused_single(Net &n, void *out, hipStream_t st) {
+    HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, 1, (int)n.plan.fused_lds_bytes,
+                               (int)n.compute, final_mode(n), st));
+}
+
+static kern::StepArgs pack_args(const StepPlan::Pack &pk) {
+    kern::StepArgs a;
+    a.n_ohi = (int32_t)pk.n_ohi;
+    a.n_olo = (int32_t)pk.n_olo;
+    a.n_shi = 1;
+    a.n_slo = 1;
+    a.t_ohi = (int32_t)pk.t_ohi;
+    a.t_olo = (int32_t)pk.t_olo;
+    a.t_shi = (int32_t)pk.t_one;
+    a.t_slo = (int32_t)pk.t_one;
+    a.R = 1;
+    a.log2R = 0;
+    a.n_out = pk.n;
+    return a;
+}
+
+// Matrix-core step: pack both operands K-contiguous, then one GEMM launch.
+static void run_mfma_step(Net &n, const StepPlan &s, const void *A, int ta, const void *B, int tb, void *C, int tc,
+                          hipStream_t st) {
+    DeviceState &D = *n.dev;
+    const int tp = n.compute == HTN_BF16 ? 2 : (int)inter_dtype(n.compute);
+    void *pa = (unsigned char *)D.d_ws + s.ws_pa;
+    void *pb = (unsigned char *)D.d_ws + s.ws_pb;
+    HIP_TRY(kern::launch_step(A, ta, nullptr, ta, pa, tp, false, false, D.d_tab, pack_args(s.pack_a), st));
+    HIP_TRY(kern::launch_step(B, tb, nullptr, tb, pb, tp, false, false, D.d_tab, pack_args(s.pack_b), st));
+    HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, st));
+}
+
+static void run_steps(Net &n, void *out, hipStream_t st) {
+    DeviceState &D = *n.dev;
+    const Plan &P = n.plan;
+    const int tin = (int)input_dtype(n.compute), tint = (int)inter_dtype(n.compute);
+    if (D.n_prep) HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep, D.prep_max, tin, tint, D.d_tab, st));
+    for (int k : P.kernel_steps) {
+        const StepPlan &s = P.steps[k];
+        auto operand = [&](int id, const void *&ptr, int &t) {
+            if (id < 0) {
+                ptr = nullptr;
+                t = tint;
+            } else if (P.ws_off[id] >= 0) {
+                ptr = (const unsigned char *)D.d_ws + P.ws_off[id];
+                t = tint;
+            } else {
+                ptr = D.in[P.values[id].base];
+                t = tin;
+            }
+        };
+        const void *A, *B;
+        int ta, tb;
+        operand(s.a, A, ta);
+        operand(s.b, B, tb);
+        void *C;
+        int tc;
+        bool comp = false;
+        if (s.final_step) {
+            C = out;
+            tc = n.final_sum == HTN_SUM_PLAIN ? tint : 0;
+            comp = n.final_sum == HTN_SUM_COMPENSATED;
+        } else {
+            C = (unsigned char *)D.d_ws + P.ws_off[s.c];
+            tc = tint;
+        }
+        if (s.mfma) {
+            run_mfma_step(n, s, A, ta, B, tb, C, tc, st);
+            continue;
+        }
+        kern::StepArgs a;
+        a.n_ohi = (int32_t)s.n_ohi;
+        a.n_olo = (int32_t)s.n_olo;
+        a.n_shi = (int32_t)s.n_shi;
+        a.n_slo = (int32_t)s.n_slo;
+        a.t_ohi = (int32_t)s.t_ohi;
+        a.t_olo = (int32_t)s.t_olo;
+        a.t_shi = (int32_t)s.t_shi;
+        a.t_slo = (int32_t)s.t_slo;
+        a.R = s.r_global;
+        a.log2R = 0;
+        while ((1 << a.log2R) < a.R) ++a.log2R;
+        a.n_out = s.n_out;
+        HIP_TRY(kern::launch_step(A, ta, B, tb, C, tc, tc == 0, comp, D.d_tab, a, st));
+    }
+}
+
+static void contract_one(Net &n, void *out, hipStream_t st) {
+    if (use_fused(n))
+        run_fused_single(n, out, st);
+    else
+        run_steps(n, out, st);
+}
+
+static void replan(Net &n) {
+    auto old_path = n.path;
+    try {
+        build_plan(n);
+    } catch (...) {
+        n.path = old_path;
+        throw;
+    }
+}
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks, const int32_t *labels,
+                      int32_t n_labels, const int64_t *label_dims, const void *const *data, int32_t data_on_device,
+                      int32_t n_out, const int32_t *out_labels, htn_dtype storage, htn_dtype compute,
+                      htn_final_sum final_sum) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_tensors < 1) return fail(HTN_E_ARG, "n_tensors < 1");
+    if (!ranks || !labels || !label_dims) return fail(HTN_E_ARG, "ranks/labels/label_dims is NULL");
+    if (n_labels < 1) return fail(HTN_E_ARG, "n_labels < 1");
+    if (n_out < 0 || (n_out > 0 && !out_labels)) return fail(HTN_E_ARG, "bad output labels");
+    if (storage < HTN_F64 || storage > HTN_BF16 || compute < HTN_F64 || compute > HTN_BF16)
+        return fail(HTN_E_ARG, "bad dtype");
+    if (final_sum < HTN_SUM_PLAIN || final_sum > HTN_SUM_COMPENSATED) return fail(HTN_E_ARG, "bad final_sum");
+    htn_net *n = new htn_net;
+    try {
+        n->n_t = n_tensors;
+        n->dims.assign(label_dims, label_dims + n_labels);
+        n->labels.resize(n_tensors);
+        int off = 0;
+        for (int i = 0; i < n_tensors; ++i) {
+            if (ranks[i] < 0) throw Error{HTN_E_SHAPE, "negative rank"};
+            n->labels[i].assign(labels + off, labels + off + ranks[i]);
+            off += ranks[i];
+        }
+        n->out_labels.assign(out_labels, out_labels + n_out);
+        n->storage = storage;
+        n->compute = compute;
+        n->final_sum = final_sum;
+        validate_structure(*n);
+        n->sizes.resize(n_tensors);
+        for (int i = 0; i < n_tensors; ++i) {
+            int64_t s = 1;
+            for (int l : n->labels[i]) s *= n->dims[l];
+            n->sizes[i] = s;
+        }
+        set_data(*n, data, data_on_device);
+        n->path = greedy_path(*n);
+        n->path_kind = HTN_PATH_GREEDY;
+        build_plan(*n);
+    } catch (...) {
+        delete n;
+        throw;
+    }
+    *out = n;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_set_path(htn_net_t net, int32_t n_steps, const int32_t *ssa_pairs) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    auto old = net->path;
+    int old_kind = net->path_kind;
+    try {
+        if (n_steps >= 0) {
+            if (n_steps > 0 && !ssa_pairs) return fail(HTN_E_ARG, "ssa_pairs is NULL");
+            std::vector<std::pair<int, int>> p(n_steps);
+            for (int t = 0; t < n_steps; ++t) p[t] = {ssa_pairs[2 * t], ssa_pairs[2 * t + 1]};
+            check_path(*net, p);
+            net->path = p;
+            net->path_kind = 0;
+        } else if (n_steps == HTN_PATH_GREEDY || n_steps == HTN_PATH_LEARNED) {
+            net->path = greedy_path(*net);
+            net->path_kind = n_steps;
+        } else {
+            return fail(HTN_E_ARG, "unknown path selector");
+        }
+        build_plan(*net);
+    } catch (...) {
+        net->path = old;
+        net->path_kind = old_kind;
+        throw;
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_get_path(htn_net_t net, int32_t *n_steps, int32_t *ssa_pairs, int32_t capacity, double *mults) {
+    API_GUARD_BEGIN
+    if (!net || !n_steps) return fail(HTN_E_ARG, "NULL argument");
+    *n_steps = (int32_t)net->path.size();
+    if (ssa_pairs)
+        for (int t = 0; t < (int)net->path.size() && t < capacity; ++t) {
+            ssa_pairs[2 * t] = net->path[t].first;
+            ssa_pairs[2 * t + 1] = net->path[t].second;
+        }
+    if (mults) *mults = net->plan.mults;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    switch (opt) {
+        case HTN_OPT_EXEC:
+            if (value < HTN_EXEC_AUTO || value > HTN_EXEC_FUSED) return fail(HTN_E_ARG, "bad exec mode");
+            net->exec = (htn_exec_mode)value;
+            return HTN_OK;
+        case HTN_OPT_MAX_INTERMEDIATE: {
+            if (value < 1 || value > 2147483647)
+                return fail(HTN_E_ARG, "cap outside [1, 2^31-1] (offsets are 32-bit)");
+            int64_t old = net->max_intermediate;
+            net->max_intermediate = value;
+            try {
+                replan(*net);
+            } catch (...) {
+                net->max_intermediate = old;
+                throw;
+            }
+            return HTN_OK;
+        }
+        case HTN_OPT_FUSED_LDS_BYTES: {
+            if (value < 1024 || value > 163840) return fail(HTN_E_ARG, "LDS budget outside [1024, 163840]");
+            net->fused_lds_budget = value;
+            replan(*net);
+            return HTN_OK;
+        }
+        case HTN_OPT_MFMA:
+            net->allow_mfma = value ? 1 : 0;
+            replan(*net);
+            return HTN_OK;
+    }
+    return fail(HTN_E_ARG, "unknown option");
+    API_GUARD_END
+}
+
+htn_status htn_get_info(htn_net_t net, htn_info *info) {
+    API_GUARD_BEGIN
+    if (!net || !info) return fail(HTN_E_ARG, "NULL argument");
+    const Plan &P = net->plan;
+    std::memset(info, 0, sizeof(*info));
+    int64_t oe = 1;
+    for (int l : net->out_labels) oe *= net->dims[l];
+    info->out_elements = oe;
+    info->out_dtype = (int32_t)out_dtype(*net);
+    info->n_steps = (int32_t)net->path.size();
+    info->n_kernel_steps = (int32_t)P.kernel_steps.size();
+    info->n_absorbed = P.n_absorbed;
+    info->fused_ok = P.fused_ok ? 1 : 0;
+    info->fused_lds_bytes = (int32_t)P.fused_lds_bytes;
+    info->mults = P.mults;
+    info->peak_elements = P.peak;
+    info->workspace_bytes = P.ws_bytes;
+    int64_t ib = 0;
+    for (int i = 0; i < net->n_t; ++i) ib += net->sizes[i] * dtype_size(input_dtype(net->compute));
+    info->input_bytes = ib;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_contract(htn_net_t net, void *out_device, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!net || !out_device) return fail(HTN_E_ARG, "NULL argument");
+    ensure_device(*net);
+    contract_one(*net, out_device, (hipStream_t)hip_stream);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_update_data(htn_net_t net, const void *const *data, int32_t data_on_device) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    set_data(*net, data, data_on_device);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+void htn_destroy(htn_net_t net) {
+    if (!net) return;
+    try {
+        release_device(*net);
+    } catch (...) {
+    }
+    delete net;
+}
+
+htn_status htn_plan_json(htn_net_t net, char *buf, int64_t capacity, int64_t *needed) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    std::string s = plan_json(*net);
+    if (needed) *needed = (int64_t)s.size() + 1;
+    if (buf && capacity > 0) {
+        size_t n = std::min<size_t>((size_t)capacity - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+// ---------------------------------------------------------------- batch
+
+static void batch_free(htn_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    for (auto &g : b->groups) dfree(g.d_order);
+    dfree(b->d_desc);
+    dfree(b->d_outs);
+    dfree(b->d_stamps);
+}
+
+htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
+    API_GUARD_BEGIN
+    if (!out || n < 1 || !nets) return fail(HTN_E_ARG, "bad batch arguments");
+    *out = nullptr;
+    htn_batch *b = new htn_batch;
+    try {
+        b->nets.assign(nets, nets + n);
+        std::vector<kern::FusedDesc> desc(n);
+        for (int i = 0; i < n; ++i) {
+            if (!nets[i]) throw Error{HTN_E_ARG, "nets[" + std::to_string(i) + "] is NULL"};
+            Net &net = *nets[i];
+            ensure_device(net);
+            b->versions.push_back(net.plan_version);
+            desc[i] = kern::FusedDesc{net.dev->d_prog, net.dev->d_tab, (const void *const *)net.dev->d_inptrs,
+                                      net.dev->d_ws};
+            if (!use_fused(net)) {
+                b->step_nets.push_back(i);
+                continue;
+            }
+            int c = (int)net.compute, fm = final_mode(net);
+            if (c == HTN_F64 && fm == kern::FM_F64) fm = kern::FM_INTER;
+            auto it = std::find_if(b->groups.begin(), b->groups.end(),
+                                   [&](const htn_batch::Group &g) { return g.compute == c && g.fm == fm; });
+            if (it == b->groups.end()) {
+                b->groups.push_back({});
+                it = b->groups.end() - 1;
+                it->compute = c;
+                it->fm = fm;
+            }
+            it->idx.push_back(i);
+            it->lds = std::max<int>(it->lds, (int)net.plan.fused_lds_bytes);
+        }
+        for (auto &g : b->groups) {
+            std::stable_sort(g.idx.begin(), g.idx.end(),
+                             [&](int x, int y) { return nets[x]->plan.mults > nets[y]->plan.mults; });
+            g.d_order = dalloc<int32_t>(g.idx.size());
+            HIP_TRY(hipMemcpy(g.d_order, g.idx.data(), g.idx.size() * 4, hipMemcpyHostToDevice));
+        }
+        b->d_desc = dalloc<kern::FusedDesc>(n);
+        HIP_TRY(hipMemcpy(b->d_desc, desc.data(), n * sizeof(kern::FusedDesc), hipMemcpyHostToDevice));
+        b->d_outs = dalloc<void *>(n);
+        b->d_stamps = dalloc<int64_t>(2 * (size_t)n);
+    } catch (...) {
+        batch_free(b);
+        delete b;
+        throw;
+    }
+    *out = b;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
+    API_GUARD_BEGIN
+    if (!b) return fail(HTN_E_ARG, "batch is NULL");
+    b->use_graph = use_graph != 0;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
+    for (auto &g : b->groups)
+        HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, (int)g.idx.size(), g.lds,
+                                   g.compute, g.fm, st));
+    for (int i : b->step_nets) run_steps(*b->nets[i], outs[i], st);
+}
+
+htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!b || !outs) return fail(HTN_E_ARG, "NULL argument");
+    const int n = (int)b->nets.size();
+    for (int i = 0; i < n; ++i) {
+        if (!outs[i]) return fail(HTN_E_ARG, "outs[" + std::to_string(i) + "] is NULL");
+        if (b->nets[i]->plan_version != b->versions[i] || b->nets[i]->data_dirty)
+            return fail(HTN_E_STATE, "net " + std::to_string(i) + " changed after htn_batch_create");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<void *> ov(outs, outs + n);
+    if (ov != b->outs_uploaded) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipMemcpy(b->d_outs, ov.data(), n * sizeof(void *), hipMemcpyHostToDevice));
+        b->outs_uploaded = ov;
+    }
+    if (b->use_graph && st != nullptr) {
+        if (b->gexec && (b->graph_outs != ov || b->graph_stream != st)) {
+            (void)hipGraphExecDestroy(b->gexec);
+            (void)hipGraphDestroy(b->graph);
+            b->gexec = nullptr;
+            b->graph = nullptr;
+        }
+        if (!b->gexec) {
+            batch_enqueue(b, outs, st);  // first run eagerly (also sets kernel attributes)
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                batch_enqueue(b, outs, st);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIP_TRY(hipStreamEndCapture(st, &b->graph));
+            HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            b->graph_outs = ov;
+            b->graph_stream = st;
+            return HTN_OK;
+        }
+        HIP_TRY(hipGraphLaunch(b->gexec, st));
+        return HTN_OK;
+    }
+    batch_enqueue(b, outs, st);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_timestamps(htn_batch_t b, int64_t *ticks) {
+    API_GUARD_BEGIN
+    if (!b || !ticks) return fail(HTN_E_ARG, "NULL argument");
+    const int n = (int)b->nets.size();
+    std::vector<int64_t> st(2 * (size_t)n);
+    HIP_TRY(hipMemcpy(st.data(), b->d_stamps, st.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<char> fused(n, 0);
+    int64_t t0 = INT64_MAX;
+    for (auto &g : b->groups)
+        for (int i : g.idx) {
+            fused[i] = 1;
+            t0 = std::min(t0, st[2 * i]);
+        }
+    for (int i = 0; i < n; ++i) ticks[i] = fused[i] ? st[2 * i + 1] - t0 : -1;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+void htn_batch_destroy(htn_batch_t b) {
+    if (!b) return;
+    batch_free(b);
+    delete b;
+}
+
+htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream) {
+    htn_batch_t b = nullptr;
+    htn_status s = htn_batch_create(&b, n, nets);
+    if (s != HTN_OK) return s;
+    s = htn_batch_run(b, outs, hip_stream);
+    if (s == HTN_OK) {
+        // The batch's device buffers are read by the launch: wait before
+        // releasing them.
+        hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+        if (e != hipSuccess) s = fail(HTN_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    htn_batch_destroy(b);
+    return s;
+}
+
+const char *htn_status_string(htn_status s) {
+    switch (s) {
+        case HTN_OK: return "HTN_OK";
+        case HTN_E_ARG: return "HTN_E_ARG";
+        case HTN_E_LABEL: return "HTN_E_LABEL";
+        case HTN_E_SHAPE: return "HTN_E_SHAPE";
+        case HTN_E_PATH: return "HTN_E_PATH";
+        case HTN_E_OOM: return "HTN_E_OOM";
+        case HTN_E_DEVICE: return "HTN_E_DEVICE";
+        case HTN_E_UNSUPPORTED: return "HTN_E_UNSUPPORTED";
+        case HTN_E_STATE: return "HTN_E_STATE";
+    }
+    return "unknown status";
+}
+
+const char *htn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Internal data structures of the h-TN library: network description,
+// contraction plan, device state.  Host-only C++ (no HIP types here, so the
+// planner can be reasoned about and exercised without a GPU).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "htn.h"
+
+namespace htn {
+
+// Threads per workgroup of the fused and per-step kernels.
+constexpr int kBlock = 256;
+// Largest number of coefficient tensors folded into one operand load.
+constexpr int kMaxScales = 16;
+
+// Largest extent product kept in the low half of a two-level offset table.
+constexpr int64_t kTabLoMax = 1024;
+
+// One pairwise step of the path (or a planner-added unary final step).
+struct StepPlan {
+    int a = -1, b = -1;  // operand SSA ids; b < 0: unary step
+    int c = -1;          // result SSA id
+    std::vector<int> a_labels, b_labels;  // operand labels (physical order)
+    std::vector<int> c_labels;            // result labels (physical order)
+    std::vector<int> sum_labels;          // labels summed in this step
+    double mults = 0.0;                   // paper's cost of the step
+    bool absorbed = false;   // folded into the larger operand's load
+    bool final_step = false; // writes the net's output
+    bool synthetic = false;  // added by the planner, not part of the path
+    // Kernel geometry (kernel steps only).  Output index o = o_hi*n_olo+o_lo,
+    // summed index s = s_hi*n_slo+s_lo.  Each table entry is an (A offset,
+    // B offset) pair; the operand offset of (o, s) is the sum of the four
+    // table entries it selects.
+    int64_t n_out = 1, n_sum = 1;
+    int64_t n_ohi = 1, n_olo = 1, n_shi = 1, n_slo = 1;
+    int64_t t_ohi = 0, t_olo = 0, t_shi = 0, t_slo = 0;  // offsets in pairs
+    int r_fused = 1;   // lanes per output in the fused kernel (kBlock = block mode)
+    int r_global = 1;  // lanes per output in the per-step kernel
+    // Matrix-core steps (mfma = 1): C[b][m][n] = sum_k A[b][m][k] B[b][n][k]
+    // after packing A to [batch][M][K] and B to [batch][N][K] (same K order).
+    int mfma = 0;
+    std::vector<int> g_batch, g_m, g_n, g_k;  // label groups
+    int64_t gb = 1, gm = 1, gn = 1, gk = 1;   // group extents
+    struct Pack {
+        int64_t n = 0, n_ohi = 1, n_olo = 1, t_ohi = 0, t_olo = 0, t_one = 0;
+    } pack_a, pack_b;
+    int64_t ws_pa = -1, ws_pb = -1;  // workspace byte offsets of the packed operands
+};
+
+// An SSA value: an input tensor (possibly with coefficient tensors folded
+// in) or the result of a kernel step.
+struct Value {
+    std::vector<int> labels;  // physical order
+    int64_t size = 1;
+    bool input = false;
+    int base = -1;            // original tensor id when `input`
+    std::vector<int> scales;  // original tensor ids folded into it
+    int producer = -1;        // step index when not `input`
+};
+
+// A scale table: entry e of the target multiplies by
+// scale_tensor[hi[e / n_lo] + lo[e % n_lo]].
+struct ScaleRef {
+    int tensor = -1;
+    int64_t t_hi = 0, t_lo = 0;  // offsets (in pairs; the .x half is used)
+    int64_t n_lo = 1;
+};
+
+// Materialisation of an input with folded coefficients (per-step executor)
+// or its load into LDS (fused executor).
+struct LoadPlan {
+    int value = -1;   // SSA id
+    int base = -1;    // original tensor id
+    int64_t size = 0;
+    std::vector<ScaleRef> scales;
+};
+
+struct Plan {
+    std::vector<StepPlan> steps;     // path steps + optional synthetic final
+    std::vector<Value> values;       // indexed by SSA id
+    std::vector<int> kernel_steps;   // indices into steps, execution order
+    std::vector<LoadPlan> loads;     // inputs needing scaling (by first use)
+    std::vector<int32_t> tables;     // flat (x, y) pairs
+    int final_value = -1;
+    double mults = 0.0;
+    double peak = 0.0;
+    int n_absorbed = 0;
+    // per-step executor workspace (bytes), offsets per SSA id (-1: input)
+    int64_t ws_bytes = 0;
+    std::vector<int64_t> ws_off;
+    // fused executor: program words, LDS need and spill scratch.  Values
+    // that do not fit the LDS budget live in a per-network global scratch
+    // (fused_scratch_bytes); fused_pure means nothing spilled.
+    bool fused_ok = false;
+    bool fused_pure = false;
+    int64_t fused_lds_bytes = 0;
+    int64_t fused_scratch_bytes = 0;
+    std::vector<int32_t> program;
+};
+
+struct DeviceState;  // defined in the executor
+
+struct Net {
+    // structure
+    int n_t = 0;
+    std::vector<std::vector<int>> labels;
+    std::vector<int64_t> dims;
+    std::vector<int> out_labels;
+    std::vector<int64_t> sizes;
+    htn_dtype storage = HTN_F64, compute = HTN_F64;
+    htn_final_sum final_sum = HTN_SUM_PLAIN;
+    // options
+    htn_exec_mode exec = HTN_EXEC_AUTO;
+    int64_t max_intermediate = (int64_t(1) << 31) - 1;
+    int64_t fused_lds_budget = 65536;
+    double fused_max_mults = 67108864.0;  // AUTO runs larger spilled nets step by step
+    int allow_mfma = 1;
+    // data
+    bool data_on_device = false;
+    std::vector<const void *> user_ptrs;          // borrowed device pointers
+    std::vector<std::vector<unsigned char>> host;  // host copies (compute input dtype)
+    bool data_dirty = true;
+    // path and plan
+    std::vector<std::pair<int, int>> path;
+    int path_kind = HTN_PATH_GREEDY;
+    Plan plan;
+    int plan_version = 0;
+    DeviceState *dev = nullptr;
+};
+
+// Element sizes.
+inline int dtype_size(htn_dtype t) { return t == HTN_F64 ? 8 : (t == HTN_F32 ? 4 : 2); }
+// Type of inputs as stored on the device for a compute type.
+inline htn_dtype input_dtype(htn_dtype compute) { return compute; }
+// Type of intermediates for a compute type.
+inline htn_dtype inter_dtype(htn_dtype compute) { return compute == HTN_F64 ? HTN_F64 : HTN_F32; }
+inline htn_dtype out_dtype(const Net &n) {
+    return n.final_sum == HTN_SUM_PLAIN ? inter_dtype(n.compute) : HTN_F64;
+}
+
+// planner.cpp
+struct Error {
+    htn_status st;
+    std::string msg;
+};
+void validate_structure(const Net &n);                       // throws Error
+std::vector<std::pair<int, int>> greedy_path(const Net &n);  // throws Error
+void check_path(const Net &n, const std::vector<std::pair<int, int>> &p);  // throws Error
+void build_plan(Net &n);                                     // throws Error
+std::string plan_json(const Net &n);
+
+}  // namespace htn

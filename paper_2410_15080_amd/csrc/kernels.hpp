@@ -1,0 +1,68 @@
+// Host-side launchers of the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace htn {
+namespace kern {
+
+// dtype codes follow htn_dtype: 0 f64, 1 f32, 2 bf16.
+
+// Final-step accumulation modes.
+enum FinalMode { FM_INTER = 0, FM_F64 = 1, FM_COMP = 2 };
+
+// Geometry of one pairwise step (see StepPlan).
+struct StepArgs {
+    int32_t n_ohi, n_olo, n_shi, n_slo;
+    int32_t t_ohi, t_olo, t_shi, t_slo;
+    int32_t R;       // lanes per output, power of two <= 64
+    int32_t log2R;
+    int64_t n_out;
+};
+
+// Generic contraction C[o] = sum_s A[offA(o,s)] * B[offB(o,s)] (B == NULL:
+// unary).  ta/tb: operand dtypes; acc_f64: accumulate in FP64; comp:
+// Neumaier compensation (needs acc_f64); tc: output dtype (0 or 1).
+hipError_t launch_step(const void *A, int ta, const void *B, int tb, void *C, int tc, bool acc_f64, bool comp,
+                       const int2 *tab, const StepArgs &s, hipStream_t st);
+
+// Scaled-input materialisation (one launch for all inputs of a net).
+constexpr int kMaxScalesDev = 16;
+struct PrepDesc {
+    const void *src;   // input in its device dtype
+    void *dst;         // intermediate-dtype copy
+    int32_t size;
+    int32_t ns;
+    const void *sp[kMaxScalesDev];
+    int32_t thi[kMaxScalesDev], tlo[kMaxScalesDev], nlo[kMaxScalesDev];
+};
+hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin, int tinter, const int2 *tab,
+                       hipStream_t st);
+
+// Fused whole-network kernel.
+struct FusedDesc {
+    const int32_t *prog;
+    const int2 *tab;
+    const void *const *in;  // device array of input pointers
+    void *scratch;          // spill space for values that do not fit LDS
+};
+// nets[order[b]] is run by workgroup b; outs[net] receives its result.
+// stamps (optional): [2*net] start, [2*net+1] end, 100 MHz ticks.
+// out1 (optional): output of a single-network launch, used instead of outs.
+hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
+                        int n_blocks, int lds_bytes, int compute, int fm, hipStream_t st);
+
+// Matrix-core GEMM C[b][m][n] = sum_k A[b][m][k] B[b][n][k] on packed,
+// K-contiguous operands (mfma.hip).  tin: 0 f64, 1 f32, 2 bf16; tout: 0 f64,
+// 1 f32.  FP32-accumulating inputs with tout == 0 add every `kchunk` K
+// elements into FP64 accumulators.
+hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
+                       int kchunk, hipStream_t st);
+
+// Element-wise dtype conversion on the device.
+hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);
+
+}  // namespace kern
+}  // namespace htn

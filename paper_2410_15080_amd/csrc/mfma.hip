@@ -1,0 +1,234 @@
+// Matrix-core (MFMA) GEMM for pairwise steps that are dense matrix products.
+//
+//   C[b][m][n] = sum_k A[b][m][k] * B[b][n][k]
+//
+// Operands are packed K-contiguous by the step's pack kernels, so every
+// lane's MFMA fragment is a contiguous LDS read.  Workgroup tile 128x128,
+// four wave64s each owning a 64x64 sub-tile (4x4 MFMA 16x16 blocks), K
+// staged through double-buffered LDS.  Per input type:
+//   double : v_mfma_f64_16x16x4_f64,  FP64 accumulation
+//   float  : v_mfma_f32_16x16x4_f32,  FP32 accumulation per K-chunk
+//   bf16   : v_mfma_f32_16x16x32_bf16, FP32 accumulation per K-chunk
+// With FP32 accumulation, every `kchunk` elements of K the partial products
+// are added into FP64 accumulators (the signed QPD sum is combined in FP64).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace htn {
+namespace kern {
+
+typedef uint16_t bf16_t;
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int GBM = 128, GBN = 128;
+
+template <typename T>
+struct MfmaOp;
+
+template <>
+struct MfmaOp<double> {
+    typedef double frag;
+    typedef d4_t acc;
+    static constexpr int KI = 4;   // K per instruction
+    static constexpr int KPL = 1;  // K values per lane
+    static constexpr int BK = 16;
+    static constexpr int PAD = 1;
+    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static frag ld(const double *p) { return *p; }
+};
+
+template <>
+struct MfmaOp<float> {
+    typedef float frag;
+    typedef f4_t acc;
+    static constexpr int KI = 4;
+    static constexpr int KPL = 1;
+    static constexpr int BK = 32;
+    static constexpr int PAD = 1;
+    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static frag ld(const float *p) { return *p; }
+};
+
+template <>
+struct MfmaOp<bf16_t> {
+    typedef bf8_t frag;
+    typedef f4_t acc;
+    static constexpr int KI = 32;
+    static constexpr int KPL = 8;
+    static constexpr int BK = 64;
+    static constexpr int PAD = 8;
+    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static frag ld(const bf16_t *p) { return *(const bf8_t *)p; }
+};
+
+// Load a GBM x BK tile (rows r0.., K-columns k0..) of a [rows][K] operand
+// into registers: 16 bytes per load, zero outside the matrix.
+template <typename T>
+struct TileLoader {
+    static constexpr int BK = MfmaOp<T>::BK;
+    static constexpr int EPV = 16 / sizeof(T);               // elements per 16B vector
+    static constexpr int VPR = BK / EPV;                      // vectors per row
+    static constexpr int NV = GBM * VPR / 256;                // vectors per thread
+    uint4 v[NV];
+    __device__ __forceinline__ void load(const T *__restrict__ src, int rows, int K, int r0, int k0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int idx = threadIdx.x + i * 256;
+            const int r = idx / VPR, c = (idx % VPR) * EPV;
+            const int gr = r0 + r, gk = k0 + c;
+            if (gr < rows && gk + EPV <= K && ((K % EPV) == 0)) {
+                v[i] = *(const uint4 *)(src + (int64_t)gr * K + gk);
+            } else {
+                T tmp[EPV];
+#pragma unroll
+                for (int e = 0; e < EPV; ++e) {
+                    const bool ok = gr < rows && gk + e < K;
+                    tmp[e] = ok ? src[(int64_t)gr * K + gk + e] : T(0);
+                }
+                v[i] = *(const uint4 *)tmp;
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T *lds) const {
+        constexpr int LD = BK + MfmaOp<T>::PAD;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int idx = threadIdx.x + i * 256;
+            const int r = idx / VPR, c = (idx % VPR) * EPV;
+            const T *tv = (const T *)&v[i];
+#pragma unroll
+            for (int e = 0; e < EPV; ++e) lds[r * LD + c + e] = tv[e];
+        }
+    }
+};
+
+template <typename T, typename TOUT, bool COMBINE64>
+__global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, TOUT *__restrict__ C,
+                                             int M, int N, int K, int64_t sA, int64_t sB, int64_t sC, int kchunk) {
+    typedef MfmaOp<T> Op;
+    constexpr int BK = Op::BK;
+    constexpr int LD = BK + Op::PAD;
+    __shared__ __align__(16) T As[2][GBM * LD];
+    __shared__ __align__(16) T Bs[2][GBN * LD];
+    const int bz = blockIdx.z;
+    A += bz * sA;
+    B += bz * sB;
+    C += bz * sC;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = (lane >> 4) * Op::KPL;
+
+    typename Op::acc acc[4][4];
+    d4_t acc64[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = typename Op::acc{0, 0, 0, 0};
+            acc64[i][j] = d4_t{0, 0, 0, 0};
+        }
+
+    TileLoader<T> la, lb;
+    const int nk = (K + BK - 1) / BK;
+    la.load(A, M, K, m0, 0);
+    lb.load(B, N, K, n0, 0);
+    la.store(As[0]);
+    lb.store(Bs[0]);
+    __syncthreads();
+    int since = 0;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) {
+            la.load(A, M, K, m0, (kt + 1) * BK);
+            lb.load(B, N, K, n0, (kt + 1) * BK);
+        }
+        const T *as = As[cur];
+        const T *bs = Bs[cur];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += Op::KI) {
+            typename Op::frag fa[4], fb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = Op::ld(as + (wm + 16 * i + lr) * LD + kk + lk);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = Op::ld(bs + (wn + 16 * j + lr) * LD + kk + lk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(fa[i], fb[j], acc[i][j]);
+        }
+        if constexpr (COMBINE64) {
+            since += BK;
+            if (since >= kchunk || kt + 1 == nk) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            acc64[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = 0;
+                        }
+                since = 0;
+            }
+        }
+        if (kt + 1 < nk) {
+            la.store(As[cur ^ 1]);
+            lb.store(Bs[cur ^ 1]);
+        }
+        __syncthreads();
+    }
+    // D block layout: lane holds rows 4*(lane/16)+r, column lane%16.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm < M && gn < N) {
+                    if constexpr (COMBINE64)
+                        C[(int64_t)gm * N + gn] = (TOUT)acc64[i][j][r];
+                    else
+                        C[(int64_t)gm * N + gn] = (TOUT)acc[i][j][r];
+                }
+            }
+}
+
+hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
+                       int kchunk, hipStream_t st) {
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch);
+    const int64_t sA = (int64_t)M * K, sB = (int64_t)N * K, sC = (int64_t)M * N;
+    if (tin == 0 && tout == 0) {
+        hipLaunchKernelGGL((k_gemm<double, double, false>), grid, dim3(256), 0, st, (const double *)A,
+                           (const double *)B, (double *)C, M, N, K, sA, sB, sC, kchunk);
+    } else if (tin == 1 && tout == 0) {
+        hipLaunchKernelGGL((k_gemm<float, double, true>), grid, dim3(256), 0, st, (const float *)A, (const float *)B,
+                           (double *)C, M, N, K, sA, sB, sC, kchunk);
+    } else if (tin == 1 && tout == 1) {
+        hipLaunchKernelGGL((k_gemm<float, float, false>), grid, dim3(256), 0, st, (const float *)A, (const float *)B,
+                           (float *)C, M, N, K, sA, sB, sC, kchunk);
+    } else if (tin == 2 && tout == 0) {
+        hipLaunchKernelGGL((k_gemm<bf16_t, double, true>), grid, dim3(256), 0, st, (const bf16_t *)A,
+                           (const bf16_t *)B, (double *)C, M, N, K, sA, sB, sC, kchunk);
+    } else if (tin == 2 && tout == 1) {
+        hipLaunchKernelGGL((k_gemm<bf16_t, float, false>), grid, dim3(256), 0, st, (const bf16_t *)A,
+                           (const bf16_t *)B, (float *)C, M, N, K, sA, sB, sC, kchunk);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kern
+}  // namespace htn

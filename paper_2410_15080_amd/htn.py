@@ -1,0 +1,324 @@
+"""Python binding of libhtn (include/htn.h): same names, argument marshalling
+only.  Every computation runs in the HIP library; there is no fallback.
+
+Tensors may be numpy arrays or torch tensors (host or device).  Device
+tensors are borrowed by the library, so the returned :class:`Net` keeps a
+reference to them.  Streams are torch streams or raw hipStream_t integers.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhtn.so")
+
+HTN_F64, HTN_F32, HTN_BF16 = 0, 1, 2
+HTN_SUM_PLAIN, HTN_SUM_FP64, HTN_SUM_COMPENSATED = 0, 1, 2
+HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
+HTN_PATH_GREEDY, HTN_PATH_LEARNED = -1, -2
+HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
+
+STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
+          "HTN_E_DEVICE", "HTN_E_UNSUPPORTED", "HTN_E_STATE"]
+
+
+class HtnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{self.name}: {message}")
+
+
+class htn_info(ctypes.Structure):
+    _fields_ = [("out_elements", ctypes.c_int64), ("out_dtype", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_kernel_steps", ctypes.c_int32),
+                ("n_absorbed", ctypes.c_int32), ("fused_ok", ctypes.c_int32),
+                ("fused_lds_bytes", ctypes.c_int32), ("mults", ctypes.c_double),
+                ("peak_elements", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("input_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libhtn.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_15080_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64 = ctypes.c_int32, ctypes.c_int64
+    i32p = ctypes.POINTER(I32)
+    i64p = ctypes.POINTER(I64)
+    sigs = {
+        "htn_create": (I32, [ctypes.POINTER(P), I32, i32p, i32p, I32, i64p, ctypes.POINTER(P), I32, I32,
+                             i32p, I32, I32, I32]),
+        "htn_set_path": (I32, [P, I32, i32p]),
+        "htn_get_path": (I32, [P, i32p, i32p, I32, ctypes.POINTER(ctypes.c_double)]),
+        "htn_set_option": (I32, [P, I32, I64]),
+        "htn_get_info": (I32, [P, ctypes.POINTER(htn_info)]),
+        "htn_contract": (I32, [P, P, P]),
+        "htn_contract_batch": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P]),
+        "htn_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
+        "htn_batch_set_graph": (I32, [P, I32]),
+        "htn_batch_run": (I32, [P, ctypes.POINTER(P), P]),
+        "htn_batch_timestamps": (I32, [P, i64p]),
+        "htn_batch_destroy": (None, [P]),
+        "htn_update_data": (I32, [P, ctypes.POINTER(P), I32]),
+        "htn_destroy": (None, [P]),
+        "htn_status_string": (ctypes.c_char_p, [I32]),
+        "htn_last_error": (ctypes.c_char_p, []),
+        "htn_plan_json": (I32, [P, ctypes.c_char_p, I64, i64p]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols(header: str | None = None):
+    """Function names declared in include/htn.h."""
+    header = header or os.path.join(os.path.dirname(_HERE), "include", "htn.h")
+    text = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(htn_\w+)\s*\(", text, re.M)))
+
+
+def _check(st: int):
+    if st != 0:
+        lib = load_library()
+        raise HtnError(st, lib.htn_last_error().decode())
+
+
+def _arr(x, dtype):
+    a = np.ascontiguousarray(np.asarray(x, dtype=dtype))
+    return a, a.ctypes.data_as(ctypes.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    name = str(getattr(t, "dtype", t))
+    if "float64" in name:
+        return HTN_F64
+    if "float32" in name:
+        return HTN_F32
+    if "bfloat16" in name:
+        return HTN_BF16
+    raise TypeError(f"unsupported tensor dtype {name}")
+
+
+def _is_device(t) -> bool:
+    return hasattr(t, "is_cuda") and bool(t.is_cuda)
+
+
+def _data_ptr(t) -> int:
+    if hasattr(t, "data_ptr"):
+        return int(t.data_ptr())
+    return int(t.ctypes.data)
+
+
+class Net:
+    """Handle of an htn_net_t plus the Python objects it borrows."""
+
+    def __init__(self, handle, keep, n_tensors):
+        self.handle = handle
+        self._keep = keep
+        self.n_tensors = n_tensors
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                htn_destroy(self)
+            except Exception:
+                pass
+
+
+class Batch:
+    def __init__(self, handle, nets):
+        self.handle = handle
+        self.nets = nets
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                htn_batch_destroy(self)
+            except Exception:
+                pass
+
+
+def _marshal_data(tensors, storage):
+    keep = []
+    ptrs = []
+    on_dev = None
+    for t in tensors:
+        if not hasattr(t, "data_ptr"):
+            t = np.ascontiguousarray(t)
+        elif not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        d = _is_device(t)
+        if on_dev is None:
+            on_dev = d
+        elif on_dev != d:
+            raise ValueError("all tensors must be on the host or all on the device")
+        if _dtype_code(t) != storage:
+            raise ValueError("every tensor must have the storage dtype")
+        keep.append(t)
+        ptrs.append(_data_ptr(t))
+    arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+    return keep, arr, int(bool(on_dev))
+
+
+def htn_create(tensors, labels, dims, out_labels=(), compute=HTN_F64, final_sum=HTN_SUM_PLAIN,
+               storage=None) -> Net:
+    lib = load_library()
+    if storage is None:
+        storage = _dtype_code(tensors[0])
+    for t, ls in zip(tensors, labels):
+        shape = tuple(t.shape)
+        if len(shape) != len(ls) or any(0 <= l < len(dims) and shape[k] != dims[l] for k, l in enumerate(ls)):
+            raise ValueError(f"tensor shape {shape} does not match labels {ls}")
+    keep, ptrs, on_dev = _marshal_data(tensors, storage)
+    ranks, rp = _arr([len(l) for l in labels], np.int32)
+    flat, fp = _arr([x for l in labels for x in l] or [0], np.int32)
+    d, dp = _arr(dims, np.int64)
+    o, op = _arr(list(out_labels) or [0], np.int32)
+    h = ctypes.c_void_p()
+    _check(lib.htn_create(ctypes.byref(h), len(tensors), rp, fp, len(dims), dp, ptrs, on_dev,
+                          len(out_labels), op, storage, compute, final_sum))
+    return Net(h, keep if on_dev else [], len(tensors))
+
+
+def htn_set_path(net: Net, path) -> None:
+    lib = load_library()
+    if isinstance(path, int):
+        _check(lib.htn_set_path(net.handle, path, None))
+        return
+    a, p = _arr(np.asarray(path, dtype=np.int32).reshape(-1) if len(path) else [0], np.int32)
+    _check(lib.htn_set_path(net.handle, len(path), p))
+
+
+def htn_get_path(net: Net):
+    """Returns (list of (i, j) pairs, multiplication count)."""
+    lib = load_library()
+    n = ctypes.c_int32()
+    m = ctypes.c_double()
+    _check(lib.htn_get_path(net.handle, ctypes.byref(n), None, 0, ctypes.byref(m)))
+    buf = np.zeros(max(1, 2 * n.value), dtype=np.int32)
+    _check(lib.htn_get_path(net.handle, ctypes.byref(n), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            n.value, ctypes.byref(m)))
+    return [(int(buf[2 * t]), int(buf[2 * t + 1])) for t in range(n.value)], float(m.value)
+
+
+def htn_set_option(net: Net, opt: int, value: int) -> None:
+    _check(load_library().htn_set_option(net.handle, opt, int(value)))
+
+
+def htn_get_info(net: Net) -> htn_info:
+    info = htn_info()
+    _check(load_library().htn_get_info(net.handle, ctypes.byref(info)))
+    return info
+
+
+def htn_contract(net: Net, out, stream=None) -> None:
+    _check(load_library().htn_contract(net.handle, ctypes.c_void_p(_data_ptr(out)), _stream_ptr(stream)))
+
+
+def htn_contract_batch(nets, outs, stream=None) -> None:
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+    os_ = (ctypes.c_void_p * len(outs))(*[_data_ptr(o) for o in outs])
+    _check(lib.htn_contract_batch(len(nets), hs, os_, _stream_ptr(stream)))
+
+
+def htn_batch_create(nets) -> Batch:
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+    h = ctypes.c_void_p()
+    _check(lib.htn_batch_create(ctypes.byref(h), len(nets), hs))
+    return Batch(h, list(nets))
+
+
+def htn_batch_set_graph(batch: Batch, use_graph: bool) -> None:
+    _check(load_library().htn_batch_set_graph(batch.handle, 1 if use_graph else 0))
+
+
+def htn_batch_run(batch: Batch, outs, stream=None) -> None:
+    os_ = (ctypes.c_void_p * len(outs))(*[_data_ptr(o) for o in outs])
+    _check(load_library().htn_batch_run(batch.handle, os_, _stream_ptr(stream)))
+
+
+def htn_batch_timestamps(batch: Batch) -> np.ndarray:
+    t = np.zeros(len(batch.nets), dtype=np.int64)
+    _check(load_library().htn_batch_timestamps(batch.handle, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return t
+
+
+def htn_batch_destroy(batch: Batch) -> None:
+    if batch.handle:
+        load_library().htn_batch_destroy(batch.handle)
+        batch.handle = None
+
+
+def htn_update_data(net: Net, tensors, storage=None) -> None:
+    if storage is None:
+        storage = _dtype_code(tensors[0])
+    keep, ptrs, on_dev = _marshal_data(tensors, storage)
+    _check(load_library().htn_update_data(net.handle, ptrs, on_dev))
+    net._keep = keep if on_dev else []
+
+
+def htn_destroy(net: Net) -> None:
+    if net.handle:
+        load_library().htn_destroy(net.handle)
+        net.handle = None
+
+
+def htn_status_string(status: int) -> str:
+    return load_library().htn_status_string(status).decode()
+
+
+def htn_last_error() -> str:
+    return load_library().htn_last_error().decode()
+
+
+def htn_plan_json(net: Net) -> str:
+    lib = load_library()
+    need = ctypes.c_int64()
+    _check(lib.htn_plan_json(net.handle, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.htn_plan_json(net.handle, buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def output_dtype_name(net: Net) -> str:
+    return {HTN_F64: "float64", HTN_F32: "float32", HTN_BF16: "bfloat16"}[htn_get_info(net).out_dtype]
+
+
+def new_output(net: Net, device="cuda"):
+    """Allocate a torch tensor of the net's output shape (flat) and dtype."""
+    import torch
+    info = htn_get_info(net)
+    dt = {HTN_F64: torch.float64, HTN_F32: torch.float32}[info.out_dtype]
+    return torch.empty(max(1, info.out_elements), dtype=dt, device=device)

@@ -1,0 +1,165 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header
+declares, validates structure, and accounts cost exactly like the oracle's
+cost model.  Nothing here touches a GPU (htn_create with host data and
+path planning make no HIP call)."""
+
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_15080_amd import htn
+from workloads import configs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = htn.load_library()
+    declared = htn.declared_symbols()
+    assert len(declared) >= 17
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for code, name in enumerate(htn.STATUS):
+        assert htn.htn_status_string(code) == name
+
+
+def _host_net(net_w, **kw):
+    return htn.htn_create(net_w.tensors, net_w.labels, net_w.dims, net_w.out_labels, **kw)
+
+
+def test_worked_example_paths_and_costs():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    rng = np.random.default_rng(0)
+    ts = [rng.uniform(-1, 1, size=[g["dims"][l] for l in ls]) for ls in g["labels"]]
+    net = htn.htn_create(ts, g["labels"], g["dims"], [])
+    htn.htn_set_path(net, g["path"])
+    path, mults = htn.htn_get_path(net)
+    assert path == [tuple(p) for p in g["path"]]
+    assert mults == g["expected_total"]
+    # FLOP-greedy never does worse than the printed order here
+    htn.htn_set_path(net, htn.HTN_PATH_GREEDY)
+    gpath, gm = htn.htn_get_path(net)
+    assert gm <= g["expected_total"]
+    assert gm == sum(oracle.path_cost(g["labels"], g["dims"], [], gpath))
+
+
+def _random_ssa_path(labels, rng):
+    """A random valid SSA path (any pair order, connected or not)."""
+    live = list(range(len(labels)))
+    nxt = len(labels)
+    path = []
+    while len(live) > 1:
+        i, j = rng.sample(live, 2)
+        path.append((i, j))
+        live.remove(i)
+        live.remove(j)
+        live.append(nxt)
+        nxt += 1
+    return path
+
+
+@pytest.mark.parametrize("maker", ["grid", "ring", "gates"])
+def test_planner_cost_matches_oracle_cost_model(maker):
+    rng = random.Random(3)
+    for seed in range(4):
+        if maker == "grid":
+            w = configs.grid_network(seed)
+        elif maker == "ring":
+            w = configs.ring_of_rings(seed)
+        else:
+            w, _ = configs.circuit_cut_gates(seed, 2)
+        net = _host_net(w)
+        path, m = htn.htn_get_path(net)
+        assert m == sum(oracle.path_cost(w.labels, w.dims, w.out_labels, path))
+        if maker == "gates":
+            rp = _random_ssa_path(w.labels, rng)
+            htn.htn_set_path(net, rp)
+            _, m2 = htn.htn_get_path(net)
+            assert m2 == sum(oracle.path_cost(w.labels, w.dims, w.out_labels, rp))
+
+
+def test_random_paths_on_small_networks_match_cost_model():
+    rng = random.Random(5)
+    nrng = np.random.default_rng(5)
+    for _ in range(40):
+        n_labels = int(nrng.integers(3, 7))
+        dims = [int(d) for d in nrng.integers(2, 5, size=n_labels)]
+        labels = [[int(x) for x in nrng.choice(n_labels, size=int(nrng.integers(1, 4)), replace=False)]
+                  for _ in range(int(nrng.integers(2, 6)))]
+        used = sorted({l for ls in labels for l in ls})
+        out = [int(x) for x in nrng.choice(used, size=min(len(used), int(nrng.integers(0, 3))), replace=False)]
+        ts = [nrng.uniform(-1, 1, size=[dims[l] for l in ls]) for ls in labels]
+        net = htn.htn_create(ts, labels, dims, out)
+        rp = _random_ssa_path(labels, rng)
+        htn.htn_set_path(net, rp)
+        _, m = htn.htn_get_path(net)
+        assert m == sum(oracle.path_cost(labels, dims, out, rp))
+
+
+def test_absorption_folds_coefficient_vectors():
+    w = configs.grid_network(0)
+    net = _host_net(w)
+    info = htn.htn_get_info(net)
+    assert info.n_absorbed == 24          # every CT folds into a QT load
+    assert info.n_kernel_steps == 15      # 16 QTs -> 15 pairwise kernels
+    plan = json.loads(htn.htn_plan_json(net))
+    assert sum(1 for s in plan["steps"] if s["absorbed"]) == 24
+
+
+def test_marginal_plan_is_one_big_contraction():
+    w = configs.marginal_network(0, out_bits=12)
+    net = _host_net(w)
+    plan = json.loads(htn.htn_plan_json(net))
+    last = plan["steps"][-1]
+    assert last["final"] and last["n_out"] == 4096 * 4096 and last["n_sum"] == 256
+    assert plan["mults"] == 4 * 4 ** 5 * 4096 + 4096 * 4096 * 256
+
+
+def _expect(status, fn, *a, **kw):
+    with pytest.raises(htn.HtnError) as e:
+        fn(*a, **kw)
+    assert e.value.name == status, str(e.value)
+
+
+def test_structural_errors():
+    a = np.ones((2, 3))
+    b = np.ones((3, 4))
+    _expect("HTN_E_LABEL", htn.htn_create, [a, b], [[0, 1], [1, 5]], [2, 3, 4], [])
+    _expect("HTN_E_LABEL", htn.htn_create, [np.ones((2, 2))], [[0, 0]], [2, 3], [])
+    _expect("HTN_E_LABEL", htn.htn_create, [a, b], [[0, 1], [1, 2]], [2, 3, 4, 5], [3])
+    _expect("HTN_E_LABEL", htn.htn_create, [a, b], [[0, 1], [1, 2]], [2, 3, 4], [0, 0])
+    net = htn.htn_create([a, b], [[0, 1], [1, 2]], [2, 3, 4], [0, 2])
+    _expect("HTN_E_PATH", htn.htn_set_path, net, [(0, 0)])
+    _expect("HTN_E_PATH", htn.htn_set_path, net, [(0, 2)])
+    _expect("HTN_E_PATH", htn.htn_set_path, net, [(0, 1), (2, 0)])
+    _expect("HTN_E_ARG", htn.htn_set_path, net, -7)
+    _expect("HTN_E_ARG", htn.htn_set_option, net, htn.HTN_OPT_EXEC, 9)
+    # a failed call leaves the previous path in place
+    htn.htn_set_path(net, [(1, 0)])
+    _expect("HTN_E_PATH", htn.htn_set_path, net, [(1, 1)])
+    assert htn.htn_get_path(net)[0] == [(1, 0)]
+
+
+def test_intermediate_cap_reports_oom():
+    w = configs.marginal_network(0, out_bits=8)
+    net = _host_net(w)
+    _expect("HTN_E_OOM", htn.htn_set_option, net, htn.HTN_OPT_MAX_INTERMEDIATE, 1000)
+    # the previous plan survives
+    assert htn.htn_get_info(net).out_elements == 256 * 256
+
+
+def test_output_dtype_follows_final_sum():
+    w = configs.grid_network(0)
+    for compute, fs, want in [(htn.HTN_F64, htn.HTN_SUM_PLAIN, htn.HTN_F64),
+                              (htn.HTN_F32, htn.HTN_SUM_PLAIN, htn.HTN_F32),
+                              (htn.HTN_F32, htn.HTN_SUM_COMPENSATED, htn.HTN_F64),
+                              (htn.HTN_BF16, htn.HTN_SUM_FP64, htn.HTN_F64)]:
+        net = _host_net(w, compute=compute, final_sum=fs)
+        assert htn.htn_get_info(net).out_dtype == want

@@ -1,0 +1,215 @@
+"""GPU parity: libhtn (through the C ABI) against the CPU oracle.
+
+FP64 results must match the oracle's double-double value to 1e-10
+relative (scalars) or the stated absolute bound (marginals).
+"""
+
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_15080_amd import htn
+from workloads import configs
+from workloads import statevector as sv
+
+from gpu_helpers import create, contract, rel_err, run
+
+pytestmark = pytest.mark.gpu
+
+EXECS = [htn.HTN_EXEC_STEPS, htn.HTN_EXEC_FUSED]
+REL_F64 = 1e-10
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+def test_wire_cut_circuit_matches_oracle_and_statevector(exec_mode):
+    for seed in range(3):
+        w = configs.circuit_cut_wires(seed)
+        got = float(run(w, exec_mode=exec_mode))
+        ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        full = sv.run_ops(sv.zero_state(10), configs.circuit1_full_ops(seed), {q: "Z" for q in range(10)})
+        assert abs(got - float(ref)) <= REL_F64 * abs(float(ref))
+        assert abs(got - full) < 1e-14
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+def test_gate_cut_circuits(exec_mode):
+    for n_cuts in (1, 2):
+        w, _ = configs.circuit_cut_gates(1, n_cuts)
+        got = float(run(w, exec_mode=exec_mode))
+        ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        assert abs(got - float(ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+@pytest.mark.parametrize("seed", range(6))
+def test_grid_f64(exec_mode, seed):
+    w = configs.grid_network(seed)
+    got = float(run(w, exec_mode=exec_mode))
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    ref = float(hi) + float(lo)
+    assert abs(got - ref) <= REL_F64 * abs(ref), (got, ref)
+
+
+def test_grid_fused_all_in_lds_and_spilled_agree():
+    """The same network with a large and a tiny LDS budget (everything
+    spilled to global scratch)."""
+    w = configs.grid_network(2)
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    ref = float(hi) + float(lo)
+    for lds in (163840, 65536, 4096, 1024):
+        got = float(run(w, exec_mode=htn.HTN_EXEC_FUSED, lds=lds))
+        assert abs(got - ref) <= REL_F64 * abs(ref), (lds, got, ref)
+
+
+def _random_network(rng):
+    n_labels = int(rng.integers(3, 8))
+    dims = [int(d) for d in rng.integers(1, 6, size=n_labels)]
+    n_t = int(rng.integers(1, 6))
+    labels = []
+    for _ in range(n_t):
+        r = int(rng.integers(1, min(4, n_labels) + 1))
+        labels.append([int(x) for x in rng.choice(n_labels, size=r, replace=False)])
+    used = sorted({l for ls in labels for l in ls})
+    n_out = int(rng.integers(0, 4))
+    out = [int(x) for x in rng.choice(used, size=min(n_out, len(used)), replace=False)]
+    tensors = [rng.uniform(-1, 1, size=[dims[l] for l in ls]) for ls in labels]
+    from workloads.network import Network
+    return Network(tensors, labels, dims, out)
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+def test_random_networks_hyperedges_outputs_dangling_labels(exec_mode):
+    """Arbitrary label layouts: hyperedges in 3+ tensors, labels summed out
+    of one tensor, open outputs in any order, size-1 extents, one tensor."""
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        w = _random_network(rng)
+        got = run(w, exec_mode=exec_mode)
+        ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def _random_connected_path(labels, rng):
+    live = {i: set(ls) for i, ls in enumerate(labels)}
+    nxt = len(labels)
+    path = []
+    while len(live) > 1:
+        ids = sorted(live)
+        pairs = [(a, b) for ai, a in enumerate(ids) for b in ids[ai + 1:] if live[a] & live[b]]
+        a, b = rng.choice(pairs) if pairs else tuple(rng.sample(ids, 2))
+        if rng.random() < 0.5:
+            a, b = b, a
+        path.append((a, b))
+        live[nxt] = live.pop(a) | live.pop(b)
+        nxt += 1
+    return path
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+def test_path_independence(exec_mode):
+    """Greedy, operand-swapped greedy and random connected paths agree."""
+    rng = random.Random(7)
+    w = configs.grid_network(4)
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    ref = float(hi) + float(lo)
+    net = create(w, exec_mode=exec_mode)
+    greedy, _ = htn.htn_get_path(net)
+    paths = [greedy, [(b, a) for a, b in greedy]] + [_random_connected_path(w.labels, rng) for _ in range(3)]
+    for p in paths:
+        try:
+            got = float(run(w, exec_mode=exec_mode, path=p))
+        except htn.HtnError as e:
+            assert e.name == "HTN_E_OOM"
+            continue
+        assert abs(got - ref) <= REL_F64 * abs(ref), (p, got, ref)
+
+
+def test_batch_equals_single_and_oracle():
+    import torch
+    ws = [configs.grid_network(s) for s in range(48)]
+    nets = [create(w) for w in ws]
+    outs = [htn.new_output(n) for n in nets]
+    htn.htn_contract_batch(nets, outs)
+    torch.cuda.synchronize()
+    for w, n, o in zip(ws, nets, outs):
+        single = htn.new_output(n)
+        htn.htn_contract(n, single)
+        torch.cuda.synchronize()
+        assert float(o.item()) == float(single.item())   # same plan, same kernel
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = float(hi) + float(lo)
+        assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref)
+
+
+def test_batch_graph_replays_match_eager():
+    import torch
+    ws = [configs.grid_network(100 + s) for s in range(32)]
+    nets = [create(w) for w in ws]
+    outs = [htn.new_output(n) for n in nets]
+    b = htn.htn_batch_create(nets)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        htn.htn_batch_run(b, outs, stream)
+    stream.synchronize()
+    eager = [float(o.item()) for o in outs]
+    htn.htn_batch_set_graph(b, True)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            htn.htn_batch_run(b, outs, stream)
+        stream.synchronize()
+        assert [float(o.item()) for o in outs] == eager, rep
+    t = htn.htn_batch_timestamps(b)
+    assert (t > 0).all()
+
+
+def test_ring_of_rings_f64():
+    for seed in range(2):
+        w = configs.ring_of_rings(seed)
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = float(hi) + float(lo)
+        for exec_mode in (htn.HTN_EXEC_STEPS, htn.HTN_EXEC_AUTO):
+            got = float(run(w, exec_mode=exec_mode))
+            assert abs(got - ref) <= REL_F64 * abs(ref), (seed, exec_mode, got, ref)
+
+
+def test_marginal_small_full_compare():
+    w = configs.marginal_network(3, out_bits=6)
+    ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    for exec_mode in EXECS:
+        got = run(w, exec_mode=exec_mode)
+        assert np.abs(got - ref).max() <= 1e-15
+        assert abs(got.sum() - 1.0) < 1e-12
+
+
+def test_marginal_full_size_sampled_entries():
+    """4096 x 4096 marginal: 64 sampled entries recomputed one by one by the
+    naive oracle on sliced tensors, plus the sum invariant."""
+    w = configs.marginal_network(0, out_bits=12)
+    got = run(w)
+    assert got.shape == (4096, 4096)
+    assert abs(got.sum() - 1.0) < 1e-9
+    rng = np.random.default_rng(0)
+    c = 4
+    for _ in range(64):
+        x1, x2 = (int(v) for v in rng.integers(0, 4096, size=2))
+        t1 = w.tensors[0][..., x1]
+        t2 = w.tensors[1][..., x2]
+        labels = [list(range(c)), list(range(c, 2 * c))] + w.labels[2:]
+        ref, _ = oracle.naive_contract([t1, t2] + w.tensors[2:], labels, w.dims[:2 * c], [])
+        assert abs(got[x1, x2] - float(ref)) <= 1e-17 + 1e-12 * abs(float(ref))
+
+
+def test_update_data_reuses_plan():
+    w = configs.grid_network(9)
+    net = create(w, on_device=False)
+    a = float(contract(net, ()))
+    w2 = configs.grid_network(9)
+    w2.tensors = [t * 0.5 if k == 0 else t for k, t in enumerate(w2.tensors)]
+    htn.htn_update_data(net, [np.ascontiguousarray(t) for t in w2.tensors])
+    b = float(contract(net, ()))
+    assert abs(b - 0.5 * a) <= 1e-13 * abs(a)
