@@ -92,6 +92,7 @@ typedef enum { HTN_EXEC_AUTO = 0, HTN_EXEC_STEPS = 1, HTN_EXEC_FUSED = 2 } htn_e
 /* Path selectors for htn_set_path's n_steps argument. */
 #define HTN_PATH_GREEDY (-1)
 #define HTN_PATH_LEARNED (-2)
+#define HTN_PATH_SAMPLED (-3)
 
 /* ---------------------------------------------------------------------
  * htn_create — build a net from tensors and labels.
@@ -141,10 +142,17 @@ htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks,
  *                 pairs sharing a label, with the fewest multiplications;
  *                 ties go to the smaller result, then to the lower ids;
  *                 disconnected parts are joined last, smallest first.
- *   HTN_PATH_LEARNED  path proposed by the installed cost model
- *                 (htn_model_set); falls back to FLOP-greedy when no model
- *                 is installed or when the model does not predict the
- *                 candidate to be faster than the greedy path.
+ *   HTN_PATH_SAMPLED  the cheapest (by multiplications) of the FLOP-greedy
+ *                 path and HTN_OPT_PATH_SAMPLES Boltzmann-sampled greedy
+ *                 paths: at each step a sharing pair is drawn with weight
+ *                 exp(-(log2 cost - log2 min cost) / T), T cycling through
+ *                 0.25, 0.5, 1, 2; deterministic for a given
+ *                 HTN_OPT_PATH_SEED.  Never costlier than FLOP-greedy.
+ *   HTN_PATH_LEARNED  the candidate (FLOP-greedy plus the sampled paths)
+ *                 with the lowest total time predicted by the installed
+ *                 cost model (htn_model_set); FLOP-greedy when no model is
+ *                 installed or when no candidate is predicted faster than
+ *                 FLOP-greedy.
  * Errors: HTN_E_PATH for a malformed path; HTN_E_OOM if an intermediate
  * exceeds the size cap (htn_set_option HTN_OPT_MAX_INTERMEDIATE).
  * ------------------------------------------------------------------- */
@@ -161,7 +169,9 @@ typedef enum {
     HTN_OPT_EXEC = 0,              /* htn_exec_mode                            */
     HTN_OPT_MAX_INTERMEDIATE = 1,  /* cap on intermediate elements (default 2^31-1) */
     HTN_OPT_FUSED_LDS_BYTES = 2,   /* LDS budget of the fused kernel (default 65536) */
-    HTN_OPT_MFMA = 3               /* 1: allow matrix-core steps (default), 0: VALU only */
+    HTN_OPT_MFMA = 3,              /* 1: allow matrix-core steps (default), 0: VALU only */
+    HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
+    HTN_OPT_PATH_SEED = 5          /* seed of the path sampler (default 0) */
 } htn_option;
 
 htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value);
@@ -205,10 +215,22 @@ htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *out
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets);
 htn_status htn_batch_set_graph(htn_batch_t batch, int32_t use_graph);
 htn_status htn_batch_run(htn_batch_t batch, void *const *outs, void *hip_stream);
-/* Per-net completion times of the last run, in ticks of the device's
- * constant 100 MHz clock after the launch's first workgroup started
- * (fused nets only; -1 for nets run step by step).                        */
+/* Per-net start and completion times of the last run: ticks[2*i] and
+ * ticks[2*i+1], in ticks of the device's constant 100 MHz clock counted
+ * from the first workgroup start of the run (fused nets only; -1 for nets
+ * run step by step).  ticks holds 2*n values.  Synchronise the stream of
+ * the run first.                                                          */
 htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
+/* Per-phase timing of the fused kernel.  A fused network runs as a sequence
+ * of phases separated by workgroup barriers (phase 0 loads the operands of
+ * the first step; phase k >= 1 runs kernel step k-1 of the plan and loads
+ * the operands of the next).  With max_phases > 0 every run records, for
+ * each fused net and each of its first max_phases phases, the clock at the
+ * end of the phase.  htn_batch_phase_times writes n * max_phases values
+ * ([net][phase], 100 MHz ticks counted from the first workgroup start; -1
+ * for phases not recorded).  Set before a graph is captured.             */
+htn_status htn_batch_set_phase_timing(htn_batch_t batch, int32_t max_phases);
+htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
 void htn_batch_destroy(htn_batch_t batch);
 
 /* htn_update_data — replace the tensor values (same structure and path).
@@ -225,6 +247,13 @@ const char *htn_last_error(void);
  * bytes including the terminating NUL; *needed receives the full length
  * plus one.                                                               */
 htn_status htn_plan_json(htn_net_t net, char *buf, int64_t capacity, int64_t *needed);
+
+/* htn_plan_tables — the plan's offset-table arena (int32 pairs as laid out
+ * on the device), for tools that check a plan on the host.  Same buffer
+ * convention as htn_plan_json: writes min(capacity, size) int32 values;
+ * *needed receives the arena length in int32 values.  Offsets named in
+ * htn_plan_json ("t_*" fields) index pairs of this arena.                  */
+htn_status htn_plan_tables(htn_net_t net, int32_t *buf, int64_t capacity, int64_t *needed);
 
 #ifdef __cplusplus
 }

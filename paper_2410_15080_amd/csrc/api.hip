@@ -20,10 +20,15 @@ static htn_status fail(htn_status s, const std::string &m) {
     return s;
 }
 
-#define HIP_TRY(x)                                                                                  \
-    do {                                                                                            \
-        hipError_t e_ = (x);                                                                        \
-        if (e_ != hipSuccess) throw Error{HTN_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+// On failure the thread's sticky HIP error is cleared so that it is not
+// reported again by an unrelated later call.
+#define HIP_TRY(x)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) {                                                           \
+            (void)hipGetLastError();                                                      \
+            throw Error{HTN_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};    \
+        }                                                                                 \
     } while (0)
 
 #define API_GUARD_BEGIN try {
@@ -52,6 +57,9 @@ struct DeviceState {
     kern::PrepDesc *d_prep = nullptr;
     int n_prep = 0, prep_max = 0;
     kern::FusedDesc *d_fdesc = nullptr;
+    kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of the fused path
+    std::vector<kern::FPrepEntry> fprep;
+    int fprep_max = 0;
     int plan_uploaded = -1;
 };
 }  // namespace htn
@@ -63,6 +71,8 @@ struct htn_batch {
         int compute = 0, fm = 0, lds = 0;
         std::vector<int> idx;  // net indices, heaviest first
         int32_t *d_order = nullptr;
+        kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of every net
+        int n_fprep = 0, fprep_max = 0;
     };
     std::vector<htn_net *> nets;
     std::vector<int> versions;
@@ -77,6 +87,8 @@ struct htn_batch {
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
     std::vector<void *> graph_outs;
+    int64_t *d_phase = nullptr;  // per-phase clock of fused nets (optional)
+    int max_phases = 0;
 };
 
 // ------------------------------------------------------------- helpers
@@ -152,6 +164,7 @@ static void release_device(Net &n) {
     dfree(D.d_ws);
     dfree(D.d_prep);
     dfree(D.d_fdesc);
+    dfree(D.d_fprep);
     delete n.dev;
     n.dev = nullptr;
 }
@@ -207,9 +220,16 @@ static void upload_inputs(Net &n) {
 static void upload_plan(Net &n) {
     DeviceState &D = *n.dev;
     Plan &P = n.plan;
+    // the fused program carries the device addresses of its inputs
+    std::vector<int32_t> prog = P.program;
+    for (auto &ps : P.ptr_slots) {
+        const uint64_t a = (uint64_t)(uintptr_t)D.in[ps.second];
+        prog[ps.first] = (int32_t)(uint32_t)(a & 0xffffffffu);
+        prog[ps.first + 1] = (int32_t)(uint32_t)(a >> 32);
+    }
     dfree(D.d_prog);
-    D.d_prog = dalloc<int32_t>(P.program.size());
-    HIP_TRY(hipMemcpy(D.d_prog, P.program.data(), P.program.size() * 4, hipMemcpyHostToDevice));
+    D.d_prog = dalloc<int32_t>(prog.size());
+    HIP_TRY(hipMemcpy(D.d_prog, prog.data(), prog.size() * 4, hipMemcpyHostToDevice));
     dfree(D.d_tab);
     D.d_tab = dalloc<int2>(P.tables.size() / 2);
     HIP_TRY(hipMemcpy(D.d_tab, P.tables.data(), P.tables.size() * 4, hipMemcpyHostToDevice));
@@ -223,7 +243,7 @@ static void upload_plan(Net &n) {
     std::vector<kern::PrepDesc> prep;
     int pmax = 0;
     for (const LoadPlan &lp : P.loads) {
-        if (lp.scales.empty()) continue;
+        if (!lp.needs_copy()) continue;
         kern::PrepDesc q;
         std::memset(&q, 0, sizeof(q));
         q.src = D.in[lp.base];
@@ -236,6 +256,9 @@ static void upload_plan(Net &n) {
             q.tlo[k] = (int32_t)lp.scales[k].t_lo;
             q.nlo[k] = (int32_t)lp.scales[k].n_lo;
         }
+        q.sthi = (int32_t)lp.src_thi;
+        q.stlo = (int32_t)lp.src_tlo;
+        q.snlo = (int32_t)lp.src_nlo;
         pmax = std::max<int>(pmax, q.size);
         prep.push_back(q);
     }
@@ -246,6 +269,19 @@ static void upload_plan(Net &n) {
     if (!prep.empty()) {
         D.d_prep = dalloc<kern::PrepDesc>(prep.size());
         HIP_TRY(hipMemcpy(D.d_prep, prep.data(), prep.size() * sizeof(kern::PrepDesc), hipMemcpyHostToDevice));
+    }
+    D.fprep.clear();
+    D.fprep_max = 0;
+    for (const LoadPlan &lp : P.loads) {
+        D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws});
+        D.fprep_max = std::max<int>(D.fprep_max, (int)lp.size);
+    }
+    dfree(D.d_fprep);
+    D.d_fprep = nullptr;
+    if (!D.fprep.empty()) {
+        D.d_fprep = dalloc<kern::FPrepEntry>(D.fprep.size());
+        HIP_TRY(hipMemcpy(D.d_fprep, D.fprep.data(), D.fprep.size() * sizeof(kern::FPrepEntry),
+                          hipMemcpyHostToDevice));
     }
     kern::FusedDesc fd{D.d_prog, D.d_tab, (const void *const *)D.d_inptrs, D.d_ws};
     dfree(D.d_fdesc);
@@ -273,15 +309,26 @@ static int final_mode(const Net &n) {
     return kern::FM_INTER;
 }
 
+static bool use_fused_in_batch(const Net &n) {
+    if (n.exec == HTN_EXEC_STEPS) return false;
+    if (n.exec == HTN_EXEC_FUSED) return n.plan.fused_possible;
+    return n.plan.fused_batch_ok;
+}
+
 static bool use_fused(const Net &n) {
     if (n.exec == HTN_EXEC_STEPS) return false;
-    if (n.exec == HTN_EXEC_FUSED) return true;  // spills to global scratch if needed
+    if (n.exec == HTN_EXEC_FUSED) {
+        if (!n.plan.fused_possible)
+            throw Error{HTN_E_UNSUPPORTED, "fused kernel: program and table slots exceed the LDS budget"};
+        return true;  // values that do not fit LDS spill to global scratch
+    }
     return n.plan.fused_ok;
 }
 
 static void run_fused_single(Net &n, void *out, hipStream_t st) {
-    HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, 1, (int)n.plan.fused_lds_bytes,
-                               (int)n.compute, final_mode(n), st));
+    HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, st));
+    HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, nullptr, 0, 1,
+                               (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), st));
 }
 
 static kern::StepArgs pack_args(const StepPlan::Pack &pk) {
@@ -450,8 +497,14 @@ htn_status htn_set_path(htn_net_t net, int32_t n_steps, const int32_t *ssa_pairs
             check_path(*net, p);
             net->path = p;
             net->path_kind = 0;
-        } else if (n_steps == HTN_PATH_GREEDY || n_steps == HTN_PATH_LEARNED) {
+        } else if (n_steps == HTN_PATH_GREEDY) {
             net->path = greedy_path(*net);
+            net->path_kind = n_steps;
+        } else if (n_steps == HTN_PATH_SAMPLED) {
+            net->path = sampled_path(*net, net->path_samples, net->path_seed);
+            net->path_kind = n_steps;
+        } else if (n_steps == HTN_PATH_LEARNED) {
+            net->path = learned_path(*net);
             net->path_kind = n_steps;
         } else {
             return fail(HTN_E_ARG, "unknown path selector");
@@ -510,6 +563,13 @@ htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
         case HTN_OPT_MFMA:
             net->allow_mfma = value ? 1 : 0;
             replan(*net);
+            return HTN_OK;
+        case HTN_OPT_PATH_SAMPLES:
+            if (value < 0 || value > 100000) return fail(HTN_E_ARG, "path samples outside [0, 100000]");
+            net->path_samples = (int)value;
+            return HTN_OK;
+        case HTN_OPT_PATH_SEED:
+            net->path_seed = (uint64_t)value;
             return HTN_OK;
     }
     return fail(HTN_E_ARG, "unknown option");
@@ -580,6 +640,16 @@ htn_status htn_plan_json(htn_net_t net, char *buf, int64_t capacity, int64_t *ne
     API_GUARD_END
 }
 
+htn_status htn_plan_tables(htn_net_t net, int32_t *buf, int64_t capacity, int64_t *needed) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    const auto &t = net->plan.tables;
+    if (needed) *needed = (int64_t)t.size();
+    if (buf && capacity > 0) std::memcpy(buf, t.data(), sizeof(int32_t) * (size_t)std::min<int64_t>(capacity, t.size()));
+    return HTN_OK;
+    API_GUARD_END
+}
+
 // ---------------------------------------------------------------- batch
 
 static void batch_free(htn_batch *b) {
@@ -587,10 +657,14 @@ static void batch_free(htn_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    for (auto &g : b->groups) dfree(g.d_order);
+    for (auto &g : b->groups) {
+        dfree(g.d_order);
+        dfree(g.d_fprep);
+    }
     dfree(b->d_desc);
     dfree(b->d_outs);
     dfree(b->d_stamps);
+    dfree(b->d_phase);
 }
 
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
@@ -608,7 +682,7 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
             b->versions.push_back(net.plan_version);
             desc[i] = kern::FusedDesc{net.dev->d_prog, net.dev->d_tab, (const void *const *)net.dev->d_inptrs,
                                       net.dev->d_ws};
-            if (!use_fused(net)) {
+            if (!use_fused_in_batch(net)) {
                 b->step_nets.push_back(i);
                 continue;
             }
@@ -630,6 +704,17 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
                              [&](int x, int y) { return nets[x]->plan.mults > nets[y]->plan.mults; });
             g.d_order = dalloc<int32_t>(g.idx.size());
             HIP_TRY(hipMemcpy(g.d_order, g.idx.data(), g.idx.size() * 4, hipMemcpyHostToDevice));
+            std::vector<kern::FPrepEntry> fp;
+            for (int i : g.idx) {
+                const DeviceState &D = *nets[i]->dev;
+                fp.insert(fp.end(), D.fprep.begin(), D.fprep.end());
+                g.fprep_max = std::max(g.fprep_max, D.fprep_max);
+            }
+            g.n_fprep = (int)fp.size();
+            if (!fp.empty()) {
+                g.d_fprep = dalloc<kern::FPrepEntry>(fp.size());
+                HIP_TRY(hipMemcpy(g.d_fprep, fp.data(), fp.size() * sizeof(kern::FPrepEntry), hipMemcpyHostToDevice));
+            }
         }
         b->d_desc = dalloc<kern::FusedDesc>(n);
         HIP_TRY(hipMemcpy(b->d_desc, desc.data(), n * sizeof(kern::FusedDesc), hipMemcpyHostToDevice));
@@ -655,8 +740,10 @@ htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
 
 static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
     for (auto &g : b->groups)
-        HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, (int)g.idx.size(), g.lds,
-                                   g.compute, g.fm, st));
+        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, st));
+    for (auto &g : b->groups)
+        HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
+                                   (int)g.idx.size(), g.lds, g.compute, g.fm, st));
     for (int i : b->step_nets) run_steps(*b->nets[i], outs[i], st);
 }
 
@@ -721,7 +808,44 @@ htn_status htn_batch_timestamps(htn_batch_t b, int64_t *ticks) {
             fused[i] = 1;
             t0 = std::min(t0, st[2 * i]);
         }
-    for (int i = 0; i < n; ++i) ticks[i] = fused[i] ? st[2 * i + 1] - t0 : -1;
+    for (int i = 0; i < n; ++i) {
+        ticks[2 * i] = fused[i] ? st[2 * i] - t0 : -1;
+        ticks[2 * i + 1] = fused[i] ? st[2 * i + 1] - t0 : -1;
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_set_phase_timing(htn_batch_t b, int32_t max_phases) {
+    API_GUARD_BEGIN
+    if (!b || max_phases < 0) return fail(HTN_E_ARG, "bad arguments");
+    if (b->gexec) return fail(HTN_E_STATE, "phase timing must be set before the graph is captured");
+    dfree(b->d_phase);
+    b->d_phase = nullptr;
+    b->max_phases = max_phases;
+    if (max_phases > 0) {
+        const size_t n = (size_t)max_phases * b->nets.size();
+        b->d_phase = dalloc<int64_t>(n);
+        std::vector<int64_t> neg(n, -1);
+        HIP_TRY(hipMemcpy(b->d_phase, neg.data(), n * 8, hipMemcpyHostToDevice));
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_phase_times(htn_batch_t b, int64_t *ticks) {
+    API_GUARD_BEGIN
+    if (!b || !ticks) return fail(HTN_E_ARG, "NULL argument");
+    if (!b->d_phase) return fail(HTN_E_STATE, "phase timing is off");
+    const int n = (int)b->nets.size();
+    const size_t cnt = (size_t)b->max_phases * n;
+    std::vector<int64_t> ph(cnt), st(2 * (size_t)n);
+    HIP_TRY(hipMemcpy(ph.data(), b->d_phase, cnt * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st.data(), b->d_stamps, st.size() * 8, hipMemcpyDeviceToHost));
+    int64_t t0 = INT64_MAX;
+    for (auto &g : b->groups)
+        for (int i : g.idx) t0 = std::min(t0, st[2 * i]);
+    for (size_t k = 0; k < cnt; ++k) ticks[k] = ph[k] >= 0 ? ph[k] - t0 : -1;
     return HTN_OK;
     API_GUARD_END
 }

@@ -14,7 +14,7 @@ namespace htn {
 // Threads per workgroup of the fused and per-step kernels.
 constexpr int kBlock = 256;
 // Largest number of coefficient tensors folded into one operand load.
-constexpr int kMaxScales = 16;
+constexpr int kMaxScales = 8;
 
 // Largest extent product kept in the low half of a two-level offset table.
 constexpr int64_t kTabLoMax = 1024;
@@ -48,6 +48,15 @@ struct StepPlan {
         int64_t n = 0, n_ohi = 1, n_olo = 1, t_ohi = 0, t_olo = 0, t_one = 0;
     } pack_a, pack_b;
     int64_t ws_pa = -1, ws_pb = -1;  // workspace byte offsets of the packed operands
+    // Register-tiled steps (tile = 1, fused kernel): a plain GEMM view
+    // C[m][n] = sum_k A[k][m] B[k][n] with A laid out [K][M] and B [K][N]
+    // (same K order), so the inner loop has unit strides; C is written
+    // through offset tables t_cm[m] + t_cn[n] into its consumer's layout.
+    int tile = 0;
+    std::vector<int> t_gm, t_gn, t_gk;  // tiled view's groups (ascending labels)
+    int64_t tM = 1, tN = 1, tK = 1;
+    int64_t t_cm = 0, t_cn = 0;  // table offsets (pairs, .x used)
+    int TM = 1, TN = 1, GX = 16;  // per-thread tile and thread-grid width
 };
 
 // An SSA value: an input tensor (possibly with coefficient tensors folded
@@ -73,9 +82,17 @@ struct ScaleRef {
 // or its load into LDS (fused executor).
 struct LoadPlan {
     int value = -1;   // SSA id
+    // digit form of the load (fused kernel): value labels in layout order
+    // with extents, the base tensor's stride and each scale's stride per
+    // label (0 when the scale does not carry it)
     int base = -1;    // original tensor id
     int64_t size = 0;
     std::vector<ScaleRef> scales;
+    // Layout change: entry e of the value reads the base tensor at
+    // src_hi[e / src_nlo] + src_lo[e % src_nlo] (src_nlo = 0: same layout).
+    int64_t src_thi = 0, src_tlo = 0, src_nlo = 0;
+    int64_t desc_word = -1;  // word offset of its digit-form descriptor in the fused image
+    bool needs_copy() const { return !scales.empty() || src_nlo > 0; }
 };
 
 struct Plan {
@@ -94,11 +111,18 @@ struct Plan {
     // fused executor: program words, LDS need and spill scratch.  Values
     // that do not fit the LDS budget live in a per-network global scratch
     // (fused_scratch_bytes); fused_pure means nothing spilled.
-    bool fused_ok = false;
+    bool fused_ok = false;        // AUTO picks the fused kernel
+    bool fused_batch_ok = false;  // batches run the net in the fused launch
+    bool fused_possible = false;  // program and table slots fit the LDS budget
     bool fused_pure = false;
     int64_t fused_lds_bytes = 0;
     int64_t fused_scratch_bytes = 0;
     std::vector<int32_t> program;
+    // word positions of device-pointer slots in `program`: (position, tensor);
+    // the executor writes the tensor's device address there at upload
+    std::vector<std::pair<int64_t, int>> ptr_slots;
+    std::vector<std::pair<int64_t, int>> fused_in_ptr_slots;
+    int64_t fused_input_bytes = 0;  // front of the workspace: materialised inputs
 };
 
 struct DeviceState;  // defined in the executor
@@ -116,8 +140,11 @@ struct Net {
     htn_exec_mode exec = HTN_EXEC_AUTO;
     int64_t max_intermediate = (int64_t(1) << 31) - 1;
     int64_t fused_lds_budget = 65536;
-    double fused_max_mults = 67108864.0;  // AUTO runs larger spilled nets step by step
+    double fused_max_mults = 67108864.0;        // AUTO runs larger spilled nets step by step
+    double batch_fused_max_mults = 33554432.0;  // batch limit for nets with matrix-core steps
     int allow_mfma = 1;
+    int path_samples = 32;      // sampled-greedy candidates
+    uint64_t path_seed = 0;
     // data
     bool data_on_device = false;
     std::vector<const void *> user_ptrs;          // borrowed device pointers
@@ -148,6 +175,10 @@ struct Error {
 };
 void validate_structure(const Net &n);                       // throws Error
 std::vector<std::pair<int, int>> greedy_path(const Net &n);  // throws Error
+std::vector<std::pair<int, int>> sampled_path(const Net &n, int n_samples, uint64_t seed);
+std::vector<std::vector<std::pair<int, int>>> candidate_paths(const Net &n, int n_samples, uint64_t seed);
+// cost_model.cpp
+std::vector<std::pair<int, int>> learned_path(const Net &n);
 void check_path(const Net &n, const std::vector<std::pair<int, int>> &p);  // throws Error
 void build_plan(Net &n);                                     // throws Error
 std::string plan_json(const Net &n);

@@ -22,7 +22,8 @@ namespace kern {
 
 typedef uint16_t bf16_t;  // bfloat16 bit pattern
 
-enum { OP_END = 0, OP_LOAD = 1, OP_STEP = 2, OP_SYNC = 3 };
+enum { OP_END = 0, OP_LOAD = 1, OP_STEP = 2, OP_SYNC = 3, OP_TSTEP = 4, OP_TCOPY = 5, OP_COPY = 6 };
+constexpr int kMaxRankLoad = 16, kMaxScalesLoad = 8;
 constexpr int kBlk = 256;
 
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -203,7 +204,12 @@ __global__ __launch_bounds__(kBlk) void k_prep(const PrepDesc *__restrict__ desc
     TI *dst = (TI *)q.dst;
     const int ns = q.ns;
     for (int e = blockIdx.x * kBlk + threadIdx.x; e < q.size; e += gridDim.x * kBlk) {
-        TI v = Ld<TI, TIN>::get(src + e);
+        int se = e;
+        if (q.snlo > 0) {
+            const int eh = e / q.snlo;
+            se = tab[q.sthi + eh].x + tab[q.stlo + (e - eh * q.snlo)].x;
+        }
+        TI v = Ld<TI, TIN>::get(src + se);
         for (int k = 0; k < ns; ++k) {
             const int eh = e / q.nlo[k];
             const int el = e - eh * q.nlo[k];
@@ -298,18 +304,38 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
             const T *b0 = B;
             if constexpr (!UNARY) b0 = B + (x.y + y.y);
             if (R == 1) {
+                ACC s1 = 0, s2 = 0, s3 = 0;
                 for (int sh = 0; sh < n_shi; ++sh) {
                     const int2 h = tsh[sh];
                     const T *a1 = a0 + h.x;
                     const T *b1 = b0;
                     if constexpr (!UNARY) b1 = b0 + h.y;
-                    for (int sl = 0; sl < n_slo; ++sl) {
+                    int sl = 0;
+                    if constexpr (!COMP) {
+                        // four independent partial sums (ILP)
+                        for (; sl + 4 <= n_slo; sl += 4) {
+                            const int2 l0 = tsl[sl], l1 = tsl[sl + 1], l2 = tsl[sl + 2], l3 = tsl[sl + 3];
+                            ACC p0 = (ACC)a1[l0.x], p1 = (ACC)a1[l1.x], p2 = (ACC)a1[l2.x], p3 = (ACC)a1[l3.x];
+                            if constexpr (!UNARY) {
+                                p0 *= (ACC)b1[l0.y];
+                                p1 *= (ACC)b1[l1.y];
+                                p2 *= (ACC)b1[l2.y];
+                                p3 *= (ACC)b1[l3.y];
+                            }
+                            s += p0;
+                            s1 += p1;
+                            s2 += p2;
+                            s3 += p3;
+                        }
+                    }
+                    for (; sl < n_slo; ++sl) {
                         const int2 l = tsl[sl];
                         ACC p = (ACC)a1[l.x];
                         if constexpr (!UNARY) p *= (ACC)b1[l.y];
                         accum<COMP>(s, c, p);
                     }
                 }
+                s += (s1 + s2) + s3;
             } else {
                 int sh = sub / n_slo, sl = sub - sh * n_slo;
                 while (sh < n_shi) {
@@ -331,89 +357,350 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     }
 }
 
+// Register-tiled step: C[tcm[m] + tcn[n]] = sum_k A[k*M + m] * B[k*N + n].
+// Thread (tx, ty) of a GX x (kBlk/GX) grid owns outputs m = m0 + tx + GX*i,
+// n = n0 + ty + GY*j (i < TM, j < TN).  Across a wave, A reads are
+// consecutive or broadcast, B reads broadcast or consecutive.
+template <typename T, typename ACC, int TM, int TN, typename TOUT>
+__device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int *tcm, const int *tcn, int M, int N,
+                                      int K, int GX) {
+    int lgx = 0;
+    while ((1 << lgx) < GX) ++lgx;
+    const int GY = kBlk >> lgx;
+    const int tx = threadIdx.x & (GX - 1), ty = threadIdx.x >> lgx;
+    const int SM = GX * TM, SN = GY * TN;
+    for (int m0 = 0; m0 < M; m0 += SM) {
+        if (m0 + tx >= M) break;
+        for (int n0 = 0; n0 < N; n0 += SN) {
+            if (n0 + ty >= N) break;
+            int mi[TM], nj[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int m = m0 + tx + GX * i;
+                mi[i] = m < M ? m : M - 1;
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int nn = n0 + ty + GY * j;
+                nj[j] = nn < N ? nn : N - 1;
+            }
+            // U independent partial sums over k hide LDS latency (ILP)
+            constexpr int U = TM * TN >= 16 ? 1 : (TM * TN >= 8 ? 2 : (TM * TN >= 4 ? 4 : 8));
+            ACC acc[U][TM][TN];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[u][i][j] = 0;
+            const T *a = A;
+            const T *b = B;
+            int k = 0;
+            for (; k + U <= K; k += U) {
+                T av[U][TM], bv[U][TN];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) av[u][i] = a[u * M + mi[i]];
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) bv[u][j] = b[u * N + nj[j]];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc[u][i][j] += (ACC)av[u][i] * (ACC)bv[u][j];
+                a += U * M;
+                b += U * N;
+            }
+            for (; k < K; ++k) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[0][i][j] += (ACC)a[mi[i]] * (ACC)b[nj[j]];
+                a += M;
+                b += N;
+            }
+#pragma unroll
+            for (int u = 1; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[0][i][j] += acc[u][i][j];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int m = m0 + tx + GX * i;
+                if (m < M) {
+                    const int cm = tcm[m];
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const int nn = n0 + ty + GY * j;
+                        if (nn < N) C[cm + tcn[nn]] = st_cvt<TOUT>(acc[0][i][j]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, typename ACC, typename TOUT>
+__device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int *tcm, const int *tcn, int M,
+                                          int N, int K, int TM, int TN, int GX) {
+    switch (TM * 8 + TN) {
+        case 9: tstep<T, ACC, 1, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 10: tstep<T, ACC, 1, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 12: tstep<T, ACC, 1, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 17: tstep<T, ACC, 2, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 18: tstep<T, ACC, 2, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 20: tstep<T, ACC, 2, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 33: tstep<T, ACC, 4, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 34: tstep<T, ACC, 4, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        default: tstep<T, ACC, 4, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+    }
+}
+
+// OP_TSTEP: [a, b, c, M, N, K, t_cm, t_cn, TM, TN, GX, final]
+template <typename T, int FM>
+__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, const int *itab, void *out) {
+    const int la = p[1], lb = p[2], lc = p[3];
+    const int M = p[4], N = p[5], K = p[6];
+    const int *tcm = itab + p[7];
+    const int *tcn = itab + p[8];
+    const int TM = p[9], TN = p[10], GX = p[11];
+    const bool fin = p[12] != 0;
+    typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
+    if (la >= 0 && lb >= 0 && (fin || lc >= 0)) {
+        if (!fin)
+            tstep_sel<T, T, T>(sm + la, sm + lb, sm + lc, tcm, tcn, M, N, K, TM, TN, GX);
+        else
+            tstep_sel<T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, tcn, M, N, K, TM, TN, GX);
+    } else {
+        const T *A = la >= 0 ? sm + la : scr + (-la - 2);
+        const T *B = lb >= 0 ? sm + lb : scr + (-lb - 2);
+        if (!fin)
+            tstep_sel<T, T, T>(A, B, lc >= 0 ? sm + lc : scr + (-lc - 2), tcm, tcn, M, N, K, TM, TN, GX);
+        else
+            tstep_sel<T, TO, TO>(A, B, (TO *)out, tcm, tcn, M, N, K, TM, TN, GX);
+    }
+}
+
+// Input materialisation for the fused kernel.  A descriptor (in the fused
+// image) gives the input's device address, its destination in the network's
+// workspace and the digit form of its planned layout: element e of the
+// value has mixed-radix digits over the value's labels; its source offset
+// and each coefficient tensor's offset are dot products of the digits with
+// per-label strides.  Each thread walks e = e0, e0 + stride, ... advancing
+// the digits by the digits of the stride with carries (no division in the
+// loop).
+// Descriptor words: [base ptr (2), dst element offset (2), size, rank, ns,
+//   scale ptrs (2 each), per label k: (extent, source stride, scale strides)]
+__device__ __forceinline__ const void *word_ptr(const int32_t *w) {
+    return (const void *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
+}
+
+template <typename T, typename TIN>
+__global__ __launch_bounds__(kBlk) void k_fprep(const FPrepEntry *__restrict__ entries) {
+    const FPrepEntry en = entries[blockIdx.y];
+    const int32_t *p = en.desc;
+    const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
+    const int size = p[4], rk = p[5], ns = p[6];
+    const int32_t *per = p + 7 + 2 * ns;
+    const int W = 2 + ns;
+    const TIN *src = (const TIN *)word_ptr(p);
+    T *o = (T *)en.ws + dst_off;
+    const TIN *sp[kMaxScalesLoad];
+#pragma unroll
+    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
+    const int e0 = blockIdx.x * kBlk + threadIdx.x;
+    const int stride = gridDim.x * kBlk;
+    int dig[kMaxRankLoad], inc[kMaxRankLoad];
+    int so = 0, sc[kMaxScalesLoad];
+#pragma unroll
+    for (int q = 0; q < kMaxScalesLoad; ++q) sc[q] = 0;
+    {
+        int e = e0, c = stride;
+#pragma unroll
+        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
+            if (k < rk) {
+                const int dim = per[k * W];
+                dig[k] = e % dim;
+                e /= dim;
+                inc[k] = c % dim;
+                c /= dim;
+                so += dig[k] * per[k * W + 1];
+#pragma unroll
+                for (int q = 0; q < kMaxScalesLoad; ++q)
+                    if (q < ns) sc[q] += dig[k] * per[k * W + 2 + q];
+            }
+        }
+    }
+    for (int e = e0; e < size; e += stride) {
+        T v = Ld<T, TIN>::get(src + so);
+#pragma unroll
+        for (int q = 0; q < kMaxScalesLoad; ++q)
+            if (q < ns) v *= Ld<T, TIN>::get(sp[q] + sc[q]);
+        o[e] = v;
+        int carry = 0;
+#pragma unroll
+        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
+            if (k < rk) {
+                const int dim = per[k * W];
+                int dd = dig[k] + inc[k] + carry;
+                carry = dd >= dim;
+                if (carry) dd -= dim;
+                const int delta = dd - dig[k];
+                so += delta * per[k * W + 1];
+#pragma unroll
+                for (int q = 0; q < kMaxScalesLoad; ++q)
+                    if (q < ns) sc[q] += delta * per[k * W + 2 + q];
+                dig[k] = dd;
+            }
+        }
+    }
+}
+
+// Contiguous 16-byte-chunk copies of one phase.  The copies that follow a
+// step are issued into registers before the step's arithmetic and written
+// to LDS after it, so their global latency overlaps the computation.
+constexpr int kPrefetch = 4;  // staged chunks per thread
+struct CopyOp {
+    const uint4 *src;
+    uint4 *dst;
+    int n;
+};
+
+__device__ __forceinline__ CopyOp decode_copy(const int32_t *p, const int32_t *image, const unsigned char *ws,
+                                              unsigned char *smem) {
+    // [kind, src chunk, chunks, dst chunk]; kind 0: image words, 1: workspace
+    CopyOp c;
+    c.src = p[1] == 0 ? (const uint4 *)(image) + p[2] : (const uint4 *)ws + p[2];
+    c.dst = (uint4 *)smem + p[4];
+    c.n = p[3];
+    return c;
+}
+
+// The fused kernel.  A workgroup copies its network's program into LDS and
+// interprets it: COPY moves tables or materialised inputs into LDS,
+// STEP / TSTEP contract two values, SYNC ends a phase.
 template <typename T, typename TIN, int FM>
 __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
                                                void *const *__restrict__ outs, int64_t *__restrict__ stamps,
-                                               void *out1) {
+                                               void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T *sm = reinterpret_cast<T *>(smem);
     const int net = order ? order[blockIdx.x] : (int)blockIdx.x;
+    int phase = 0;
     const FusedDesc d = nets[net];
     const int64_t t0 = stamps ? (int64_t)wall_clock64() : 0;
-    const int32_t *p = d.prog + 3;
+    int32_t *img = reinterpret_cast<int32_t *>(smem);
+    {
+        const int nw = d.prog[0];
+        for (int i = threadIdx.x; i < nw; i += kBlk) img[i] = d.prog[i];
+    }
+    __syncthreads();
+    int32_t *slots = img + img[3];
+    const int slot_words = img[4];
+    unsigned char *red = smem + img[5];  // reduction scratch (256 bytes)
+    const int32_t *gimg = d.prog + img[6];
+    T *sm = reinterpret_cast<T *>(smem);
     T *scr = (T *)d.scratch;
+    void *out = out1 ? out1 : outs[net];
+    const int32_t *p = img + 8;
     for (;;) {
         const int op = p[0];
         if (op == OP_END) break;
         if (op == OP_SYNC) {
             __syncthreads();
+            if (phase_ticks && threadIdx.x == 0 && phase < max_phases)
+                phase_ticks[(int64_t)net * max_phases + phase] = (int64_t)wall_clock64();
+            ++phase;
             p += 1;
             continue;
         }
-        if (op == OP_LOAD) {
-            const int base = p[1], dst = p[2], size = p[3], ns = p[4];
-            const TIN *src = (const TIN *)d.in[base];
-            T *out = dst >= 0 ? sm + dst : scr + (-dst - 2);
-            for (int e = threadIdx.x; e < size; e += kBlk) {
-                T v = Ld<T, TIN>::get(src + e);
-                for (int k = 0; k < ns; ++k) {
-                    const int32_t *r = p + 5 + 4 * k;
-                    const TIN *sp = (const TIN *)d.in[r[0]];
-                    const int eh = e / r[3];
-                    const int el = e - eh * r[3];
-                    v *= Ld<T, TIN>::get(sp + d.tab[r[1] + eh].x + d.tab[r[2] + el].x);
-                }
-                out[e] = v;
-            }
-            p += 5 + 4 * ns;
+        if (op == OP_COPY) {
+            const CopyOp c = decode_copy(p, gimg, (const unsigned char *)d.scratch, smem);
+            for (int i = threadIdx.x; i < c.n; i += kBlk) c.dst[i] = c.src[i];
+            p += 5;
             continue;
         }
-        // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final]
-        // Locations: >= 0 LDS offset, <= -2 scratch offset -loc-2, -1 none.
-        const int la = p[1], lb = p[2], lc = p[3];
-        const bool unary = lb == -1;
-        const bool fin = p[13] != 0;
-        const int R = p[12];
-        const bool all_lds = la >= 0 && (unary || lb >= 0) && (fin || lc >= 0);
-        if (all_lds) {
-            // every operand in LDS: the compiler sees LDS pointers
-            const T *A = sm + la;
-            const T *B = unary ? nullptr : sm + lb;
-            if (!fin) {
-                if (unary)
-                    fstep<T, T, false, true, T>(A, B, sm + lc, d.tab, p + 4, R, (T *)smem);
-                else
-                    fstep<T, T, false, false, T>(A, B, sm + lc, d.tab, p + 4, R, (T *)smem);
-            } else {
-                typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
-                constexpr bool CMP = (FM == FM_COMP);
-                TO *C = (TO *)(out1 ? out1 : outs[net]);
-                if (unary)
-                    fstep<T, TO, CMP, true, TO>(A, B, C, d.tab, p + 4, R, (TO *)smem);
-                else
-                    fstep<T, TO, CMP, false, TO>(A, B, C, d.tab, p + 4, R, (TO *)smem);
-            }
+        const int step_len = op == OP_TSTEP ? 14 : 15;
+        // issue the following copies (next phase's tables and operands)
+        CopyOp cps[4];
+        int starts[5] = {0, 0, 0, 0, 0};
+        int nc = 0, tot = 0;
+        const int32_t *q = p + step_len;
+        while (nc < 4 && q[0] == OP_COPY) {
+            cps[nc] = decode_copy(q, gimg, (const unsigned char *)d.scratch, smem);
+            starts[nc] = tot;
+            tot += cps[nc].n;
+            ++nc;
+            q += 5;
+        }
+        starts[nc] = tot;
+        uint4 stg[kPrefetch];
+#pragma unroll
+        for (int j = 0; j < kPrefetch; ++j) {
+            const int c = threadIdx.x + j * kBlk;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < nc && c >= starts[k] && c < starts[k + 1]) stg[j] = cps[k].src[c - starts[k]];
+        }
+        if (op == OP_TSTEP) {
+            tstep_dispatch<T, FM>(p, sm, scr, slots + p[13] * slot_words, out);
         } else {
-            // some operand spilled: generic (flat) addressing
-            const T *A = la >= 0 ? sm + la : scr + (-la - 2);
-            const T *B = unary ? nullptr : (lb >= 0 ? sm + lb : scr + (-lb - 2));
-            if (!fin) {
-                T *C = lc >= 0 ? sm + lc : scr + (-lc - 2);
-                if (unary)
-                    fstep<T, T, false, true, T>(A, B, C, d.tab, p + 4, R, (T *)smem);
-                else
-                    fstep<T, T, false, false, T>(A, B, C, d.tab, p + 4, R, (T *)smem);
+            // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot]
+            const int2 *itab2 = reinterpret_cast<const int2 *>(slots + p[14] * slot_words);
+            const int la = p[1], lb = p[2], lc = p[3];
+            const bool unary = lb == -1;
+            const bool fin = p[13] != 0;
+            const int R = p[12];
+            typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
+            constexpr bool CMP = (FM == FM_COMP);
+            if (la >= 0 && (unary || lb >= 0) && (fin || lc >= 0)) {
+                const T *A = sm + la;
+                const T *B = unary ? nullptr : sm + lb;
+                if (!fin) {
+                    if (unary)
+                        fstep<T, T, false, true, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                    else
+                        fstep<T, T, false, false, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                } else {
+                    if (unary)
+                        fstep<T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                    else
+                        fstep<T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                }
             } else {
-                typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
-                constexpr bool CMP = (FM == FM_COMP);
-                TO *C = (TO *)(out1 ? out1 : outs[net]);
-                if (unary)
-                    fstep<T, TO, CMP, true, TO>(A, B, C, d.tab, p + 4, R, (TO *)smem);
-                else
-                    fstep<T, TO, CMP, false, TO>(A, B, C, d.tab, p + 4, R, (TO *)smem);
+                const T *A = la >= 0 ? sm + la : scr + (-la - 2);
+                const T *B = unary ? nullptr : (lb >= 0 ? sm + lb : scr + (-lb - 2));
+                if (!fin) {
+                    T *C = lc >= 0 ? sm + lc : scr + (-lc - 2);
+                    if (unary)
+                        fstep<T, T, false, true, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                    else
+                        fstep<T, T, false, false, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                } else {
+                    if (unary)
+                        fstep<T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                    else
+                        fstep<T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                }
             }
         }
-        p += 14;
+        // land the staged chunks, copy any remainder directly
+#pragma unroll
+        for (int j = 0; j < kPrefetch; ++j) {
+            const int c = threadIdx.x + j * kBlk;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < nc && c >= starts[k] && c < starts[k + 1]) cps[k].dst[c - starts[k]] = stg[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nc)
+                for (int c = threadIdx.x + kPrefetch * kBlk; c < starts[k + 1]; c += kBlk)
+                    if (c >= starts[k]) cps[k].dst[c - starts[k]] = cps[k].src[c - starts[k]];
+        p = q;
     }
     if (stamps && threadIdx.x == 0) {
         stamps[2 * net] = t0;
@@ -421,37 +708,61 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
     }
 }
 
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st) {
+    if (n_entries <= 0) return hipSuccess;
+    int bx = (max_size + kBlk * 4 - 1) / (kBlk * 4);
+    bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+    for (int first = 0; first < n_entries; first += 65535) {
+        const int cnt = n_entries - first < 65535 ? n_entries - first : 65535;
+        dim3 grid(bx, cnt);
+        if (compute == 0)
+            hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(kBlk), 0, st, entries + first);
+        else if (compute == 1)
+            hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(kBlk), 0, st, entries + first);
+        else
+            hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(kBlk), 0, st, entries + first);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T, typename TIN, int FM>
 static hipError_t go_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
-                           void *out1, int n_blocks, int lds_bytes, hipStream_t st) {
+                           void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
+                           hipStream_t st) {
     static int configured = -1;
     if (lds_bytes > configured) {
         hipError_t e = hipFuncSetAttribute((const void *)k_fused<T, TIN, FM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
         configured = lds_bytes;
     }
     hipLaunchKernelGGL((k_fused<T, TIN, FM>), dim3(n_blocks), dim3(kBlk), lds_bytes, st, nets, order, outs, stamps,
-                       out1);
+                       out1, phase_ticks, max_phases);
     return hipGetLastError();
 }
 
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
-                        int n_blocks, int lds_bytes, int compute, int fm, hipStream_t st) {
+                        int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
+                        hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
     if (compute == 0) {
-        if (fm == FM_COMP) return go_fused<double, double, FM_COMP>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
-        return go_fused<double, double, FM_INTER>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
+        if (fm == FM_COMP) return go_fused<double, double, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
+        return go_fused<double, double, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
     }
     if (compute == 1) {
-        if (fm == FM_COMP) return go_fused<float, float, FM_COMP>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
-        if (fm == FM_F64) return go_fused<float, float, FM_F64>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
-        return go_fused<float, float, FM_INTER>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
+        if (fm == FM_COMP) return go_fused<float, float, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
+        if (fm == FM_F64) return go_fused<float, float, FM_F64>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
+        return go_fused<float, float, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
     }
     if (compute == 2) {
-        if (fm == FM_COMP) return go_fused<float, bf16_t, FM_COMP>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
-        if (fm == FM_F64) return go_fused<float, bf16_t, FM_F64>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
-        return go_fused<float, bf16_t, FM_INTER>(nets, order, outs, stamps, out1, n_blocks, lds_bytes, st);
+        if (fm == FM_COMP) return go_fused<float, bf16_t, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
+        if (fm == FM_F64) return go_fused<float, bf16_t, FM_F64>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
+        return go_fused<float, bf16_t, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
     }
     return hipErrorInvalidValue;
 }

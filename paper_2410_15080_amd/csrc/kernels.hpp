@@ -37,6 +37,7 @@ struct PrepDesc {
     int32_t ns;
     const void *sp[kMaxScalesDev];
     int32_t thi[kMaxScalesDev], tlo[kMaxScalesDev], nlo[kMaxScalesDev];
+    int32_t sthi, stlo, snlo;  // source gather table (snlo = 0: same layout)
 };
 hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin, int tinter, const int2 *tab,
                        hipStream_t st);
@@ -51,8 +52,11 @@ struct FusedDesc {
 // nets[order[b]] is run by workgroup b; outs[net] receives its result.
 // stamps (optional): [2*net] start, [2*net+1] end, 100 MHz ticks.
 // out1 (optional): output of a single-network launch, used instead of outs.
+// phase_ticks (optional): [net * max_phases + k] receives the clock at the
+// end of the network's k-th phase (after its barrier).
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
-                        int n_blocks, int lds_bytes, int compute, int fm, hipStream_t st);
+                        int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
+                        hipStream_t st);
 
 // Matrix-core GEMM C[b][m][n] = sum_k A[b][m][k] B[b][n][k] on packed,
 // K-contiguous operands (mfma.hip).  tin: 0 f64, 1 f32, 2 bf16; tout: 0 f64,
@@ -60,6 +64,15 @@ hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const
 // elements into FP64 accumulators.
 hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
                        int kchunk, hipStream_t st);
+
+// Materialisation of fused-kernel inputs: each entry names a digit-form load
+// descriptor (in a fused image) and the network's workspace.  grid.y =
+// entries; max_size bounds the elements of any entry.
+struct FPrepEntry {
+    const int32_t *desc;
+    void *ws;
+};
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st);
 
 // Element-wise dtype conversion on the device.
 hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);

@@ -1,5 +1,10 @@
 // Matrix-core (MFMA) GEMM for pairwise steps that are dense matrix products.
 //
+// Fragment layouts (checked on gfx950 with an in-bounds probe): A and B
+// lanes hold row/column lane%16 and K slice lane/16; the 16x16 result
+// block holds column lane%16 in every register, with rows 4*(lane/16)+r for
+// the FP32-accumulating instructions and lane/16+4*r for the FP64 one.
+//
 //   C[b][m][n] = sum_k A[b][m][k] * B[b][n][k]
 //
 // Operands are packed K-contiguous by the step's pack kernels, so every
@@ -36,6 +41,8 @@ struct MfmaOp<double> {
     static constexpr int KPL = 1;  // K values per lane
     static constexpr int BK = 16;
     static constexpr int PAD = 1;
+    // output block: lane holds rows lane/16 + 4*r (interleaved)
+    __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
     __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -50,6 +57,8 @@ struct MfmaOp<float> {
     static constexpr int KPL = 1;
     static constexpr int BK = 32;
     static constexpr int PAD = 1;
+    // output block: lane holds rows 4*(lane/16) + r (blocked)
+    __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
     __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -64,6 +73,7 @@ struct MfmaOp<bf16_t> {
     static constexpr int KPL = 8;
     static constexpr int BK = 64;
     static constexpr int PAD = 8;
+    __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
     __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
@@ -187,14 +197,15 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
         }
         __syncthreads();
     }
-    // D block layout: lane holds rows 4*(lane/16)+r, column lane%16.
+    // D block: column lane%16; the row of register r depends on the
+    // instruction (Op::row).
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int gm = m0 + wm + 16 * i + Op::row(lane, r);
                 const int gn = n0 + wn + 16 * j + (lane & 15);
                 if (gm < M && gn < N) {
                     if constexpr (COMBINE64)

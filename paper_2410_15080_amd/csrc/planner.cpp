@@ -61,11 +61,30 @@ static std::vector<int> sorted_union(const std::vector<int> &a, const std::vecto
 
 static bool contains(const std::vector<int> &v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
 
-// FLOP-greedy: among live pairs that share a label, contract the one with
-// the fewest multiplications (product of the extents of the union of the
-// two label sets); ties: smaller result, then lower (i, j).  When no pair
-// shares a label the two smallest live tensors are joined (outer product).
-std::vector<std::pair<int, int>> greedy_path(const Net &n) {
+// splitmix64: a small deterministic generator for path sampling.
+struct Rng {
+    uint64_t s;
+    explicit Rng(uint64_t seed) : s(seed) {}
+    uint64_t next() {
+        uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+// Greedy pairwise order.  Candidates are live pairs that share a label; a
+// pair's cost is its multiplication count (product of the extents of the
+// union of the two label sets).  Without a generator the cheapest pair is
+// taken (ties: smaller result, then lower (i, j)) -- the FLOP-greedy path.
+// With a generator a pair is drawn with probability proportional to
+// exp(-(log2 cost - log2 min cost) / temperature) (Boltzmann-sampled greedy).
+// When no pair shares a label the two smallest live tensors are joined.
+// *total receives the path's multiplication count and *peak its largest
+// intermediate.
+static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, double temperature, double *total,
+                                                   double *peak) {
     const int N = n.n_t;
     const int L = (int)n.dims.size();
     std::vector<std::vector<int>> lab(2 * N);
@@ -81,61 +100,128 @@ std::vector<std::pair<int, int>> greedy_path(const Net &n) {
     }
     std::vector<std::pair<int, int>> path;
     int next = N, n_alive = N;
+    double tot = 0.0, pk = 0.0;
     std::vector<std::vector<int>> holders(L);
+    struct Cand {
+        double cost, os;
+        int i, j;
+    };
+    std::vector<Cand> cands;
+    auto eval = [&](int i, int j, Cand &c, std::vector<int> *kept_out) {
+        std::vector<int> u = sorted_union(lab[i], lab[j]);
+        c.cost = prod_dims(n, u);
+        c.i = i;
+        c.j = j;
+        double os = 1.0;
+        for (int l : u) {
+            int r = ref[l] - (int)contains(lab[i], l) - (int)contains(lab[j], l);
+            if (is_out[l] || r > 0) {
+                os *= (double)n.dims[l];
+                if (kept_out) kept_out->push_back(l);
+            }
+        }
+        c.os = os;
+    };
     while (n_alive > 1) {
         for (auto &h : holders) h.clear();
         for (int i = 0; i < next; ++i)
             if (alive[i])
                 for (int l : lab[i]) holders[l].push_back(i);
-        bool found = false;
-        double bc = 0, bs = 0;
-        int bi = -1, bj = -1;
-        std::vector<int> bkept;
-        auto consider = [&](int i, int j, bool shared_only) {
-            (void)shared_only;
-            std::vector<int> u = sorted_union(lab[i], lab[j]);
-            double cost = prod_dims(n, u);
-            std::vector<int> kept;
-            for (int l : u) {
-                int r = ref[l] - (int)contains(lab[i], l) - (int)contains(lab[j], l);
-                if (is_out[l] || r > 0) kept.push_back(l);
-            }
-            double os = prod_dims(n, kept);
-            bool better = !found || cost < bc || (cost == bc && (os < bs || (os == bs && (i < bi || (i == bi && j < bj)))));
-            if (better) {
-                found = true;
-                bc = cost;
-                bs = os;
-                bi = i;
-                bj = j;
-                bkept = kept;
-            }
-        };
+        cands.clear();
         for (int l = 0; l < L; ++l) {
             const auto &h = holders[l];
             for (size_t x = 0; x < h.size(); ++x)
-                for (size_t y = x + 1; y < h.size(); ++y) consider(std::min(h[x], h[y]), std::max(h[x], h[y]), true);
+                for (size_t y = x + 1; y < h.size(); ++y) {
+                    Cand c;
+                    eval(std::min(h[x], h[y]), std::max(h[x], h[y]), c, nullptr);
+                    cands.push_back(c);
+                }
         }
-        if (!found) {
-            // disconnected: join the two smallest live tensors
+        // the same pair can appear under several shared labels
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) {
+            if (a.cost != b.cost) return a.cost < b.cost;
+            if (a.os != b.os) return a.os < b.os;
+            if (a.i != b.i) return a.i < b.i;
+            return a.j < b.j;
+        });
+        cands.erase(std::unique(cands.begin(), cands.end(),
+                                [](const Cand &a, const Cand &b) { return a.i == b.i && a.j == b.j; }),
+                    cands.end());
+        int bi, bj;
+        if (cands.empty()) {
             std::vector<std::pair<double, int>> sz;
             for (int i = 0; i < next; ++i)
                 if (alive[i]) sz.push_back({prod_dims(n, lab[i]), i});
             std::sort(sz.begin(), sz.end());
-            int i = std::min(sz[0].second, sz[1].second), j = std::max(sz[0].second, sz[1].second);
-            consider(i, j, false);
+            bi = std::min(sz[0].second, sz[1].second);
+            bj = std::max(sz[0].second, sz[1].second);
+        } else if (!rng || cands.size() == 1) {
+            bi = cands[0].i;
+            bj = cands[0].j;
+        } else {
+            const double lmin = std::log2(cands[0].cost);
+            double wsum = 0.0;
+            std::vector<double> wts(cands.size());
+            for (size_t k = 0; k < cands.size(); ++k) {
+                wts[k] = std::exp(-(std::log2(cands[k].cost) - lmin) / temperature);
+                wsum += wts[k];
+            }
+            double r = rng->uniform() * wsum;
+            size_t k = 0;
+            while (k + 1 < cands.size() && r >= wts[k]) r -= wts[k++];
+            bi = cands[k].i;
+            bj = cands[k].j;
         }
+        Cand c;
+        std::vector<int> kept;
+        eval(bi, bj, c, &kept);
+        tot += c.cost;
+        pk = std::max(pk, c.os);
         path.push_back({bi, bj});
         for (int l : lab[bi]) ref[l]--;
         for (int l : lab[bj]) ref[l]--;
         alive[bi] = alive[bj] = 0;
-        lab[next] = bkept;
-        for (int l : bkept) ref[l]++;
+        lab[next] = kept;
+        for (int l : kept) ref[l]++;
         alive[next] = 1;
         ++next;
         --n_alive;
     }
+    if (total) *total = tot;
+    if (peak) *peak = pk;
     return path;
+}
+
+std::vector<std::pair<int, int>> greedy_path(const Net &n) { return greedy_core(n, nullptr, 1.0, nullptr, nullptr); }
+
+std::vector<std::vector<std::pair<int, int>>> candidate_paths(const Net &n, int n_samples, uint64_t seed) {
+    std::vector<std::vector<std::pair<int, int>>> out;
+    out.push_back(greedy_path(n));
+    static const double temps[] = {0.25, 0.5, 1.0, 2.0};
+    Rng rng(seed * 0x9e3779b97f4a7c15ull + 12345);
+    for (int k = 0; k < n_samples; ++k) out.push_back(greedy_core(n, &rng, temps[k % 4], nullptr, nullptr));
+    return out;
+}
+
+// Cheapest of the FLOP-greedy path and n_samples Boltzmann-sampled greedy
+// paths (by multiplication count, among those within the intermediate cap);
+// ties keep the earlier candidate, so the result is never worse than
+// FLOP-greedy.
+std::vector<std::pair<int, int>> sampled_path(const Net &n, int n_samples, uint64_t seed) {
+    double best_m = 0.0;
+    std::vector<std::pair<int, int>> best;
+    Rng rng(seed * 0x9e3779b97f4a7c15ull + 12345);
+    static const double temps[] = {0.25, 0.5, 1.0, 2.0};
+    for (int k = -1; k < n_samples; ++k) {
+        double m, pk;
+        auto p = k < 0 ? greedy_core(n, nullptr, 1.0, &m, &pk) : greedy_core(n, &rng, temps[k % 4], &m, &pk);
+        if (pk > (double)n.max_intermediate && k >= 0) continue;
+        if (best.empty() || m < best_m) {
+            best = p;
+            best_m = m;
+        }
+    }
+    return best;
 }
 
 void check_path(const Net &n, const std::vector<std::pair<int, int>> &p) {
@@ -243,7 +329,45 @@ struct FirstFit {
 
 // ------------------------------------------------------------ build_plan
 
-enum { OP_END = 0, OP_LOAD = 1, OP_STEP = 2, OP_SYNC = 3 };
+enum { OP_END = 0, OP_LOAD = 1, OP_STEP = 2, OP_SYNC = 3, OP_TSTEP = 4, OP_COPY = 6 };
+
+// One-level offset table over a label group (pairs, .x = offset).
+static void flat_table(const Net &n, const std::vector<int> &group, const std::vector<int64_t> &st,
+                       std::vector<int32_t> &tab, int64_t &off) {
+    off = (int64_t)tab.size() / 2;
+    int64_t count = (int64_t)prod_dims(n, group);
+    std::vector<int64_t> dig(group.size(), 0);
+    for (int64_t e = 0; e < count; ++e) {
+        int64_t o = 0;
+        for (size_t k = 0; k < group.size(); ++k) o += dig[k] * st[k];
+        tab.push_back((int32_t)o);
+        tab.push_back(0);
+        for (int k = (int)group.size() - 1; k >= 0; --k) {
+            if (++dig[k] < n.dims[group[k]]) break;
+            dig[k] = 0;
+        }
+    }
+}
+
+// Register tile of a tiled step: TM x TN outputs per thread on a GX x GY
+// thread grid (GX * GY = kBlock).  Cost model per thread: passes over the
+// output times K times (FMAs + operand loads), loads weighted 1/2.
+static void choose_tile(StepPlan &s) {
+    double best = 0;
+    for (int tm : {1, 2, 4})
+        for (int tn : {1, 2, 4})
+            for (int gx = 1; gx <= kBlock; gx *= 2) {
+                const int gy = kBlock / gx;
+                const double passes = std::ceil((double)s.tM / (gx * tm)) * std::ceil((double)s.tN / (gy * tn));
+                const double cost = passes * (double)s.tK * (tm * tn + 0.5 * (tm + tn));
+                if (best == 0 || cost < best - 1e-9) {
+                    best = cost;
+                    s.TM = tm;
+                    s.TN = tn;
+                    s.GX = gx;
+                }
+            }
+}
 
 // Steps that are dense matrix products go to the matrix cores: every summed
 // label is carried by both operands (K), the kept labels split into batch
@@ -423,6 +547,71 @@ void build_plan(Net &n) {
     for (size_t k = 0; k < P.steps.size(); ++k)
         if (!P.steps[k].absorbed) P.kernel_steps.push_back((int)k);
 
+    // Layout pass.  Each value is consumed by exactly one kernel step, so its
+    // physical label order can be chosen for that consumer: operands of a
+    // register-tiled step are laid out [K][M] and [K][N] with the same K
+    // order.  Intermediates take the layout when their producer writes them;
+    // inputs are permuted when they are loaded (or materialised).
+    auto set_layout = [&](int v, const std::vector<int> &order) {
+        Value &val = P.values[v];
+        if (val.input) {
+            val.labels = order;
+            return true;
+        }
+        StepPlan &prod = P.steps[val.producer];
+        if (prod.mfma || prod.final_step) return false;
+        val.labels = order;
+        prod.c_labels = order;
+        return true;
+    };
+    for (int k : P.kernel_steps) {
+        StepPlan &s = P.steps[k];
+        if (s.b < 0) continue;
+        if (s.final_step && n.final_sum == HTN_SUM_COMPENSATED) continue;
+        std::vector<int> al = P.values[s.a].labels, bl = P.values[s.b].labels;
+        std::vector<int> K, M, Nn;
+        bool ok = true;
+        for (int l : s.sum_labels)
+            if (!contains(al, l) || !contains(bl, l)) ok = false;
+        for (int l : al)
+            if (!contains(s.sum_labels, l)) {
+                if (contains(bl, l)) ok = false;  // batch label
+                M.push_back(l);
+            }
+        for (int l : bl)
+            if (!contains(s.sum_labels, l)) Nn.push_back(l);
+        if (!ok) continue;
+        const int64_t mM = (int64_t)prod_dims(n, M), nN = (int64_t)prod_dims(n, Nn);
+        if (mM * nN < kBlock) continue;  // fewer outputs than threads: split the sums instead
+        K = s.sum_labels;
+        std::sort(K.begin(), K.end());
+        std::sort(M.begin(), M.end());
+        std::sort(Nn.begin(), Nn.end());
+        std::vector<int> wa = K, wb = K;
+        wa.insert(wa.end(), M.begin(), M.end());
+        wb.insert(wb.end(), Nn.begin(), Nn.end());
+        // Both operands must accept the layout (an MFMA or final producer
+        // keeps its own); otherwise fall back to the table-driven step.
+        auto can = [&](int v) { return P.values[v].input || !(P.steps[P.values[v].producer].mfma); };
+        if (!can(s.a) || !can(s.b)) continue;
+        set_layout(s.a, wa);
+        set_layout(s.b, wb);
+        s.tile = 1;
+        s.tM = mM;
+        s.tN = nN;
+        s.tK = (int64_t)prod_dims(n, K);
+        s.t_gm = M;
+        s.t_gn = Nn;
+        s.t_gk = K;
+    }
+    for (int k : P.kernel_steps) {
+        StepPlan &s = P.steps[k];
+        s.a_labels = P.values[s.a].labels;
+        if (s.b >= 0) s.b_labels = P.values[s.b].labels;
+        if (!s.final_step) s.c_labels = P.values[s.c].labels;
+        if (s.tile) s.sum_labels = s.t_gk;
+    }
+
     // Offset tables and lane counts of every kernel step.
     for (int k : P.kernel_steps) {
         StepPlan &s = P.steps[k];
@@ -439,6 +628,16 @@ void build_plan(Net &n) {
         }
         group_tables(n, s.c_labels, oa, ob, P.tables, s.n_ohi, s.n_olo, s.t_ohi, s.t_olo);
         group_tables(n, s.sum_labels, ua, ub, P.tables, s.n_shi, s.n_slo, s.t_shi, s.t_slo);
+        if (s.tile) {
+            // C offsets of (m, n): tables over the M and N groups
+            auto stc = strides_of(n, s.c_labels);
+            std::vector<int64_t> cm, cn;
+            for (int l : s.t_gm) cm.push_back(stride_in(s.c_labels, stc, l));
+            for (int l : s.t_gn) cn.push_back(stride_in(s.c_labels, stc, l));
+            flat_table(n, s.t_gm, cm, P.tables, s.t_cm);
+            flat_table(n, s.t_gn, cn, P.tables, s.t_cn);
+            choose_tile(s);
+        }
         if (s.mfma) {
             // pack A -> [batch][M][K], B -> [batch][N][K]: unary permutes
             auto pack = [&](const std::vector<int> &src, const std::vector<int64_t> &st, const std::vector<int> &mid,
@@ -498,6 +697,15 @@ void build_plan(Net &n) {
             lp.base = P.values[id].base;
             lp.size = P.values[id].size;
             scale_tables(P.values[id], lp);
+            const auto &vl = P.values[id].labels;
+            const auto &bl = n.labels[lp.base];
+            if (vl != bl) {
+                auto stb = strides_of(n, bl);
+                std::vector<int64_t> sa, zero(vl.size(), 0);
+                for (int l : vl) sa.push_back(stride_in(bl, stb, l));
+                int64_t n_hi;
+                group_tables(n, vl, sa, zero, P.tables, n_hi, lp.src_nlo, lp.src_thi, lp.src_tlo);
+            }
             load_of[id] = (int)P.loads.size();
             P.loads.push_back(lp);
         }
@@ -511,7 +719,7 @@ void build_plan(Net &n) {
         FirstFit ff;
         P.ws_off.assign(P.values.size(), -1);
         for (auto &lp : P.loads)
-            if (!lp.scales.empty()) P.ws_off[lp.value] = ff.alloc(lp.size * es, 256);
+            if (lp.needs_copy()) P.ws_off[lp.value] = ff.alloc(lp.size * es, 256);
         const int64_t pes = n.compute == HTN_BF16 ? 2 : es;  // packed operand element size
         for (int k : P.kernel_steps) {
             StepPlan &s = P.steps[k];
@@ -528,86 +736,240 @@ void build_plan(Net &n) {
         P.ws_bytes = std::max<int64_t>(ff.peak, 256);
     }
 
-    // Fused executor program.  Phase 0 loads the operands of kernel step 0;
-    // phase k runs step k and loads the inputs of step k+1; a barrier ends
-    // every phase.  Offsets are in elements of the intermediate type.  A
-    // value goes to LDS when it fits the budget (after a 256-byte reduction
-    // scratch), otherwise to the network's global scratch.  Locations are
-    // encoded as loc >= 0: LDS offset; loc <= -2: scratch offset -loc-2;
-    // -1: the network's output (final step) / no operand.
+    // Fused executor.  Inputs are first materialised (permuted into their
+    // planned layout, coefficient tensors applied) by one prep launch into
+    // the front of the network's workspace; the fused kernel then only moves
+    // contiguous 16-byte chunks (OP_COPY) and computes.  Device image
+    // (int32 words): [0] program words, [1] LDS bytes, [2] op count,
+    // [3] LDS word offset of table slot 0, [4] words per slot, [5] LDS byte
+    // offset of the 256-byte reduction scratch, [6] image word offset of the
+    // step tables, [7] image word offset of the load descriptors; ops from
+    // word 8; then step tables; then load descriptors (digit form, read by
+    // the prep kernel).  Phase 0 copies the tables and LDS-resident operands
+    // of step 0; phase k runs step k and copies those of step k+1 (the
+    // kernel issues these copies before the step's arithmetic); a barrier
+    // ends each phase.  Value locations: >= 0 LDS element offset; <= -2
+    // workspace element offset -loc-2; -1 the network's output / none.
     {
         const int64_t es = dtype_size(inter_dtype(n.compute));
-        const int64_t scratch = 256 / es;
-        const int64_t budget = std::max<int64_t>(0, n.fused_lds_budget / es - scratch);
-        FirstFit lds_ff, glb_ff;
+        const auto &ks = P.kernel_steps;
+        // step tables, each step's block padded to 16 bytes
+        std::vector<int32_t> gtab;
+        std::vector<int64_t> tab_off(ks.size()), tab_words(ks.size());
+        std::vector<std::vector<int32_t>> rel(ks.size());
+        int64_t slot_words = 4;
+        for (size_t q = 0; q < ks.size(); ++q) {
+            const StepPlan &s = P.steps[ks[q]];
+            tab_off[q] = (int64_t)gtab.size();
+            auto put_x = [&](int64_t pair_off, int64_t count) {
+                const int32_t o = (int32_t)(gtab.size() - tab_off[q]);
+                for (int64_t e = 0; e < count; ++e) gtab.push_back(P.tables[2 * (pair_off + e)]);
+                return o;
+            };
+            auto put_pairs = [&](int64_t pair_off, int64_t count) {
+                if ((gtab.size() - tab_off[q]) % 2) gtab.push_back(0);
+                const int32_t o = (int32_t)((gtab.size() - tab_off[q]) / 2);
+                for (int64_t e = 0; e < 2 * count; ++e) gtab.push_back(P.tables[2 * pair_off + e]);
+                return o;
+            };
+            if (s.tile) {
+                rel[q] = {put_x(s.t_cm, s.tM), put_x(s.t_cn, s.tN)};
+            } else {
+                rel[q] = {put_pairs(s.t_ohi, s.n_ohi), put_pairs(s.t_olo, s.n_olo), put_pairs(s.t_shi, s.n_shi),
+                          put_pairs(s.t_slo, s.n_slo)};
+            }
+            while (gtab.size() % 4) gtab.push_back(0);
+            tab_words[q] = (int64_t)gtab.size() - tab_off[q];
+            slot_words = std::max(slot_words, tab_words[q]);
+        }
+        slot_words = (slot_words + 3) / 4 * 4;
+
+        // load descriptors (digit form) for the prep kernel
+        bool loads_fit = true;
+        std::vector<int32_t> ldesc;
+        std::vector<int64_t> ld_off(P.loads.size(), -1);
+        P.fused_in_ptr_slots.clear();
+        for (size_t li = 0; li < P.loads.size(); ++li) {
+            const LoadPlan &lp = P.loads[li];
+            const auto &vl = P.values[lp.value].labels;
+            const auto &bl = n.labels[lp.base];
+            auto stb = strides_of(n, bl);
+            const int rk = (int)vl.size(), ns = (int)lp.scales.size();
+            if (rk > 16 || ns > kMaxScales) loads_fit = false;
+            ld_off[li] = (int64_t)ldesc.size();
+            // [base ptr (2), dst element offset in workspace (2), size, rank, ns, scale ptrs (2 each),
+            //  per label: extent, source stride, scale strides]
+            P.fused_in_ptr_slots.push_back({(int64_t)ldesc.size(), lp.base});
+            ldesc.insert(ldesc.end(), {0, 0, 0, 0, (int32_t)lp.size, rk, ns});
+            for (size_t q = 0; q < lp.scales.size(); ++q) {
+                P.fused_in_ptr_slots.push_back({(int64_t)ldesc.size(), lp.scales[q].tensor});
+                ldesc.push_back(0);
+                ldesc.push_back(0);
+            }
+            std::vector<std::vector<int64_t>> sst;
+            for (auto &sc : lp.scales) sst.push_back(strides_of(n, n.labels[sc.tensor]));
+            for (int k = 0; k < rk; ++k) {
+                const int l = vl[k];
+                ldesc.push_back((int32_t)n.dims[l]);
+                ldesc.push_back((int32_t)stride_in(bl, stb, l));
+                for (int q = 0; q < ns; ++q)
+                    ldesc.push_back((int32_t)stride_in(n.labels[lp.scales[q].tensor], sst[q], l));
+            }
+        }
+
+        // workspace: materialised inputs first, spill scratch after
+        FirstFit glb_ff;
+        std::vector<int64_t> in_off(P.values.size(), -1);
+        for (size_t li = 0; li < P.loads.size(); ++li) {
+            const LoadPlan &lp = P.loads[li];
+            in_off[lp.value] = glb_ff.alloc(lp.size, 32);
+            ldesc[ld_off[li] + 2] = (int32_t)(in_off[lp.value] & 0xffffffff);
+            ldesc[ld_off[li] + 3] = (int32_t)(in_off[lp.value] >> 32);
+        }
+        const int64_t inputs_end = glb_ff.peak;
+
+        struct OpRec {
+            int kind;
+            int step = -1, value = -1, q = -1;
+            std::vector<int32_t> w;
+        };
+        std::vector<OpRec> seq;
+        auto copies_of_step = [&](size_t q) {
+            OpRec t;
+            t.kind = OP_COPY;
+            t.q = (int)q;
+            // [kind 0: image words, src chunk, chunks, dst chunk]
+            t.w = {OP_COPY, 0, (int32_t)(tab_off[q] / 4), (int32_t)(tab_words[q] / 4), 0};
+            seq.push_back(t);
+            const StepPlan &s = P.steps[ks[q]];
+            for (int id : {s.a, s.b})
+                if (id >= 0 && P.values[id].input) {
+                    OpRec r;
+                    r.kind = OP_COPY;
+                    r.value = id;
+                    r.w = {OP_COPY, 1, 0, 0, 0};
+                    seq.push_back(r);
+                }
+        };
+        if (!ks.empty()) copies_of_step(0);
+        seq.push_back(OpRec{OP_SYNC, -1, -1, -1, {OP_SYNC}});
+        for (size_t q = 0; q < ks.size(); ++q) {
+            const StepPlan &s = P.steps[ks[q]];
+            OpRec r;
+            r.step = ks[q];
+            r.q = (int)q;
+            const int32_t slot = (int32_t)(q % 2);
+            if (s.tile) {
+                r.kind = OP_TSTEP;
+                r.w = {OP_TSTEP, 0, 0, 0, (int32_t)s.tM, (int32_t)s.tN, (int32_t)s.tK, rel[q][0], rel[q][1],
+                       s.TM, s.TN, s.GX, s.final_step ? 1 : 0, slot};
+            } else {
+                r.kind = OP_STEP;
+                r.w = {OP_STEP, 0, 0, 0, (int32_t)s.n_ohi, (int32_t)s.n_olo, (int32_t)s.n_shi, (int32_t)s.n_slo,
+                       rel[q][0], rel[q][1], rel[q][2], rel[q][3], s.r_fused, s.final_step ? 1 : 0, slot};
+            }
+            seq.push_back(r);
+            if (q + 1 < ks.size()) copies_of_step(q + 1);
+            seq.push_back(OpRec{OP_SYNC, -1, -1, -1, {OP_SYNC}});
+        }
+        int64_t prog_words = 8 + 1;
+        for (auto &r : seq) prog_words += (int64_t)r.w.size();
+        prog_words = (prog_words + 3) / 4 * 4;
+        const int64_t slot0 = prog_words;
+        const int64_t scratch_byte = (slot0 + 2 * slot_words) * 4;
+        const int64_t values_byte = scratch_byte + 256;
+        const int64_t vbase = (values_byte + es - 1) / es;
+        const int64_t budget = std::max<int64_t>(0, n.fused_lds_budget / es - vbase);
+        const int64_t ealign = 16 / es;  // 16-byte aligned LDS values
+
+        FirstFit lds_ff;
+        glb_ff.peak = inputs_end;
         std::vector<int64_t> loc(P.values.size(), INT64_MIN);
         auto place = [&](int64_t size) -> int64_t {
             const int64_t old_peak = lds_ff.peak;
-            const int64_t off = lds_ff.alloc(size, 4);
-            if (off + size <= budget) return scratch + off;
+            const int64_t off = lds_ff.alloc((size + ealign - 1) / ealign * ealign, 16);
+            if (off + size <= budget) return vbase + off;
             lds_ff.release(off);
             lds_ff.peak = old_peak;
-            return -(glb_ff.alloc(size, 64) + 2);
+            return -1;
+        };
+        auto place_or_spill = [&](int64_t size) -> int64_t {
+            const int64_t l = place(size);
+            if (l >= 0) return l;
+            return -(glb_ff.alloc(size, 32) + 2);
         };
         auto unplace = [&](int64_t l) {
             if (l >= 0)
-                lds_ff.release(l - scratch);
-            else if (l <= -2)
+                lds_ff.release(l - vbase);
+            else if (l <= -2 && -l - 2 >= inputs_end)
                 glb_ff.release(-l - 2);
         };
-        std::vector<int32_t> prog = {0, 0, 0};
+        // keep spill scratch above the inputs area
+        glb_ff.used[0] = inputs_end;
         int n_ops = 0;
-        auto emit_loads = [&](const StepPlan &s) {
-            for (int id : {s.a, s.b}) {
-                if (id < 0 || !P.values[id].input) continue;
-                const LoadPlan &lp = P.loads[load_of[id]];
-                loc[id] = place(lp.size);
-                prog.push_back(OP_LOAD);
-                prog.push_back(lp.base);
-                prog.push_back((int32_t)loc[id]);
-                prog.push_back((int32_t)lp.size);
-                prog.push_back((int32_t)lp.scales.size());
-                for (auto &r : lp.scales) {
-                    prog.push_back(r.tensor);
-                    prog.push_back((int32_t)r.t_hi);
-                    prog.push_back((int32_t)r.t_lo);
-                    prog.push_back((int32_t)r.n_lo);
+        std::vector<int> pending;
+        for (auto &r : seq) {
+            if (r.kind == OP_COPY && r.value >= 0) {
+                const int64_t sz = P.values[r.value].size;
+                const int64_t l = place(sz);
+                if (l >= 0) {
+                    loc[r.value] = l;
+                    const int64_t bytes = (sz * es + 15) / 16 * 16;
+                    r.w[2] = (int32_t)(in_off[r.value] * es / 16);
+                    r.w[3] = (int32_t)(bytes / 16);
+                    r.w[4] = (int32_t)(l * es / 16);
+                } else {
+                    loc[r.value] = -(in_off[r.value] + 2);  // read in place
+                    r.w[3] = 0;
                 }
-                ++n_ops;
+            } else if (r.kind == OP_COPY) {
+                r.w[4] = (int32_t)((slot0 + (r.q % 2) * slot_words) / 4);
+            } else if (r.kind == OP_STEP || r.kind == OP_TSTEP) {
+                const StepPlan &s = P.steps[r.step];
+                int64_t cl = -1;
+                if (!s.final_step) cl = loc[s.c] = place_or_spill(P.values[s.c].size);
+                r.w[1] = (int32_t)loc[s.a];
+                r.w[2] = s.b >= 0 ? (int32_t)loc[s.b] : -1;
+                r.w[3] = (int32_t)cl;
+                pending.push_back(s.a);
+                pending.push_back(s.b);
+            } else if (r.kind == OP_SYNC) {
+                for (int id : pending)
+                    if (id >= 0) unplace(loc[id]);
+                pending.clear();
             }
-        };
-        const auto &ks = P.kernel_steps;
-        if (!ks.empty()) emit_loads(P.steps[ks[0]]);
-        prog.push_back(OP_SYNC);
-        ++n_ops;
-        for (size_t q = 0; q < ks.size(); ++q) {
-            const StepPlan &s = P.steps[ks[q]];
-            int64_t cl = -1;
-            if (!s.final_step) cl = loc[s.c] = place(P.values[s.c].size);
-            prog.push_back(OP_STEP);
-            prog.push_back((int32_t)loc[s.a]);
-            prog.push_back(s.b >= 0 ? (int32_t)loc[s.b] : -1);
-            prog.push_back((int32_t)cl);
-            for (int64_t x : {s.n_ohi, s.n_olo, s.n_shi, s.n_slo, s.t_ohi, s.t_olo, s.t_shi, s.t_slo})
-                prog.push_back((int32_t)x);
-            prog.push_back(s.r_fused);
-            prog.push_back(s.final_step ? 1 : 0);
             ++n_ops;
-            if (q + 1 < ks.size()) emit_loads(P.steps[ks[q + 1]]);
-            prog.push_back(OP_SYNC);
-            ++n_ops;
-            for (int id : {s.a, s.b})
-                if (id >= 0) unplace(loc[id]);
         }
+        std::vector<int32_t> prog = {0, 0, n_ops, (int32_t)slot0, (int32_t)slot_words, (int32_t)scratch_byte, 0, 0};
+        for (auto &r : seq)
+            if (!(r.kind == OP_COPY && r.w[3] == 0)) prog.insert(prog.end(), r.w.begin(), r.w.end());
         prog.push_back(OP_END);
-        prog[0] = (int32_t)prog.size();
-        P.fused_lds_bytes = (scratch + lds_ff.peak) * es;
-        P.fused_scratch_bytes = glb_ff.peak * es;
+        prog.resize(prog_words, 0);
+        prog[0] = (int32_t)prog_words;
+        prog[6] = (int32_t)prog.size();
+        prog.insert(prog.end(), gtab.begin(), gtab.end());
+        prog[7] = (int32_t)prog.size();
+        for (auto &ps : P.fused_in_ptr_slots) ps.first += prog[7];
+        for (size_t li = 0; li < P.loads.size(); ++li) P.loads[li].desc_word = prog[7] + ld_off[li];
+        prog.insert(prog.end(), ldesc.begin(), ldesc.end());
+        P.fused_lds_bytes = (vbase + lds_ff.peak) * es;
+        // 16-byte chunk copies may read up to 15 bytes past a value's end
+        P.fused_scratch_bytes = (glb_ff.peak * es + 255) / 256 * 256;
+        P.fused_input_bytes = inputs_end * es;
         prog[1] = (int32_t)P.fused_lds_bytes;
-        prog[2] = n_ops;
         P.program = std::move(prog);
-        P.fused_pure = P.fused_scratch_bytes == 0;
-        P.fused_ok = P.fused_pure || P.mults <= n.fused_max_mults;
+        P.ptr_slots = P.fused_in_ptr_slots;
+        P.fused_pure = glb_ff.peak <= inputs_end;
+        bool has_mfma = false;
+        for (const auto &st : P.steps) has_mfma |= st.mfma != 0;
+        // The fused kernel needs its program and table slots in LDS.  Dense
+        // matrix-core steps run best on the whole GPU: AUTO then uses the
+        // per-step executor.
+        P.fused_possible = loads_fit && values_byte <= n.fused_lds_budget;
+        P.fused_ok = P.fused_possible && !has_mfma && (P.fused_pure || P.mults <= n.fused_max_mults);
+        // In a batch, throughput favours the fused kernel unless the network
+        // is large enough to occupy the GPU by itself.
+        P.fused_batch_ok = P.fused_possible && (P.fused_ok || P.mults <= n.batch_fused_max_mults);
     }
     if (P.tables.empty()) P.tables.assign(2, 0);
     n.plan = std::move(P);
@@ -627,6 +989,8 @@ std::string plan_json(const Net &n) {
     std::ostringstream o;
     o.precision(17);
     o << "{\"n_tensors\":" << n.n_t << ",\"mults\":" << P.mults << ",\"peak\":" << P.peak
+      << ",\"fused_possible\":" << (P.fused_possible ? "true" : "false")
+      << ",\"elem_bytes\":" << dtype_size(inter_dtype(n.compute))
       << ",\"n_absorbed\":" << P.n_absorbed << ",\"fused_ok\":" << (P.fused_ok ? "true" : "false")
       << ",\"fused_pure\":" << (P.fused_pure ? "true" : "false") << ",\"fused_lds_bytes\":" << P.fused_lds_bytes
       << ",\"fused_scratch_bytes\":" << P.fused_scratch_bytes << ",\"ws_bytes\":" << P.ws_bytes
@@ -645,15 +1009,35 @@ std::string plan_json(const Net &n) {
         o << ",\"mults\":" << s.mults << ",\"absorbed\":" << (s.absorbed ? "true" : "false")
           << ",\"final\":" << (s.final_step ? "true" : "false") << ",\"synthetic\":" << (s.synthetic ? "true" : "false")
           << ",\"n_out\":" << s.n_out << ",\"n_sum\":" << s.n_sum << ",\"r_fused\":" << s.r_fused
-          << ",\"r_global\":" << s.r_global << ",\"mfma\":" << s.mfma << ",\"gemm\":[" << s.gb << "," << s.gm
-          << "," << s.gn << "," << s.gk << "]}";
+          << ",\"r_global\":" << s.r_global << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
+          << s.n_slo << "," << s.t_ohi << "," << s.t_olo << "," << s.t_shi << "," << s.t_slo << "],\"pack_a\":["
+          << s.pack_a.n_ohi << "," << s.pack_a.n_olo << "," << s.pack_a.t_ohi << "," << s.pack_a.t_olo << "],\"pack_b\":["
+          << s.pack_b.n_ohi << "," << s.pack_b.n_olo << "," << s.pack_b.t_ohi << "," << s.pack_b.t_olo
+          << "],\"t_cm\":" << s.t_cm << ",\"t_cn\":" << s.t_cn << ",\"mfma\":" << s.mfma << ",\"gemm\":[" << s.gb << "," << s.gm
+          << "," << s.gn << "," << s.gk << "],\"tile\":" << s.tile << ",\"tmnk\":[" << s.tM << "," << s.tN << ","
+          << s.tK << "],\"tcfg\":[" << s.TM << "," << s.TN << "," << s.GX << "]}";
     }
-    o << "],\"loads\":[";
+    o << "],\"values\":[";
+    for (size_t v = 0; v < P.values.size(); ++v) {
+        o << (v ? "," : "") << "{\"labels\":";
+        json_ints(o, P.values[v].labels);
+        o << ",\"input\":" << (P.values[v].input ? "true" : "false") << ",\"base\":" << P.values[v].base << "}";
+    }
+    o << "],\"program\":";
+    {
+        // pointer slots hold the tensor id in the low word here
+        std::vector<int> pw(P.program.begin(), P.program.end());
+        for (auto &ps : P.ptr_slots) pw[ps.first] = ps.second;
+        json_ints(o, pw);
+    }
+    o << ",\"loads\":[";
     for (size_t k = 0; k < P.loads.size(); ++k) {
         const LoadPlan &lp = P.loads[k];
         o << (k ? "," : "") << "{\"value\":" << lp.value << ",\"base\":" << lp.base << ",\"size\":" << lp.size
-          << ",\"scales\":[";
-        for (size_t q = 0; q < lp.scales.size(); ++q) o << (q ? "," : "") << lp.scales[q].tensor;
+          << ",\"src\":[" << lp.src_thi << "," << lp.src_tlo << "," << lp.src_nlo << "],\"scales\":[";
+        for (size_t q = 0; q < lp.scales.size(); ++q)
+            o << (q ? "," : "") << "[" << lp.scales[q].tensor << "," << lp.scales[q].t_hi << "," << lp.scales[q].t_lo
+              << "," << lp.scales[q].n_lo << "]";
         o << "]}";
     }
     o << "]}";

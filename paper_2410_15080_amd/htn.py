@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libhtn.so")
 HTN_F64, HTN_F32, HTN_BF16 = 0, 1, 2
 HTN_SUM_PLAIN, HTN_SUM_FP64, HTN_SUM_COMPENSATED = 0, 1, 2
 HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
-HTN_PATH_GREEDY, HTN_PATH_LEARNED = -1, -2
+HTN_PATH_GREEDY, HTN_PATH_LEARNED, HTN_PATH_SAMPLED = -1, -2, -3
 HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
+HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED = 4, 5
 
 STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
           "HTN_E_DEVICE", "HTN_E_UNSUPPORTED", "HTN_E_STATE"]
@@ -72,11 +73,14 @@ def load_library():
         "htn_batch_run": (I32, [P, ctypes.POINTER(P), P]),
         "htn_batch_timestamps": (I32, [P, i64p]),
         "htn_batch_destroy": (None, [P]),
+        "htn_batch_set_phase_timing": (I32, [P, I32]),
+        "htn_batch_phase_times": (I32, [P, i64p]),
         "htn_update_data": (I32, [P, ctypes.POINTER(P), I32]),
         "htn_destroy": (None, [P]),
         "htn_status_string": (ctypes.c_char_p, [I32]),
         "htn_last_error": (ctypes.c_char_p, []),
         "htn_plan_json": (I32, [P, ctypes.c_char_p, I64, i64p]),
+        "htn_plan_tables": (I32, [P, i32p, I64, i64p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -245,11 +249,17 @@ def htn_contract(net: Net, out, stream=None) -> None:
     _check(load_library().htn_contract(net.handle, ctypes.c_void_p(_data_ptr(out)), _stream_ptr(stream)))
 
 
+def pointer_array(outs):
+    """Device addresses of `outs` as a C array, reusable across calls."""
+    if isinstance(outs, ctypes.Array):
+        return outs
+    return (ctypes.c_void_p * len(outs))(*[_data_ptr(o) for o in outs])
+
+
 def htn_contract_batch(nets, outs, stream=None) -> None:
     lib = load_library()
     hs = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
-    os_ = (ctypes.c_void_p * len(outs))(*[_data_ptr(o) for o in outs])
-    _check(lib.htn_contract_batch(len(nets), hs, os_, _stream_ptr(stream)))
+    _check(lib.htn_contract_batch(len(nets), hs, pointer_array(outs), _stream_ptr(stream)))
 
 
 def htn_batch_create(nets) -> Batch:
@@ -265,14 +275,26 @@ def htn_batch_set_graph(batch: Batch, use_graph: bool) -> None:
 
 
 def htn_batch_run(batch: Batch, outs, stream=None) -> None:
-    os_ = (ctypes.c_void_p * len(outs))(*[_data_ptr(o) for o in outs])
-    _check(load_library().htn_batch_run(batch.handle, os_, _stream_ptr(stream)))
+    """outs: output tensors, or a pointer_array() built once for them."""
+    _check(load_library().htn_batch_run(batch.handle, pointer_array(outs), _stream_ptr(stream)))
 
 
 def htn_batch_timestamps(batch: Batch) -> np.ndarray:
-    t = np.zeros(len(batch.nets), dtype=np.int64)
+    t = np.zeros(2 * len(batch.nets), dtype=np.int64)
     _check(load_library().htn_batch_timestamps(batch.handle, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-    return t
+    return t.reshape(-1, 2)
+
+
+def htn_batch_set_phase_timing(batch: Batch, max_phases: int) -> None:
+    _check(load_library().htn_batch_set_phase_timing(batch.handle, int(max_phases)))
+    batch.max_phases = int(max_phases)
+
+
+def htn_batch_phase_times(batch: Batch) -> np.ndarray:
+    """[n_nets, max_phases] clock ticks (100 MHz) at the end of each phase."""
+    t = np.zeros(len(batch.nets) * batch.max_phases, dtype=np.int64)
+    _check(load_library().htn_batch_phase_times(batch.handle, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return t.reshape(len(batch.nets), batch.max_phases)
 
 
 def htn_batch_destroy(batch: Batch) -> None:
@@ -310,6 +332,16 @@ def htn_plan_json(net: Net) -> str:
     buf = ctypes.create_string_buffer(need.value)
     _check(lib.htn_plan_json(net.handle, buf, need.value, ctypes.byref(need)))
     return buf.value.decode()
+
+
+def htn_plan_tables(net: Net) -> np.ndarray:
+    lib = load_library()
+    need = ctypes.c_int64()
+    _check(lib.htn_plan_tables(net.handle, None, 0, ctypes.byref(need)))
+    buf = np.zeros(max(1, need.value), dtype=np.int32)
+    _check(lib.htn_plan_tables(net.handle, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), need.value,
+                               ctypes.byref(need)))
+    return buf[: need.value]
 
 
 def output_dtype_name(net: Net) -> str:

@@ -1,0 +1,218 @@
+"""Host replay of libhtn plans (test tool).
+
+Executes a plan exported by htn_plan_json / htn_plan_tables with numpy,
+following the documented semantics of each device operation (materialised
+loads, table-driven pairwise steps, operand packs + dense products, and the
+fused kernel's register-tiled steps).  Comparing its result with the oracle
+checks the planner's tables and layouts on the CPU, independently of the
+GPU kernels.
+"""
+
+import json
+
+import numpy as np
+
+from paper_2410_15080_amd import htn
+
+
+def _two_level(tab, t_hi, t_lo, n_lo, n, col):
+    e = np.arange(n)
+    return tab[t_hi + e // n_lo, col] + tab[t_lo + e % n_lo, col]
+
+
+def _load(w, tab, lp, vals):
+    base = np.ascontiguousarray(w.tensors[lp["base"]], dtype=np.float64).ravel()
+    size = lp["size"]
+    thi, tlo, nlo = lp["src"]
+    e = np.arange(size)
+    se = e if nlo == 0 else _two_level(tab, thi, tlo, nlo, size, 0)
+    v = base[se].copy()
+    for t, shi, slo, snlo in lp["scales"]:
+        sc = np.ascontiguousarray(w.tensors[t], dtype=np.float64).ravel()
+        v *= sc[_two_level(tab, shi, slo, snlo, size, 0)]
+    vals[lp["value"]] = v
+
+
+def _generic_step(tab, s, A, B):
+    n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo = s["geom"]
+    oa = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 0)
+    sa = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 0)
+    prod = A[oa[:, None] + sa[None, :]]
+    if B is not None:
+        ob = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 1)
+        sb = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 1)
+        prod = prod * B[ob[:, None] + sb[None, :]]
+    return prod.sum(axis=1)
+
+
+def _mfma_step(tab, s, A, B):
+    gb, gm, gn, gk = s["gemm"]
+    pa = A[_two_level(tab, s["pack_a"][2], s["pack_a"][3], s["pack_a"][1], gb * gm * gk, 0)]
+    pb = B[_two_level(tab, s["pack_b"][2], s["pack_b"][3], s["pack_b"][1], gb * gn * gk, 0)]
+    c = np.einsum("bmk,bnk->bmn", pa.reshape(gb, gm, gk), pb.reshape(gb, gn, gk))
+    return c.ravel()
+
+
+def _tile_step(tab, s, A, B, out_size):
+    M, N, K = s["tmnk"]
+    c = A.reshape(K, M).T @ B.reshape(K, N)
+    cm = tab[s["t_cm"] + np.arange(M), 0]
+    cn = tab[s["t_cn"] + np.arange(N), 0]
+    out = np.full(out_size, np.nan)
+    out[cm[:, None] + cn[None, :]] = c
+    return out
+
+
+OP_END, OP_STEP, OP_SYNC, OP_TSTEP, OP_COPY = 0, 2, 3, 4, 6
+
+
+def run_program(w, prog, n_loads, elem_bytes=8):
+    """Interpret the fused path's device image (same encoding the kernels
+    read): the prep kernel's load descriptors materialise the inputs into
+    the workspace, then the fused program copies and contracts.  LDS and
+    the workspace are modelled as float64 arrays addressed by element
+    offsets; every LDS access is checked to lie between the end of the
+    program, table slots and reduction scratch and the requested LDS size,
+    and every copy to stay inside its slot or value."""
+    prog = np.asarray(prog, dtype=np.int64)
+    n_words, lds_bytes, _, slot0, slot_words, red_byte, tab_base, ld_base = (int(x) for x in prog[:8])
+    assert slot0 >= 8 and slot0 % 4 == 0 and slot_words % 4 == 0
+    assert red_byte >= 4 * (slot0 + 2 * slot_words)
+    lo_elem = (red_byte + 256 + elem_bytes - 1) // elem_bytes
+    hi_elem = lds_bytes // elem_bytes
+    lds = np.full(lds_bytes // elem_bytes + 4, np.nan)
+    ws = np.full(1 << 22, np.nan)
+    ins = [np.ascontiguousarray(t, dtype=np.float64).ravel() for t in w.tensors]
+    # prep: materialise inputs
+    p = ld_base
+    for _ in range(n_loads):
+        base = int(prog[p])                               # pointer slot holds the tensor id
+        dst = int(prog[p + 2]) | (int(prog[p + 3]) << 32)
+        size, rk, ns = (int(x) for x in prog[p + 4:p + 7])
+        sct = [int(prog[p + 7 + 2 * q]) for q in range(ns)]
+        per = prog[p + 7 + 2 * ns:p + 7 + 2 * ns + rk * (2 + ns)].reshape(rk, 2 + ns)
+        rem = np.arange(size)
+        so = np.zeros(size, dtype=np.int64)
+        sc = np.zeros((ns, size), dtype=np.int64)
+        for k in range(rk - 1, -1, -1):
+            d = rem % per[k, 0]
+            rem //= per[k, 0]
+            so += d * per[k, 1]
+            for q in range(ns):
+                sc[q] += d * per[k, 2 + q]
+        v = ins[base][so].copy()
+        for q in range(ns):
+            v *= ins[sct[q]][sc[q]]
+        ws[dst:dst + size] = v
+        p += 7 + 2 * ns + rk * (2 + ns)
+    # tables live in the image as int32 words; LDS slots as separate arrays
+    slots = {}
+    result = None
+    epc = 16 // elem_bytes  # elements per 16-byte chunk
+
+    def at(loc, size=1):
+        if loc >= 0:
+            assert lo_elem <= loc and loc + size <= hi_elem, (loc, size, lo_elem, hi_elem)
+            return lds, loc
+        return ws, -loc - 2
+
+    p = 8
+    while True:
+        op = int(prog[p])
+        if op == OP_END:
+            break
+        if op == OP_SYNC:
+            p += 1
+            continue
+        if op == OP_COPY:
+            kind, src, n, dst = (int(x) for x in prog[p + 1:p + 5])
+            if kind == 0:
+                words = prog[tab_base + 4 * src:tab_base + 4 * (src + n)]
+                slot_idx = (4 * dst - slot0) // slot_words
+                assert 4 * dst == slot0 + slot_idx * slot_words and slot_idx in (0, 1) and 4 * n <= slot_words
+                slots[slot_idx] = words.copy()
+            else:
+                d0 = dst * 16 // elem_bytes
+                at(d0, n * epc)
+                lds[d0:d0 + n * epc] = ws[src * epc:(src + n) * epc]
+            p += 5
+            continue
+        if op == OP_TSTEP:
+            la, lb, lc, M, N, K, tcm, tcn, _, _, _, fin, slot = (int(x) for x in prog[p + 1:p + 14])
+            tab = slots[slot]
+            aa, ao = at(la, K * M)
+            ba, bo = at(lb, K * N)
+            A = aa[ao:ao + K * M].reshape(K, M)
+            B = ba[bo:bo + K * N].reshape(K, N)
+            c = A.T @ B
+            offs = tab[tcm:tcm + M][:, None] + tab[tcn:tcn + N][None, :]
+            if fin:
+                result = np.full(int(offs.max()) + 1, np.nan)
+                result[offs] = c
+            else:
+                ca, co = at(lc, int(offs.max()) + 1)
+                ca[co + offs] = c
+            p += 14
+            continue
+        assert op == OP_STEP, op
+        la, lb, lc, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, _, fin, slot = (
+            int(x) for x in prog[p + 1:p + 15])
+        tab = slots[slot].reshape(-1, 2)
+        oa = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 0)
+        sa = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 0)
+        aa, ao = at(la, int((oa[:, None] + sa[None, :]).max()) + 1)
+        prod = aa[ao + oa[:, None] + sa[None, :]]
+        if lb != -1:
+            ob = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 1)
+            sb = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 1)
+            ba, bo = at(lb, int((ob[:, None] + sb[None, :]).max()) + 1)
+            prod = prod * ba[bo + ob[:, None] + sb[None, :]]
+        c = prod.sum(axis=1)
+        if fin:
+            result = c
+        else:
+            ca, co = at(lc, c.size)
+            ca[co:co + c.size] = c
+        p += 15
+    return result
+
+
+def replay(w, net, executor="steps"):
+    """Replay the net's plan on the host.  executor: "steps" (per-step
+    kernels, matrix-core steps as packed products) or "fused" (the fused
+    kernel's program: tiled steps use their [K][M] x [K][N] view)."""
+    plan = json.loads(htn.htn_plan_json(net))
+    shape = tuple(w.dims[l] for l in w.out_labels)
+    if executor == "program":
+        return run_program(w, plan["program"], len(plan["loads"]), plan["elem_bytes"]).reshape(shape)
+    tab = htn.htn_plan_tables(net).reshape(-1, 2).astype(np.int64)
+    vals = {}
+    values = plan["values"]
+    for lp in plan["loads"]:
+        needs = executor == "fused" or lp["scales"] or lp["src"][2] > 0
+        if needs:
+            _load(w, tab, lp, vals)
+
+    def get(v):
+        if v in vals:
+            return vals[v]
+        assert values[v]["input"], v
+        return np.ascontiguousarray(w.tensors[values[v]["base"]], dtype=np.float64).ravel()
+
+    result = None
+    for s in plan["steps"]:
+        if s["absorbed"]:
+            continue
+        A = get(s["a"])
+        B = get(s["b"]) if s["b"] >= 0 else None
+        out_size = s["n_out"]
+        if executor == "fused" and s["tile"]:
+            C = _tile_step(tab, s, A, B, out_size)
+        elif executor == "steps" and s["mfma"]:
+            C = _mfma_step(tab, s, A, B)
+        else:
+            C = _generic_step(tab, s, A, B)
+        vals[s["c"]] = C
+        if s["final"]:
+            result = C
+    return result.reshape(shape)

@@ -58,7 +58,7 @@ def test_grid_fused_all_in_lds_and_spilled_agree():
     w = configs.grid_network(2)
     hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
     ref = float(hi) + float(lo)
-    for lds in (163840, 65536, 4096, 1024):
+    for lds in (163840, 65536, 32768, 24576):
         got = float(run(w, exec_mode=htn.HTN_EXEC_FUSED, lds=lds))
         assert abs(got - ref) <= REL_F64 * abs(ref), (lds, got, ref)
 
@@ -121,7 +121,7 @@ def test_path_independence(exec_mode):
         try:
             got = float(run(w, exec_mode=exec_mode, path=p))
         except htn.HtnError as e:
-            assert e.name == "HTN_E_OOM"
+            assert e.name in ("HTN_E_OOM", "HTN_E_UNSUPPORTED")
             continue
         assert abs(got - ref) <= REL_F64 * abs(ref), (p, got, ref)
 
@@ -164,7 +164,7 @@ def test_batch_graph_replays_match_eager():
         stream.synchronize()
         assert [float(o.item()) for o in outs] == eager, rep
     t = htn.htn_batch_timestamps(b)
-    assert (t > 0).all()
+    assert (t[:, 0] >= 0).all() and (t[:, 1] > t[:, 0]).all()
 
 
 def test_ring_of_rings_f64():
