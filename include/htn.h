@@ -171,7 +171,8 @@ typedef enum {
     HTN_OPT_FUSED_LDS_BYTES = 2,   /* LDS budget of the fused kernel (default 65536) */
     HTN_OPT_MFMA = 3,              /* 1: allow matrix-core steps (default), 0: VALU only */
     HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
-    HTN_OPT_PATH_SEED = 5          /* seed of the path sampler (default 0) */
+    HTN_OPT_PATH_SEED = 5,         /* seed of the path sampler (default 0) */
+    HTN_OPT_FUSED_THREADS = 6      /* threads per network in the fused kernel: 64 or 256 (default) */
 } htn_option;
 
 htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value);

@@ -68,7 +68,7 @@ struct htn_net : public Net {};
 
 struct htn_batch {
     struct Group {
-        int compute = 0, fm = 0, lds = 0;
+        int compute = 0, fm = 0, lds = 0, threads = 256;
         std::vector<int> idx;  // net indices, heaviest first
         int32_t *d_order = nullptr;
         kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of every net
@@ -328,7 +328,7 @@ static bool use_fused(const Net &n) {
 static void run_fused_single(Net &n, void *out, hipStream_t st) {
     HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, st));
     HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, nullptr, 0, 1,
-                               (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), st));
+                               (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), n.fused_threads, st));
 }
 
 static kern::StepArgs pack_args(const StepPlan::Pack &pk) {
@@ -571,6 +571,18 @@ htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
         case HTN_OPT_PATH_SEED:
             net->path_seed = (uint64_t)value;
             return HTN_OK;
+        case HTN_OPT_FUSED_THREADS: {
+            if (value != 64 && value != 256) return fail(HTN_E_ARG, "fused threads must be 64 or 256");
+            const int old = net->fused_threads;
+            net->fused_threads = (int)value;
+            try {
+                replan(*net);
+            } catch (...) {
+                net->fused_threads = old;
+                throw;
+            }
+            return HTN_OK;
+        }
     }
     return fail(HTN_E_ARG, "unknown option");
     API_GUARD_END
@@ -688,13 +700,16 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
             }
             int c = (int)net.compute, fm = final_mode(net);
             if (c == HTN_F64 && fm == kern::FM_F64) fm = kern::FM_INTER;
-            auto it = std::find_if(b->groups.begin(), b->groups.end(),
-                                   [&](const htn_batch::Group &g) { return g.compute == c && g.fm == fm; });
+            const int th = net.fused_threads;
+            auto it = std::find_if(b->groups.begin(), b->groups.end(), [&](const htn_batch::Group &g) {
+                return g.compute == c && g.fm == fm && g.threads == th;
+            });
             if (it == b->groups.end()) {
                 b->groups.push_back({});
                 it = b->groups.end() - 1;
                 it->compute = c;
                 it->fm = fm;
+                it->threads = th;
             }
             it->idx.push_back(i);
             it->lds = std::max<int>(it->lds, (int)net.plan.fused_lds_bytes);
@@ -743,7 +758,7 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
         HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, st));
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
-                                   (int)g.idx.size(), g.lds, g.compute, g.fm, st));
+                                   (int)g.idx.size(), g.lds, g.compute, g.fm, g.threads, st));
     for (int i : b->step_nets) run_steps(*b->nets[i], outs[i], st);
 }
 

@@ -55,7 +55,11 @@ struct StepPlan {
     int tile = 0;
     std::vector<int> t_gm, t_gn, t_gk;  // tiled view's groups (ascending labels)
     int64_t tM = 1, tN = 1, tK = 1;
-    int64_t t_cm = 0, t_cn = 0;  // table offsets (pairs, .x used)
+    int64_t t_cm = 0, t_cn = 0;  // table offsets (pairs, .x used; per-step executor replay)
+    // C offset of m (and of n) from mixed-radix digits: per label of the
+    // group (last fastest) its extent, magic multiplier (2 words) and C
+    // stride; floor(x / d) = (x * magic) >> 40.
+    std::vector<int32_t> c_digits_m, c_digits_n;
     int TM = 1, TN = 1, GX = 16;  // per-thread tile and thread-grid width
 };
 
@@ -140,6 +144,7 @@ struct Net {
     htn_exec_mode exec = HTN_EXEC_AUTO;
     int64_t max_intermediate = (int64_t(1) << 31) - 1;
     int64_t fused_lds_budget = 65536;
+    int fused_threads = 256;  // threads per network in the fused kernel (64 or 256)
     double fused_max_mults = 67108864.0;        // AUTO runs larger spilled nets step by step
     double batch_fused_max_mults = 33554432.0;  // batch limit for nets with matrix-core steps
     int allow_mfma = 1;

@@ -240,7 +240,67 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
 
 // One step inside the fused kernel.  A, B point into LDS; C into LDS or, for
 // the final step, global memory.
-template <typename T, typename ACC, bool COMP, bool UNARY, typename TOUT>
+// Sum over the summed index space (n_shi x n_slo, two-level tables) of one
+// output, visiting s = start, start + stride, ... in (sh, sl) form with
+// stride = dq * n_slo + dr (dr < n_slo).  Plain sums keep four independent
+// partial sums, so four table reads and four operand reads are in flight
+// together; compensated sums stay sequential.
+template <typename T, typename ACC, bool COMP, bool UNARY>
+__device__ __forceinline__ void strided_sum(const T *a0, const T *b0, const int2 *tsh, const int2 *tsl, int sh, int sl,
+                                            int dq, int dr, int n_shi, int n_slo, ACC &s, ACC &c) {
+    if constexpr (!COMP) {
+        ACC s1 = 0, s2 = 0, s3 = 0;
+        while (sh < n_shi) {
+            int hv[4], lv[4];
+            hv[0] = sh;
+            lv[0] = sl;
+#pragma unroll
+            for (int u = 1; u < 4; ++u) {
+                hv[u] = hv[u - 1] + dq;
+                lv[u] = lv[u - 1] + dr;
+                if (lv[u] >= n_slo) {
+                    lv[u] -= n_slo;
+                    ++hv[u];
+                }
+            }
+            sh = hv[3] + dq;
+            sl = lv[3] + dr;
+            if (sl >= n_slo) {
+                sl -= n_slo;
+                ++sh;
+            }
+            ACC pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = hv[u] < n_shi;
+                const int2 h = tsh[ok ? hv[u] : 0], l = tsl[lv[u]];
+                ACC q = (ACC)a0[h.x + l.x];
+                if constexpr (!UNARY) q *= (ACC)b0[h.y + l.y];
+                pv[u] = ok ? q : ACC(0);
+            }
+            s += pv[0];
+            s1 += pv[1];
+            s2 += pv[2];
+            s3 += pv[3];
+        }
+        s += (s1 + s2) + s3;
+    } else {
+        while (sh < n_shi) {
+            const int2 h = tsh[sh], l = tsl[sl];
+            ACC q = (ACC)a0[h.x + l.x];
+            if constexpr (!UNARY) q *= (ACC)b0[h.y + l.y];
+            accum<COMP>(s, c, q);
+            sh += dq;
+            sl += dr;
+            if (sl >= n_slo) {
+                sl -= n_slo;
+                ++sh;
+            }
+        }
+    }
+}
+
+template <int BLK, typename T, typename ACC, bool COMP, bool UNARY, typename TOUT>
 __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int2 *__restrict__ tab,
                                       const int32_t *g, int R, ACC *scratch) {
     const int n_ohi = g[0], n_olo = g[1], n_shi = g[2], n_slo = g[3];
@@ -250,9 +310,9 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     const int2 *tsl = tab + g[7];
     const int n_out = n_ohi * n_olo;
     const int tid = threadIdx.x;
-    if (R == kBlk) {
+    if (R == BLK) {
         // whole workgroup per output (tiny outputs, long sums)
-        const int dq = kBlk / n_slo, dr = kBlk - dq * n_slo;
+        const int dq = BLK / n_slo, dr = BLK - dq * n_slo;
         for (int o = 0; o < n_out; ++o) {
             const int oh = o / n_olo, ol = o - oh * n_olo;
             const int2 x = toh[oh], y = tol[ol];
@@ -260,19 +320,8 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
             const T *b0 = B;
             if constexpr (!UNARY) b0 = B + (x.y + y.y);
             ACC s = 0, c = 0;
-            int sh = tid / n_slo, sl = tid - sh * n_slo;
-            while (sh < n_shi) {
-                const int2 h = tsh[sh], l = tsl[sl];
-                ACC p = (ACC)a0[h.x + l.x];
-                if constexpr (!UNARY) p *= (ACC)b0[h.y + l.y];
-                accum<COMP>(s, c, p);
-                sh += dq;
-                sl += dr;
-                if (sl >= n_slo) {
-                    sl -= n_slo;
-                    ++sh;
-                }
-            }
+            const int sh = tid / n_slo, sl = tid - sh * n_slo;
+            strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
             lane_reduce<COMP>(s, c, 64);
             if ((tid & 63) == 0) {
                 scratch[2 * (tid >> 6)] = s;
@@ -281,7 +330,7 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
             __syncthreads();
             if (tid == 0) {
                 ACC ts = scratch[0], tc = scratch[1];
-                for (int w = 1; w < kBlk / 64; ++w) combine<COMP>(ts, tc, scratch[2 * w], scratch[2 * w + 1]);
+                for (int w = 1; w < BLK / 64; ++w) combine<COMP>(ts, tc, scratch[2 * w], scratch[2 * w + 1]);
                 C[o] = st_cvt<TOUT>(COMP ? ts + tc : ts);
             }
             __syncthreads();
@@ -290,7 +339,7 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     }
     int log2R = 0;
     while ((1 << log2R) < R) ++log2R;
-    const int groups = kBlk >> log2R;
+    const int groups = BLK >> log2R;
     const int gi = tid >> log2R, sub = tid & (R - 1);
     const int dq = R / n_slo, dr = R - dq * n_slo;
     for (int o0 = 0; o0 < n_out; o0 += groups) {
@@ -337,19 +386,8 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
                 }
                 s += (s1 + s2) + s3;
             } else {
-                int sh = sub / n_slo, sl = sub - sh * n_slo;
-                while (sh < n_shi) {
-                    const int2 h = tsh[sh], l = tsl[sl];
-                    ACC p = (ACC)a0[h.x + l.x];
-                    if constexpr (!UNARY) p *= (ACC)b0[h.y + l.y];
-                    accum<COMP>(s, c, p);
-                    sh += dq;
-                    sl += dr;
-                    if (sl >= n_slo) {
-                        sl -= n_slo;
-                        ++sh;
-                    }
-                }
+                const int sh = sub / n_slo, sl = sub - sh * n_slo;
+                strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
             }
         }
         lane_reduce<COMP>(s, c, R);
@@ -361,12 +399,29 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
 // Thread (tx, ty) of a GX x (kBlk/GX) grid owns outputs m = m0 + tx + GX*i,
 // n = n0 + ty + GY*j (i < TM, j < TN).  Across a wave, A reads are
 // consecutive or broadcast, B reads broadcast or consecutive.
-template <typename T, typename ACC, int TM, int TN, typename TOUT>
-__device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int *tcm, const int *tcn, int M, int N,
-                                      int K, int GX) {
+// Offset of index x of a label group from its digit descriptors (per label,
+// last fastest: extent, magic (2 words), stride).
+__device__ __forceinline__ int digit_offset(uint32_t x, const int32_t *dg, int nl) {
+    int off = 0;
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        if (k < nl) {
+            const int32_t *q = dg + 4 * k;
+            const uint64_t magic = ((uint64_t)(uint32_t)q[2] << 32) | (uint32_t)q[1];
+            const uint32_t quo = (uint32_t)(((uint64_t)x * magic) >> 40);
+            off += (int)(x - quo * (uint32_t)q[0]) * q[3];
+            x = quo;
+        }
+    }
+    return off;
+}
+
+template <int BLK, typename T, typename ACC, int TM, int TN, typename TOUT>
+__device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int32_t *dgm, int nm, const int32_t *dgn,
+                                      int nn_l, int M, int N, int K, int GX) {
     int lgx = 0;
     while ((1 << lgx) < GX) ++lgx;
-    const int GY = kBlk >> lgx;
+    const int GY = BLK >> lgx;
     const int tx = threadIdx.x & (GX - 1), ty = threadIdx.x >> lgx;
     const int SM = GX * TM, SN = GY * TN;
     for (int m0 = 0; m0 < M; m0 += SM) {
@@ -428,15 +483,18 @@ __device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j) acc[0][i][j] += acc[u][i][j];
+            int cn[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) cn[j] = digit_offset((uint32_t)nj[j], dgn, nn_l);
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int m = m0 + tx + GX * i;
                 if (m < M) {
-                    const int cm = tcm[m];
+                    const int cm = digit_offset((uint32_t)m, dgm, nm);
 #pragma unroll
                     for (int j = 0; j < TN; ++j) {
                         const int nn = n0 + ty + GY * j;
-                        if (nn < N) C[cm + tcn[nn]] = st_cvt<TOUT>(acc[0][i][j]);
+                        if (nn < N) C[cm + cn[j]] = st_cvt<TOUT>(acc[0][i][j]);
                     }
                 }
             }
@@ -444,44 +502,46 @@ __device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int
     }
 }
 
-template <typename T, typename ACC, typename TOUT>
-__device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int *tcm, const int *tcn, int M,
-                                          int N, int K, int TM, int TN, int GX) {
+template <int BLK, typename T, typename ACC, typename TOUT>
+__device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int32_t *tcm, int nm,
+                                          const int32_t *tcn, int nn_l, int M, int N, int K, int TM, int TN, int GX) {
     switch (TM * 8 + TN) {
-        case 9: tstep<T, ACC, 1, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 10: tstep<T, ACC, 1, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 12: tstep<T, ACC, 1, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 17: tstep<T, ACC, 2, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 18: tstep<T, ACC, 2, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 20: tstep<T, ACC, 2, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 33: tstep<T, ACC, 4, 1, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        case 34: tstep<T, ACC, 4, 2, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
-        default: tstep<T, ACC, 4, 4, TOUT>(A, B, C, tcm, tcn, M, N, K, GX); break;
+        case 9: tstep<BLK, T, ACC, 1, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 10: tstep<BLK, T, ACC, 1, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 12: tstep<BLK, T, ACC, 1, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 17: tstep<BLK, T, ACC, 2, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 18: tstep<BLK, T, ACC, 2, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 20: tstep<BLK, T, ACC, 2, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 33: tstep<BLK, T, ACC, 4, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 34: tstep<BLK, T, ACC, 4, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        default: tstep<BLK, T, ACC, 4, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
     }
 }
 
-// OP_TSTEP: [a, b, c, M, N, K, t_cm, t_cn, TM, TN, GX, final]
-template <typename T, int FM>
-__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, const int *itab, void *out) {
+// OP_TSTEP: [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M, digits of N]
+template <int BLK, typename T, int FM>
+__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, void *out) {
     const int la = p[1], lb = p[2], lc = p[3];
     const int M = p[4], N = p[5], K = p[6];
-    const int *tcm = itab + p[7];
-    const int *tcn = itab + p[8];
-    const int TM = p[9], TN = p[10], GX = p[11];
-    const bool fin = p[12] != 0;
+    const int TM = p[7], TN = p[8], GX = p[9];
+    const bool fin = p[10] != 0;
+    const int nm = p[11], nn_l = p[12];
+    const int32_t *tcm = p + 13;
+    const int32_t *tcn = p + 13 + 4 * nm;
     typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
     if (la >= 0 && lb >= 0 && (fin || lc >= 0)) {
         if (!fin)
-            tstep_sel<T, T, T>(sm + la, sm + lb, sm + lc, tcm, tcn, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, T, T>(sm + la, sm + lb, sm + lc, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
         else
-            tstep_sel<T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, tcn, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
     } else {
         const T *A = la >= 0 ? sm + la : scr + (-la - 2);
         const T *B = lb >= 0 ? sm + lb : scr + (-lb - 2);
         if (!fin)
-            tstep_sel<T, T, T>(A, B, lc >= 0 ? sm + lc : scr + (-lc - 2), tcm, tcn, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, T, T>(A, B, lc >= 0 ? sm + lc : scr + (-lc - 2), tcm, nm, tcn, nn_l, M, N, K, TM, TN,
+                                    GX);
         else
-            tstep_sel<T, TO, TO>(A, B, (TO *)out, tcm, tcn, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, TO, TO>(A, B, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
     }
 }
 
@@ -490,73 +550,55 @@ __device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, 
 // workspace and the digit form of its planned layout: element e of the
 // value has mixed-radix digits over the value's labels; its source offset
 // and each coefficient tensor's offset are dot products of the digits with
-// per-label strides.  Each thread walks e = e0, e0 + stride, ... advancing
-// the digits by the digits of the stride with carries (no division in the
-// loop).
+// per-label strides.  Digits are extracted with precomputed magic
+// multipliers: floor(e / d) = (e * magic) >> 40, exact for e < 2^24 and
+// d < 2^16.
 // Descriptor words: [base ptr (2), dst element offset (2), size, rank, ns,
-//   scale ptrs (2 each), per label k: (extent, source stride, scale strides)]
+//   scale ptrs (2 each), per label k: (extent, magic (2), source stride,
+//   scale strides)]
 __device__ __forceinline__ const void *word_ptr(const int32_t *w) {
     return (const void *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
 }
 
 template <typename T, typename TIN>
-__global__ __launch_bounds__(kBlk) void k_fprep(const FPrepEntry *__restrict__ entries) {
-    const FPrepEntry en = entries[blockIdx.y];
+__global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
+    // one wave per entry; descriptor words are uniform (scalar loads)
+    const FPrepEntry en = entries[blockIdx.x];
     const int32_t *p = en.desc;
     const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
     const int size = p[4], rk = p[5], ns = p[6];
     const int32_t *per = p + 7 + 2 * ns;
-    const int W = 2 + ns;
+    const int W = 4 + ns;
     const TIN *src = (const TIN *)word_ptr(p);
     T *o = (T *)en.ws + dst_off;
     const TIN *sp[kMaxScalesLoad];
 #pragma unroll
     for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
-    const int e0 = blockIdx.x * kBlk + threadIdx.x;
-    const int stride = gridDim.x * kBlk;
-    int dig[kMaxRankLoad], inc[kMaxRankLoad];
-    int so = 0, sc[kMaxScalesLoad];
+    for (int e = threadIdx.x; e < size; e += 64) {
+        uint32_t rem = (uint32_t)e;
+        int so = 0;
+        int sc[kMaxScalesLoad];
 #pragma unroll
-    for (int q = 0; q < kMaxScalesLoad; ++q) sc[q] = 0;
-    {
-        int e = e0, c = stride;
+        for (int q = 0; q < kMaxScalesLoad; ++q) sc[q] = 0;
 #pragma unroll
         for (int k = kMaxRankLoad - 1; k >= 0; --k) {
             if (k < rk) {
-                const int dim = per[k * W];
-                dig[k] = e % dim;
-                e /= dim;
-                inc[k] = c % dim;
-                c /= dim;
-                so += dig[k] * per[k * W + 1];
+                const int32_t *pk = per + k * W;
+                const uint64_t magic = ((uint64_t)(uint32_t)pk[2] << 32) | (uint32_t)pk[1];
+                const uint32_t quo = (uint32_t)(((uint64_t)rem * magic) >> 40);
+                const int dgt = (int)(rem - quo * (uint32_t)pk[0]);
+                rem = quo;
+                so += dgt * pk[3];
 #pragma unroll
                 for (int q = 0; q < kMaxScalesLoad; ++q)
-                    if (q < ns) sc[q] += dig[k] * per[k * W + 2 + q];
+                    if (q < ns) sc[q] += dgt * pk[4 + q];
             }
         }
-    }
-    for (int e = e0; e < size; e += stride) {
         T v = Ld<T, TIN>::get(src + so);
 #pragma unroll
         for (int q = 0; q < kMaxScalesLoad; ++q)
             if (q < ns) v *= Ld<T, TIN>::get(sp[q] + sc[q]);
         o[e] = v;
-        int carry = 0;
-#pragma unroll
-        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
-            if (k < rk) {
-                const int dim = per[k * W];
-                int dd = dig[k] + inc[k] + carry;
-                carry = dd >= dim;
-                if (carry) dd -= dim;
-                const int delta = dd - dig[k];
-                so += delta * per[k * W + 1];
-#pragma unroll
-                for (int q = 0; q < kMaxScalesLoad; ++q)
-                    if (q < ns) sc[q] += delta * per[k * W + 2 + q];
-                dig[k] = dd;
-            }
-        }
     }
 }
 
@@ -564,27 +606,48 @@ __global__ __launch_bounds__(kBlk) void k_fprep(const FPrepEntry *__restrict__ e
 // step are issued into registers before the step's arithmetic and written
 // to LDS after it, so their global latency overlaps the computation.
 constexpr int kPrefetch = 4;  // staged chunks per thread
+// Global-memory view of a copy source: the image and the workspace both
+// live in device memory, so the loads are plain global loads (no flat
+// address-space dispatch) and stay independent of LDS traffic.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_uint4;
+
 struct CopyOp {
-    const uint4 *src;
-    uint4 *dst;
+    const g_uint4 *src;
+    int dst;  // 16-byte chunk index in LDS
     int n;
 };
 
-__device__ __forceinline__ CopyOp decode_copy(const int32_t *p, const int32_t *image, const unsigned char *ws,
-                                              unsigned char *smem) {
+__device__ __forceinline__ CopyOp decode_copy(const int32_t *p, const int32_t *image, const unsigned char *ws) {
     // [kind, src chunk, chunks, dst chunk]; kind 0: image words, 1: workspace
     CopyOp c;
-    c.src = p[1] == 0 ? (const uint4 *)(image) + p[2] : (const uint4 *)ws + p[2];
-    c.dst = (uint4 *)smem + p[4];
+    const u32x4 *s = p[1] == 0 ? (const u32x4 *)(image) + p[2] : (const u32x4 *)ws + p[2];
+    c.src = (const g_uint4 *)s;
+    c.dst = p[4];
     c.n = p[3];
     return c;
+}
+
+// Copy n 16-byte chunks from global memory to LDS, four independent loads
+// in flight per thread.
+template <int BLK>
+__device__ __forceinline__ void copy_chunks(const g_uint4 *src, u32x4 *dst, int n) {
+    for (int c0 = threadIdx.x; c0 < n; c0 += 4 * BLK) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u * BLK < n) v[u] = src[c0 + u * BLK];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u * BLK < n) dst[c0 + u * BLK] = v[u];
+    }
 }
 
 // The fused kernel.  A workgroup copies its network's program into LDS and
 // interprets it: COPY moves tables or materialised inputs into LDS,
 // STEP / TSTEP contract two values, SYNC ends a phase.
-template <typename T, typename TIN, int FM>
-__global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
+template <int BLK, typename T, typename TIN, int FM>
+__global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
                                                void *const *__restrict__ outs, int64_t *__restrict__ stamps,
                                                void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -593,10 +656,8 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
     const FusedDesc d = nets[net];
     const int64_t t0 = stamps ? (int64_t)wall_clock64() : 0;
     int32_t *img = reinterpret_cast<int32_t *>(smem);
-    {
-        const int nw = d.prog[0];
-        for (int i = threadIdx.x; i < nw; i += kBlk) img[i] = d.prog[i];
-    }
+    // program words (a multiple of four) as 16-byte chunks
+    copy_chunks<BLK>((const g_uint4 *)d.prog, (u32x4 *)smem, d.prog[0] / 4);
     __syncthreads();
     int32_t *slots = img + img[3];
     const int slot_words = img[4];
@@ -618,35 +679,55 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
             continue;
         }
         if (op == OP_COPY) {
-            const CopyOp c = decode_copy(p, gimg, (const unsigned char *)d.scratch, smem);
-            for (int i = threadIdx.x; i < c.n; i += kBlk) c.dst[i] = c.src[i];
+            const CopyOp c = decode_copy(p, gimg, (const unsigned char *)d.scratch);
+            copy_chunks<BLK>(c.src, (u32x4 *)smem + c.dst, c.n);
             p += 5;
             continue;
         }
-        const int step_len = op == OP_TSTEP ? 14 : 15;
-        // issue the following copies (next phase's tables and operands)
+        const int step_len = op == OP_TSTEP ? 13 + 4 * (p[11] + p[12]) : 15;
+        // issue the following copies (next phase's tables and operands):
+        // each thread stages up to kPrefetch chunks in registers while the
+        // step runs
         CopyOp cps[4];
         int starts[5] = {0, 0, 0, 0, 0};
         int nc = 0, tot = 0;
         const int32_t *q = p + step_len;
         while (nc < 4 && q[0] == OP_COPY) {
-            cps[nc] = decode_copy(q, gimg, (const unsigned char *)d.scratch, smem);
+            cps[nc] = decode_copy(q, gimg, (const unsigned char *)d.scratch);
             starts[nc] = tot;
             tot += cps[nc].n;
             ++nc;
             q += 5;
         }
         starts[nc] = tot;
-        uint4 stg[kPrefetch];
+        u32x4 stg0, stg1, stg2, stg3;
+        int dst0 = -1, dst1 = -1, dst2 = -1, dst3 = -1;
+        {
+            const g_uint4 *src[kPrefetch];
+            int dst[kPrefetch];
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const int c = threadIdx.x + j * kBlk;
+            for (int j = 0; j < kPrefetch; ++j) {
+                const int c = threadIdx.x + j * BLK;
+                src[j] = cps[0].src;
+                dst[j] = -1;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < nc && c >= starts[k] && c < starts[k + 1]) stg[j] = cps[k].src[c - starts[k]];
+                for (int k = 0; k < 4; ++k)
+                    if (k < nc && c >= starts[k] && c < starts[k + 1]) {
+                        src[j] = cps[k].src + (c - starts[k]);
+                        dst[j] = cps[k].dst + (c - starts[k]);
+                    }
+            }
+            if (dst[0] >= 0) stg0 = *src[0];
+            if (dst[1] >= 0) stg1 = *src[1];
+            if (dst[2] >= 0) stg2 = *src[2];
+            if (dst[3] >= 0) stg3 = *src[3];
+            dst0 = dst[0];
+            dst1 = dst[1];
+            dst2 = dst[2];
+            dst3 = dst[3];
         }
         if (op == OP_TSTEP) {
-            tstep_dispatch<T, FM>(p, sm, scr, slots + p[13] * slot_words, out);
+            tstep_dispatch<BLK, T, FM>(p, sm, scr, out);
         } else {
             // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot]
             const int2 *itab2 = reinterpret_cast<const int2 *>(slots + p[14] * slot_words);
@@ -661,14 +742,14 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
                 const T *B = unary ? nullptr : sm + lb;
                 if (!fin) {
                     if (unary)
-                        fstep<T, T, false, true, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, true, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
                     else
-                        fstep<T, T, false, false, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, false, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
                 } else {
                     if (unary)
-                        fstep<T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
                     else
-                        fstep<T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
                 }
             } else {
                 const T *A = la >= 0 ? sm + la : scr + (-la - 2);
@@ -676,30 +757,31 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
                 if (!fin) {
                     T *C = lc >= 0 ? sm + lc : scr + (-lc - 2);
                     if (unary)
-                        fstep<T, T, false, true, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, true, T>(A, B, C, itab2, p + 4, R, (T *)red);
                     else
-                        fstep<T, T, false, false, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, false, T>(A, B, C, itab2, p + 4, R, (T *)red);
                 } else {
                     if (unary)
-                        fstep<T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
                     else
-                        fstep<T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
                 }
             }
         }
         // land the staged chunks, copy any remainder directly
-#pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const int c = threadIdx.x + j * kBlk;
+        u32x4 *lds4 = (u32x4 *)smem;
+        if (dst0 >= 0) lds4[dst0] = stg0;
+        if (dst1 >= 0) lds4[dst1] = stg1;
+        if (dst2 >= 0) lds4[dst2] = stg2;
+        if (dst3 >= 0) lds4[dst3] = stg3;
+        if (tot > kPrefetch * BLK) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (k < nc && c >= starts[k] && c < starts[k + 1]) cps[k].dst[c - starts[k]] = stg[j];
+                if (k < nc && starts[k + 1] > kPrefetch * BLK) {
+                    const int skip = max(0, kPrefetch * BLK - starts[k]);
+                    copy_chunks<BLK>(cps[k].src + skip, lds4 + cps[k].dst + skip, cps[k].n - skip);
+                }
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (k < nc)
-                for (int c = threadIdx.x + kPrefetch * kBlk; c < starts[k + 1]; c += kBlk)
-                    if (c >= starts[k]) cps[k].dst[c - starts[k]] = cps[k].src[c - starts[k]];
         p = q;
     }
     if (stamps && threadIdx.x == 0) {
@@ -709,31 +791,25 @@ __global__ __launch_bounds__(kBlk) void k_fused(const FusedDesc *__restrict__ ne
 }
 
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st) {
+    (void)max_size;
     if (n_entries <= 0) return hipSuccess;
-    int bx = (max_size + kBlk * 4 - 1) / (kBlk * 4);
-    bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
-    for (int first = 0; first < n_entries; first += 65535) {
-        const int cnt = n_entries - first < 65535 ? n_entries - first : 65535;
-        dim3 grid(bx, cnt);
-        if (compute == 0)
-            hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(kBlk), 0, st, entries + first);
-        else if (compute == 1)
-            hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(kBlk), 0, st, entries + first);
-        else
-            hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(kBlk), 0, st, entries + first);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    dim3 grid(n_entries);
+    if (compute == 0)
+        hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries);
+    else if (compute == 1)
+        hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries);
+    else
+        hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries);
+    return hipGetLastError();
 }
 
-template <typename T, typename TIN, int FM>
+template <int BLK, typename T, typename TIN, int FM>
 static hipError_t go_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
                            void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
                            hipStream_t st) {
     static int configured = -1;
     if (lds_bytes > configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_fused<T, TIN, FM>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_fused<BLK, T, TIN, FM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -741,29 +817,41 @@ static hipError_t go_fused(const FusedDesc *nets, const int32_t *order, void *co
         }
         configured = lds_bytes;
     }
-    hipLaunchKernelGGL((k_fused<T, TIN, FM>), dim3(n_blocks), dim3(kBlk), lds_bytes, st, nets, order, outs, stamps,
-                       out1, phase_ticks, max_phases);
+    hipLaunchKernelGGL((k_fused<BLK, T, TIN, FM>), dim3(n_blocks), dim3(BLK), lds_bytes, st, nets, order, outs,
+                       stamps, out1, phase_ticks, max_phases);
     return hipGetLastError();
+}
+
+template <int BLK>
+static hipError_t launch_fused_blk(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
+                                   void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
+                                   int compute, int fm, hipStream_t st) {
+#define HTN_GO(T, TIN, F) go_fused<BLK, T, TIN, F>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st)
+    if (compute == 0) return fm == FM_COMP ? HTN_GO(double, double, FM_COMP) : HTN_GO(double, double, FM_INTER);
+    if (compute == 1) {
+        if (fm == FM_COMP) return HTN_GO(float, float, FM_COMP);
+        if (fm == FM_F64) return HTN_GO(float, float, FM_F64);
+        return HTN_GO(float, float, FM_INTER);
+    }
+    if (compute == 2) {
+        if (fm == FM_COMP) return HTN_GO(float, bf16_t, FM_COMP);
+        if (fm == FM_F64) return HTN_GO(float, bf16_t, FM_F64);
+        return HTN_GO(float, bf16_t, FM_INTER);
+    }
+#undef HTN_GO
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
                         int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
-                        hipStream_t st) {
+                        int threads, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    if (compute == 0) {
-        if (fm == FM_COMP) return go_fused<double, double, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-        return go_fused<double, double, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-    }
-    if (compute == 1) {
-        if (fm == FM_COMP) return go_fused<float, float, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-        if (fm == FM_F64) return go_fused<float, float, FM_F64>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-        return go_fused<float, float, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-    }
-    if (compute == 2) {
-        if (fm == FM_COMP) return go_fused<float, bf16_t, FM_COMP>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-        if (fm == FM_F64) return go_fused<float, bf16_t, FM_F64>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-        return go_fused<float, bf16_t, FM_INTER>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st);
-    }
+    if (threads == 64)
+        return launch_fused_blk<64>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes,
+                                    compute, fm, st);
+    if (threads == 256)
+        return launch_fused_blk<256>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes,
+                                     compute, fm, st);
     return hipErrorInvalidValue;
 }
 

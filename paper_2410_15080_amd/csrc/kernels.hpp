@@ -54,9 +54,10 @@ struct FusedDesc {
 // out1 (optional): output of a single-network launch, used instead of outs.
 // phase_ticks (optional): [net * max_phases + k] receives the clock at the
 // end of the network's k-th phase (after its barrier).
+// threads: workgroup size of the fused kernel (64 or 256), as planned.
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
                         int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
-                        hipStream_t st);
+                        int threads, hipStream_t st);
 
 // Matrix-core GEMM C[b][m][n] = sum_k A[b][m][k] B[b][n][k] on packed,
 // K-contiguous operands (mfma.hip).  tin: 0 f64, 1 f32, 2 bf16; tout: 0 f64,

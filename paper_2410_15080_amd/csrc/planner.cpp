@@ -350,16 +350,23 @@ static void flat_table(const Net &n, const std::vector<int> &group, const std::v
 }
 
 // Register tile of a tiled step: TM x TN outputs per thread on a GX x GY
-// thread grid (GX * GY = kBlock).  Cost model per thread: passes over the
-// output times K times (FMAs + operand loads), loads weighted 1/2.
-static void choose_tile(StepPlan &s) {
+// thread grid (GX * GY = threads).  The kernel runs U = 16 / (TM*TN)
+// (at most 8, at least 1) independent partial sums over k.  Modelled time
+// of a thread, in FMA-issue slots: passes * (30 + blocks * max(24, U *
+// (TM*TN + (TM+TN)/2)) + tail * 24) with blocks = floor(K / U) and
+// tail = K mod U: a k-block cannot finish faster than one LDS round trip
+// (~24 slots), so large tiles and few passes win when K is small.
+static void choose_tile(StepPlan &s, int threads) {
     double best = 0;
     for (int tm : {1, 2, 4})
         for (int tn : {1, 2, 4})
-            for (int gx = 1; gx <= kBlock; gx *= 2) {
-                const int gy = kBlock / gx;
+            for (int gx = 1; gx <= threads; gx *= 2) {
+                const int gy = threads / gx;
                 const double passes = std::ceil((double)s.tM / (gx * tm)) * std::ceil((double)s.tN / (gy * tn));
-                const double cost = passes * (double)s.tK * (tm * tn + 0.5 * (tm + tn));
+                const int u = tm * tn >= 16 ? 1 : (tm * tn >= 8 ? 2 : (tm * tn >= 4 ? 4 : 8));
+                const double blocks = std::floor((double)s.tK / u), tail = (double)(s.tK % u);
+                const double per = 30.0 + blocks * std::max(24.0, u * (tm * tn + 0.5 * (tm + tn))) + tail * 24.0;
+                const double cost = passes * per;
                 if (best == 0 || cost < best - 1e-9) {
                     best = cost;
                     s.TM = tm;
@@ -581,8 +588,9 @@ void build_plan(Net &n) {
         for (int l : bl)
             if (!contains(s.sum_labels, l)) Nn.push_back(l);
         if (!ok) continue;
+        if (M.size() > 8 || Nn.size() > 8) continue;  // digit descriptors hold up to 8 labels
         const int64_t mM = (int64_t)prod_dims(n, M), nN = (int64_t)prod_dims(n, Nn);
-        if (mM * nN < kBlock) continue;  // fewer outputs than threads: split the sums instead
+        if (mM * nN < n.fused_threads) continue;  // fewer outputs than threads: split the sums instead
         K = s.sum_labels;
         std::sort(K.begin(), K.end());
         std::sort(M.begin(), M.end());
@@ -636,7 +644,20 @@ void build_plan(Net &n) {
             for (int l : s.t_gn) cn.push_back(stride_in(s.c_labels, stc, l));
             flat_table(n, s.t_gm, cm, P.tables, s.t_cm);
             flat_table(n, s.t_gn, cn, P.tables, s.t_cn);
-            choose_tile(s);
+            auto digits = [&](const std::vector<int> &g, const std::vector<int64_t> &st, std::vector<int32_t> &out) {
+                out.clear();
+                for (size_t k = 0; k < g.size(); ++k) {
+                    const uint64_t d = (uint64_t)n.dims[g[k]];
+                    const uint64_t magic = ((uint64_t(1) << 40) + d - 1) / d;
+                    out.push_back((int32_t)d);
+                    out.push_back((int32_t)(uint32_t)(magic & 0xffffffffu));
+                    out.push_back((int32_t)(uint32_t)(magic >> 32));
+                    out.push_back((int32_t)st[k]);
+                }
+            };
+            digits(s.t_gm, cm, s.c_digits_m);
+            digits(s.t_gn, cn, s.c_digits_n);
+            choose_tile(s, n.fused_threads);
         }
         if (s.mfma) {
             // pack A -> [batch][M][K], B -> [batch][N][K]: unary permutes
@@ -658,12 +679,13 @@ void build_plan(Net &n) {
         s.n_out = s.n_ohi * s.n_olo;
         s.n_sum = s.n_shi * s.n_slo;
         // fused kernel: lanes per output
-        if (s.n_out >= kBlock) {
+        const int fth = n.fused_threads;
+        if (s.n_out >= fth) {
             s.r_fused = 1;
-        } else if (s.n_out <= 2 && s.n_sum >= 512) {
-            s.r_fused = kBlock;  // whole block per output
+        } else if (s.n_out <= 2 && s.n_sum >= 512 && fth > 64) {
+            s.r_fused = fth;  // whole block per output
         } else {
-            int r = std::min<int64_t>(64, pow2floor(kBlock / s.n_out));
+            int r = std::min<int64_t>(64, pow2floor(fth / s.n_out));
             r = std::min(r, pow2ceil(s.n_sum));
             s.r_fused = std::max(1, r);
         }
@@ -773,7 +795,7 @@ void build_plan(Net &n) {
                 return o;
             };
             if (s.tile) {
-                rel[q] = {put_x(s.t_cm, s.tM), put_x(s.t_cn, s.tN)};
+                rel[q] = {0, 0};  // offsets computed from digits: no tables
             } else {
                 rel[q] = {put_pairs(s.t_ohi, s.n_ohi), put_pairs(s.t_olo, s.n_olo), put_pairs(s.t_shi, s.n_shi),
                           put_pairs(s.t_slo, s.n_slo)};
@@ -798,7 +820,7 @@ void build_plan(Net &n) {
             if (rk > 16 || ns > kMaxScales) loads_fit = false;
             ld_off[li] = (int64_t)ldesc.size();
             // [base ptr (2), dst element offset in workspace (2), size, rank, ns, scale ptrs (2 each),
-            //  per label: extent, source stride, scale strides]
+            //  per label: extent, magic (2), source stride, scale strides]
             P.fused_in_ptr_slots.push_back({(int64_t)ldesc.size(), lp.base});
             ldesc.insert(ldesc.end(), {0, 0, 0, 0, (int32_t)lp.size, rk, ns});
             for (size_t q = 0; q < lp.scales.size(); ++q) {
@@ -808,9 +830,15 @@ void build_plan(Net &n) {
             }
             std::vector<std::vector<int64_t>> sst;
             for (auto &sc : lp.scales) sst.push_back(strides_of(n, n.labels[sc.tensor]));
+            if (lp.size >= (int64_t(1) << 24)) loads_fit = false;  // magic division range
             for (int k = 0; k < rk; ++k) {
                 const int l = vl[k];
+                if (n.dims[l] >= 65536) loads_fit = false;
+                // floor(e / d) = (e * magic) >> 40 for e < 2^24, d < 2^16
+                const uint64_t magic = ((uint64_t(1) << 40) + (uint64_t)n.dims[l] - 1) / (uint64_t)n.dims[l];
                 ldesc.push_back((int32_t)n.dims[l]);
+                ldesc.push_back((int32_t)(uint32_t)(magic & 0xffffffffu));
+                ldesc.push_back((int32_t)(uint32_t)(magic >> 32));
                 ldesc.push_back((int32_t)stride_in(bl, stb, l));
                 for (int q = 0; q < ns; ++q)
                     ldesc.push_back((int32_t)stride_in(n.labels[lp.scales[q].tensor], sst[q], l));
@@ -840,7 +868,7 @@ void build_plan(Net &n) {
             t.q = (int)q;
             // [kind 0: image words, src chunk, chunks, dst chunk]
             t.w = {OP_COPY, 0, (int32_t)(tab_off[q] / 4), (int32_t)(tab_words[q] / 4), 0};
-            seq.push_back(t);
+            if (tab_words[q] > 0) seq.push_back(t);
             const StepPlan &s = P.steps[ks[q]];
             for (int id : {s.a, s.b})
                 if (id >= 0 && P.values[id].input) {
@@ -861,8 +889,12 @@ void build_plan(Net &n) {
             const int32_t slot = (int32_t)(q % 2);
             if (s.tile) {
                 r.kind = OP_TSTEP;
-                r.w = {OP_TSTEP, 0, 0, 0, (int32_t)s.tM, (int32_t)s.tN, (int32_t)s.tK, rel[q][0], rel[q][1],
-                       s.TM, s.TN, s.GX, s.final_step ? 1 : 0, slot};
+                // [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M (4 each), digits of N]
+                r.w = {OP_TSTEP, 0, 0, 0, (int32_t)s.tM, (int32_t)s.tN, (int32_t)s.tK, s.TM, s.TN, s.GX,
+                       s.final_step ? 1 : 0, (int32_t)(s.c_digits_m.size() / 4), (int32_t)(s.c_digits_n.size() / 4)};
+                r.w.insert(r.w.end(), s.c_digits_m.begin(), s.c_digits_m.end());
+                r.w.insert(r.w.end(), s.c_digits_n.begin(), s.c_digits_n.end());
+                (void)slot;
             } else {
                 r.kind = OP_STEP;
                 r.w = {OP_STEP, 0, 0, 0, (int32_t)s.n_ohi, (int32_t)s.n_olo, (int32_t)s.n_shi, (int32_t)s.n_slo,

@@ -90,21 +90,26 @@ def run_program(w, prog, n_loads, elem_bytes=8):
         dst = int(prog[p + 2]) | (int(prog[p + 3]) << 32)
         size, rk, ns = (int(x) for x in prog[p + 4:p + 7])
         sct = [int(prog[p + 7 + 2 * q]) for q in range(ns)]
-        per = prog[p + 7 + 2 * ns:p + 7 + 2 * ns + rk * (2 + ns)].reshape(rk, 2 + ns)
-        rem = np.arange(size)
+        per = prog[p + 7 + 2 * ns:p + 7 + 2 * ns + rk * (4 + ns)].reshape(rk, 4 + ns)
+        rem = np.arange(size, dtype=np.uint64)
         so = np.zeros(size, dtype=np.int64)
         sc = np.zeros((ns, size), dtype=np.int64)
         for k in range(rk - 1, -1, -1):
-            d = rem % per[k, 0]
-            rem //= per[k, 0]
-            so += d * per[k, 1]
+            dim = int(per[k, 0])
+            magic = (int(per[k, 1]) & 0xffffffff) | ((int(per[k, 2]) & 0xffffffff) << 32)
+            # the kernel's division: (rem * magic) >> 40, exact for rem < 2^24, dim < 2^16
+            quo = np.array([(int(r) * magic) >> 40 for r in rem], dtype=np.uint64)
+            assert (quo == rem // np.uint64(dim)).all()
+            d = (rem - quo * np.uint64(dim)).astype(np.int64)
+            rem = quo
+            so += d * per[k, 3]
             for q in range(ns):
-                sc[q] += d * per[k, 2 + q]
+                sc[q] += d * per[k, 4 + q]
         v = ins[base][so].copy()
         for q in range(ns):
             v *= ins[sct[q]][sc[q]]
         ws[dst:dst + size] = v
-        p += 7 + 2 * ns + rk * (2 + ns)
+        p += 7 + 2 * ns + rk * (4 + ns)
     # tables live in the image as int32 words; LDS slots as separate arrays
     slots = {}
     result = None
@@ -138,21 +143,36 @@ def run_program(w, prog, n_loads, elem_bytes=8):
             p += 5
             continue
         if op == OP_TSTEP:
-            la, lb, lc, M, N, K, tcm, tcn, _, _, _, fin, slot = (int(x) for x in prog[p + 1:p + 14])
-            tab = slots[slot]
+            la, lb, lc, M, N, K, _, _, _, fin, nm, nn = (int(x) for x in prog[p + 1:p + 13])
+            dg = prog[p + 13:p + 13 + 4 * (nm + nn)].reshape(-1, 4)
             aa, ao = at(la, K * M)
             ba, bo = at(lb, K * N)
             A = aa[ao:ao + K * M].reshape(K, M)
             B = ba[bo:bo + K * N].reshape(K, N)
             c = A.T @ B
-            offs = tab[tcm:tcm + M][:, None] + tab[tcn:tcn + N][None, :]
+
+            def digit_offsets(x, rows):
+                # mixed-radix digits, last label fastest; the kernel's
+                # division (x * magic) >> 40 must be exact
+                x = [int(v) for v in x]
+                off = np.zeros(len(x), dtype=np.int64)
+                for d, lo, hi, st in rows[::-1]:
+                    magic = (int(lo) & 0xffffffff) | ((int(hi) & 0xffffffff) << 32)
+                    for i, v in enumerate(x):
+                        q = (v * magic) >> 40
+                        assert q == v // int(d)
+                        off[i] += (v - q * int(d)) * int(st)
+                        x[i] = q
+                return off
+
+            offs = digit_offsets(range(M), dg[:nm])[:, None] + digit_offsets(range(N), dg[nm:])[None, :]
             if fin:
                 result = np.full(int(offs.max()) + 1, np.nan)
                 result[offs] = c
             else:
                 ca, co = at(lc, int(offs.max()) + 1)
                 ca[co + offs] = c
-            p += 14
+            p += 13 + 4 * (nm + nn)
             continue
         assert op == OP_STEP, op
         la, lb, lc, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, _, fin, slot = (

@@ -213,3 +213,30 @@ def test_update_data_reuses_plan():
     htn.htn_update_data(net, [np.ascontiguousarray(t) for t in w2.tensors])
     b = float(contract(net, ()))
     assert abs(b - 0.5 * a) <= 1e-13 * abs(a)
+
+
+@pytest.mark.parametrize("threads,lds", [(64, 24576), (64, 32768), (64, 65536), (256, 20480)])
+def test_fused_block_sizes_and_budgets(threads, lds):
+    """Grid networks on sampled paths, fused kernel with one wave or four
+    waves per network and several LDS budgets (small budgets spill)."""
+    import torch
+    ws = [configs.grid_network(200 + s) for s in range(24)]
+    nets = []
+    for w in ws:
+        n = create(w, exec_mode=htn.HTN_EXEC_FUSED)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_THREADS, threads)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, lds)
+        htn.htn_set_option(n, htn.HTN_OPT_PATH_SAMPLES, 8)
+        htn.htn_set_path(n, htn.HTN_PATH_SAMPLED)
+        nets.append(n)
+    outs = [htn.new_output(n) for n in nets]
+    htn.htn_contract_batch(nets, outs)
+    torch.cuda.synchronize()
+    for w, n, o in zip(ws, nets, outs):
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = float(hi) + float(lo)
+        assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref)
+        single = htn.new_output(n)
+        htn.htn_contract(n, single)
+        torch.cuda.synchronize()
+        assert float(single.item()) == float(o.item())

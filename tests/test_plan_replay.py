@@ -16,10 +16,12 @@ from workloads import configs
 from workloads.network import Network
 
 
-def _check(w, path=None, lds=None):
+def _check(w, path=None, lds=None, threads=None):
     net = htn.htn_create(w.tensors, w.labels, w.dims, w.out_labels)
     if lds is not None:
         htn.htn_set_option(net, htn.HTN_OPT_FUSED_LDS_BYTES, lds)
+    if threads is not None:
+        htn.htn_set_option(net, htn.HTN_OPT_FUSED_THREADS, threads)
     if path is not None:
         try:
             htn.htn_set_path(net, path)
@@ -55,6 +57,18 @@ def _random_network(rng):
 @pytest.mark.parametrize("seed", range(8))
 def test_replay_grid(seed):
     _check(configs.grid_network(seed))
+    _check(configs.grid_network(seed), threads=64, lds=16384)
+
+
+def test_replay_sampled_paths():
+    for seed in range(6):
+        w = configs.grid_network(seed)
+        net = htn.htn_create(w.tensors, w.labels, w.dims, w.out_labels)
+        htn.htn_set_option(net, htn.HTN_OPT_PATH_SAMPLES, 16)
+        htn.htn_set_path(net, htn.HTN_PATH_SAMPLED)
+        path, _ = htn.htn_get_path(net)
+        _check(w, path=path)
+        _check(w, path=path, threads=64, lds=16384)
 
 
 def test_replay_random_networks():
