@@ -149,10 +149,11 @@ htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks,
  *                 0.25, 0.5, 1, 2; deterministic for a given
  *                 HTN_OPT_PATH_SEED.  Never costlier than FLOP-greedy.
  *   HTN_PATH_LEARNED  the candidate (FLOP-greedy plus the sampled paths)
- *                 with the lowest total time predicted by the installed
- *                 cost model (htn_model_set); FLOP-greedy when no model is
- *                 installed or when no candidate is predicted faster than
- *                 FLOP-greedy.
+ *                 with the lowest total time predicted by the net's cost
+ *                 model (htn_set_model); FLOP-greedy when the net has no
+ *                 model or when no candidate is predicted faster than
+ *                 FLOP-greedy.  Runs the model on the current device and
+ *                 waits for it.
  * Errors: HTN_E_PATH for a malformed path; HTN_E_OOM if an intermediate
  * exceeds the size cap (htn_set_option HTN_OPT_MAX_INTERMEDIATE).
  * ------------------------------------------------------------------- */
@@ -233,6 +234,92 @@ htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
 htn_status htn_batch_set_phase_timing(htn_batch_t batch, int32_t max_phases);
 htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
 void htn_batch_destroy(htn_batch_t batch);
+
+/* ---------------------------------------------------------------------
+ * Learned cost model (HTN_PATH_LEARNED).
+ *
+ * The paper chooses contraction orders with a hyper-optimised search over
+ * a FLOP objective (Sec. 4.2; Sec. 6.1, Step 3).  FLOPs are a poor proxy
+ * for time on a GPU when networks are small: a step's duration depends on
+ * its kernel class, shape and where its operands live.  The model here
+ * predicts the natural log of a kernel step's duration in microseconds
+ * from HTN_MODEL_FEATURES features of the step (htn_step_features) with a
+ * multilayer perceptron
+ *     h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  y = w3 . h2 + b3,
+ * HTN_MODEL_HIDDEN units per hidden layer, FP32 weights and arithmetic, all
+ * on the GPU (forward, backward and Adam kernels).  A candidate path's
+ * predicted time is the sum of exp(y) over its kernel steps.
+ *
+ * Parameter layout (htn_model_param_count() floats, in this order):
+ *     W1 [HIDDEN][FEATURES] (row = hidden unit), b1 [HIDDEN],
+ *     W2 [HIDDEN][HIDDEN], b2 [HIDDEN], w3 [HIDDEN], b3 [1].
+ * Training minimises the mean squared error (1/n) sum (y_s - t_s)^2 of the
+ * predictions y_s against targets t_s (log microseconds) with Adam
+ * (b1 = 0.9, b2 = 0.999, eps = 1e-8).
+ *
+ * Step features (row of HTN_MODEL_FEATURES floats; "lg" = log2(v) / 8):
+ *   0 lg(1 + multiplications)  1 lg(outputs)  2 lg(summed terms per output)
+ *   3 lg(size of operand A)    4 lg(size of operand B; 1 if unary)
+ *   5-7 lg(M), lg(N), lg(K) of a register-tiled step (0 otherwise)
+ *   8 lg(outputs per thread of a tiled step)   9 lg(lanes per output)
+ *   10 tiled step  11 one lane per output  12 several lanes per output
+ *   13 whole workgroup per output  14 matrix-core step  15 unary step
+ *   16 final step  17-19 operand A / operand B / result outside LDS
+ *   20 lg(1 + 16-byte chunks the fused kernel copies during the step)
+ *   21 fused executor  22 FP64 compute  23 element bytes / 8
+ * ------------------------------------------------------------------- */
+#define HTN_MODEL_FEATURES 24
+#define HTN_MODEL_HIDDEN 64
+typedef struct htn_model *htn_model_t;
+
+int64_t htn_model_param_count(void);
+/* htn_model_create — a model on the current device with weights drawn
+ * uniformly from +-sqrt(6 / fan_in) (seeded splitmix64), zero biases and
+ * zero Adam state.                                                        */
+htn_status htn_model_create(htn_model_t *out, uint64_t seed);
+/* Host copies of the parameters (htn_model_param_count() floats).  Setting
+ * parameters clears the Adam state.                                       */
+htn_status htn_model_set_params(htn_model_t model, const float *params);
+htn_status htn_model_get_params(htn_model_t model, float *params);
+/* htn_model_forward — y[s] for the n rows of x; x [n][FEATURES] and y [n]
+ * are device arrays.  Asynchronous on hip_stream.                         */
+htn_status htn_model_forward(htn_model_t model, int32_t n, const float *x, float *y, void *hip_stream);
+/* htn_model_gradients — on device arrays: grad (param_count floats)
+ * receives the gradient of the mean squared error of the n rows of x
+ * against t [n], loss (1 float, may be NULL) the error itself.  No update
+ * is made.  Asynchronous on hip_stream.                                   */
+htn_status htn_model_gradients(htn_model_t model, int32_t n, const float *x, const float *t, float *grad,
+                               float *loss, void *hip_stream);
+/* htn_model_adam_step — one Adam update of the parameters with gradient
+ * grad (device, param_count floats) and learning rate lr.               */
+htn_status htn_model_adam_step(htn_model_t model, const float *grad, float lr, void *hip_stream);
+/* htn_model_train — minibatch Adam on the n samples (device x [n][FEATURES],
+ * t [n]) for `epochs` passes, each pass over a permutation of the samples
+ * drawn from splitmix64(seed) in minibatches of `batch`.  epoch_loss
+ * (host, `epochs` floats, may be NULL) receives each pass's mean minibatch
+ * loss.  Synchronous.                                                     */
+htn_status htn_model_train(htn_model_t model, int32_t n, const float *x, const float *t, int32_t epochs,
+                           int32_t batch, float lr, uint64_t seed, float *epoch_loss, void *hip_stream);
+void htn_model_destroy(htn_model_t model);
+
+/* htn_set_model — the model HTN_PATH_LEARNED uses for this net (NULL: none).
+ * The model is borrowed and must be alive at every later htn_set_path
+ * call with HTN_PATH_LEARNED.                                             */
+htn_status htn_set_model(htn_net_t net, htn_model_t model);
+
+/* htn_step_features — features of the current plan's kernel steps, in
+ * execution order, as rows of HTN_MODEL_FEATURES floats (host array).
+ * *n_steps receives the number of kernel steps; min(capacity, n_steps)
+ * rows are written.                                                       */
+htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, int32_t *n_steps);
+
+/* htn_batch_step_times — timing collector.  After a run with phase timing
+ * on (htn_batch_set_phase_timing), the duration in microseconds of each
+ * kernel step of each fused net: times[i * capacity + q] for net i and
+ * kernel step q < capacity, NaN where the step was not recorded (nets run
+ * step by step, steps beyond max_phases).  A fused step's duration is that
+ * of its phase: its arithmetic and the copies issued for the next step.  */
+htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacity);
 
 /* htn_update_data — replace the tensor values (same structure and path).
  * Same data / data_on_device semantics as htn_create.                     */

@@ -2,6 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <limits>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -523,6 +526,7 @@ htn_status htn_get_path(htn_net_t net, int32_t *n_steps, int32_t *ssa_pairs, int
     API_GUARD_BEGIN
     if (!net || !n_steps) return fail(HTN_E_ARG, "NULL argument");
     *n_steps = (int32_t)net->path.size();
+    if (mults) *mults = net->plan.mults;
     if (ssa_pairs)
         for (int t = 0; t < (int)net->path.size() && t < capacity; ++t) {
             ssa_pairs[2 * t] = net->path[t].first;
@@ -865,6 +869,33 @@ htn_status htn_batch_phase_times(htn_batch_t b, int64_t *ticks) {
     API_GUARD_END
 }
 
+htn_status htn_batch_step_times(htn_batch_t b, float *times, int32_t capacity) {
+    API_GUARD_BEGIN
+    if (!b || !times || capacity < 0) return fail(HTN_E_ARG, "bad arguments");
+    if (!b->d_phase) return fail(HTN_E_STATE, "phase timing is off");
+    const int n = (int)b->nets.size();
+    const int mp = b->max_phases;
+    std::vector<int64_t> ph((size_t)mp * n), st(2 * (size_t)n);
+    HIP_TRY(hipMemcpy(ph.data(), b->d_phase, ph.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st.data(), b->d_stamps, st.size() * 8, hipMemcpyDeviceToHost));
+    const float nan = std::numeric_limits<float>::quiet_NaN();
+    for (size_t k = 0; k < (size_t)n * capacity; ++k) times[k] = nan;
+    for (auto &g : b->groups)
+        for (int i : g.idx) {
+            const Plan &P = b->nets[i]->plan;
+            const int64_t *t = ph.data() + (size_t)i * mp;
+            for (int q = 0; q < (int)P.kernel_steps.size() && q < capacity; ++q) {
+                const int f = P.steps[P.kernel_steps[q]].f_phase;
+                if (f < 0 || f >= mp || t[f] < 0) continue;
+                const int64_t begin = f == 0 ? st[2 * (size_t)i] : t[f - 1];
+                if (begin < 0) continue;
+                times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f;  // 100 MHz ticks -> us
+            }
+        }
+    return HTN_OK;
+    API_GUARD_END
+}
+
 void htn_batch_destroy(htn_batch_t b) {
     if (!b) return;
     batch_free(b);
@@ -884,6 +915,254 @@ htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *out
     }
     htn_batch_destroy(b);
     return s;
+}
+
+// ------------------------------------------------------------ cost model
+
+}  // extern "C"
+
+struct htn_model {
+    int device = -1;
+    float *d_p = nullptr, *d_m = nullptr, *d_v = nullptr, *d_g = nullptr;
+    int64_t step = 0;  // Adam steps taken
+    int64_t cap = 0;   // samples the work arrays hold
+    float *d_x = nullptr, *d_t = nullptr, *d_y = nullptr, *d_z1 = nullptr, *d_z2 = nullptr, *d_d1 = nullptr,
+          *d_d2 = nullptr, *d_dy = nullptr, *d_loss = nullptr;
+    int32_t *d_idx = nullptr;
+    int64_t idx_cap = 0, loss_cap = 0;
+    std::mutex predict_mu;  // model_predict shares d_x / d_y between threads
+};
+
+namespace {
+
+// Runs a block with the model's device current.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        HIP_TRY(hipGetDevice(&prev));
+        if (prev != dev) HIP_TRY(hipSetDevice(dev));
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void model_free_work(htn_model *m) {
+    for (float *p : {m->d_x, m->d_t, m->d_y, m->d_z1, m->d_z2, m->d_d1, m->d_d2, m->d_dy}) dfree(p);
+    m->d_x = m->d_t = m->d_y = m->d_z1 = m->d_z2 = m->d_d1 = m->d_d2 = m->d_dy = nullptr;
+    m->cap = 0;
+}
+
+void model_reserve(htn_model *m, int64_t n) {
+    if (n <= m->cap) return;
+    model_free_work(m);
+    const int64_t F = HTN_MODEL_FEATURES, H = HTN_MODEL_HIDDEN;
+    m->d_x = dalloc<float>(n * F);
+    m->d_t = dalloc<float>(n);
+    m->d_y = dalloc<float>(n);
+    m->d_z1 = dalloc<float>(n * H);
+    m->d_z2 = dalloc<float>(n * H);
+    m->d_d1 = dalloc<float>(n * H);
+    m->d_d2 = dalloc<float>(n * H);
+    m->d_dy = dalloc<float>(n);
+    m->cap = n;
+}
+
+uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t &s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+}  // namespace
+
+namespace htn {
+std::vector<float> model_predict(htn_model *m, const std::vector<float> &x) {
+    const int64_t n = (int64_t)(x.size() / HTN_MODEL_FEATURES);
+    std::vector<float> y(n);
+    if (n == 0) return y;
+    std::lock_guard<std::mutex> lock(m->predict_mu);
+    DeviceScope ds(m->device);
+    model_reserve(m, n);
+    HIP_TRY(hipMemcpy(m->d_x, x.data(), x.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(kern::launch_mlp_forward(m->d_p, m->d_x, nullptr, (int)n, m->d_y, nullptr, nullptr, nullptr));
+    HIP_TRY(hipMemcpy(y.data(), m->d_y, n * 4, hipMemcpyDeviceToHost));
+    return y;
+}
+}  // namespace htn
+
+extern "C" {
+
+int64_t htn_model_param_count(void) { return kern::model_param_count(); }
+
+htn_status htn_model_create(htn_model_t *out, uint64_t seed) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    const int64_t np = kern::model_param_count();
+    const int F = HTN_MODEL_FEATURES, H = HTN_MODEL_HIDDEN;
+    std::vector<float> p(np, 0.0f);
+    uint64_t s = seed;
+    auto fill = [&](int64_t off, int64_t count, int fan_in) {
+        const double a = std::sqrt(6.0 / fan_in);
+        for (int64_t k = 0; k < count; ++k) p[off + k] = (float)((2.0 * uniform01(s) - 1.0) * a);
+    };
+    fill(0, (int64_t)H * F, F);                          // W1
+    fill((int64_t)H * F + H, (int64_t)H * H, H);         // W2
+    fill((int64_t)H * F + H + H * H + H, H, H);          // w3
+    auto *m = new htn_model();
+    try {
+        HIP_TRY(hipGetDevice(&m->device));
+        m->d_p = dalloc<float>(np);
+        m->d_m = dalloc<float>(np);
+        m->d_v = dalloc<float>(np);
+        m->d_g = dalloc<float>(np);
+        HIP_TRY(hipMemcpy(m->d_p, p.data(), np * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(m->d_m, 0, np * 4));
+        HIP_TRY(hipMemset(m->d_v, 0, np * 4));
+    } catch (...) {
+        htn_model_destroy(m);
+        throw;
+    }
+    *out = m;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_set_params(htn_model_t m, const float *params) {
+    API_GUARD_BEGIN
+    if (!m || !params) return fail(HTN_E_ARG, "NULL argument");
+    DeviceScope ds(m->device);
+    const int64_t np = kern::model_param_count();
+    HIP_TRY(hipMemcpy(m->d_p, params, np * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->d_m, 0, np * 4));
+    HIP_TRY(hipMemset(m->d_v, 0, np * 4));
+    m->step = 0;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_get_params(htn_model_t m, float *params) {
+    API_GUARD_BEGIN
+    if (!m || !params) return fail(HTN_E_ARG, "NULL argument");
+    DeviceScope ds(m->device);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(params, m->d_p, kern::model_param_count() * 4, hipMemcpyDeviceToHost));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_forward(htn_model_t m, int32_t n, const float *x, float *y, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!m || n < 0 || (n > 0 && (!x || !y))) return fail(HTN_E_ARG, "bad arguments");
+    DeviceScope ds(m->device);
+    HIP_TRY(kern::launch_mlp_forward(m->d_p, x, nullptr, n, y, nullptr, nullptr, (hipStream_t)hip_stream));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_gradients(htn_model_t m, int32_t n, const float *x, const float *t, float *grad, float *loss,
+                               void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!m || n <= 0 || !x || !t || !grad) return fail(HTN_E_ARG, "bad arguments");
+    DeviceScope ds(m->device);
+    model_reserve(m, n);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(kern::launch_mlp_forward(m->d_p, x, nullptr, n, m->d_y, m->d_z1, m->d_z2, st));
+    HIP_TRY(kern::launch_mlp_backward(m->d_p, x, t, nullptr, n, m->d_y, m->d_z1, m->d_z2, m->d_d1, m->d_d2, m->d_dy,
+                                      grad, loss, st));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_adam_step(htn_model_t m, const float *grad, float lr, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!m || !grad) return fail(HTN_E_ARG, "NULL argument");
+    DeviceScope ds(m->device);
+    HIP_TRY(kern::launch_adam(m->d_p, m->d_m, m->d_v, grad, lr, ++m->step, (hipStream_t)hip_stream));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_model_train(htn_model_t m, int32_t n, const float *x, const float *t, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float *epoch_loss, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!m || n <= 0 || !x || !t || epochs < 0 || batch <= 0) return fail(HTN_E_ARG, "bad arguments");
+    DeviceScope ds(m->device);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const int32_t nb_max = std::min(batch, n);
+    const int64_t n_mb = (n + nb_max - 1) / nb_max;
+    model_reserve(m, nb_max);
+    if (m->idx_cap < n) {
+        dfree(m->d_idx);
+        m->d_idx = nullptr;
+        m->d_idx = dalloc<int32_t>(n);
+        m->idx_cap = n;
+    }
+    if (m->loss_cap < n_mb) {
+        dfree(m->d_loss);
+        m->d_loss = nullptr;
+        m->d_loss = dalloc<float>(n_mb);
+        m->loss_cap = n_mb;
+    }
+    std::vector<int32_t> perm(n);
+    std::vector<float> losses(n_mb);
+    for (int e = 0; e < epochs; ++e) {
+        // Fisher-Yates permutation from splitmix64(seed, epoch)
+        uint64_t s = seed * 0x9e3779b97f4a7c15ull + (uint64_t)e;
+        for (int32_t i = 0; i < n; ++i) perm[i] = i;
+        for (int32_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int32_t)(splitmix64(s) % (uint64_t)(i + 1))]);
+        HIP_TRY(hipMemcpyAsync(m->d_idx, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+        for (int64_t k = 0; k < n_mb; ++k) {
+            const int32_t b0 = (int32_t)(k * nb_max), nb = std::min<int32_t>(nb_max, n - b0);
+            HIP_TRY(kern::launch_mlp_forward(m->d_p, x, m->d_idx + b0, nb, m->d_y, m->d_z1, m->d_z2, st));
+            HIP_TRY(kern::launch_mlp_backward(m->d_p, x, t, m->d_idx + b0, nb, m->d_y, m->d_z1, m->d_z2, m->d_d1,
+                                              m->d_d2, m->d_dy, m->d_g, m->d_loss + k, st));
+            HIP_TRY(kern::launch_adam(m->d_p, m->d_m, m->d_v, m->d_g, lr, ++m->step, st));
+        }
+        // the permutation buffer is reused next epoch: wait for this one
+        HIP_TRY(hipStreamSynchronize(st));
+        if (epoch_loss) {
+            HIP_TRY(hipMemcpy(losses.data(), m->d_loss, n_mb * 4, hipMemcpyDeviceToHost));
+            double a = 0.0;
+            for (float v : losses) a += v;
+            epoch_loss[e] = (float)(a / (double)n_mb);
+        }
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+void htn_model_destroy(htn_model_t m) {
+    if (!m) return;
+    model_free_work(m);
+    for (float *p : {m->d_p, m->d_m, m->d_v, m->d_g, m->d_loss}) dfree(p);
+    dfree(m->d_idx);
+    delete m;
+}
+
+htn_status htn_set_model(htn_net_t net, htn_model_t model) {
+    API_GUARD_BEGIN
+    if (!net) return fail(HTN_E_ARG, "net is NULL");
+    net->model = model;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, int32_t *n_steps) {
+    API_GUARD_BEGIN
+    if (!net || !n_steps || capacity < 0 || (capacity > 0 && !features)) return fail(HTN_E_ARG, "bad arguments");
+    std::vector<float> rows;
+    step_features(*net, rows);
+    const int32_t k = (int32_t)(rows.size() / HTN_MODEL_FEATURES);
+    *n_steps = k;
+    std::copy(rows.begin(), rows.begin() + (size_t)std::min(k, capacity) * HTN_MODEL_FEATURES, features);
+    return HTN_OK;
+    API_GUARD_END
 }
 
 const char *htn_status_string(htn_status s) {

@@ -61,6 +61,10 @@ struct StepPlan {
     // stride; floor(x / d) = (x * magic) >> 40.
     std::vector<int32_t> c_digits_m, c_digits_n;
     int TM = 1, TN = 1, GX = 16;  // per-thread tile and thread-grid width
+    // Fused-program facts (features of the learned cost model).
+    int f_phase = -1;           // phase of the fused kernel that runs the step
+    int f_spill = 0;            // bit 0: A, bit 1: B, bit 2: C outside LDS
+    int64_t f_copy_chunks = 0;  // 16-byte chunks copied while the step runs
 };
 
 // An SSA value: an input tensor (possibly with coefficient tensors folded
@@ -161,6 +165,7 @@ struct Net {
     Plan plan;
     int plan_version = 0;
     DeviceState *dev = nullptr;
+    struct htn_model *model = nullptr;  // cost model of HTN_PATH_LEARNED (borrowed)
 };
 
 // Element sizes.
@@ -182,8 +187,15 @@ void validate_structure(const Net &n);                       // throws Error
 std::vector<std::pair<int, int>> greedy_path(const Net &n);  // throws Error
 std::vector<std::pair<int, int>> sampled_path(const Net &n, int n_samples, uint64_t seed);
 std::vector<std::vector<std::pair<int, int>>> candidate_paths(const Net &n, int n_samples, uint64_t seed);
+// A copy of a net's structure and options without its data, path or plan.
+Net structure_copy(const Net &n);
 // cost_model.cpp
-std::vector<std::pair<int, int>> learned_path(const Net &n);
+constexpr int kFeatures = HTN_MODEL_FEATURES;
+// Appends one row of kFeatures floats per kernel step of n.plan.
+void step_features(const Net &n, std::vector<float> &rows);
+std::vector<std::pair<int, int>> learned_path(const Net &n);  // throws Error
+// api.hip: the model's predictions for rows of x (runs on the current device).
+std::vector<float> model_predict(struct htn_model *m, const std::vector<float> &x);
 void check_path(const Net &n, const std::vector<std::pair<int, int>> &p);  // throws Error
 void build_plan(Net &n);                                     // throws Error
 std::string plan_json(const Net &n);

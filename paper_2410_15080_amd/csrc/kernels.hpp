@@ -78,5 +78,19 @@ hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, 
 // Element-wise dtype conversion on the device.
 hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);
 
+// Cost-model MLP (mlp.hip).  Samples are rows of x ([.][HTN_MODEL_FEATURES]);
+// idx (optional) maps batch position s to its row.  z1, z2, d1, d2 are
+// [n][HTN_MODEL_HIDDEN] work arrays; forward keeps pre-activations in
+// z1/z2 when they are non-null.  backward writes d(loss)/d(params) to grad
+// and, when loss is non-null, the batch's mean squared error.
+int64_t model_param_count();
+hipError_t launch_mlp_forward(const float *prm, const float *x, const int32_t *idx, int n, float *y, float *z1,
+                              float *z2, hipStream_t st);
+hipError_t launch_mlp_backward(const float *prm, const float *x, const float *t, const int32_t *idx, int n,
+                               const float *y, const float *z1, const float *z2, float *d1, float *d2, float *dy,
+                               float *grad, float *loss, hipStream_t st);
+// One Adam step (b1 0.9, b2 0.999, eps 1e-8); step counts from 1.
+hipError_t launch_adam(float *p, float *m, float *v, const float *g, float lr, int64_t step, hipStream_t st);
+
 }  // namespace kern
 }  // namespace htn

@@ -224,6 +224,28 @@ std::vector<std::pair<int, int>> sampled_path(const Net &n, int n_samples, uint6
     return best;
 }
 
+Net structure_copy(const Net &n) {
+    Net t;
+    t.n_t = n.n_t;
+    t.labels = n.labels;
+    t.dims = n.dims;
+    t.out_labels = n.out_labels;
+    t.sizes = n.sizes;
+    t.storage = n.storage;
+    t.compute = n.compute;
+    t.final_sum = n.final_sum;
+    t.exec = n.exec;
+    t.max_intermediate = n.max_intermediate;
+    t.fused_lds_budget = n.fused_lds_budget;
+    t.fused_threads = n.fused_threads;
+    t.fused_max_mults = n.fused_max_mults;
+    t.batch_fused_max_mults = n.batch_fused_max_mults;
+    t.allow_mfma = n.allow_mfma;
+    t.path_samples = n.path_samples;
+    t.path_seed = n.path_seed;
+    return t;
+}
+
 void check_path(const Net &n, const std::vector<std::pair<int, int>> &p) {
     const int N = n.n_t;
     if ((int)p.size() != N - 1)
@@ -940,6 +962,7 @@ void build_plan(Net &n) {
         glb_ff.used[0] = inputs_end;
         int n_ops = 0;
         std::vector<int> pending;
+        int phase = 0, last_step = -1;
         for (auto &r : seq) {
             if (r.kind == OP_COPY && r.value >= 0) {
                 const int64_t sz = P.values[r.value].size;
@@ -954,10 +977,12 @@ void build_plan(Net &n) {
                     loc[r.value] = -(in_off[r.value] + 2);  // read in place
                     r.w[3] = 0;
                 }
+                if (last_step >= 0) P.steps[last_step].f_copy_chunks += r.w[3];
             } else if (r.kind == OP_COPY) {
                 r.w[4] = (int32_t)((slot0 + (r.q % 2) * slot_words) / 4);
+                if (last_step >= 0) P.steps[last_step].f_copy_chunks += r.w[3];
             } else if (r.kind == OP_STEP || r.kind == OP_TSTEP) {
-                const StepPlan &s = P.steps[r.step];
+                StepPlan &s = P.steps[r.step];
                 int64_t cl = -1;
                 if (!s.final_step) cl = loc[s.c] = place_or_spill(P.values[s.c].size);
                 r.w[1] = (int32_t)loc[s.a];
@@ -965,10 +990,17 @@ void build_plan(Net &n) {
                 r.w[3] = (int32_t)cl;
                 pending.push_back(s.a);
                 pending.push_back(s.b);
+                s.f_phase = phase;
+                s.f_spill = (loc[s.a] < 0 ? 1 : 0) | (s.b >= 0 && loc[s.b] < 0 ? 2 : 0) |
+                            (!s.final_step && cl < 0 ? 4 : 0);
+                s.f_copy_chunks = 0;
+                last_step = r.step;
             } else if (r.kind == OP_SYNC) {
                 for (int id : pending)
                     if (id >= 0) unplace(loc[id]);
                 pending.clear();
+                ++phase;
+                last_step = -1;
             }
             ++n_ops;
         }

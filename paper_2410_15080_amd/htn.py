@@ -23,6 +23,7 @@ HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
 HTN_PATH_GREEDY, HTN_PATH_LEARNED, HTN_PATH_SAMPLED = -1, -2, -3
 HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
 HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS = 4, 5, 6
+HTN_MODEL_FEATURES, HTN_MODEL_HIDDEN = 24, 64
 
 STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
           "HTN_E_DEVICE", "HTN_E_UNSUPPORTED", "HTN_E_STATE"]
@@ -54,11 +55,19 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_15080_amd/build.py")
+    try:
+        # torch carries its own HIP runtime (same soname); loading it first
+        # makes the library bind to that one, so torch and the library share
+        # one runtime whichever of them touches the GPU first
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I32, I64 = ctypes.c_int32, ctypes.c_int64
     i32p = ctypes.POINTER(I32)
     i64p = ctypes.POINTER(I64)
+    f32p = ctypes.POINTER(ctypes.c_float)
     sigs = {
         "htn_create": (I32, [ctypes.POINTER(P), I32, i32p, i32p, I32, i64p, ctypes.POINTER(P), I32, I32,
                              i32p, I32, I32, I32]),
@@ -81,6 +90,18 @@ def load_library():
         "htn_last_error": (ctypes.c_char_p, []),
         "htn_plan_json": (I32, [P, ctypes.c_char_p, I64, i64p]),
         "htn_plan_tables": (I32, [P, i32p, I64, i64p]),
+        "htn_batch_step_times": (I32, [P, f32p, I32]),
+        "htn_model_param_count": (I64, []),
+        "htn_model_create": (I32, [ctypes.POINTER(P), ctypes.c_uint64]),
+        "htn_model_set_params": (I32, [P, f32p]),
+        "htn_model_get_params": (I32, [P, f32p]),
+        "htn_model_forward": (I32, [P, I32, P, P, P]),
+        "htn_model_gradients": (I32, [P, I32, P, P, P, P, P]),
+        "htn_model_adam_step": (I32, [P, P, ctypes.c_float, P]),
+        "htn_model_train": (I32, [P, I32, P, P, I32, I32, ctypes.c_float, ctypes.c_uint64, f32p, P]),
+        "htn_model_destroy": (None, [P]),
+        "htn_set_model": (I32, [P, P]),
+        "htn_step_features": (I32, [P, f32p, I32, i32p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -155,6 +176,20 @@ class Net:
         if getattr(self, "handle", None):
             try:
                 htn_destroy(self)
+            except Exception:
+                pass
+
+
+class Model:
+    """Handle of an htn_model_t (cost model on the device)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                htn_model_destroy(self)
             except Exception:
                 pass
 
@@ -354,3 +389,103 @@ def new_output(net: Net, device="cuda"):
     info = htn_get_info(net)
     dt = {HTN_F64: torch.float64, HTN_F32: torch.float32}[info.out_dtype]
     return torch.empty(max(1, info.out_elements), dtype=dt, device=device)
+
+
+# ------------------------------------------------------------ cost model
+
+def _f32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _device_f32(t, name):
+    if not (_is_device(t) and str(t.dtype) == "torch.float32" and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    return ctypes.c_void_p(_data_ptr(t))
+
+
+def htn_model_param_count() -> int:
+    return int(load_library().htn_model_param_count())
+
+
+def htn_model_create(seed: int = 0) -> Model:
+    h = ctypes.c_void_p()
+    _check(load_library().htn_model_create(ctypes.byref(h), ctypes.c_uint64(seed)))
+    return Model(h)
+
+
+def htn_model_set_params(model: Model, params) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != htn_model_param_count():
+        raise ValueError("wrong parameter count")
+    _check(load_library().htn_model_set_params(model.handle, _f32p(a)))
+
+
+def htn_model_get_params(model: Model) -> np.ndarray:
+    a = np.zeros(htn_model_param_count(), dtype=np.float32)
+    _check(load_library().htn_model_get_params(model.handle, _f32p(a)))
+    return a
+
+
+def htn_model_forward(model: Model, x, y, stream=None) -> None:
+    """x: [n, HTN_MODEL_FEATURES] float32 device tensor; y: [n] float32 device tensor."""
+    n = int(x.shape[0])
+    if tuple(x.shape) != (n, HTN_MODEL_FEATURES) or y.numel() != n:
+        raise ValueError("shape mismatch")
+    _check(load_library().htn_model_forward(model.handle, n, _device_f32(x, "x"), _device_f32(y, "y"),
+                                            _stream_ptr(stream)))
+
+
+def htn_model_gradients(model: Model, x, t, grad, loss=None, stream=None) -> None:
+    n = int(x.shape[0])
+    if tuple(x.shape) != (n, HTN_MODEL_FEATURES) or t.numel() != n or grad.numel() != htn_model_param_count():
+        raise ValueError("shape mismatch")
+    lp = _device_f32(loss, "loss") if loss is not None else None
+    _check(load_library().htn_model_gradients(model.handle, n, _device_f32(x, "x"), _device_f32(t, "t"),
+                                              _device_f32(grad, "grad"), lp, _stream_ptr(stream)))
+
+
+def htn_model_adam_step(model: Model, grad, lr: float, stream=None) -> None:
+    _check(load_library().htn_model_adam_step(model.handle, _device_f32(grad, "grad"), float(lr),
+                                              _stream_ptr(stream)))
+
+
+def htn_model_train(model: Model, x, t, epochs: int, batch: int, lr: float, seed: int = 0,
+                    stream=None) -> np.ndarray:
+    """Returns the mean minibatch loss of each epoch."""
+    n = int(x.shape[0])
+    if tuple(x.shape) != (n, HTN_MODEL_FEATURES) or t.numel() != n:
+        raise ValueError("shape mismatch")
+    losses = np.zeros(max(1, epochs), dtype=np.float32)
+    _check(load_library().htn_model_train(model.handle, n, _device_f32(x, "x"), _device_f32(t, "t"), int(epochs),
+                                          int(batch), float(lr), ctypes.c_uint64(seed), _f32p(losses),
+                                          _stream_ptr(stream)))
+    return losses[:epochs]
+
+
+def htn_model_destroy(model: Model) -> None:
+    if model.handle:
+        load_library().htn_model_destroy(model.handle)
+        model.handle = None
+
+
+def htn_set_model(net: Net, model) -> None:
+    """Attach a cost model to a net (None detaches); the net keeps a reference."""
+    net._model = model
+    _check(load_library().htn_set_model(net.handle, model.handle if model is not None else None))
+
+
+def htn_step_features(net: Net) -> np.ndarray:
+    """[kernel steps, HTN_MODEL_FEATURES] features of the current plan."""
+    lib = load_library()
+    k = ctypes.c_int32()
+    _check(lib.htn_step_features(net.handle, None, 0, ctypes.byref(k)))
+    a = np.zeros((max(1, k.value), HTN_MODEL_FEATURES), dtype=np.float32)
+    _check(lib.htn_step_features(net.handle, _f32p(a), k.value, ctypes.byref(k)))
+    return a[: k.value]
+
+
+def htn_batch_step_times(batch: Batch, capacity: int) -> np.ndarray:
+    """[nets, capacity] kernel-step durations (microseconds, NaN if not recorded)."""
+    a = np.zeros((len(batch.nets), max(1, capacity)), dtype=np.float32)
+    _check(load_library().htn_batch_step_times(batch.handle, _f32p(a), int(capacity)))
+    return a[:, :capacity]
