@@ -1,28 +1,31 @@
 #!/usr/bin/env python3
 """h-TN contraction throughput on one MI355X.
 
-Workload (one "step"): a batch of 1024 seeded 4x4-grid h-TNs -- 16 quantum
-tensors, 24 cuts, each cut a wire cut (dim 4, Pauli-basis weights 1/2) or a
-CZ gate cut (dim 6, six QPD weights) drawn 50/50 per edge, QT entries
-U[-1,1] -- contracted in FP64 to each network's scalar <O>.  The batch
-runs as one input-materialisation launch plus one launch of the fused
+Default workload (one "step"): a batch of 1024 seeded 4x4-grid h-TNs -- 16
+quantum tensors, 24 cuts, each cut a wire cut (dim 4, Pauli-basis weights
+1/2) or a CZ gate cut (dim 6, six QPD weights) drawn 50/50 per edge, QT
+entries U[-1,1] -- contracted in FP64 to each network's scalar <O>.  The
+batch runs as one input-materialisation launch plus one launch of the fused
 kernel (one workgroup per network).  Inputs are resident in HBM before
 timing.
+
+Other workloads (--workload), each printing one JSON line of the same form:
+  random     512 random networks of uneven size (3-12 QTs, 2-14 cuts), FP32
+             with an FP64 final sum, one graph launch per batch; per-network
+             latency p50/p99 from device timestamps
+  marginal   one 4096 x 4096 marginal: two [4]^4 x 4096 QTs joined by four
+             CutQC wire tensors (a 4096 x 4096 x 256 matrix product after the
+             coefficient fold), FP64 / FP32 / BF16 inputs, FP64 output
+  ring       256 ring-of-rings networks (64 QTs, 3-6 cuts each), FP64 / FP32
+             / BF16 with a compensated FP64 final sum
 
 Reported:
   value        GFLOP/s = 2 * (multiplications of the FLOP-greedy paths) / time;
                the same numerator for every path variant, so a cheaper
                path shows up as higher throughput, never as extra flops
   htns_per_s   networks per second
-  path         order executed: "sampled" (cheapest of FLOP-greedy and 32
-               Boltzmann-sampled greedy paths) by default
-  batched_greedy_path  the same batch executed on the FLOP-greedy paths
-  plain_fp64   the same networks contracted one at a time on their
-               FLOP-greedy paths, one kernel launch per pairwise step
-  roofline     the fused kernel against the FP64 vector-ALU peak, on the
-               multiplications it actually executes
-  cpu_baseline the CPU oracle (FP64 variable elimination) on a bounded
-               sample of the same networks, on the host's cores
+  roofline     the dominant kernel against its bound, on the work it executes
+  cpu_baseline the CPU oracle on a bounded sample of the same workload
 """
 
 import argparse
@@ -35,7 +38,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_VALU_PEAK_TFLOPS = 78.6
+PEAK = {"f64_valu": 78.6, "f32_valu": 157.3, "f64_mfma": 78.6, "f32_mfma": 157.3, "bf16_mfma": 2500.0,
+        "hbm_gbs": 8000.0}
+METRIC = "h-TN contraction GFLOP/s & h-TNs/s vs plain FP64 path, at stated rel. error"
 
 
 def parse():
@@ -43,13 +48,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--workload", choices=["grid", "random", "marginal", "ring"], default="grid")
+    ap.add_argument("--batch", type=int, default=None, help="networks per batch (default per workload)")
+    ap.add_argument("--dtype", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--lds", type=int, default=65536)
+    ap.add_argument("--threads", type=int, default=256, choices=[64, 256])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--path", choices=["greedy", "sampled", "learned"], default="sampled")
     ap.add_argument("--samples", type=int, default=32)
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="measure the fused kernel's workgroup size and LDS budget first "
+                         "(auto: on for the random and ring batches)")
     return ap.parse_args()
 
 
@@ -57,12 +68,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ws, seconds):
+def dtype_code(name):
+    from paper_2410_15080_amd import htn
+    return {"f64": htn.HTN_F64, "f32": htn.HTN_F32, "bf16": htn.HTN_BF16}[name]
+
+
+def cpu_baseline(ws, seconds, mults):
     """Time the oracle (FP64 variable elimination) on as many networks as fit
     in about `seconds`, one network per host thread."""
     import oracle
-    cores = len(os.sched_getaffinity(0))
-    cores = max(1, min(cores, 16))
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
     oracle.set_num_threads(1)
 
     def one(w):
@@ -76,7 +91,383 @@ def cpu_baseline(ws, seconds):
             list(ex.map(one, chunk))
             done += len(chunk)
     dt = time.perf_counter() - t0
-    return done, dt, cores
+    cm = float(sum(mults[:done]))
+    return {"value": 2.0 * cm / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "htns_per_s": done / dt,
+            "sample": f"first {done} of the {len(ws)} networks, FP64 variable elimination, one network per "
+                      f"thread, {dt:.1f} s"}
+
+
+def oracle_ref(w):
+    import oracle
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    return float(hi) + float(lo)
+
+
+class Timer:
+    """Times a callable that enqueues work on `stream`: wall clock over the
+    K timed calls (bracketed by synchronisation) and the mean of per-call
+    HIP event intervals on the same stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+
+    def run(self, fn, steps, warmup):
+        import numpy as np
+        import torch
+        with torch.cuda.stream(self.stream):
+            for _ in range(warmup):
+                fn()
+        self.stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(self.stream):
+            for k in range(steps):
+                ev[k][0].record(self.stream)
+                fn()
+                ev[k][1].record(self.stream)
+        self.stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def make_nets(ws, compute, final_sum, args, path):
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    dev = torch.device("cuda:0")
+    tdt = {htn.HTN_F64: torch.float64, htn.HTN_F32: torch.float32, htn.HTN_BF16: torch.float32}[compute]
+    storage = htn.HTN_F64 if compute == htn.HTN_F64 else htn.HTN_F32
+    nets, greedy = [], []
+    for w in ws:
+        ts = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(dev).to(tdt) for t in w.tensors]
+        n = htn.htn_create(ts, w.labels, w.dims, w.out_labels, compute=compute, final_sum=final_sum,
+                           storage=storage)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, args.lds)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_THREADS, args.threads)
+        greedy.append(htn.htn_get_info(n).mults)
+        nets.append(n)
+    if path != "greedy":
+        model = None
+        if path == "learned":
+            model = train_model(ws, compute, final_sum, args)
+        for n in nets:
+            htn.htn_set_option(n, htn.HTN_OPT_PATH_SAMPLES, args.samples)
+            if model is not None:
+                htn.htn_set_model(n, model)
+            htn.htn_set_path(n, htn.HTN_PATH_SAMPLED if path == "sampled" else htn.HTN_PATH_LEARNED)
+    return nets, greedy
+
+
+def train_model(ws, compute, final_sum, args):
+    """Cost model trained on step timings of a disjoint set of networks of
+    the same workload (seeds offset by 10^5)."""
+    from paper_2410_15080_amd import learned
+    from workloads import configs
+    log("training the cost model")
+    kind = ws[0].meta.get("config")
+    if kind == "grid":
+        tws = [configs.grid_network(100000 + s) for s in range(128)]
+    elif kind == "random_batch":
+        tws = configs.random_batch(100000, n=256)
+    else:
+        tws = ws[: min(32, len(ws))]
+    tnets, _ = make_nets(tws, compute, final_sum, args, "greedy")
+    X, t = learned.collect_step_timings(tnets, runs=2)
+    model, losses = learned.train_cost_model(X, t, epochs=150, batch=256, lr=2e-3)
+    log(f"  {X.shape[0]} step timings, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    return model
+
+
+def autotune(nets, args, workload):
+    """Applies htn_autotune when asked; returns its choice (or None)."""
+    import torch
+    from paper_2410_15080_amd import htn
+    if args.autotune == "off" or (args.autotune == "auto" and workload not in ("random", "ring")):
+        return None
+    log("autotuning the fused kernel configuration")
+    tmp = torch.empty(len(nets), dtype=torch.float64, device="cuda")
+    th, lds, ms = htn.htn_autotune(nets, [tmp[i:i + 1] for i in range(len(nets))])
+    log(f"  {th} threads, {lds} B LDS: {ms:.3f} ms")
+    return {"threads": th, "lds_bytes": lds, "tuned_ms": round(ms, 4)}
+
+
+def batch_runner(nets, out_dtype, use_graph=False):
+    import torch
+    from paper_2410_15080_amd import htn
+    dev = torch.device("cuda:0")
+    out = torch.empty(len(nets), dtype=out_dtype, device=dev)
+    outs = htn.pointer_array([out[i:i + 1] for i in range(len(nets))])
+    b = htn.htn_batch_create(nets)
+    htn.htn_batch_set_graph(b, use_graph)
+    stream = torch.cuda.Stream()
+    return b, out, outs, stream
+
+
+# ------------------------------------------------------------------ grid
+
+def bench_grid(args):
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    n_nets = args.batch or 1024
+    log(f"generating {n_nets} grid networks")
+    ws = [configs.grid_network(s) for s in range(n_nets)]
+    nets, greedy_list = make_nets(ws, htn.HTN_F64, htn.HTN_SUM_PLAIN, args, "greedy")
+    greedy_mults = float(sum(greedy_list))
+    b, out, outs, stream = batch_runner(nets, torch.float64)
+    timer = Timer(stream)
+    log("timing the batch on FLOP-greedy paths")
+    g_ms, _ = timer.run(lambda: htn.htn_batch_run(b, outs, stream), max(3, args.steps // 2), 2)
+    g_res = out.cpu().numpy()
+    htn.htn_batch_destroy(b)
+    if args.path != "greedy":
+        log(f"planning {args.path} paths")
+        nets, _ = make_nets(ws, htn.HTN_F64, htn.HTN_SUM_PLAIN, args, args.path)
+    infos = [htn.htn_get_info(n) for n in nets]
+    mults = float(sum(i.mults for i in infos))
+    in_bytes = sum(i.input_bytes for i in infos)
+    b, out, outs, stream = batch_runner(nets, torch.float64)
+    timer = Timer(stream)
+    log(f"timing {args.steps} steps")
+    ms_per_step, kern_ms = timer.run(lambda: htn.htn_batch_run(b, outs, stream), args.steps, args.warmup)
+    got = out.cpu().numpy()
+    errs = []
+    for i in range(0, n_nets, max(1, n_nets // 32)):
+        ref = oracle_ref(ws[i])
+        errs.append(max(abs(got[i] - ref), abs(g_res[i] - ref)) / abs(ref))
+    htns = n_nets / (ms_per_step * 1e-3)
+
+    plain = None
+    if not args.no_plain:
+        n_plain = min(n_nets, 256)
+        pnets, pm = make_nets(ws[:n_plain], htn.HTN_F64, htn.HTN_SUM_PLAIN, args, "greedy")
+        pouts = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(n_plain)]
+        for n in pnets:
+            htn.htn_set_option(n, htn.HTN_OPT_EXEC, htn.HTN_EXEC_STEPS)
+
+        def plain_all():
+            for n, o in zip(pnets, pouts):
+                htn.htn_contract(n, o, stream)
+        log(f"timing plain per-network path on {n_plain} networks")
+        p_ms, _ = Timer(stream).run(plain_all, 1, 1)
+        pv = np.array([float(o.item()) for o in pouts])
+        plain = {"htns_per_s": n_plain / (p_ms * 1e-3), "gflops": 2.0 * sum(pm) / (p_ms * 1e-3) / 1e9,
+                 "networks": n_plain, "path": "flop-greedy",
+                 "max_abs_diff_vs_batched": float(np.abs(pv - got[:n_plain]).max())}
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle")
+        cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
+    achieved = 2.0 * mults / (kern_ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC,
+        "value": round(2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
+        "ms_per_step": round(ms_per_step, 4), "dtype": "f64",
+        "config": {"workload": "grid4x4_htn_batch", "networks": n_nets, "qts_per_net": 16,
+                   "cuts_per_net": 24, "cut_dims": "wire 4 / CZ gate 6, 50/50 by seed",
+                   "path": args.path, "path_samples": args.samples,
+                   "executor": "input prep + fused kernel, one workgroup per network",
+                   "lds_budget_bytes": args.lds, "threads_per_network": args.threads,
+                   "fused_networks": sum(1 for i in infos if i.fused_ok)},
+        "htns_per_s": round(htns, 1),
+        "max_rel_err_vs_oracle": float(max(errs)),
+        "greedy_mults_per_step": greedy_mults,
+        "executed_mults_per_step": mults,
+        "batched_greedy_path": {"ms_per_step": round(g_ms, 4), "htns_per_s": round(n_nets / (g_ms * 1e-3), 1),
+                                "gflops": round(2.0 * greedy_mults / (g_ms * 1e-3) / 1e9, 3)},
+        "plain_fp64_path": plain,
+        "speedup_vs_plain_fp64": (htns / plain["htns_per_s"]) if plain else None,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5), "traffic": None,
+                     "kernel": "k_fused<256,double,double,0> (+ k_fprep)", "kernel_ms": round(kern_ms, 4),
+                     "input_bytes": in_bytes},
+        "cpu_baseline": cpu,
+    }
+
+
+# ---------------------------------------------------------------- random
+
+def bench_random(args):
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    n_nets = args.batch or 512
+    compute = dtype_code(args.dtype or "f32")
+    log(f"generating {n_nets} random networks")
+    ws = configs.random_batch(0, n=n_nets, dtype=np.float64)
+    nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
+    greedy_mults = float(sum(greedy_list))
+    infos = [htn.htn_get_info(n) for n in nets]
+    mults = float(sum(i.mults for i in infos))
+    in_bytes = sum(i.input_bytes for i in infos)
+    tuned = autotune(nets, args, "random")
+    n_fused = sum(1 for n in nets if json.loads(htn.htn_plan_json(n))["fused_batch_ok"])
+    b, out, outs, stream = batch_runner(nets, torch.float64, use_graph=True)
+    log(f"timing {args.steps} graph launches")
+    ms_per_step, kern_ms = Timer(stream).run(lambda: htn.htn_batch_run(b, outs, stream), args.steps, args.warmup)
+    got = out.cpu().numpy()
+    t = htn.htn_batch_timestamps(b)
+    lat_us = t[:, 1] / 100.0
+    # error on every network the oracle finishes quickly
+    errs, bounds = [], []
+    import oracle
+    for i, w in enumerate(ws):
+        if greedy_list[i] > 2e6:
+            continue
+        ref = oracle_ref(w)
+        absw = [np.abs(x) for x in w.tensors]
+        hi, lo = oracle.ve_contract(absw, w.labels, w.dims, w.out_labels)
+        errs.append(abs(got[i] - ref))
+        bounds.append(float(hi) + float(lo))
+    errs, bounds = np.array(errs), np.array(bounds)
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle")
+        cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
+    achieved = 2.0 * mults / (kern_ms * 1e-3) / 1e12
+    peak = PEAK["f32_valu"] if compute != htn.HTN_F64 else PEAK["f64_valu"]
+    return {
+        "metric": METRIC,
+        "value": round(2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
+        "ms_per_step": round(ms_per_step, 4), "dtype": args.dtype or "f32",
+        "config": {"workload": "random_htn_batch", "networks": n_nets, "qts": "U{3..12}", "cuts": "U{s-1..14}",
+                   "final_sum": "fp64", "path": args.path, "graph": True, "autotuned": tuned,
+                   "fused_capable_networks": n_fused},
+        "htns_per_s": round(n_nets / (ms_per_step * 1e-3), 1),
+        "latency_us": {"p50": float(np.percentile(lat_us, 50)), "p99": float(np.percentile(lat_us, 99)),
+                       "max": float(lat_us.max())},
+        "error_vs_oracle": {"networks": int(errs.size),
+                            "max_abs_err_over_abs_network": float((errs / np.maximum(bounds, 1e-300)).max())},
+        "greedy_mults_per_step": greedy_mults, "executed_mults_per_step": mults,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 5), "traffic": None,
+                     "kernel": "graph: k_fused + k_fprep + per-step kernels of the largest networks",
+                     "kernel_ms": round(kern_ms, 4), "input_bytes": in_bytes,
+                     "hbm_gbs_on_inputs": round(in_bytes / (kern_ms * 1e-3) / 1e9, 2)},
+        "cpu_baseline": cpu,
+    }
+
+
+# -------------------------------------------------------------- marginal
+
+def bench_marginal(args):
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    import oracle
+    name = args.dtype or "f64"
+    compute = dtype_code(name)
+    w = configs.marginal_network(0, out_bits=12)
+    nets, greedy = make_nets([w], compute, htn.HTN_SUM_FP64, args, "greedy")
+    net = nets[0]
+    htn.htn_set_option(net, htn.HTN_OPT_EXEC, htn.HTN_EXEC_STEPS)
+    plan = json.loads(htn.htn_plan_json(net))
+    gemm = [s for s in plan["steps"] if s.get("mfma")]
+    out = torch.empty(4096 * 4096, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    log("timing the marginal contraction")
+    ms, kern_ms = Timer(stream).run(lambda: htn.htn_contract(net, out, stream), args.steps, args.warmup)
+    R = out.view(4096, 4096).cpu().numpy()
+    # sampled entries against the naive oracle on sliced tensors
+    rng = np.random.default_rng(0)
+    c = 4
+    errs = []
+    for _ in range(16):
+        x1, x2 = (int(v) for v in rng.integers(0, 4096, size=2))
+        ts = [w.tensors[0][..., x1], w.tensors[1][..., x2]] + list(w.tensors[2:])
+        ls = [w.labels[0][:c], w.labels[1][:c]] + list(w.labels[2:])
+        ref, _ = oracle.naive_contract(ts, ls, w.dims, [])
+        errs.append(abs(R[x1, x2] - float(ref)))
+    gflop = 2.0 * greedy[0] / 1e9
+    mf = 2.0 * float(np.prod(gemm[0]["gemm"])) / 1e9 if gemm else gflop
+    peak = {"f64": PEAK["f64_mfma"], "f32": PEAK["f32_mfma"], "bf16": PEAK["bf16_mfma"]}[name]
+    achieved = mf / (kern_ms * 1e-3) / 1e3
+    out_bytes = 4096 * 4096 * 8
+    cpu = None
+    if not args.no_cpu:
+        # oracle: the naive sum on a block of outputs, scaled per output
+        log("timing CPU oracle")
+        blk = 8
+        ts = [w.tensors[0][..., :blk], w.tensors[1][..., :blk]] + list(w.tensors[2:])
+        dims = list(w.dims)
+        dims[2 * c] = dims[2 * c + 1] = blk
+        t0 = time.perf_counter()
+        oracle.naive_contract(ts, w.labels, dims, w.out_labels)
+        dt = (time.perf_counter() - t0) * (4096 / blk) ** 2
+        cpu = {"value": gflop / dt, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"naive knitting sum on an {blk}x{blk} output block, scaled to 4096x4096 "
+                         f"(extrapolated: {dt:.0f} s)"}
+    return {
+        "metric": METRIC,
+        "value": round(gflop / (ms * 1e-3), 3), "unit": "GFLOP/s", "ms_per_step": round(ms, 4), "dtype": name,
+        "config": {"workload": "marginal_4096x4096", "qts": "2 x [4^4 x 4096]", "cut_tensors": "4 x CutQC c_w",
+                   "gemm": gemm[0]["gemm"] if gemm else None, "output": "fp64 4096x4096"},
+        "htns_per_s": round(1.0 / (ms * 1e-3), 2),
+        "sum_minus_one": float(R.sum() - 1.0),
+        "max_abs_err_sampled": float(max(errs)),
+        "roofline": {"bound": "mfma" if name != "bf16" else "hbm",
+                     "achieved": round(achieved if name != "bf16" else out_bytes / (kern_ms * 1e-3) / 1e9, 3),
+                     "peak": peak if name != "bf16" else PEAK["hbm_gbs"],
+                     "unit": "TFLOP/s" if name != "bf16" else "GB/s",
+                     "frac": round(achieved / peak if name != "bf16" else out_bytes / (kern_ms * 1e-3) / 1e9
+                                   / PEAK["hbm_gbs"], 4),
+                     "traffic": None, "kernel": "k_gemm (+ pack and fold steps)", "kernel_ms": round(kern_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+
+
+# ------------------------------------------------------------------ ring
+
+def bench_ring(args):
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    n_nets = args.batch or 256
+    name = args.dtype or "f64"
+    compute = dtype_code(name)
+    log(f"generating {n_nets} ring-of-rings networks")
+    ws = [configs.ring_of_rings(s) for s in range(n_nets)]
+    path = "greedy" if args.path == "sampled" else args.path
+    nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_COMPENSATED, args, path)
+    infos = [htn.htn_get_info(n) for n in nets]
+    mults = float(sum(i.mults for i in infos))
+    in_bytes = sum(i.input_bytes for i in infos)
+    tuned = autotune(nets, args, "ring")
+    b, out, outs, stream = batch_runner(nets, torch.float64, use_graph=True)
+    log(f"timing {args.steps} graph launches")
+    ms, kern_ms = Timer(stream).run(lambda: htn.htn_batch_run(b, outs, stream), args.steps, args.warmup)
+    got = out.cpu().numpy()
+    rel = []
+    for i in range(0, n_nets, max(1, n_nets // 16)):
+        ref = oracle_ref(ws[i])
+        rel.append(abs(got[i] - ref) / abs(ref))
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle")
+        cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
+    gbs = in_bytes / (kern_ms * 1e-3) / 1e9
+    return {
+        "metric": METRIC,
+        "value": round(2.0 * float(sum(greedy_list)) / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
+        "ms_per_step": round(ms, 4), "dtype": name,
+        "config": {"workload": "ring_of_rings_batch", "networks": n_nets, "qts_per_net": 64,
+                   "final_sum": "compensated fp64", "path": path, "graph": True, "autotuned": tuned},
+        "htns_per_s": round(n_nets / (ms * 1e-3), 1),
+        "max_rel_err_vs_oracle": float(max(rel)),
+        "greedy_mults_per_step": float(sum(greedy_list)), "executed_mults_per_step": mults,
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                     "frac": round(gbs / PEAK["hbm_gbs"], 5), "traffic": None, "input_bytes": in_bytes,
+                     "kernel": "graph: k_fprep + k_fused", "kernel_ms": round(kern_ms, 4)},
+        "cpu_baseline": cpu,
+    }
 
 
 def main():
@@ -85,138 +476,16 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (networks of a batch "
               "are independent and would shard across GPUs without communication)", file=sys.stderr)
         return 2
-    import numpy as np
     import torch
-
-    import oracle
-    from paper_2410_15080_amd import htn
-    from workloads import configs
-
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    log(f"generating {args.batch} grid networks")
-    ws = [configs.grid_network(s) for s in range(args.batch)]
-    nets = []
-    greedy_list = []
-    for w in ws:
-        ts = [torch.from_numpy(np.ascontiguousarray(t)).to(dev) for t in w.tensors]
-        n = htn.htn_create(ts, w.labels, w.dims, w.out_labels, compute=htn.HTN_F64)
-        htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, args.lds)
-        greedy_list.append(htn.htn_get_info(n).mults)
-        nets.append(n)
-    greedy_mults = float(sum(greedy_list))
-    out = torch.empty(args.batch, dtype=torch.float64, device=dev)
-    outs = htn.pointer_array([out[i:i + 1] for i in range(args.batch)])
-    stream = torch.cuda.Stream()
-
-    def time_batch(steps, warmup):
-        batch = htn.htn_batch_create(nets)
-        with torch.cuda.stream(stream):
-            for _ in range(warmup):
-                htn.htn_batch_run(batch, outs, stream)
-        stream.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            for k in range(steps):
-                ev[k][0].record(stream)
-                htn.htn_batch_run(batch, outs, stream)
-                ev[k][1].record(stream)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return wall * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
-
-    # the FLOP-greedy paths (transparency)
-    log("timing the batch on FLOP-greedy paths")
-    g_ms, _ = time_batch(max(3, args.steps // 2), 2)
-    g_res = out.cpu().numpy()
-    # the executed path
-    if args.path != "greedy":
-        log(f"planning {args.path} paths")
-        for n in nets:
-            htn.htn_set_option(n, htn.HTN_OPT_PATH_SAMPLES, args.samples)
-            htn.htn_set_path(n, htn.HTN_PATH_SAMPLED if args.path == "sampled" else htn.HTN_PATH_LEARNED)
-    infos = [htn.htn_get_info(n) for n in nets]
-    mults = float(sum(i.mults for i in infos))
-    n_fused = sum(1 for i in infos if i.fused_ok)
-    in_bytes = sum(i.input_bytes for i in infos)
-    log(f"timing {args.steps} steps")
-    ms_per_step, kern_ms = time_batch(args.steps, args.warmup)
-    got = out.cpu().numpy()
-    # correctness on a sample against the oracle (double-double)
-    errs = []
-    for i in range(0, args.batch, max(1, args.batch // 32)):
-        hi, lo = oracle.ve_contract(ws[i].tensors, ws[i].labels, ws[i].dims, ws[i].out_labels)
-        ref = float(hi) + float(lo)
-        errs.append(max(abs(got[i] - ref), abs(g_res[i] - ref)) / abs(ref))
-    max_rel = float(max(errs))
-    gflops = 2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9
-    htns = args.batch / (ms_per_step * 1e-3)
-
-    plain = None
-    if not args.no_plain:
-        n_plain = min(args.batch, 256)
-        pouts = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(n_plain)]
-        for n in nets[:n_plain]:
-            htn.htn_set_path(n, htn.HTN_PATH_GREEDY)
-            htn.htn_set_option(n, htn.HTN_OPT_EXEC, htn.HTN_EXEC_STEPS)
-        plain_mults = float(sum(htn.htn_get_info(n).mults for n in nets[:n_plain]))
-        with torch.cuda.stream(stream):
-            for n, o in zip(nets[:n_plain], pouts):
-                htn.htn_contract(n, o, stream)
-        stream.synchronize()
-        log(f"timing plain per-network path on {n_plain} networks")
-        t1 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            for n, o in zip(nets[:n_plain], pouts):
-                htn.htn_contract(n, o, stream)
-        stream.synchronize()
-        dtp = time.perf_counter() - t1
-        pm = float(sum(i.mults for i in infos[:n_plain]))
-        pv = np.array([float(o.item()) for o in pouts])
-        plain = {"htns_per_s": n_plain / dtp, "gflops": 2.0 * plain_mults / dtp / 1e9, "networks": n_plain,
-                 "path": "flop-greedy",
-                 "max_abs_diff_vs_batched": float(np.abs(pv - got[:n_plain]).max())}
-
-    cpu = None
-    if not args.no_cpu:
-        log("timing CPU oracle")
-        done, dtc, cores = cpu_baseline(ws, args.cpu_seconds)
-        cm = float(sum(greedy_list[:done]))  # same numerator as the headline
-        cpu = {"value": 2.0 * cm / dtc / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-               "htns_per_s": done / dtc,
-               "sample": f"first {done} of the {args.batch} grid networks, FP64 variable elimination, "
-                         f"one network per thread, {dtc:.1f} s"}
-
-    achieved = 2.0 * mults / (kern_ms * 1e-3) / 1e12
-    greedy_batched = {"ms_per_step": round(g_ms, 4), "htns_per_s": round(args.batch / (g_ms * 1e-3), 1),
-                      "gflops": round(2.0 * greedy_mults / (g_ms * 1e-3) / 1e9, 3)}
-    line = {
-        "metric": "h-TN contraction GFLOP/s & h-TNs/s vs plain FP64 path, at stated rel. error",
-        "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "grid4x4_htn_batch", "networks": args.batch, "qts_per_net": 16,
-                   "cuts_per_net": 24, "cut_dims": "wire 4 / CZ gate 6, 50/50 by seed",
-                   "path": args.path, "path_samples": args.samples,
-                   "executor": "input prep + fused kernel, one workgroup per network",
-                   "lds_budget_bytes": args.lds, "fused_networks": n_fused},
-        "htns_per_s": round(htns, 1),
-        "max_rel_err_vs_oracle": max_rel,
-        "greedy_mults_per_step": greedy_mults,
-        "executed_mults_per_step": mults,
-        "batched_greedy_path": greedy_batched,
-        "plain_fp64_path": plain,
-        "speedup_vs_plain_fp64": (htns / plain["htns_per_s"]) if plain else None,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 5), "traffic": None,
-                     "kernel": "k_fused<double,double>", "kernel_ms": round(kern_ms, 4),
-                     "input_bytes": in_bytes},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+    fn = {"grid": bench_grid, "random": bench_random, "marginal": bench_marginal, "ring": bench_ring}[args.workload]
+    line = fn(args)
+    head = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"), "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": line.pop("dtype"),
+            "data": "synthetic", "config": line.pop("config")}
+    head.update(line)
+    print(json.dumps(head), flush=True)
     return 0
 
 

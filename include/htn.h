@@ -173,7 +173,7 @@ typedef enum {
     HTN_OPT_MFMA = 3,              /* 1: allow matrix-core steps (default), 0: VALU only */
     HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
     HTN_OPT_PATH_SEED = 5,         /* seed of the path sampler (default 0) */
-    HTN_OPT_FUSED_THREADS = 6      /* threads per network in the fused kernel: 64 or 256 (default) */
+    HTN_OPT_FUSED_THREADS = 6      /* threads per network in the fused kernel: 64, 256 (default) or 512 */
 } htn_option;
 
 htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value);
@@ -205,9 +205,13 @@ htn_status htn_contract(htn_net_t net, void *out_device, void *hip_stream);
 
 /* htn_contract_batch — contract n independent nets, outs[i] receiving net
  * i's result, with as few launches as possible: every net that fits the
- * fused kernel runs in one launch (one workgroup per net, heaviest first);
- * the others run step by step on the same stream.  Equivalent to
- * htn_batch_create + htn_batch_run + htn_batch_destroy.                  */
+ * fused kernel runs in one launch (one workgroup per net, heaviest first).
+ * The others, and fused-capable nets whose work exceeds
+ * max(2^20, 4 x the batch's fused work per resident workgroup slot) (they
+ * would hold one workgroup long after the rest finish), run step by step
+ * on up to three side streams forked from and joined back to hip_stream,
+ * overlapping the fused launch.  Equivalent to htn_batch_create +
+ * htn_batch_run + htn_batch_destroy.                                      */
 htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream);
 
 /* Reusable batch: plans the combined launch once.  The nets must outlive
@@ -219,9 +223,10 @@ htn_status htn_batch_set_graph(htn_batch_t batch, int32_t use_graph);
 htn_status htn_batch_run(htn_batch_t batch, void *const *outs, void *hip_stream);
 /* Per-net start and completion times of the last run: ticks[2*i] and
  * ticks[2*i+1], in ticks of the device's constant 100 MHz clock counted
- * from the first workgroup start of the run (fused nets only; -1 for nets
- * run step by step).  ticks holds 2*n values.  Synchronise the stream of
- * the run first.                                                          */
+ * from the start of the run (a clock read enqueued ahead of the run's
+ * kernels).  Fused nets are stamped by their workgroup, nets run step by
+ * step by clock reads around their kernels.  ticks holds 2*n values.
+ * Synchronise the stream of the run first.                                */
 htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
 /* Per-phase timing of the fused kernel.  A fused network runs as a sequence
  * of phases separated by workgroup barriers (phase 0 loads the operands of
@@ -229,7 +234,7 @@ htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
  * the operands of the next).  With max_phases > 0 every run records, for
  * each fused net and each of its first max_phases phases, the clock at the
  * end of the phase.  htn_batch_phase_times writes n * max_phases values
- * ([net][phase], 100 MHz ticks counted from the first workgroup start; -1
+ * ([net][phase], 100 MHz ticks counted from the start of the run; -1
  * for phases not recorded).  Set before a graph is captured.             */
 htn_status htn_batch_set_phase_timing(htn_batch_t batch, int32_t max_phases);
 htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
@@ -320,6 +325,22 @@ htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, i
  * step by step, steps beyond max_phases).  A fused step's duration is that
  * of its phase: its arithmetic and the copies issued for the next step.  */
 htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacity);
+
+/* htn_autotune — pick the fused kernel's workgroup size and LDS budget for
+ * a set of nets by measurement.  Each candidate (threads, LDS bytes) in
+ *   (64, 32K) (64, 48K) (64, 64K) (256, 32K) (256, 48K) (256, 64K)
+ *   (256, 96K) (256, 160K) (512, 64K) (512, 96K) (512, 160K)
+ * is applied to every net (HTN_OPT_FUSED_THREADS / HTN_OPT_FUSED_LDS_BYTES,
+ * which replans them on their current paths), the nets are run as one
+ * batch (htn_batch_create/run) twice to warm up and five times timed with
+ * HIP events on hip_stream, and the candidate with the lowest median time
+ * is applied and left in place.  outs as for htn_contract_batch.
+ * best_threads, best_lds_bytes and best_ms (median milliseconds) receive
+ * the choice (each may be NULL).  Synchronous.  A candidate that fails to
+ * plan or launch is skipped; if none runs the nets keep their previous
+ * settings and HTN_E_UNSUPPORTED is returned.                             */
+htn_status htn_autotune(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream,
+                        int32_t *best_threads, int32_t *best_lds_bytes, float *best_ms);
 
 /* htn_update_data — replace the tensor values (same structure and path).
  * Same data / data_on_device semantics as htn_create.                     */

@@ -92,7 +92,23 @@ struct htn_batch {
     std::vector<void *> graph_outs;
     int64_t *d_phase = nullptr;  // per-phase clock of fused nets (optional)
     int max_phases = 0;
+    // Nets run step by step go on side streams, forked from and joined back
+    // to the caller's stream, so they overlap each other and the fused
+    // launch; side_of[k] is the side stream of step_nets[k].
+    std::vector<hipStream_t> sides;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<int> side_of;
 };
+
+// Side streams of a batch (nets run step by step in parallel).
+static constexpr int kSideStreams = 3;
+// A net eligible for the fused launch still runs step by step in a batch
+// when it would hold one workgroup far longer than the batch's average
+// share: above max(kStragglerFloor, kStragglerFactor * mean mults per
+// resident workgroup slot).
+static constexpr double kStragglerFloor = 1048576.0;
+static constexpr double kStragglerFactor = 4.0;
 
 // ------------------------------------------------------------- helpers
 
@@ -276,7 +292,8 @@ static void upload_plan(Net &n) {
     D.fprep.clear();
     D.fprep_max = 0;
     for (const LoadPlan &lp : P.loads) {
-        D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws});
+        for (int64_t e0 = 0; e0 < lp.size; e0 += kern::kFPrepChunk)
+            D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws, (int32_t)e0});
         D.fprep_max = std::max<int>(D.fprep_max, (int)lp.size);
     }
     dfree(D.d_fprep);
@@ -359,7 +376,8 @@ static void run_mfma_step(Net &n, const StepPlan &s, const void *A, int ta, cons
     void *pb = (unsigned char *)D.d_ws + s.ws_pb;
     HIP_TRY(kern::launch_step(A, ta, nullptr, ta, pa, tp, false, false, D.d_tab, pack_args(s.pack_a), st));
     HIP_TRY(kern::launch_step(B, tb, nullptr, tb, pb, tp, false, false, D.d_tab, pack_args(s.pack_b), st));
-    HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, st));
+    void *kpart = s.ksplit > 1 ? (unsigned char *)D.d_ws + s.ws_kpart : nullptr;
+    HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, s.ksplit, kpart, st));
 }
 
 static void run_steps(Net &n, void *out, hipStream_t st) {
@@ -413,6 +431,11 @@ static void run_steps(Net &n, void *out, hipStream_t st) {
         a.log2R = 0;
         while ((1 << a.log2R) < a.R) ++a.log2R;
         a.n_out = s.n_out;
+        if (s.split_global > 1) {
+            a.split = s.split_global;
+            a.chunk = (s.n_sum + s.split_global - 1) / s.split_global;
+            a.part = (double *)((unsigned char *)D.d_ws + s.ws_part);
+        }
         HIP_TRY(kern::launch_step(A, ta, B, tb, C, tc, tc == 0, comp, D.d_tab, a, st));
     }
 }
@@ -576,7 +599,8 @@ htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
             net->path_seed = (uint64_t)value;
             return HTN_OK;
         case HTN_OPT_FUSED_THREADS: {
-            if (value != 64 && value != 256) return fail(HTN_E_ARG, "fused threads must be 64 or 256");
+            if (value != 64 && value != 256 && value != 512)
+                return fail(HTN_E_ARG, "fused threads must be 64, 256 or 512");
             const int old = net->fused_threads;
             net->fused_threads = (int)value;
             try {
@@ -681,6 +705,12 @@ static void batch_free(htn_batch *b) {
     dfree(b->d_outs);
     dfree(b->d_stamps);
     dfree(b->d_phase);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t q : b->sides) (void)hipStreamDestroy(q);
+    b->ev_fork = nullptr;
+    b->ev_join.clear();
+    b->sides.clear();
 }
 
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
@@ -691,14 +721,24 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
     try {
         b->nets.assign(nets, nets + n);
         std::vector<kern::FusedDesc> desc(n);
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i < n; ++i)
             if (!nets[i]) throw Error{HTN_E_ARG, "nets[" + std::to_string(i) + "] is NULL"};
+        // straggler threshold from the work of the fused-eligible nets and
+        // the workgroup slots of the device
+        double fused_total = 0.0;
+        for (int i = 0; i < n; ++i)
+            if (use_fused_in_batch(*nets[i])) fused_total += nets[i]->plan.mults;
+        int dev = 0, cus = 256;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const double straggler = std::max(kStragglerFloor, kStragglerFactor * fused_total / (2.0 * cus));
+        for (int i = 0; i < n; ++i) {
             Net &net = *nets[i];
             ensure_device(net);
             b->versions.push_back(net.plan_version);
             desc[i] = kern::FusedDesc{net.dev->d_prog, net.dev->d_tab, (const void *const *)net.dev->d_inptrs,
                                       net.dev->d_ws};
-            if (!use_fused_in_batch(net)) {
+            if (!use_fused_in_batch(net) || net.plan.mults > straggler) {
                 b->step_nets.push_back(i);
                 continue;
             }
@@ -738,7 +778,28 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
         b->d_desc = dalloc<kern::FusedDesc>(n);
         HIP_TRY(hipMemcpy(b->d_desc, desc.data(), n * sizeof(kern::FusedDesc), hipMemcpyHostToDevice));
         b->d_outs = dalloc<void *>(n);
-        b->d_stamps = dalloc<int64_t>(2 * (size_t)n);
+        b->d_stamps = dalloc<int64_t>(2 * (size_t)n + 1);  // [2n]: start of the run
+        if (!b->step_nets.empty()) {
+            // heaviest first, each to the least loaded side stream
+            std::stable_sort(b->step_nets.begin(), b->step_nets.end(),
+                             [&](int x, int y) { return nets[x]->plan.mults > nets[y]->plan.mults; });
+            const int ns = std::min<int>(kSideStreams, (int)b->step_nets.size());
+            std::vector<double> load(ns, 0.0);
+            for (int i : b->step_nets) {
+                const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                b->side_of.push_back(q);
+                load[q] += nets[i]->plan.mults;
+            }
+            HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+            for (int q = 0; q < ns; ++q) {
+                hipStream_t sq = nullptr;
+                HIP_TRY(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
+                b->sides.push_back(sq);
+                hipEvent_t e = nullptr;
+                HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                b->ev_join.push_back(e);
+            }
+        }
     } catch (...) {
         batch_free(b);
         delete b;
@@ -757,13 +818,35 @@ htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
     API_GUARD_END
 }
 
+// Launch sequence of a batch run: a clock read marks the start; input
+// materialisation and the fused launch go on the caller's stream; nets run
+// step by step (the large ones) are spread over the side streams, forked
+// after the fused launch is queued; the caller's stream finally waits for
+// every side stream.  Every net's start and completion clock lands in
+// d_stamps.
 static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
+    const size_t n = b->nets.size();
+    HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * n, st));
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, st));
+    if (!b->sides.empty()) {
+        HIP_TRY(hipEventRecord(b->ev_fork, st));
+        for (hipStream_t q : b->sides) HIP_TRY(hipStreamWaitEvent(q, b->ev_fork, 0));
+    }
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
                                    (int)g.idx.size(), g.lds, g.compute, g.fm, g.threads, st));
-    for (int i : b->step_nets) run_steps(*b->nets[i], outs[i], st);
+    for (size_t k = 0; k < b->step_nets.size(); ++k) {
+        const int i = b->step_nets[k];
+        hipStream_t ss = b->sides[b->side_of[k]];
+        HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * (size_t)i, ss));
+        run_steps(*b->nets[i], outs[i], ss);
+        HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * (size_t)i + 1, ss));
+    }
+    for (size_t q = 0; q < b->sides.size(); ++q) {
+        HIP_TRY(hipEventRecord(b->ev_join[q], b->sides[q]));
+        HIP_TRY(hipStreamWaitEvent(st, b->ev_join[q], 0));
+    }
 }
 
 htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
@@ -818,19 +901,10 @@ htn_status htn_batch_timestamps(htn_batch_t b, int64_t *ticks) {
     API_GUARD_BEGIN
     if (!b || !ticks) return fail(HTN_E_ARG, "NULL argument");
     const int n = (int)b->nets.size();
-    std::vector<int64_t> st(2 * (size_t)n);
+    std::vector<int64_t> st(2 * (size_t)n + 1);
     HIP_TRY(hipMemcpy(st.data(), b->d_stamps, st.size() * 8, hipMemcpyDeviceToHost));
-    std::vector<char> fused(n, 0);
-    int64_t t0 = INT64_MAX;
-    for (auto &g : b->groups)
-        for (int i : g.idx) {
-            fused[i] = 1;
-            t0 = std::min(t0, st[2 * i]);
-        }
-    for (int i = 0; i < n; ++i) {
-        ticks[2 * i] = fused[i] ? st[2 * i] - t0 : -1;
-        ticks[2 * i + 1] = fused[i] ? st[2 * i + 1] - t0 : -1;
-    }
+    const int64_t t0 = st[2 * (size_t)n];
+    for (size_t k = 0; k < 2 * (size_t)n; ++k) ticks[k] = st[k] - t0;
     return HTN_OK;
     API_GUARD_END
 }
@@ -858,12 +932,10 @@ htn_status htn_batch_phase_times(htn_batch_t b, int64_t *ticks) {
     if (!b->d_phase) return fail(HTN_E_STATE, "phase timing is off");
     const int n = (int)b->nets.size();
     const size_t cnt = (size_t)b->max_phases * n;
-    std::vector<int64_t> ph(cnt), st(2 * (size_t)n);
+    std::vector<int64_t> ph(cnt), st(2 * (size_t)n + 1);
     HIP_TRY(hipMemcpy(ph.data(), b->d_phase, cnt * 8, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(st.data(), b->d_stamps, st.size() * 8, hipMemcpyDeviceToHost));
-    int64_t t0 = INT64_MAX;
-    for (auto &g : b->groups)
-        for (int i : g.idx) t0 = std::min(t0, st[2 * i]);
+    const int64_t t0 = st[2 * (size_t)n];
     for (size_t k = 0; k < cnt; ++k) ticks[k] = ph[k] >= 0 ? ph[k] - t0 : -1;
     return HTN_OK;
     API_GUARD_END
@@ -915,6 +987,93 @@ htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *out
     }
     htn_batch_destroy(b);
     return s;
+}
+
+htn_status htn_autotune(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream,
+                        int32_t *best_threads, int32_t *best_lds_bytes, float *best_ms) {
+    API_GUARD_BEGIN
+    if (n < 1 || !nets || !outs) return fail(HTN_E_ARG, "bad arguments");
+    for (int i = 0; i < n; ++i)
+        if (!nets[i] || !outs[i]) return fail(HTN_E_ARG, "NULL net or output");
+    static const int cand[][2] = {{64, 32768},   {64, 49152},   {64, 65536},   {256, 32768},
+                                  {256, 49152},  {256, 65536},  {256, 98304},  {256, 163840},
+                                  {512, 65536},  {512, 98304},  {512, 163840}};
+    const hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<int> old_threads(n);
+    std::vector<int64_t> old_lds(n);
+    for (int i = 0; i < n; ++i) {
+        old_threads[i] = nets[i]->fused_threads;
+        old_lds[i] = nets[i]->fused_lds_budget;
+    }
+    auto apply = [&](int threads, int64_t lds) {
+        for (int i = 0; i < n; ++i) {
+            nets[i]->fused_threads = threads;
+            nets[i]->fused_lds_budget = lds;
+            replan(*nets[i]);
+        }
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = -1.0f;
+    int bt = old_threads[0];
+    int64_t bl = old_lds[0];
+    try {
+        for (const auto &c : cand) {
+            htn_batch_t b = nullptr;
+            try {
+                apply(c[0], c[1]);
+                if (htn_batch_create(&b, n, nets) != HTN_OK) continue;
+                // two runs to warm up (first-use uploads, kernel attributes)
+                bool ok = htn_batch_run(b, outs, st) == HTN_OK && htn_batch_run(b, outs, st) == HTN_OK;
+                std::vector<float> ms;
+                for (int r = 0; ok && r < 5; ++r) {
+                    HIP_TRY(hipEventRecord(e0, st));
+                    ok = htn_batch_run(b, outs, st) == HTN_OK;
+                    HIP_TRY(hipEventRecord(e1, st));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float t = 0.0f;
+                    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                    ms.push_back(t);
+                }
+                HIP_TRY(hipStreamSynchronize(st));
+                htn_batch_destroy(b);
+                b = nullptr;
+                if (!ok) continue;  // e.g. an LDS budget the device refuses
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (best < 0.0f || med < best) {
+                    best = med;
+                    bt = c[0];
+                    bl = c[1];
+                }
+            } catch (const Error &) {
+                if (b) htn_batch_destroy(b);
+                (void)hipStreamSynchronize(st);
+            }
+        }
+        if (best < 0.0f) throw Error{HTN_E_UNSUPPORTED, "no candidate configuration ran"};
+        apply(bt, bl);
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (int i = 0; i < n; ++i) {
+            nets[i]->fused_threads = old_threads[i];
+            nets[i]->fused_lds_budget = old_lds[i];
+            try {
+                replan(*nets[i]);
+            } catch (...) {
+            }
+        }
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_threads) *best_threads = bt;
+    if (best_lds_bytes) *best_lds_bytes = (int32_t)bl;
+    if (best_ms) *best_ms = best;
+    return HTN_OK;
+    API_GUARD_END
 }
 
 // ------------------------------------------------------------ cost model

@@ -39,6 +39,15 @@ struct StepPlan {
     int64_t t_ohi = 0, t_olo = 0, t_shi = 0, t_slo = 0;  // offsets in pairs
     int r_fused = 1;   // lanes per output in the fused kernel (kBlock = block mode)
     int r_global = 1;  // lanes per output in the per-step kernel
+    // per-step kernel: lane groups per output, each summing one chunk of
+    // the summed range (split sums of few outputs with long sums), and the
+    // workspace byte offset of their (sum, compensation) partials
+    int split_global = 1;
+    int64_t ws_part = -1;
+    // matrix-core steps: K ranges computed in parallel and their partial
+    // products' workspace byte offset
+    int ksplit = 1;
+    int64_t ws_kpart = -1;
     // Matrix-core steps (mfma = 1): C[b][m][n] = sum_k A[b][m][k] B[b][n][k]
     // after packing A to [batch][M][K] and B to [batch][N][K] (same K order).
     int mfma = 0;
@@ -148,7 +157,7 @@ struct Net {
     htn_exec_mode exec = HTN_EXEC_AUTO;
     int64_t max_intermediate = (int64_t(1) << 31) - 1;
     int64_t fused_lds_budget = 65536;
-    int fused_threads = 256;  // threads per network in the fused kernel (64 or 256)
+    int fused_threads = 256;  // threads per network in the fused kernel (64, 256 or 512)
     double fused_max_mults = 67108864.0;        // AUTO runs larger spilled nets step by step
     double batch_fused_max_mults = 33554432.0;  // batch limit for nets with matrix-core steps
     int allow_mfma = 1;

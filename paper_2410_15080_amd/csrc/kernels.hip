@@ -9,104 +9,55 @@
 //  k_prep   applies coefficient tensors folded into an input (entry-wise
 //           scaling, Sec. 4.3's fusion of CTs into the QTs they join) and
 //           converts to the intermediate type.
-//  k_fused  one workgroup contracts an entire network: inputs are loaded
-//           once from HBM into LDS (with their coefficient scales), every
-//           pairwise step runs LDS-to-LDS, the last step writes the result.
-//           One launch serves a batch of networks (one workgroup each).
-#include "kernels.hpp"
-
+//  k_fprep  materialises the inputs of fused networks (layout change and
+//           coefficient scaling) into their workspaces.
+//  The fused whole-network kernel lives in fused.hpp / fused_b*.hip.
 #include <type_traits>
+
+#include "kern_common.hpp"
 
 namespace htn {
 namespace kern {
-
-typedef uint16_t bf16_t;  // bfloat16 bit pattern
-
-enum { OP_END = 0, OP_LOAD = 1, OP_STEP = 2, OP_SYNC = 3, OP_TSTEP = 4, OP_TCOPY = 5, OP_COPY = 6 };
-constexpr int kMaxRankLoad = 16, kMaxScalesLoad = 8;
-constexpr int kBlk = 256;
-
-__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-__device__ __forceinline__ bf16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40u);  // keep NaN quiet
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    return (bf16_t)(u >> 16);
-}
-
-template <typename ACC, typename T>
-struct Ld {
-    __device__ __forceinline__ static ACC get(const T *p) { return (ACC)(*p); }
-};
-template <typename ACC>
-struct Ld<ACC, bf16_t> {
-    __device__ __forceinline__ static ACC get(const bf16_t *p) { return (ACC)bf2f(*p); }
-};
-
-template <typename T, typename ACC>
-__device__ __forceinline__ T st_cvt(ACC v) {
-    return (T)v;
-}
-template <>
-__device__ __forceinline__ bf16_t st_cvt<bf16_t, float>(float v) {
-    return f2bf(v);
-}
-template <>
-__device__ __forceinline__ bf16_t st_cvt<bf16_t, double>(double v) {
-    return f2bf((float)v);
-}
-
-// Neumaier accumulation (COMP) or plain accumulation.
-template <bool COMP, typename ACC>
-__device__ __forceinline__ void accum(ACC &s, ACC &c, ACC x) {
-    if constexpr (COMP) {
-        ACC t = s + x;
-        if (fabs(s) >= fabs(x))
-            c += (s - t) + x;
-        else
-            c += (x - t) + s;
-        s = t;
-    } else {
-        s += x;
-    }
-}
-
-// Combine two partial sums; with COMP the high parts are added by Knuth's
-// TwoSum and the rounding error joins the compensation terms.
-template <bool COMP, typename ACC>
-__device__ __forceinline__ void combine(ACC &s, ACC &c, ACC s2, ACC c2) {
-    if constexpr (COMP) {
-        ACC t = s + s2;
-        ACC bb = t - s;
-        ACC e = (s - (t - bb)) + (s2 - bb);
-        s = t;
-        c = c + c2 + e;
-    } else {
-        s += s2;
-    }
-}
-
-template <bool COMP, typename ACC>
-__device__ __forceinline__ void lane_reduce(ACC &s, ACC &c, int width) {
-    for (int m = width >> 1; m > 0; m >>= 1) {
-        ACC s2 = __shfl_xor(s, m);
-        ACC c2 = COMP ? __shfl_xor(c, m) : ACC(0);
-        combine<COMP>(s, c, s2, c2);
-    }
-}
-
 // ------------------------------------------------------------------ k_step
 
 template <typename TA, typename TB, typename TC, typename ACC, bool UNARY, bool COMP>
 __global__ __launch_bounds__(kBlk) void k_step(const TA *__restrict__ A, const TB *__restrict__ B, TC *__restrict__ C,
                                               const int2 *__restrict__ tab, StepArgs s) {
     const int64_t gt = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int64_t o = gt >> s.log2R;
+    const int64_t grp = gt >> s.log2R;
+    const int64_t o = s.split > 1 ? grp / s.split : grp;
+    const int jc = (int)(grp - o * s.split);  // chunk of the summed range (split > 1)
     const int sub = (int)(gt & (s.R - 1));
     const bool active = o < s.n_out;
     ACC acc = 0, cmp = 0;
-    if (active) {
+    if (active && s.split > 1) {
+        const int oh = (int)(o / s.n_olo);
+        const int ol = (int)(o - (int64_t)oh * s.n_olo);
+        const int2 x = tab[s.t_ohi + oh], y = tab[s.t_olo + ol];
+        const TA *a0 = A + (x.x + y.x);
+        const TB *b0 = B;
+        if constexpr (!UNARY) b0 = B + (x.y + y.y);
+        const int2 *th = tab + s.t_shi;
+        const int2 *tl = tab + s.t_slo;
+        const int64_t n_sum = (int64_t)s.n_shi * s.n_slo;
+        int64_t e = (int64_t)jc * s.chunk + sub;
+        const int64_t e_end = min(n_sum, (int64_t)(jc + 1) * s.chunk);
+        int sh = (int)(e / s.n_slo);
+        int sl = (int)(e - (int64_t)sh * s.n_slo);
+        const int dq = s.R / s.n_slo, dr = s.R - dq * s.n_slo;
+        for (; e < e_end; e += s.R) {
+            const int2 h = th[sh], l = tl[sl];
+            ACC p = Ld<ACC, TA>::get(a0 + h.x + l.x);
+            if constexpr (!UNARY) p *= Ld<ACC, TB>::get(b0 + h.y + l.y);
+            accum<COMP>(acc, cmp, p);
+            sh += dq;
+            sl += dr;
+            if (sl >= s.n_slo) {
+                sl -= s.n_slo;
+                ++sh;
+            }
+        }
+    } else if (active) {
         const int oh = (int)(o / s.n_olo);
         const int ol = (int)(o - (int64_t)oh * s.n_olo);
         const int2 x = tab[s.t_ohi + oh], y = tab[s.t_olo + ol];
@@ -147,16 +98,43 @@ __global__ __launch_bounds__(kBlk) void k_step(const TA *__restrict__ A, const T
         }
     }
     lane_reduce<COMP>(acc, cmp, s.R);
-    if (active && sub == 0) C[o] = st_cvt<TC>(COMP ? acc + cmp : acc);
+    if (active && sub == 0) {
+        if (s.split > 1) {
+            double *q = s.part + 2 * (o * s.split + jc);
+            q[0] = (double)acc;
+            q[1] = COMP ? (double)cmp : 0.0;
+        } else {
+            C[o] = st_cvt<TC>(COMP ? acc + cmp : acc);
+        }
+    }
+}
+
+// Second pass of a split sum: one wave per output combines its `split`
+// partial (sum, compensation) pairs, lanes striding over them, then a
+// fixed shuffle tree.
+template <typename TC, bool COMP>
+__global__ __launch_bounds__(64) void k_split_finish(const double *__restrict__ part, TC *__restrict__ C,
+                                                    int split) {
+    const int64_t o = blockIdx.x;
+    double sum = 0.0, cmp = 0.0;
+    for (int j = threadIdx.x; j < split; j += 64) {
+        const double *q = part + 2 * (o * split + j);
+        combine<COMP>(sum, cmp, q[0], q[1]);
+    }
+    lane_reduce<COMP>(sum, cmp, 64);
+    if (threadIdx.x == 0) C[o] = st_cvt<TC>(COMP ? sum + cmp : sum);
 }
 
 template <typename TA, typename TB, typename TC, typename ACC, bool U, bool CMP>
 static hipError_t go_step(const void *A, const void *B, void *C, const int2 *tab, const StepArgs &s,
                           hipStream_t st) {
-    const int64_t threads = s.n_out * (int64_t)s.R;
+    const int64_t threads = s.n_out * (int64_t)s.R * (s.split > 1 ? s.split : 1);
     const int64_t blocks = (threads + kBlk - 1) / kBlk;
     hipLaunchKernelGGL((k_step<TA, TB, TC, ACC, U, CMP>), dim3((unsigned)blocks), dim3(kBlk), 0, st,
                        (const TA *)A, (const TB *)B, (TC *)C, tab, s);
+    if (s.split > 1)
+        hipLaunchKernelGGL((k_split_finish<TC, CMP>), dim3((unsigned)s.n_out), dim3(64), 0, st, s.part, (TC *)C,
+                           s.split);
     return hipGetLastError();
 }
 
@@ -236,315 +214,6 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
     return hipGetLastError();
 }
 
-// ----------------------------------------------------------------- k_fused
-
-// One step inside the fused kernel.  A, B point into LDS; C into LDS or, for
-// the final step, global memory.
-// Sum over the summed index space (n_shi x n_slo, two-level tables) of one
-// output, visiting s = start, start + stride, ... in (sh, sl) form with
-// stride = dq * n_slo + dr (dr < n_slo).  Plain sums keep four independent
-// partial sums, so four table reads and four operand reads are in flight
-// together; compensated sums stay sequential.
-template <typename T, typename ACC, bool COMP, bool UNARY>
-__device__ __forceinline__ void strided_sum(const T *a0, const T *b0, const int2 *tsh, const int2 *tsl, int sh, int sl,
-                                            int dq, int dr, int n_shi, int n_slo, ACC &s, ACC &c) {
-    if constexpr (!COMP) {
-        ACC s1 = 0, s2 = 0, s3 = 0;
-        while (sh < n_shi) {
-            int hv[4], lv[4];
-            hv[0] = sh;
-            lv[0] = sl;
-#pragma unroll
-            for (int u = 1; u < 4; ++u) {
-                hv[u] = hv[u - 1] + dq;
-                lv[u] = lv[u - 1] + dr;
-                if (lv[u] >= n_slo) {
-                    lv[u] -= n_slo;
-                    ++hv[u];
-                }
-            }
-            sh = hv[3] + dq;
-            sl = lv[3] + dr;
-            if (sl >= n_slo) {
-                sl -= n_slo;
-                ++sh;
-            }
-            ACC pv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = hv[u] < n_shi;
-                const int2 h = tsh[ok ? hv[u] : 0], l = tsl[lv[u]];
-                ACC q = (ACC)a0[h.x + l.x];
-                if constexpr (!UNARY) q *= (ACC)b0[h.y + l.y];
-                pv[u] = ok ? q : ACC(0);
-            }
-            s += pv[0];
-            s1 += pv[1];
-            s2 += pv[2];
-            s3 += pv[3];
-        }
-        s += (s1 + s2) + s3;
-    } else {
-        while (sh < n_shi) {
-            const int2 h = tsh[sh], l = tsl[sl];
-            ACC q = (ACC)a0[h.x + l.x];
-            if constexpr (!UNARY) q *= (ACC)b0[h.y + l.y];
-            accum<COMP>(s, c, q);
-            sh += dq;
-            sl += dr;
-            if (sl >= n_slo) {
-                sl -= n_slo;
-                ++sh;
-            }
-        }
-    }
-}
-
-template <int BLK, typename T, typename ACC, bool COMP, bool UNARY, typename TOUT>
-__device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int2 *__restrict__ tab,
-                                      const int32_t *g, int R, ACC *scratch) {
-    const int n_ohi = g[0], n_olo = g[1], n_shi = g[2], n_slo = g[3];
-    const int2 *toh = tab + g[4];
-    const int2 *tol = tab + g[5];
-    const int2 *tsh = tab + g[6];
-    const int2 *tsl = tab + g[7];
-    const int n_out = n_ohi * n_olo;
-    const int tid = threadIdx.x;
-    if (R == BLK) {
-        // whole workgroup per output (tiny outputs, long sums)
-        const int dq = BLK / n_slo, dr = BLK - dq * n_slo;
-        for (int o = 0; o < n_out; ++o) {
-            const int oh = o / n_olo, ol = o - oh * n_olo;
-            const int2 x = toh[oh], y = tol[ol];
-            const T *a0 = A + (x.x + y.x);
-            const T *b0 = B;
-            if constexpr (!UNARY) b0 = B + (x.y + y.y);
-            ACC s = 0, c = 0;
-            const int sh = tid / n_slo, sl = tid - sh * n_slo;
-            strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
-            lane_reduce<COMP>(s, c, 64);
-            if ((tid & 63) == 0) {
-                scratch[2 * (tid >> 6)] = s;
-                scratch[2 * (tid >> 6) + 1] = c;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                ACC ts = scratch[0], tc = scratch[1];
-                for (int w = 1; w < BLK / 64; ++w) combine<COMP>(ts, tc, scratch[2 * w], scratch[2 * w + 1]);
-                C[o] = st_cvt<TOUT>(COMP ? ts + tc : ts);
-            }
-            __syncthreads();
-        }
-        return;
-    }
-    int log2R = 0;
-    while ((1 << log2R) < R) ++log2R;
-    const int groups = BLK >> log2R;
-    const int gi = tid >> log2R, sub = tid & (R - 1);
-    const int dq = R / n_slo, dr = R - dq * n_slo;
-    for (int o0 = 0; o0 < n_out; o0 += groups) {
-        const int o = o0 + gi;
-        const bool active = o < n_out;
-        ACC s = 0, c = 0;
-        if (active) {
-            const int oh = o / n_olo, ol = o - oh * n_olo;
-            const int2 x = toh[oh], y = tol[ol];
-            const T *a0 = A + (x.x + y.x);
-            const T *b0 = B;
-            if constexpr (!UNARY) b0 = B + (x.y + y.y);
-            if (R == 1) {
-                ACC s1 = 0, s2 = 0, s3 = 0;
-                for (int sh = 0; sh < n_shi; ++sh) {
-                    const int2 h = tsh[sh];
-                    const T *a1 = a0 + h.x;
-                    const T *b1 = b0;
-                    if constexpr (!UNARY) b1 = b0 + h.y;
-                    int sl = 0;
-                    if constexpr (!COMP) {
-                        // four independent partial sums (ILP)
-                        for (; sl + 4 <= n_slo; sl += 4) {
-                            const int2 l0 = tsl[sl], l1 = tsl[sl + 1], l2 = tsl[sl + 2], l3 = tsl[sl + 3];
-                            ACC p0 = (ACC)a1[l0.x], p1 = (ACC)a1[l1.x], p2 = (ACC)a1[l2.x], p3 = (ACC)a1[l3.x];
-                            if constexpr (!UNARY) {
-                                p0 *= (ACC)b1[l0.y];
-                                p1 *= (ACC)b1[l1.y];
-                                p2 *= (ACC)b1[l2.y];
-                                p3 *= (ACC)b1[l3.y];
-                            }
-                            s += p0;
-                            s1 += p1;
-                            s2 += p2;
-                            s3 += p3;
-                        }
-                    }
-                    for (; sl < n_slo; ++sl) {
-                        const int2 l = tsl[sl];
-                        ACC p = (ACC)a1[l.x];
-                        if constexpr (!UNARY) p *= (ACC)b1[l.y];
-                        accum<COMP>(s, c, p);
-                    }
-                }
-                s += (s1 + s2) + s3;
-            } else {
-                const int sh = sub / n_slo, sl = sub - sh * n_slo;
-                strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
-            }
-        }
-        lane_reduce<COMP>(s, c, R);
-        if (active && sub == 0) C[o] = st_cvt<TOUT>(COMP ? s + c : s);
-    }
-}
-
-// Register-tiled step: C[tcm[m] + tcn[n]] = sum_k A[k*M + m] * B[k*N + n].
-// Thread (tx, ty) of a GX x (kBlk/GX) grid owns outputs m = m0 + tx + GX*i,
-// n = n0 + ty + GY*j (i < TM, j < TN).  Across a wave, A reads are
-// consecutive or broadcast, B reads broadcast or consecutive.
-// Offset of index x of a label group from its digit descriptors (per label,
-// last fastest: extent, magic (2 words), stride).
-__device__ __forceinline__ int digit_offset(uint32_t x, const int32_t *dg, int nl) {
-    int off = 0;
-#pragma unroll
-    for (int k = 7; k >= 0; --k) {
-        if (k < nl) {
-            const int32_t *q = dg + 4 * k;
-            const uint64_t magic = ((uint64_t)(uint32_t)q[2] << 32) | (uint32_t)q[1];
-            const uint32_t quo = (uint32_t)(((uint64_t)x * magic) >> 40);
-            off += (int)(x - quo * (uint32_t)q[0]) * q[3];
-            x = quo;
-        }
-    }
-    return off;
-}
-
-template <int BLK, typename T, typename ACC, int TM, int TN, typename TOUT>
-__device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int32_t *dgm, int nm, const int32_t *dgn,
-                                      int nn_l, int M, int N, int K, int GX) {
-    int lgx = 0;
-    while ((1 << lgx) < GX) ++lgx;
-    const int GY = BLK >> lgx;
-    const int tx = threadIdx.x & (GX - 1), ty = threadIdx.x >> lgx;
-    const int SM = GX * TM, SN = GY * TN;
-    for (int m0 = 0; m0 < M; m0 += SM) {
-        if (m0 + tx >= M) break;
-        for (int n0 = 0; n0 < N; n0 += SN) {
-            if (n0 + ty >= N) break;
-            int mi[TM], nj[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int m = m0 + tx + GX * i;
-                mi[i] = m < M ? m : M - 1;
-            }
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int nn = n0 + ty + GY * j;
-                nj[j] = nn < N ? nn : N - 1;
-            }
-            // U independent partial sums over k hide LDS latency (ILP)
-            constexpr int U = TM * TN >= 16 ? 1 : (TM * TN >= 8 ? 2 : (TM * TN >= 4 ? 4 : 8));
-            ACC acc[U][TM][TN];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) acc[u][i][j] = 0;
-            const T *a = A;
-            const T *b = B;
-            int k = 0;
-            for (; k + U <= K; k += U) {
-                T av[U][TM], bv[U][TN];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) av[u][i] = a[u * M + mi[i]];
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) bv[u][j] = b[u * N + nj[j]];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) acc[u][i][j] += (ACC)av[u][i] * (ACC)bv[u][j];
-                a += U * M;
-                b += U * N;
-            }
-            for (; k < K; ++k) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) acc[0][i][j] += (ACC)a[mi[i]] * (ACC)b[nj[j]];
-                a += M;
-                b += N;
-            }
-#pragma unroll
-            for (int u = 1; u < U; ++u)
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) acc[0][i][j] += acc[u][i][j];
-            int cn[TN];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) cn[j] = digit_offset((uint32_t)nj[j], dgn, nn_l);
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int m = m0 + tx + GX * i;
-                if (m < M) {
-                    const int cm = digit_offset((uint32_t)m, dgm, nm);
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        const int nn = n0 + ty + GY * j;
-                        if (nn < N) C[cm + cn[j]] = st_cvt<TOUT>(acc[0][i][j]);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <int BLK, typename T, typename ACC, typename TOUT>
-__device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int32_t *tcm, int nm,
-                                          const int32_t *tcn, int nn_l, int M, int N, int K, int TM, int TN, int GX) {
-    switch (TM * 8 + TN) {
-        case 9: tstep<BLK, T, ACC, 1, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 10: tstep<BLK, T, ACC, 1, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 12: tstep<BLK, T, ACC, 1, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 17: tstep<BLK, T, ACC, 2, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 18: tstep<BLK, T, ACC, 2, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 20: tstep<BLK, T, ACC, 2, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 33: tstep<BLK, T, ACC, 4, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 34: tstep<BLK, T, ACC, 4, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        default: tstep<BLK, T, ACC, 4, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-    }
-}
-
-// OP_TSTEP: [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M, digits of N]
-template <int BLK, typename T, int FM>
-__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, void *out) {
-    const int la = p[1], lb = p[2], lc = p[3];
-    const int M = p[4], N = p[5], K = p[6];
-    const int TM = p[7], TN = p[8], GX = p[9];
-    const bool fin = p[10] != 0;
-    const int nm = p[11], nn_l = p[12];
-    const int32_t *tcm = p + 13;
-    const int32_t *tcn = p + 13 + 4 * nm;
-    typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
-    if (la >= 0 && lb >= 0 && (fin || lc >= 0)) {
-        if (!fin)
-            tstep_sel<BLK, T, T, T>(sm + la, sm + lb, sm + lc, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
-        else
-            tstep_sel<BLK, T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
-    } else {
-        const T *A = la >= 0 ? sm + la : scr + (-la - 2);
-        const T *B = lb >= 0 ? sm + lb : scr + (-lb - 2);
-        if (!fin)
-            tstep_sel<BLK, T, T, T>(A, B, lc >= 0 ? sm + lc : scr + (-lc - 2), tcm, nm, tcn, nn_l, M, N, K, TM, TN,
-                                    GX);
-        else
-            tstep_sel<BLK, T, TO, TO>(A, B, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
-    }
-}
-
 // Input materialisation for the fused kernel.  A descriptor (in the fused
 // image) gives the input's device address, its destination in the network's
 // workspace and the digit form of its planned layout: element e of the
@@ -562,7 +231,8 @@ __device__ __forceinline__ const void *word_ptr(const int32_t *w) {
 
 template <typename T, typename TIN>
 __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
-    // one wave per entry; descriptor words are uniform (scalar loads)
+    // one wave per entry (a chunk of one load); descriptor words are
+    // uniform (scalar loads)
     const FPrepEntry en = entries[blockIdx.x];
     const int32_t *p = en.desc;
     const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
@@ -574,7 +244,8 @@ __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ ent
     const TIN *sp[kMaxScalesLoad];
 #pragma unroll
     for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
-    for (int e = threadIdx.x; e < size; e += 64) {
+    const int e_end = min(size, en.e0 + kFPrepChunk);
+    for (int e = en.e0 + threadIdx.x; e < e_end; e += 64) {
         uint32_t rem = (uint32_t)e;
         int so = 0;
         int sc[kMaxScalesLoad];
@@ -602,192 +273,14 @@ __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ ent
     }
 }
 
-// Contiguous 16-byte-chunk copies of one phase.  The copies that follow a
-// step are issued into registers before the step's arithmetic and written
-// to LDS after it, so their global latency overlaps the computation.
-constexpr int kPrefetch = 4;  // staged chunks per thread
-// Global-memory view of a copy source: the image and the workspace both
-// live in device memory, so the loads are plain global loads (no flat
-// address-space dispatch) and stay independent of LDS traffic.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const u32x4 g_uint4;
-
-struct CopyOp {
-    const g_uint4 *src;
-    int dst;  // 16-byte chunk index in LDS
-    int n;
-};
-
-__device__ __forceinline__ CopyOp decode_copy(const int32_t *p, const int32_t *image, const unsigned char *ws) {
-    // [kind, src chunk, chunks, dst chunk]; kind 0: image words, 1: workspace
-    CopyOp c;
-    const u32x4 *s = p[1] == 0 ? (const u32x4 *)(image) + p[2] : (const u32x4 *)ws + p[2];
-    c.src = (const g_uint4 *)s;
-    c.dst = p[4];
-    c.n = p[3];
-    return c;
+// Device clock read into *dst (one thread).
+__global__ void k_stamp(int64_t *dst) {
+    if (threadIdx.x == 0) *dst = (int64_t)wall_clock64();
 }
 
-// Copy n 16-byte chunks from global memory to LDS, four independent loads
-// in flight per thread.
-template <int BLK>
-__device__ __forceinline__ void copy_chunks(const g_uint4 *src, u32x4 *dst, int n) {
-    for (int c0 = threadIdx.x; c0 < n; c0 += 4 * BLK) {
-        u32x4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (c0 + u * BLK < n) v[u] = src[c0 + u * BLK];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (c0 + u * BLK < n) dst[c0 + u * BLK] = v[u];
-    }
-}
-
-// The fused kernel.  A workgroup copies its network's program into LDS and
-// interprets it: COPY moves tables or materialised inputs into LDS,
-// STEP / TSTEP contract two values, SYNC ends a phase.
-template <int BLK, typename T, typename TIN, int FM>
-__global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
-                                               void *const *__restrict__ outs, int64_t *__restrict__ stamps,
-                                               void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int net = order ? order[blockIdx.x] : (int)blockIdx.x;
-    int phase = 0;
-    const FusedDesc d = nets[net];
-    const int64_t t0 = stamps ? (int64_t)wall_clock64() : 0;
-    int32_t *img = reinterpret_cast<int32_t *>(smem);
-    // program words (a multiple of four) as 16-byte chunks
-    copy_chunks<BLK>((const g_uint4 *)d.prog, (u32x4 *)smem, d.prog[0] / 4);
-    __syncthreads();
-    int32_t *slots = img + img[3];
-    const int slot_words = img[4];
-    unsigned char *red = smem + img[5];  // reduction scratch (256 bytes)
-    const int32_t *gimg = d.prog + img[6];
-    T *sm = reinterpret_cast<T *>(smem);
-    T *scr = (T *)d.scratch;
-    void *out = out1 ? out1 : outs[net];
-    const int32_t *p = img + 8;
-    for (;;) {
-        const int op = p[0];
-        if (op == OP_END) break;
-        if (op == OP_SYNC) {
-            __syncthreads();
-            if (phase_ticks && threadIdx.x == 0 && phase < max_phases)
-                phase_ticks[(int64_t)net * max_phases + phase] = (int64_t)wall_clock64();
-            ++phase;
-            p += 1;
-            continue;
-        }
-        if (op == OP_COPY) {
-            const CopyOp c = decode_copy(p, gimg, (const unsigned char *)d.scratch);
-            copy_chunks<BLK>(c.src, (u32x4 *)smem + c.dst, c.n);
-            p += 5;
-            continue;
-        }
-        const int step_len = op == OP_TSTEP ? 13 + 4 * (p[11] + p[12]) : 15;
-        // issue the following copies (next phase's tables and operands):
-        // each thread stages up to kPrefetch chunks in registers while the
-        // step runs
-        CopyOp cps[4];
-        int starts[5] = {0, 0, 0, 0, 0};
-        int nc = 0, tot = 0;
-        const int32_t *q = p + step_len;
-        while (nc < 4 && q[0] == OP_COPY) {
-            cps[nc] = decode_copy(q, gimg, (const unsigned char *)d.scratch);
-            starts[nc] = tot;
-            tot += cps[nc].n;
-            ++nc;
-            q += 5;
-        }
-        starts[nc] = tot;
-        u32x4 stg0, stg1, stg2, stg3;
-        int dst0 = -1, dst1 = -1, dst2 = -1, dst3 = -1;
-        {
-            const g_uint4 *src[kPrefetch];
-            int dst[kPrefetch];
-#pragma unroll
-            for (int j = 0; j < kPrefetch; ++j) {
-                const int c = threadIdx.x + j * BLK;
-                src[j] = cps[0].src;
-                dst[j] = -1;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k < nc && c >= starts[k] && c < starts[k + 1]) {
-                        src[j] = cps[k].src + (c - starts[k]);
-                        dst[j] = cps[k].dst + (c - starts[k]);
-                    }
-            }
-            if (dst[0] >= 0) stg0 = *src[0];
-            if (dst[1] >= 0) stg1 = *src[1];
-            if (dst[2] >= 0) stg2 = *src[2];
-            if (dst[3] >= 0) stg3 = *src[3];
-            dst0 = dst[0];
-            dst1 = dst[1];
-            dst2 = dst[2];
-            dst3 = dst[3];
-        }
-        if (op == OP_TSTEP) {
-            tstep_dispatch<BLK, T, FM>(p, sm, scr, out);
-        } else {
-            // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot]
-            const int2 *itab2 = reinterpret_cast<const int2 *>(slots + p[14] * slot_words);
-            const int la = p[1], lb = p[2], lc = p[3];
-            const bool unary = lb == -1;
-            const bool fin = p[13] != 0;
-            const int R = p[12];
-            typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
-            constexpr bool CMP = (FM == FM_COMP);
-            if (la >= 0 && (unary || lb >= 0) && (fin || lc >= 0)) {
-                const T *A = sm + la;
-                const T *B = unary ? nullptr : sm + lb;
-                if (!fin) {
-                    if (unary)
-                        fstep<BLK, T, T, false, true, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
-                    else
-                        fstep<BLK, T, T, false, false, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
-                } else {
-                    if (unary)
-                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
-                    else
-                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
-                }
-            } else {
-                const T *A = la >= 0 ? sm + la : scr + (-la - 2);
-                const T *B = unary ? nullptr : (lb >= 0 ? sm + lb : scr + (-lb - 2));
-                if (!fin) {
-                    T *C = lc >= 0 ? sm + lc : scr + (-lc - 2);
-                    if (unary)
-                        fstep<BLK, T, T, false, true, T>(A, B, C, itab2, p + 4, R, (T *)red);
-                    else
-                        fstep<BLK, T, T, false, false, T>(A, B, C, itab2, p + 4, R, (T *)red);
-                } else {
-                    if (unary)
-                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
-                    else
-                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
-                }
-            }
-        }
-        // land the staged chunks, copy any remainder directly
-        u32x4 *lds4 = (u32x4 *)smem;
-        if (dst0 >= 0) lds4[dst0] = stg0;
-        if (dst1 >= 0) lds4[dst1] = stg1;
-        if (dst2 >= 0) lds4[dst2] = stg2;
-        if (dst3 >= 0) lds4[dst3] = stg3;
-        if (tot > kPrefetch * BLK) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < nc && starts[k + 1] > kPrefetch * BLK) {
-                    const int skip = max(0, kPrefetch * BLK - starts[k]);
-                    copy_chunks<BLK>(cps[k].src + skip, lds4 + cps[k].dst + skip, cps[k].n - skip);
-                }
-        }
-        p = q;
-    }
-    if (stamps && threadIdx.x == 0) {
-        stamps[2 * net] = t0;
-        stamps[2 * net + 1] = (int64_t)wall_clock64();
-    }
+hipError_t launch_stamp(int64_t *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, st, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st) {
@@ -803,45 +296,6 @@ hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, 
     return hipGetLastError();
 }
 
-template <int BLK, typename T, typename TIN, int FM>
-static hipError_t go_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
-                           void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
-                           hipStream_t st) {
-    static int configured = -1;
-    if (lds_bytes > configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_fused<BLK, T, TIN, FM>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return e;
-        }
-        configured = lds_bytes;
-    }
-    hipLaunchKernelGGL((k_fused<BLK, T, TIN, FM>), dim3(n_blocks), dim3(BLK), lds_bytes, st, nets, order, outs,
-                       stamps, out1, phase_ticks, max_phases);
-    return hipGetLastError();
-}
-
-template <int BLK>
-static hipError_t launch_fused_blk(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
-                                   void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
-                                   int compute, int fm, hipStream_t st) {
-#define HTN_GO(T, TIN, F) go_fused<BLK, T, TIN, F>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st)
-    if (compute == 0) return fm == FM_COMP ? HTN_GO(double, double, FM_COMP) : HTN_GO(double, double, FM_INTER);
-    if (compute == 1) {
-        if (fm == FM_COMP) return HTN_GO(float, float, FM_COMP);
-        if (fm == FM_F64) return HTN_GO(float, float, FM_F64);
-        return HTN_GO(float, float, FM_INTER);
-    }
-    if (compute == 2) {
-        if (fm == FM_COMP) return HTN_GO(float, bf16_t, FM_COMP);
-        if (fm == FM_F64) return HTN_GO(float, bf16_t, FM_F64);
-        return HTN_GO(float, bf16_t, FM_INTER);
-    }
-#undef HTN_GO
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
                         int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
                         int threads, hipStream_t st) {
@@ -851,6 +305,9 @@ hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const
                                     compute, fm, st);
     if (threads == 256)
         return launch_fused_blk<256>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes,
+                                     compute, fm, st);
+    if (threads == 512)
+        return launch_fused_blk<512>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes,
                                      compute, fm, st);
     return hipErrorInvalidValue;
 }
@@ -892,3 +349,4 @@ hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n,
 
 }  // namespace kern
 }  // namespace htn
+

@@ -20,6 +20,12 @@ struct StepArgs {
     int32_t R;       // lanes per output, power of two <= 64
     int32_t log2R;
     int64_t n_out;
+    // Split sums: with split > 1, `split` groups of R lanes per output each
+    // sum `chunk` consecutive summed terms into part[2 * (o * split + j)]
+    // (sum, compensation); a second launch combines them in order.
+    int32_t split = 1;
+    int64_t chunk = 0;
+    double *part = nullptr;
 };
 
 // Generic contraction C[o] = sum_s A[offA(o,s)] * B[offB(o,s)] (B == NULL:
@@ -54,17 +60,25 @@ struct FusedDesc {
 // out1 (optional): output of a single-network launch, used instead of outs.
 // phase_ticks (optional): [net * max_phases + k] receives the clock at the
 // end of the network's k-th phase (after its barrier).
-// threads: workgroup size of the fused kernel (64 or 256), as planned.
+// threads: 64, 256 or 512.
 hipError_t launch_fused(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps, void *out1,
                         int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute, int fm,
                         int threads, hipStream_t st);
+// One workgroup size (instantiated in fused_b<BLK>.hip).
+template <int BLK>
+hipError_t launch_fused_blk(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
+                            void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute,
+                            int fm, hipStream_t st);
 
 // Matrix-core GEMM C[b][m][n] = sum_k A[b][m][k] B[b][n][k] on packed,
 // K-contiguous operands (mfma.hip).  tin: 0 f64, 1 f32, 2 bf16; tout: 0 f64,
 // 1 f32.  FP32-accumulating inputs with tout == 0 add every `kchunk` K
 // elements into FP64 accumulators.
+// ksplit > 1 splits K into ksplit ranges (multiples of 64) whose partial
+// products go to `part` ([ksplit][batch][M][N] of the output type) and are
+// then summed in order into C.
 hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
-                       int kchunk, hipStream_t st);
+                       int kchunk, int ksplit, void *part, hipStream_t st);
 
 // Materialisation of fused-kernel inputs: each entry names a digit-form load
 // descriptor (in a fused image) and the network's workspace.  grid.y =
@@ -72,8 +86,14 @@ hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout,
 struct FPrepEntry {
     const int32_t *desc;
     void *ws;
+    int32_t e0;  // first element of this entry's chunk of the load
 };
+// Elements per FPrepEntry chunk (one wave each).
+constexpr int kFPrepChunk = 4096;
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st);
+
+// Writes the device's constant 100 MHz clock to *dst when the launch runs.
+hipError_t launch_stamp(int64_t *dst, hipStream_t st);
 
 // Element-wise dtype conversion on the device.
 hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);

@@ -18,6 +18,8 @@
 // are added into FP64 accumulators (the signed QPD sum is combined in FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace htn {
@@ -89,19 +91,20 @@ struct TileLoader {
     static constexpr int VPR = BK / EPV;                      // vectors per row
     static constexpr int NV = GBM * VPR / 256;                // vectors per thread
     uint4 v[NV];
-    __device__ __forceinline__ void load(const T *__restrict__ src, int rows, int K, int r0, int k0) {
+    // rows of length K (the row stride); columns at or beyond klim read 0
+    __device__ __forceinline__ void load(const T *__restrict__ src, int rows, int K, int klim, int r0, int k0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int idx = threadIdx.x + i * 256;
             const int r = idx / VPR, c = (idx % VPR) * EPV;
             const int gr = r0 + r, gk = k0 + c;
-            if (gr < rows && gk + EPV <= K && ((K % EPV) == 0)) {
+            if (gr < rows && gk + EPV <= klim && ((K % EPV) == 0)) {
                 v[i] = *(const uint4 *)(src + (int64_t)gr * K + gk);
             } else {
                 T tmp[EPV];
 #pragma unroll
                 for (int e = 0; e < EPV; ++e) {
-                    const bool ok = gr < rows && gk + e < K;
+                    const bool ok = gr < rows && gk + e < klim;
                     tmp[e] = ok ? src[(int64_t)gr * K + gk + e] : T(0);
                 }
                 v[i] = *(const uint4 *)tmp;
@@ -121,18 +124,22 @@ struct TileLoader {
     }
 };
 
+// blockIdx.z = b * ksplit + kz: batch entry b, K range kz (of length kper,
+// a multiple of BK); the output of range kz goes to C + (kz * batch + b) * sC.
 template <typename T, typename TOUT, bool COMBINE64>
 __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, TOUT *__restrict__ C,
-                                             int M, int N, int K, int64_t sA, int64_t sB, int64_t sC, int kchunk) {
+                                             int M, int N, int K, int64_t sA, int64_t sB, int64_t sC, int kchunk,
+                                             int ksplit, int kper, int batch) {
     typedef MfmaOp<T> Op;
     constexpr int BK = Op::BK;
     constexpr int LD = BK + Op::PAD;
     __shared__ __align__(16) T As[2][GBM * LD];
     __shared__ __align__(16) T Bs[2][GBN * LD];
-    const int bz = blockIdx.z;
+    const int bz = blockIdx.z / ksplit, kz = blockIdx.z - bz * ksplit;
+    const int kbeg = kz * kper, kend = min(K, kbeg + kper);
     A += bz * sA;
     B += bz * sB;
-    C += bz * sC;
+    C += ((int64_t)kz * batch + bz) * sC;
     const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -149,9 +156,9 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
         }
 
     TileLoader<T> la, lb;
-    const int nk = (K + BK - 1) / BK;
-    la.load(A, M, K, m0, 0);
-    lb.load(B, N, K, n0, 0);
+    const int nk = (kend - kbeg + BK - 1) / BK;
+    la.load(A, M, K, kend, m0, kbeg);
+    lb.load(B, N, K, kend, n0, kbeg);
     la.store(As[0]);
     lb.store(Bs[0]);
     __syncthreads();
@@ -159,8 +166,8 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) {
-            la.load(A, M, K, m0, (kt + 1) * BK);
-            lb.load(B, N, K, n0, (kt + 1) * BK);
+            la.load(A, M, K, kend, m0, kbeg + (kt + 1) * BK);
+            lb.load(B, N, K, kend, n0, kbeg + (kt + 1) * BK);
         }
         const T *as = As[cur];
         const T *bs = Bs[cur];
@@ -216,29 +223,45 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
             }
 }
 
-hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
-                       int kchunk, hipStream_t st) {
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch);
+// Sum of the K-range partial products, in range order.
+template <typename TOUT>
+__global__ __launch_bounds__(256) void k_ksum(const TOUT *__restrict__ part, TOUT *__restrict__ C, int64_t total,
+                                             int ksplit) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        TOUT a = part[i];
+        for (int kz = 1; kz < ksplit; ++kz) a += part[(int64_t)kz * total + i];
+        C[i] = a;
+    }
+}
+
+template <typename T, typename TOUT, bool C64>
+static hipError_t go_gemm(const void *A, const void *B, void *C, int M, int N, int K, int batch, int kchunk,
+                          int ksplit, void *part, hipStream_t st) {
     const int64_t sA = (int64_t)M * K, sB = (int64_t)N * K, sC = (int64_t)M * N;
-    if (tin == 0 && tout == 0) {
-        hipLaunchKernelGGL((k_gemm<double, double, false>), grid, dim3(256), 0, st, (const double *)A,
-                           (const double *)B, (double *)C, M, N, K, sA, sB, sC, kchunk);
-    } else if (tin == 1 && tout == 0) {
-        hipLaunchKernelGGL((k_gemm<float, double, true>), grid, dim3(256), 0, st, (const float *)A, (const float *)B,
-                           (double *)C, M, N, K, sA, sB, sC, kchunk);
-    } else if (tin == 1 && tout == 1) {
-        hipLaunchKernelGGL((k_gemm<float, float, false>), grid, dim3(256), 0, st, (const float *)A, (const float *)B,
-                           (float *)C, M, N, K, sA, sB, sC, kchunk);
-    } else if (tin == 2 && tout == 0) {
-        hipLaunchKernelGGL((k_gemm<bf16_t, double, true>), grid, dim3(256), 0, st, (const bf16_t *)A,
-                           (const bf16_t *)B, (double *)C, M, N, K, sA, sB, sC, kchunk);
-    } else if (tin == 2 && tout == 1) {
-        hipLaunchKernelGGL((k_gemm<bf16_t, float, false>), grid, dim3(256), 0, st, (const bf16_t *)A,
-                           (const bf16_t *)B, (float *)C, M, N, K, sA, sB, sC, kchunk);
-    } else {
-        return hipErrorInvalidValue;
+    const int kper = ksplit > 1 ? ((K + ksplit - 1) / ksplit + 63) / 64 * 64 : K;
+    if (ksplit > 1) ksplit = (K + kper - 1) / kper;
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch * ksplit);
+    TOUT *dst = ksplit > 1 ? (TOUT *)part : (TOUT *)C;
+    hipLaunchKernelGGL((k_gemm<T, TOUT, C64>), grid, dim3(256), 0, st, (const T *)A, (const T *)B, dst, M, N, K, sA,
+                       sB, sC, kchunk, ksplit, kper, batch);
+    if (ksplit > 1) {
+        const int64_t total = (int64_t)batch * sC;
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL((k_ksum<TOUT>), dim3((unsigned)blocks), dim3(256), 0, st, (const TOUT *)part, (TOUT *)C,
+                           total, ksplit);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout, int M, int N, int K, int batch,
+                       int kchunk, int ksplit, void *part, hipStream_t st) {
+    if (ksplit < 1 || (ksplit > 1 && !part)) return hipErrorInvalidValue;
+    if (tin == 0 && tout == 0) return go_gemm<double, double, false>(A, B, C, M, N, K, batch, kchunk, ksplit, part, st);
+    if (tin == 1 && tout == 0) return go_gemm<float, double, true>(A, B, C, M, N, K, batch, kchunk, ksplit, part, st);
+    if (tin == 1 && tout == 1) return go_gemm<float, float, false>(A, B, C, M, N, K, batch, kchunk, ksplit, part, st);
+    if (tin == 2 && tout == 0) return go_gemm<bf16_t, double, true>(A, B, C, M, N, K, batch, kchunk, ksplit, part, st);
+    if (tin == 2 && tout == 1) return go_gemm<bf16_t, float, false>(A, B, C, M, N, K, batch, kchunk, ksplit, part, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace kern

@@ -715,6 +715,15 @@ void build_plan(Net &n) {
         int rg = 1;
         while (rg < 64 && s.n_out * rg < 131072 && (int64_t)rg * 4 <= s.n_sum) rg *= 2;
         s.r_global = rg;
+        // few outputs with long sums: split each sum over several lane
+        // groups (at least 32 terms per lane) until ~2^16 lanes run
+        int64_t sp = 1;
+        const int64_t lanes = s.n_out * rg;
+        if (lanes < 65536 && s.n_sum >= 64 * (int64_t)rg) {
+            sp = std::min<int64_t>((65536 + lanes - 1) / lanes, s.n_sum / (32 * (int64_t)rg));
+            sp = std::max<int64_t>(1, std::min<int64_t>(sp, 4096));
+        }
+        s.split_global = (int)sp;
     }
 
     // Loads of inputs with folded coefficient tensors, in first-use order.
@@ -771,8 +780,25 @@ void build_plan(Net &n) {
             if (s.mfma) {
                 s.ws_pa = ff.alloc(s.pack_a.n * pes, 256);
                 s.ws_pb = ff.alloc(s.pack_b.n * pes, 256);
+                // too few 128x128 output tiles to fill the chip: split K
+                // (ranges of >= 128) into parallel partial products
+                const int64_t tiles = ((s.gm + 127) / 128) * ((s.gn + 127) / 128) * s.gb;
+                int64_t ks = 1;
+                if (tiles < 256 && s.gk >= 256) {
+                    ks = std::min<int64_t>((512 + tiles - 1) / tiles, s.gk / 128);
+                    ks = std::min<int64_t>(ks, (int64_t(256) << 20) / std::max<int64_t>(1, s.gb * s.gm * s.gn * 8));
+                    ks = std::max<int64_t>(1, ks);
+                }
+                s.ksplit = (int)ks;
+                if (ks > 1) {
+                    s.ws_kpart = ff.alloc(ks * s.gb * s.gm * s.gn * 8, 256);
+                    ff.release(s.ws_kpart);
+                }
                 ff.release(s.ws_pa);
                 ff.release(s.ws_pb);
+            } else if (s.split_global > 1) {
+                s.ws_part = ff.alloc(s.n_out * s.split_global * 16, 256);
+                ff.release(s.ws_part);
             }
             for (int id : {s.a, s.b})
                 if (id >= 0 && P.ws_off[id] >= 0) ff.release(P.ws_off[id]);
@@ -1056,6 +1082,7 @@ std::string plan_json(const Net &n) {
       << ",\"fused_possible\":" << (P.fused_possible ? "true" : "false")
       << ",\"elem_bytes\":" << dtype_size(inter_dtype(n.compute))
       << ",\"n_absorbed\":" << P.n_absorbed << ",\"fused_ok\":" << (P.fused_ok ? "true" : "false")
+      << ",\"fused_batch_ok\":" << (P.fused_batch_ok ? "true" : "false")
       << ",\"fused_pure\":" << (P.fused_pure ? "true" : "false") << ",\"fused_lds_bytes\":" << P.fused_lds_bytes
       << ",\"fused_scratch_bytes\":" << P.fused_scratch_bytes << ",\"ws_bytes\":" << P.ws_bytes
       << ",\"final_value\":" << P.final_value << ",\"n_table_entries\":" << P.tables.size() / 2
@@ -1073,7 +1100,7 @@ std::string plan_json(const Net &n) {
         o << ",\"mults\":" << s.mults << ",\"absorbed\":" << (s.absorbed ? "true" : "false")
           << ",\"final\":" << (s.final_step ? "true" : "false") << ",\"synthetic\":" << (s.synthetic ? "true" : "false")
           << ",\"n_out\":" << s.n_out << ",\"n_sum\":" << s.n_sum << ",\"r_fused\":" << s.r_fused
-          << ",\"r_global\":" << s.r_global << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
+          << ",\"r_global\":" << s.r_global << ",\"split\":" << s.split_global << ",\"ksplit\":" << s.ksplit << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
           << s.n_slo << "," << s.t_ohi << "," << s.t_olo << "," << s.t_shi << "," << s.t_slo << "],\"pack_a\":["
           << s.pack_a.n_ohi << "," << s.pack_a.n_olo << "," << s.pack_a.t_ohi << "," << s.pack_a.t_olo << "],\"pack_b\":["
           << s.pack_b.n_ohi << "," << s.pack_b.n_olo << "," << s.pack_b.t_ohi << "," << s.pack_b.t_olo

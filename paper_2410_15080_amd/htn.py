@@ -102,6 +102,7 @@ def load_library():
         "htn_model_destroy": (None, [P]),
         "htn_set_model": (I32, [P, P]),
         "htn_step_features": (I32, [P, f32p, I32, i32p]),
+        "htn_autotune": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P, i32p, i32p, f32p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -295,6 +296,17 @@ def htn_contract_batch(nets, outs, stream=None) -> None:
     lib = load_library()
     hs = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
     _check(lib.htn_contract_batch(len(nets), hs, pointer_array(outs), _stream_ptr(stream)))
+
+
+def htn_autotune(nets, outs, stream=None):
+    """Returns (threads, lds_bytes, median ms) of the configuration applied."""
+    handles = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+    optrs = pointer_array(outs)
+    t, l = ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(load_library().htn_autotune(len(nets), handles, optrs, _stream_ptr(stream), ctypes.byref(t),
+                                       ctypes.byref(l), ctypes.byref(ms)))
+    return int(t.value), int(l.value), float(ms.value)
 
 
 def htn_batch_create(nets) -> Batch:

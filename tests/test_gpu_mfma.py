@@ -52,3 +52,55 @@ def test_gemm_step_matches_oracle(shape, compute):
     else:
         bound = (2 * U16 + (K + 2) * U32) * K
     assert err <= bound, (err, bound)
+
+
+@pytest.mark.parametrize("compute", [htn.HTN_F64, htn.HTN_F32, htn.HTN_BF16])
+def test_split_k_gemm_matches_oracle(compute):
+    """Few output tiles and a long K: the GEMM runs as parallel K ranges
+    (ragged last range) whose partial products are summed in order."""
+    M, N, K = 200, 150, 4100
+    w = _gemm_net(np.random.default_rng(5), M, N, K, 1, False)
+    fs = htn.HTN_SUM_PLAIN if compute == htn.HTN_F64 else htn.HTN_SUM_FP64
+    net = create(w, compute=compute, final_sum=fs, storage=htn.HTN_F64, exec_mode=htn.HTN_EXEC_STEPS)
+    step = json.loads(htn.htn_plan_json(net))["steps"][-1]
+    assert step["mfma"] == 1 and step["ksplit"] > 1
+    got = contract(net, (1, M, N))
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    err = float(np.abs(got - (hi + lo)).max())
+    if compute == htn.HTN_F64:
+        bound = K * 2.0 ** -52 * K
+    elif compute == htn.HTN_F32:
+        bound = (K + 2) * U32 * K
+    else:
+        bound = (2 * U16 + (K + 2) * U32) * K
+    assert err <= bound, (err, bound)
+
+
+@pytest.mark.parametrize("final_sum", [htn.HTN_SUM_PLAIN, htn.HTN_SUM_COMPENSATED])
+@pytest.mark.parametrize("compute", [htn.HTN_F64, htn.HTN_F32])
+def test_split_sum_long_reductions(final_sum, compute):
+    """A scalar (and a 3-entry vector) summing 589 824 products: the
+    per-step kernel splits each sum over many lane groups and combines the
+    partials in a second pass."""
+    rng = np.random.default_rng(9)
+    for out in ([], [2]):
+        dims = [768, 768, 3]
+        la, lb = [0, 1, 2], [1, 0]
+        a = rng.uniform(-1, 1, size=(768, 768, 3))
+        b = rng.uniform(-1, 1, size=(768, 768))
+        w = Network([a, b], [la, lb], dims, out)
+        if not out:
+            w = Network([a[..., 0], b], [[0, 1], lb], dims[:2], [])
+        net = create(w, compute=compute, final_sum=final_sum, storage=htn.HTN_F64, exec_mode=htn.HTN_EXEC_STEPS)
+        step = json.loads(htn.htn_plan_json(net))["steps"][-1]
+        assert step["split"] > 1
+        shape = tuple(w.dims[l] for l in w.out_labels)
+        got = contract(net, shape)
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = np.asarray(hi + lo)
+        u = 2.0 ** -53 if compute == htn.HTN_F64 else U32
+        # every partial is a chain of at most 32 products plus a 6-level
+        # lane tree in the compute type, then FP64: |err| <= 2 * 40 u sum |a b|
+        absum = oracle.ve_contract([np.abs(t) for t in w.tensors], w.labels, w.dims, w.out_labels)[0]
+        bound = 80 * u * np.asarray(absum).max()
+        assert float(np.abs(got - ref).max()) <= bound

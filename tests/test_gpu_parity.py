@@ -137,7 +137,10 @@ def test_batch_equals_single_and_oracle():
         single = htn.new_output(n)
         htn.htn_contract(n, single)
         torch.cuda.synchronize()
-        assert float(o.item()) == float(single.item())   # same plan, same kernel
+        if htn.htn_get_info(n).mults <= 2 ** 20:
+            assert float(o.item()) == float(single.item())   # same plan, same kernel
+        else:  # heavy nets run step by step in a batch
+            assert abs(float(o.item()) - float(single.item())) <= REL_F64 * abs(float(single.item()))
         hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
         ref = float(hi) + float(lo)
         assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref)
@@ -215,7 +218,8 @@ def test_update_data_reuses_plan():
     assert abs(b - 0.5 * a) <= 1e-13 * abs(a)
 
 
-@pytest.mark.parametrize("threads,lds", [(64, 24576), (64, 32768), (64, 65536), (256, 20480)])
+@pytest.mark.parametrize("threads,lds", [(64, 24576), (64, 32768), (64, 65536), (256, 20480), (512, 65536),
+                                         (512, 131072), (256, 163840)])
 def test_fused_block_sizes_and_budgets(threads, lds):
     """Grid networks on sampled paths, fused kernel with one wave or four
     waves per network and several LDS budgets (small budgets spill)."""
@@ -240,3 +244,53 @@ def test_fused_block_sizes_and_budgets(threads, lds):
         htn.htn_contract(n, single)
         torch.cuda.synchronize()
         assert float(single.item()) == float(o.item())
+
+
+def test_random_batch_mixed_executors_graph_and_stamps():
+    """Random networks of uneven size (the largest run step by step on a
+    second stream, the rest in the fused launch), eager and graph replays
+    against the oracle, and device timestamps for every net."""
+    import json
+
+    import torch
+    ws = configs.random_batch(3, n=128, dtype=np.float64)
+    ws = [w for i, w in enumerate(ws) if i not in (78, 79)]  # keep the oracle's time short
+    nets = [create(w) for w in ws]
+    stepped = [i for i, n in enumerate(nets) if not json.loads(htn.htn_plan_json(n))["fused_batch_ok"]]
+    assert len(stepped) >= 2
+    refs = []
+    for w in ws:
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        refs.append(float(hi) + float(lo))
+    outs = [htn.new_output(n) for n in nets]
+    b = htn.htn_batch_create(nets)
+    htn.htn_batch_set_graph(b, True)
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            htn.htn_batch_run(b, htn.pointer_array(outs), stream)
+        stream.synchronize()
+        for i, (o, ref) in enumerate(zip(outs, refs)):
+            assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref) + 1e-300, (rep, i)
+        t = htn.htn_batch_timestamps(b)
+        assert (t[:, 0] >= 0).all() and (t[:, 1] > t[:, 0]).all(), rep
+
+
+def test_autotune_picks_a_measured_configuration_and_keeps_results():
+    import torch
+    ws = [configs.grid_network(900 + s) for s in range(64)]
+    nets = [create(w) for w in ws]
+    outs = [htn.new_output(n) for n in nets]
+    threads, lds, ms = htn.htn_autotune(nets, outs)
+    assert threads in (64, 256, 512) and lds in (32768, 49152, 65536, 98304, 163840) and ms > 0
+    htn.htn_contract_batch(nets, outs)
+    torch.cuda.synchronize()
+    for w, n, o in zip(ws, nets, outs):
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = float(hi) + float(lo)
+        assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref)
+        info = htn.htn_get_info(n)
+        assert info.fused_lds_bytes <= lds

@@ -58,6 +58,7 @@ def _random_network(rng):
 def test_replay_grid(seed):
     _check(configs.grid_network(seed))
     _check(configs.grid_network(seed), threads=64, lds=16384)
+    _check(configs.grid_network(seed), threads=512, lds=131072)
 
 
 def test_replay_sampled_paths():
@@ -69,6 +70,7 @@ def test_replay_sampled_paths():
         path, _ = htn.htn_get_path(net)
         _check(w, path=path)
         _check(w, path=path, threads=64, lds=16384)
+        _check(w, path=path, threads=512, lds=98304)
 
 
 def test_replay_random_networks():

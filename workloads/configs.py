@@ -2,7 +2,7 @@
 
 Every function takes an explicit seed and returns :class:`Network` objects
 (or lists of them).  Shapes follow the paper's workloads: subcircuits of at
-most 15 qubits with 2-10 cuts (Sec. 7.1 / RQ1), six-term gate cuts
+most 15 qubits (Sec. 7.1) with 2-10 cuts (Sec. 7.2), six-term gate cuts
 (Sec. 2.1) and four-dimensional wire-cut indices (Sec. 4.1).  None of the
 paper's benchmark circuits are reproduced; these are synthetic stand-ins.
 
