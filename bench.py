@@ -64,6 +64,33 @@ def parse():
     return ap.parse_args()
 
 
+# HBM traffic per launch of a kernel on a workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs of this script scaled by the same counters
+# on a plain copy (profiles/ holds the summaries and commands).  Each record
+# carries a digest of the sources that shape the kernel and its plans; when
+# they change the record no longer applies and traffic is reported as null.
+TRAFFIC = {}
+TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
+                   "paper_2410_15080_amd/csrc/fused_b256.hip", "paper_2410_15080_amd/csrc/planner.cpp"]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key, runs_ok=True):
+    rec = TRAFFIC.get(key)
+    if not rec or not runs_ok or rec["sources"] != source_digest():
+        return None
+    return {"read_bytes": rec["read_bytes"], "write_bytes": rec["write_bytes"],
+            "bytes": rec["read_bytes"] + rec["write_bytes"], "profile": rec["profile"]}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -112,13 +139,15 @@ class Timer:
     def __init__(self, stream):
         self.stream = stream
 
-    def run(self, fn, steps, warmup):
+    def run(self, fn, steps, warmup, after_warmup=None):
         import numpy as np
         import torch
         with torch.cuda.stream(self.stream):
             for _ in range(warmup):
                 fn()
         self.stream.synchronize()
+        if after_warmup:
+            after_warmup()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -233,7 +262,10 @@ def bench_grid(args):
     b, out, outs, stream = batch_runner(nets, torch.float64)
     timer = Timer(stream)
     log(f"timing {args.steps} steps")
-    ms_per_step, kern_ms = timer.run(lambda: htn.htn_batch_run(b, outs, stream), args.steps, args.warmup)
+    ms_per_step, kern_ms = timer.run(lambda: htn.htn_batch_run(b, outs, stream), args.steps, args.warmup,
+                                     after_warmup=lambda: htn.htn_batch_set_event_timing(b, True))
+    prep_ms, fused_ms, runs = htn.htn_batch_launch_ms(b)
+    assert runs == args.steps
     got = out.cpu().numpy()
     errs = []
     for i in range(0, n_nets, max(1, n_nets // 32)):
@@ -263,7 +295,7 @@ def bench_grid(args):
     if not args.no_cpu:
         log("timing CPU oracle")
         cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
-    achieved = 2.0 * mults / (kern_ms * 1e-3) / 1e12
+    achieved = 2.0 * mults / (fused_ms * 1e-3) / 1e12
     return {
         "metric": METRIC,
         "value": round(2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
@@ -283,9 +315,12 @@ def bench_grid(args):
         "plain_fp64_path": plain,
         "speedup_vs_plain_fp64": (htns / plain["htns_per_s"]) if plain else None,
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5), "traffic": None,
-                     "kernel": "k_fused<256,double,double,0> (+ k_fprep)", "kernel_ms": round(kern_ms, 4),
-                     "input_bytes": in_bytes},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5),
+                     "traffic": measured_traffic("k_fused_grid", runs_ok=(args.lds == 65536 and args.threads == 256
+                                                                           and args.path == "sampled")),
+                     "kernel": "k_fused<256,double,double,0>", "kernel_ms": round(fused_ms, 4),
+                     "flops_per_launch": 2.0 * mults, "k_fprep_ms": round(prep_ms, 4),
+                     "batch_ms_events": round(kern_ms, 4), "input_bytes": in_bytes},
         "cpu_baseline": cpu,
     }
 

@@ -238,6 +238,15 @@ htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
  * for phases not recorded).  Set before a graph is captured.             */
 htn_status htn_batch_set_phase_timing(htn_batch_t batch, int32_t max_phases);
 htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
+/* Launch timing with HIP events.  With htn_batch_set_event_timing(batch, 1)
+ * every eager htn_batch_run (not graph replays) records events on its
+ * stream around the input-materialisation launch and around the fused
+ * launch.  htn_batch_launch_ms waits for them and returns the mean
+ * durations (milliseconds) over the runs since timing was switched on or
+ * last read, and their count; then starts a new tally.  Any argument but
+ * the batch may be NULL.                                                  */
+htn_status htn_batch_set_event_timing(htn_batch_t batch, int32_t on);
+htn_status htn_batch_launch_ms(htn_batch_t batch, float *prep_ms, float *fused_ms, int32_t *runs);
 void htn_batch_destroy(htn_batch_t batch);
 
 /* ---------------------------------------------------------------------

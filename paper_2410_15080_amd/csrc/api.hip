@@ -63,9 +63,23 @@ struct DeviceState {
     kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of the fused path
     std::vector<kern::FPrepEntry> fprep;
     int fprep_max = 0;
+    bool fprep_in_kernel = false;  // the fused workgroup materialises its inputs
     int plan_uploaded = -1;
 };
 }  // namespace htn
+
+// A network contracted on its own (htn_contract, fused) whose inputs total
+// at most this many elements materialises them inside its workgroup, which
+// saves a launch.  Batches materialise every network's inputs in one wide
+// launch instead: spread over thousands of waves it finishes sooner than
+// per-workgroup prologues.
+static constexpr int64_t kInKernelPrepMax = 65536;
+
+static kern::FusedDesc fused_desc(const DeviceState &D, bool in_kernel_prep) {
+    const bool k = in_kernel_prep && D.fprep_in_kernel;
+    return kern::FusedDesc{D.d_prog, D.d_tab, (const void *const *)D.d_inptrs, D.d_ws, k ? D.d_fprep : nullptr,
+                           k ? (int32_t)D.fprep.size() : 0};
+}
 
 struct htn_net : public Net {};
 
@@ -99,6 +113,11 @@ struct htn_batch {
     std::vector<hipEvent_t> ev_join;
     hipEvent_t ev_fork = nullptr;
     std::vector<int> side_of;
+    // Optional HIP events around the prep and fused launches of eager runs
+    // (htn_batch_set_event_timing): three per run.
+    bool event_timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
 };
 
 // Side streams of a batch (nets run step by step in parallel).
@@ -303,7 +322,10 @@ static void upload_plan(Net &n) {
         HIP_TRY(hipMemcpy(D.d_fprep, D.fprep.data(), D.fprep.size() * sizeof(kern::FPrepEntry),
                           hipMemcpyHostToDevice));
     }
-    kern::FusedDesc fd{D.d_prog, D.d_tab, (const void *const *)D.d_inptrs, D.d_ws};
+    int64_t in_elems = 0;
+    for (const LoadPlan &lp : P.loads) in_elems += lp.size;
+    D.fprep_in_kernel = !D.fprep.empty() && in_elems <= kInKernelPrepMax;
+    kern::FusedDesc fd = fused_desc(D, true);
     dfree(D.d_fdesc);
     D.d_fdesc = dalloc<kern::FusedDesc>(1);
     HIP_TRY(hipMemcpy(D.d_fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
@@ -346,7 +368,8 @@ static bool use_fused(const Net &n) {
 }
 
 static void run_fused_single(Net &n, void *out, hipStream_t st) {
-    HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, st));
+    if (!n.dev->fprep_in_kernel)
+        HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, st));
     HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, nullptr, 0, 1,
                                (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), n.fused_threads, st));
 }
@@ -711,6 +734,18 @@ static void batch_free(htn_batch *b) {
     b->ev_fork = nullptr;
     b->ev_join.clear();
     b->sides.clear();
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    b->ev_pool.clear();
+    b->ev_used = 0;
+}
+
+static hipEvent_t next_event(htn_batch *b) {
+    if (b->ev_used == b->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreate(&e));
+        b->ev_pool.push_back(e);
+    }
+    return b->ev_pool[b->ev_used++];
 }
 
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
@@ -736,8 +771,7 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
             Net &net = *nets[i];
             ensure_device(net);
             b->versions.push_back(net.plan_version);
-            desc[i] = kern::FusedDesc{net.dev->d_prog, net.dev->d_tab, (const void *const *)net.dev->d_inptrs,
-                                      net.dev->d_ws};
+            desc[i] = fused_desc(*net.dev, false);
             if (!use_fused_in_batch(net) || net.plan.mults > straggler) {
                 b->step_nets.push_back(i);
                 continue;
@@ -824,11 +858,13 @@ htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
 // after the fused launch is queued; the caller's stream finally waits for
 // every side stream.  Every net's start and completion clock lands in
 // d_stamps.
-static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
+static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool events) {
     const size_t n = b->nets.size();
     HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * n, st));
+    if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, st));
+    if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     if (!b->sides.empty()) {
         HIP_TRY(hipEventRecord(b->ev_fork, st));
         for (hipStream_t q : b->sides) HIP_TRY(hipStreamWaitEvent(q, b->ev_fork, 0));
@@ -836,6 +872,7 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st) {
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
                                    (int)g.idx.size(), g.lds, g.compute, g.fm, g.threads, st));
+    if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     for (size_t k = 0; k < b->step_nets.size(); ++k) {
         const int i = b->step_nets[k];
         hipStream_t ss = b->sides[b->side_of[k]];
@@ -873,10 +910,10 @@ htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
             b->graph = nullptr;
         }
         if (!b->gexec) {
-            batch_enqueue(b, outs, st);  // first run eagerly (also sets kernel attributes)
+            batch_enqueue(b, outs, st, false);  // first run eagerly (also sets kernel attributes)
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             try {
-                batch_enqueue(b, outs, st);
+                batch_enqueue(b, outs, st, false);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(st, &g);
@@ -892,7 +929,37 @@ htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
         HIP_TRY(hipGraphLaunch(b->gexec, st));
         return HTN_OK;
     }
-    batch_enqueue(b, outs, st);
+    batch_enqueue(b, outs, st, b->event_timing);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_set_event_timing(htn_batch_t b, int32_t on) {
+    API_GUARD_BEGIN
+    if (!b) return fail(HTN_E_ARG, "batch is NULL");
+    b->event_timing = on != 0;
+    b->ev_used = 0;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_launch_ms(htn_batch_t b, float *prep_ms, float *fused_ms, int32_t *runs) {
+    API_GUARD_BEGIN
+    if (!b) return fail(HTN_E_ARG, "batch is NULL");
+    const size_t k = b->ev_used / 3;
+    double sp = 0.0, sf = 0.0;
+    for (size_t r = 0; r < k; ++r) {
+        float a = 0.0f, c = 0.0f;
+        HIP_TRY(hipEventSynchronize(b->ev_pool[3 * r + 2]));
+        HIP_TRY(hipEventElapsedTime(&a, b->ev_pool[3 * r], b->ev_pool[3 * r + 1]));
+        HIP_TRY(hipEventElapsedTime(&c, b->ev_pool[3 * r + 1], b->ev_pool[3 * r + 2]));
+        sp += a;
+        sf += c;
+    }
+    if (prep_ms) *prep_ms = k ? (float)(sp / k) : 0.0f;
+    if (fused_ms) *fused_ms = k ? (float)(sf / k) : 0.0f;
+    if (runs) *runs = (int32_t)k;
+    b->ev_used = 0;
     return HTN_OK;
     API_GUARD_END
 }

@@ -380,6 +380,13 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
     int32_t *img = reinterpret_cast<int32_t *>(smem);
     // program words (a multiple of four) as 16-byte chunks
     copy_chunks<BLK>((const g_uint4 *)d.prog, (u32x4 *)smem, d.prog[0] / 4);
+    if (d.n_fprep > 0) {
+        // materialise the network's inputs into its workspace, one wave per
+        // entry, then make the writes visible to the workgroup's reads
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int j = wave; j < d.n_fprep; j += BLK / 64) fprep_entry<T, TIN>(d.fprep[j], lane);
+        __threadfence();
+    }
     __syncthreads();
     int32_t *slots = img + img[3];
     const int slot_words = img[4];

@@ -87,5 +87,76 @@ __device__ __forceinline__ void lane_reduce(ACC &s, ACC &c, int width) {
     }
 }
 
+// Input materialisation of fused networks.  A descriptor (in the fused
+// image) gives the input's device address, its destination in the network's
+// workspace and the digit form of its planned layout: element e of the
+// value has mixed-radix digits over the value's labels; its source offset
+// and each coefficient tensor's offset are dot products of the digits with
+// per-label strides.  Digits are extracted with precomputed magic
+// multipliers: floor(e / d) = (e * magic) >> 40, exact for e < 2^24 and
+// d < 2^16.
+// Descriptor words: [base ptr (2), dst element offset (2), size, rank, ns,
+//   scale ptrs (2 each), per label k: (extent, magic (2), source stride,
+//   scale strides)]
+__device__ __forceinline__ const void *word_ptr(const int32_t *w) {
+    return (const void *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
+}
+
+// One wave materialises one entry (a chunk of kFPrepChunk elements of one
+// load); lane = lane index 0..63.  Descriptor words are wave-uniform.
+template <typename T, typename TIN>
+__device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
+    const int32_t *p = en.desc;
+    const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
+    const int size = p[4], rk = p[5], ns = p[6];
+    const int32_t *per = p + 7 + 2 * ns;
+    const int W = 4 + ns;
+    const TIN *src = (const TIN *)word_ptr(p);
+    T *o = (T *)en.ws + dst_off;
+    const TIN *sp[kMaxScalesLoad];
+#pragma unroll
+    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
+    const int e_end = min(size, en.e0 + kFPrepChunk);
+    // four elements per lane at a time, so their gathers are in flight
+    // together
+    for (int e0 = en.e0 + lane; e0 < e_end; e0 += 4 * 64) {
+        int so[4], sc[4][kMaxScalesLoad];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(e0 + 64 * u, e_end - 1);
+            uint32_t rem = (uint32_t)e;
+            so[u] = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxScalesLoad; ++q) sc[u][q] = 0;
+#pragma unroll
+            for (int k = kMaxRankLoad - 1; k >= 0; --k) {
+                if (k < rk) {
+                    const int32_t *pk = per + k * W;
+                    const uint64_t magic = ((uint64_t)(uint32_t)pk[2] << 32) | (uint32_t)pk[1];
+                    const uint32_t quo = (uint32_t)(((uint64_t)rem * magic) >> 40);
+                    const int dgt = (int)(rem - quo * (uint32_t)pk[0]);
+                    rem = quo;
+                    so[u] += dgt * pk[3];
+#pragma unroll
+                    for (int q = 0; q < kMaxScalesLoad; ++q)
+                        if (q < ns) sc[u][q] += dgt * pk[4 + q];
+                }
+            }
+        }
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = Ld<T, TIN>::get(src + so[u]);
+#pragma unroll
+        for (int q = 0; q < kMaxScalesLoad; ++q)
+            if (q < ns) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] *= Ld<T, TIN>::get(sp[q] + sc[u][q]);
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + 64 * u < e_end) o[e0 + 64 * u] = v[u];
+    }
+}
+
 }  // namespace kern
 }  // namespace htn

@@ -214,63 +214,12 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
     return hipGetLastError();
 }
 
-// Input materialisation for the fused kernel.  A descriptor (in the fused
-// image) gives the input's device address, its destination in the network's
-// workspace and the digit form of its planned layout: element e of the
-// value has mixed-radix digits over the value's labels; its source offset
-// and each coefficient tensor's offset are dot products of the digits with
-// per-label strides.  Digits are extracted with precomputed magic
-// multipliers: floor(e / d) = (e * magic) >> 40, exact for e < 2^24 and
-// d < 2^16.
-// Descriptor words: [base ptr (2), dst element offset (2), size, rank, ns,
-//   scale ptrs (2 each), per label k: (extent, magic (2), source stride,
-//   scale strides)]
-__device__ __forceinline__ const void *word_ptr(const int32_t *w) {
-    return (const void *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
-}
-
+// Input materialisation for the fused kernel, as its own launch (one wave
+// per entry); used for networks whose inputs are too large to materialise
+// inside their fused workgroup.
 template <typename T, typename TIN>
 __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
-    // one wave per entry (a chunk of one load); descriptor words are
-    // uniform (scalar loads)
-    const FPrepEntry en = entries[blockIdx.x];
-    const int32_t *p = en.desc;
-    const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
-    const int size = p[4], rk = p[5], ns = p[6];
-    const int32_t *per = p + 7 + 2 * ns;
-    const int W = 4 + ns;
-    const TIN *src = (const TIN *)word_ptr(p);
-    T *o = (T *)en.ws + dst_off;
-    const TIN *sp[kMaxScalesLoad];
-#pragma unroll
-    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
-    const int e_end = min(size, en.e0 + kFPrepChunk);
-    for (int e = en.e0 + threadIdx.x; e < e_end; e += 64) {
-        uint32_t rem = (uint32_t)e;
-        int so = 0;
-        int sc[kMaxScalesLoad];
-#pragma unroll
-        for (int q = 0; q < kMaxScalesLoad; ++q) sc[q] = 0;
-#pragma unroll
-        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
-            if (k < rk) {
-                const int32_t *pk = per + k * W;
-                const uint64_t magic = ((uint64_t)(uint32_t)pk[2] << 32) | (uint32_t)pk[1];
-                const uint32_t quo = (uint32_t)(((uint64_t)rem * magic) >> 40);
-                const int dgt = (int)(rem - quo * (uint32_t)pk[0]);
-                rem = quo;
-                so += dgt * pk[3];
-#pragma unroll
-                for (int q = 0; q < kMaxScalesLoad; ++q)
-                    if (q < ns) sc[q] += dgt * pk[4 + q];
-            }
-        }
-        T v = Ld<T, TIN>::get(src + so);
-#pragma unroll
-        for (int q = 0; q < kMaxScalesLoad; ++q)
-            if (q < ns) v *= Ld<T, TIN>::get(sp[q] + sc[q]);
-        o[e] = v;
-    }
+    fprep_entry<T, TIN>(entries[blockIdx.x], threadIdx.x);
 }
 
 // Device clock read into *dst (one thread).

@@ -49,11 +49,16 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
                        hipStream_t st);
 
 // Fused whole-network kernel.
+struct FPrepEntry;
 struct FusedDesc {
     const int32_t *prog;
     const int2 *tab;
     const void *const *in;  // device array of input pointers
-    void *scratch;          // spill space for values that do not fit LDS
+    void *scratch;          // workspace: materialised inputs, then spill space
+    // inputs the workgroup materialises itself before its program
+    // (n_fprep = 0: already done by a separate launch)
+    const FPrepEntry *fprep;
+    int32_t n_fprep;
 };
 // nets[order[b]] is run by workgroup b; outs[net] receives its result.
 // stamps (optional): [2*net] start, [2*net+1] end, 100 MHz ticks.

@@ -103,6 +103,8 @@ def load_library():
         "htn_set_model": (I32, [P, P]),
         "htn_step_features": (I32, [P, f32p, I32, i32p]),
         "htn_autotune": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P, i32p, i32p, f32p]),
+        "htn_batch_set_event_timing": (I32, [P, I32]),
+        "htn_batch_launch_ms": (I32, [P, f32p, f32p, i32p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -342,6 +344,18 @@ def htn_batch_phase_times(batch: Batch) -> np.ndarray:
     t = np.zeros(len(batch.nets) * batch.max_phases, dtype=np.int64)
     _check(load_library().htn_batch_phase_times(batch.handle, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
     return t.reshape(len(batch.nets), batch.max_phases)
+
+
+def htn_batch_set_event_timing(batch: Batch, on: bool) -> None:
+    _check(load_library().htn_batch_set_event_timing(batch.handle, 1 if on else 0))
+
+
+def htn_batch_launch_ms(batch: Batch):
+    """(mean prep-launch ms, mean fused-launch ms, runs) since the last read."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    k = ctypes.c_int32()
+    _check(load_library().htn_batch_launch_ms(batch.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(k)))
+    return float(a.value), float(b.value), int(k.value)
 
 
 def htn_batch_destroy(batch: Batch) -> None:
