@@ -170,7 +170,9 @@ typedef enum {
     HTN_OPT_EXEC = 0,              /* htn_exec_mode                            */
     HTN_OPT_MAX_INTERMEDIATE = 1,  /* cap on intermediate elements (default 2^31-1) */
     HTN_OPT_FUSED_LDS_BYTES = 2,   /* LDS budget of the fused kernel (default 65536) */
-    HTN_OPT_MFMA = 3,              /* 1: allow matrix-core steps (default), 0: VALU only */
+    HTN_OPT_MFMA = 3,              /* 1: allow matrix cores (default): GEMM steps of the per-step
+                                      executor, 16x16-block tiled steps of the fused kernel;
+                                      0: VALU only */
     HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
     HTN_OPT_PATH_SEED = 5,         /* seed of the path sampler (default 0) */
     HTN_OPT_FUSED_THREADS = 6      /* threads per network in the fused kernel: 64, 256 (default) or 512 */
@@ -275,9 +277,10 @@ void htn_batch_destroy(htn_batch_t batch);
  *   0 lg(1 + multiplications)  1 lg(outputs)  2 lg(summed terms per output)
  *   3 lg(size of operand A)    4 lg(size of operand B; 1 if unary)
  *   5-7 lg(M), lg(N), lg(K) of a register-tiled step (0 otherwise)
- *   8 lg(outputs per thread of a tiled step)   9 lg(lanes per output)
+ *   8 lg(outputs per thread of a VALU-tiled step)   9 lg(lanes per output)
  *   10 tiled step  11 one lane per output  12 several lanes per output
- *   13 whole workgroup per output  14 matrix-core step  15 unary step
+ *   13 whole workgroup per output  14 matrix cores (GEMM step or
+ *   matrix-core tiled step)  15 unary step
  *   16 final step  17-19 operand A / operand B / result outside LDS
  *   20 lg(1 + 16-byte chunks the fused kernel copies during the step)
  *   21 fused executor  22 FP64 compute  23 element bytes / 8

@@ -36,12 +36,13 @@ void step_features(const Net &n, std::vector<float> &rows) {
         f[3] = lg((double)P.values[s.a].size);
         f[4] = s.b >= 0 ? lg((double)P.values[s.b].size) : 0.0f;
         const bool tile = fused && s.tile;
-        const bool mfma = !fused && s.mfma;
+        // matrix cores: a per-step GEMM, or a fused tiled step in MFMA mode
+        const bool mfma = (!fused && s.mfma) || (tile && s.TM == 0);
         if (tile) {
             f[5] = lg((double)s.tM);
             f[6] = lg((double)s.tN);
             f[7] = lg((double)s.tK);
-            f[8] = lg((double)(s.TM * s.TN));
+            f[8] = lg((double)std::max(1, s.TM * s.TN));
         }
         const int R = fused ? s.r_fused : s.r_global;
         if (!tile && !mfma) f[9] = lg((double)R);

@@ -281,9 +281,84 @@ __device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int
     }
 }
 
+// Matrix-core tiled step (same contract as tstep): 16x16 output blocks,
+// one wave per block, K in slices of 4 through the FP64 or FP32 16x16x4
+// MFMA with accumulation in the compute type.  Lane l supplies
+// A(m = 16 bm + l % 16, k = k0 + l / 16) and B(n = 16 bn + l % 16, same k)
+// (zero outside the matrices) and receives column l % 16 of the block in
+// rows FMfma<T>::row(l, r), r = 0..3.
+template <typename T>
+struct FMfma;
+template <>
+struct FMfma<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ static acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct FMfma<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ static acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <int BLK, typename T, typename TOUT>
+__device__ __forceinline__ void mstep(const T *A, const T *B, TOUT *C, const int32_t *dgm, int nm, const int32_t *dgn,
+                                      int nn_l, int M, int N, int K) {
+    typedef FMfma<T> Op;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nbm = (M + 15) >> 4, nbn = (N + 15) >> 4;
+    for (int blk = wave; blk < nbm * nbn; blk += BLK / 64) {
+        const int bm = blk / nbn, bn = blk - bm * nbn;
+        const int m = bm * 16 + li, n = bn * 16 + li;
+        const bool mok = m < M, nok = n < N;
+        const T *a = A + (mok ? m : 0);
+        const T *b = B + (nok ? n : 0);
+        typename Op::acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        int k0 = 0;
+        for (; k0 + 8 <= K; k0 += 8) {
+            const int k = k0 + lk;
+            T a0 = a[k * M], b0 = b[k * N], a1 = a[(k + 4) * M], b1 = b[(k + 4) * N];
+            a0 = mok ? a0 : T(0);
+            a1 = mok ? a1 : T(0);
+            b0 = nok ? b0 : T(0);
+            b1 = nok ? b1 : T(0);
+            acc0 = Op::mma(a0, b0, acc0);
+            acc1 = Op::mma(a1, b1, acc1);
+        }
+        for (; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const bool kok = k < K;
+            T a0 = a[(kok ? k : 0) * M], b0 = b[(kok ? k : 0) * N];
+            a0 = (mok && kok) ? a0 : T(0);
+            b0 = (nok && kok) ? b0 : T(0);
+            acc0 = Op::mma(a0, b0, acc0);
+        }
+        if (nok) {
+            const int cn = digit_offset((uint32_t)n, dgn, nn_l);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int mm = bm * 16 + Op::row(lane, r);
+                if (mm < M) C[digit_offset((uint32_t)mm, dgm, nm) + cn] = st_cvt<TOUT>(acc0[r] + acc1[r]);
+            }
+        }
+    }
+}
+
 template <int BLK, typename T, typename ACC, typename TOUT>
 __device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int32_t *tcm, int nm,
                                           const int32_t *tcn, int nn_l, int M, int N, int K, int TM, int TN, int GX) {
+    if constexpr (std::is_same<T, ACC>::value) {
+        if (TM == 0) {  // matrix-core mode
+            mstep<BLK, T, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K);
+            return;
+        }
+    }
     switch (TM * 8 + TN) {
         case 9: tstep<BLK, T, ACC, 1, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
         case 10: tstep<BLK, T, ACC, 1, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
@@ -298,6 +373,8 @@ __device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const
 }
 
 // OP_TSTEP: [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M, digits of N]
+// (TM = 0: matrix-core mode, planned only where the accumulator is the
+// compute type)
 template <int BLK, typename T, int FM>
 __device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, void *out) {
     const int la = p[1], lb = p[2], lc = p[3];

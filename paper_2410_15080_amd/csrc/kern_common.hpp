@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -87,6 +88,16 @@ __device__ __forceinline__ void lane_reduce(ACC &s, ACC &c, int width) {
     }
 }
 
+// Value of an input element in the compute type (bf16 bit patterns widen
+// to float).
+template <typename T, typename TIN>
+__device__ __forceinline__ T to_compute(TIN x) {
+    if constexpr (std::is_same<TIN, bf16_t>::value)
+        return (T)bf2f(x);
+    else
+        return (T)x;
+}
+
 // Input materialisation of fused networks.  A descriptor (in the fused
 // image) gives the input's device address, its destination in the network's
 // workspace and the digit form of its planned layout: element e of the
@@ -98,24 +109,28 @@ __device__ __forceinline__ void lane_reduce(ACC &s, ACC &c, int width) {
 // Descriptor words: [base ptr (2), dst element offset (2), size, rank, ns,
 //   scale ptrs (2 each), per label k: (extent, magic (2), source stride,
 //   scale strides)]
-__device__ __forceinline__ const void *word_ptr(const int32_t *w) {
-    return (const void *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
-}
-
 // One wave materialises one entry (a chunk of kFPrepChunk elements of one
-// load); lane = lane index 0..63.  Descriptor words are wave-uniform.
+// load); lane = lane index 0..63.  Descriptor words are wave-uniform and
+// read-only: they are read through the constant address space (scalar
+// loads), and the tensors through the global address space.
+typedef const int32_t __attribute__((address_space(4))) c_int32;
+
 template <typename T, typename TIN>
 __device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
-    const int32_t *p = en.desc;
+    typedef const TIN __attribute__((address_space(1))) g_tin;
+    const c_int32 *p = (const c_int32 *)en.desc;
     const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
     const int size = p[4], rk = p[5], ns = p[6];
-    const int32_t *per = p + 7 + 2 * ns;
+    const c_int32 *per = p + 7 + 2 * ns;
     const int W = 4 + ns;
-    const TIN *src = (const TIN *)word_ptr(p);
+    auto ptr_at = [&](const c_int32 *w) {
+        return (const g_tin *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
+    };
+    const g_tin *src = ptr_at(p);
     T *o = (T *)en.ws + dst_off;
-    const TIN *sp[kMaxScalesLoad];
+    const g_tin *sp[kMaxScalesLoad];
 #pragma unroll
-    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? (const TIN *)word_ptr(p + 7 + 2 * q) : nullptr;
+    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? ptr_at(p + 7 + 2 * q) : nullptr;
     const int e_end = min(size, en.e0 + kFPrepChunk);
     // four elements per lane at a time, so their gathers are in flight
     // together
@@ -131,7 +146,7 @@ __device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
 #pragma unroll
             for (int k = kMaxRankLoad - 1; k >= 0; --k) {
                 if (k < rk) {
-                    const int32_t *pk = per + k * W;
+                    const c_int32 *pk = per + k * W;
                     const uint64_t magic = ((uint64_t)(uint32_t)pk[2] << 32) | (uint32_t)pk[1];
                     const uint32_t quo = (uint32_t)(((uint64_t)rem * magic) >> 40);
                     const int dgt = (int)(rem - quo * (uint32_t)pk[0]);
@@ -145,12 +160,12 @@ __device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
         }
         T v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = Ld<T, TIN>::get(src + so[u]);
+        for (int u = 0; u < 4; ++u) v[u] = to_compute<T>(src[so[u]]);
 #pragma unroll
         for (int q = 0; q < kMaxScalesLoad; ++q)
             if (q < ns) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] *= Ld<T, TIN>::get(sp[q] + sc[u][q]);
+                for (int u = 0; u < 4; ++u) v[u] *= to_compute<T>(sp[q][sc[u][q]]);
             }
 #pragma unroll
         for (int u = 0; u < 4; ++u)

@@ -680,6 +680,15 @@ void build_plan(Net &n) {
             digits(s.t_gm, cm, s.c_digits_m);
             digits(s.t_gn, cn, s.c_digits_n);
             choose_tile(s, n.fused_threads);
+            // matrix-core mode (TM = 0): 16x16 blocks, one wave each, when
+            // the blocks are mostly filled and the accumulator is the
+            // compute type (not an FP64 final sum over FP32 data)
+            const bool acc_is_compute =
+                !s.final_step || n.compute == HTN_F64 || n.final_sum == HTN_SUM_PLAIN;
+            if (n.allow_mfma && acc_is_compute && s.tM >= 16 && s.tN >= 16 && s.tK >= 4) {
+                s.TM = 0;
+                s.TN = 0;
+            }
         }
         if (s.mfma) {
             // pack A -> [batch][M][K], B -> [batch][N][K]: unary permutes
