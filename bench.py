@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=None, help="networks per batch (default per workload)")
     ap.add_argument("--dtype", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--lds", type=int, default=65536)
-    ap.add_argument("--threads", type=int, default=256, choices=[64, 256])
+    ap.add_argument("--threads", type=int, default=256, choices=[64, 256, 512])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -69,7 +69,11 @@ def parse():
 # on a plain copy (profiles/ holds the summaries and commands).  Each record
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 22 760 x 2048 B, WRITE_SIZE 4 919 x 1024 B
+    "k_fused_grid": {"read_bytes": 46_612_480, "write_bytes": 5_037_056, "sources": "e9ddd8f5e0eb3c16",
+                     "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
+}
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
                    "paper_2410_15080_amd/csrc/fused_b256.hip", "paper_2410_15080_amd/csrc/planner.cpp"]
 
