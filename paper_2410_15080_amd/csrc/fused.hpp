@@ -581,12 +581,15 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
         if (dst2 >= 0) lds4[dst2] = stg2;
         if (dst3 >= 0) lds4[dst3] = stg3;
         if (tot > kPrefetch * BLK) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < nc && starts[k + 1] > kPrefetch * BLK) {
-                    const int skip = max(0, kPrefetch * BLK - starts[k]);
-                    copy_chunks<BLK>(cps[k].src + skip, lds4 + cps[k].dst + skip, cps[k].n - skip);
-                }
+            // rare: re-read the copy ops (their decoded form is not kept
+            // live across the step) and copy the chunks beyond the staged ones
+            int start = 0;
+            for (const int32_t *r = p + step_len; r != q; r += 5) {
+                const CopyOp c = decode_copy(r, gimg, (const unsigned char *)d.scratch);
+                const int skip = max(0, kPrefetch * BLK - start);
+                if (skip < c.n) copy_chunks<BLK>(c.src + skip, lds4 + c.dst + skip, c.n - skip);
+                start += c.n;
+            }
         }
         p = q;
     }
