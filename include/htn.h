@@ -335,7 +335,8 @@ htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, i
  * kernel step of each fused net: times[i * capacity + q] for net i and
  * kernel step q < capacity, NaN where the step was not recorded (nets run
  * step by step, steps beyond max_phases).  A fused step's duration is that
- * of its phase: its arithmetic and the copies issued for the next step.  */
+ * of its phase (its arithmetic and the copies issued for the next phase),
+ * divided equally among the independent steps that share the phase.     */
 htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacity);
 
 /* htn_autotune — pick the fused kernel's workgroup size and LDS budget for

@@ -75,10 +75,10 @@ struct DeviceState {
 // per-workgroup prologues.
 static constexpr int64_t kInKernelPrepMax = 65536;
 
-static kern::FusedDesc fused_desc(const DeviceState &D, bool in_kernel_prep) {
+static kern::FusedDesc fused_desc(const DeviceState &D, bool in_kernel_prep, bool lds_only) {
     const bool k = in_kernel_prep && D.fprep_in_kernel;
     return kern::FusedDesc{D.d_prog, D.d_tab, (const void *const *)D.d_inptrs, D.d_ws, k ? D.d_fprep : nullptr,
-                           k ? (int32_t)D.fprep.size() : 0};
+                           k ? (int32_t)D.fprep.size() : 0, lds_only ? 1 : 0};
 }
 
 struct htn_net : public Net {};
@@ -325,7 +325,7 @@ static void upload_plan(Net &n) {
     int64_t in_elems = 0;
     for (const LoadPlan &lp : P.loads) in_elems += lp.size;
     D.fprep_in_kernel = !D.fprep.empty() && in_elems <= kInKernelPrepMax;
-    kern::FusedDesc fd = fused_desc(D, true);
+    kern::FusedDesc fd = fused_desc(D, true, P.fused_lds_only);
     dfree(D.d_fdesc);
     D.d_fdesc = dalloc<kern::FusedDesc>(1);
     HIP_TRY(hipMemcpy(D.d_fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
@@ -771,7 +771,7 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
             Net &net = *nets[i];
             ensure_device(net);
             b->versions.push_back(net.plan_version);
-            desc[i] = fused_desc(*net.dev, false);
+            desc[i] = fused_desc(*net.dev, false, net.plan.fused_lds_only);
             if (!use_fused_in_batch(net) || net.plan.mults > straggler) {
                 b->step_nets.push_back(i);
                 continue;
@@ -1023,12 +1023,21 @@ htn_status htn_batch_step_times(htn_batch_t b, float *times, int32_t capacity) {
         for (int i : g.idx) {
             const Plan &P = b->nets[i]->plan;
             const int64_t *t = ph.data() + (size_t)i * mp;
+            std::vector<int> per_phase;  // steps sharing each phase
+            for (int k : P.kernel_steps) {
+                const int f = P.steps[k].f_phase;
+                if (f >= 0) {
+                    if ((int)per_phase.size() <= f) per_phase.resize(f + 1, 0);
+                    per_phase[f]++;
+                }
+            }
             for (int q = 0; q < (int)P.kernel_steps.size() && q < capacity; ++q) {
                 const int f = P.steps[P.kernel_steps[q]].f_phase;
                 if (f < 0 || f >= mp || t[f] < 0) continue;
                 const int64_t begin = f == 0 ? st[2 * (size_t)i] : t[f - 1];
                 if (begin < 0) continue;
-                times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f;  // 100 MHz ticks -> us
+                // 100 MHz ticks -> us, shared equally by the phase's steps
+                times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f / (float)per_phase[f];
             }
         }
     return HTN_OK;

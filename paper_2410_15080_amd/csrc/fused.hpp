@@ -80,16 +80,18 @@ __device__ __forceinline__ void strided_sum(const T *a0, const T *b0, const int2
 }
 
 template <int BLK, typename T, typename ACC, bool COMP, bool UNARY, typename TOUT>
+// Threads tid = 0..nthr-1 of the step's waves run it; R == nthr (the whole
+// workgroup per output) is planned only when the step owns the workgroup
+// (nthr == BLK), since it synchronises every wave.
 __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int2 *__restrict__ tab,
-                                      const int32_t *g, int R, ACC *scratch) {
+                                      const int32_t *g, int R, ACC *scratch, const int tid, const int nthr) {
     const int n_ohi = g[0], n_olo = g[1], n_shi = g[2], n_slo = g[3];
     const int2 *toh = tab + g[4];
     const int2 *tol = tab + g[5];
     const int2 *tsh = tab + g[6];
     const int2 *tsl = tab + g[7];
     const int n_out = n_ohi * n_olo;
-    const int tid = threadIdx.x;
-    if (R == BLK) {
+    if (R == BLK && nthr == BLK) {
         // whole workgroup per output (tiny outputs, long sums)
         const int dq = BLK / n_slo, dr = BLK - dq * n_slo;
         for (int o = 0; o < n_out; ++o) {
@@ -118,7 +120,7 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     }
     int log2R = 0;
     while ((1 << log2R) < R) ++log2R;
-    const int groups = BLK >> log2R;
+    const int groups = nthr >> log2R;
     const int gi = tid >> log2R, sub = tid & (R - 1);
     const int dq = R / n_slo, dr = R - dq * n_slo;
     for (int o0 = 0; o0 < n_out; o0 += groups) {
@@ -197,11 +199,11 @@ __device__ __forceinline__ int digit_offset(uint32_t x, const int32_t *dg, int n
 
 template <int BLK, typename T, typename ACC, int TM, int TN, typename TOUT>
 __device__ __forceinline__ void tstep(const T *A, const T *B, TOUT *C, const int32_t *dgm, int nm, const int32_t *dgn,
-                                      int nn_l, int M, int N, int K, int GX) {
+                                      int nn_l, int M, int N, int K, int GX, const int tid, const int nthr) {
     int lgx = 0;
     while ((1 << lgx) < GX) ++lgx;
-    const int GY = BLK >> lgx;
-    const int tx = threadIdx.x & (GX - 1), ty = threadIdx.x >> lgx;
+    const int GY = nthr >> lgx;
+    const int tx = tid & (GX - 1), ty = tid >> lgx;
     const int SM = GX * TM, SN = GY * TN;
     for (int m0 = 0; m0 < M; m0 += SM) {
         if (m0 + tx >= M) break;
@@ -308,12 +310,12 @@ struct FMfma<float> {
 
 template <int BLK, typename T, typename TOUT>
 __device__ __forceinline__ void mstep(const T *A, const T *B, TOUT *C, const int32_t *dgm, int nm, const int32_t *dgn,
-                                      int nn_l, int M, int N, int K) {
+                                      int nn_l, int M, int N, int K, const int tid, const int nthr) {
     typedef FMfma<T> Op;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nbm = (M + 15) >> 4, nbn = (N + 15) >> 4;
-    for (int blk = wave; blk < nbm * nbn; blk += BLK / 64) {
+    for (int blk = wave; blk < nbm * nbn; blk += nthr >> 6) {
         const int bm = blk / nbn, bn = blk - bm * nbn;
         const int m = bm * 16 + li, n = bn * 16 + li;
         const bool mok = m < M, nok = n < N;
@@ -352,52 +354,55 @@ __device__ __forceinline__ void mstep(const T *A, const T *B, TOUT *C, const int
 
 template <int BLK, typename T, typename ACC, typename TOUT>
 __device__ __forceinline__ void tstep_sel(const T *A, const T *B, TOUT *C, const int32_t *tcm, int nm,
-                                          const int32_t *tcn, int nn_l, int M, int N, int K, int TM, int TN, int GX) {
+                                          const int32_t *tcn, int nn_l, int M, int N, int K, int TM, int TN, int GX,
+                                          const int tid, const int nthr) {
     if constexpr (std::is_same<T, ACC>::value) {
         if (TM == 0) {  // matrix-core mode
-            mstep<BLK, T, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K);
+            mstep<BLK, T, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, tid, nthr);
             return;
         }
     }
     switch (TM * 8 + TN) {
-        case 9: tstep<BLK, T, ACC, 1, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 10: tstep<BLK, T, ACC, 1, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 12: tstep<BLK, T, ACC, 1, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 17: tstep<BLK, T, ACC, 2, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 18: tstep<BLK, T, ACC, 2, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 20: tstep<BLK, T, ACC, 2, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 33: tstep<BLK, T, ACC, 4, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        case 34: tstep<BLK, T, ACC, 4, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
-        default: tstep<BLK, T, ACC, 4, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX); break;
+        case 9: tstep<BLK, T, ACC, 1, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 10: tstep<BLK, T, ACC, 1, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 12: tstep<BLK, T, ACC, 1, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 17: tstep<BLK, T, ACC, 2, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 18: tstep<BLK, T, ACC, 2, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 20: tstep<BLK, T, ACC, 2, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 33: tstep<BLK, T, ACC, 4, 1, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        case 34: tstep<BLK, T, ACC, 4, 2, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
+        default: tstep<BLK, T, ACC, 4, 4, TOUT>(A, B, C, tcm, nm, tcn, nn_l, M, N, K, GX, tid, nthr); break;
     }
 }
 
-// OP_TSTEP: [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M, digits of N]
+// OP_TSTEP: [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, w0, nw, digits of M, digits of N]
 // (TM = 0: matrix-core mode, planned only where the accumulator is the
 // compute type)
-template <int BLK, typename T, int FM>
-__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, void *out) {
+template <int BLK, typename T, int FM, bool PURE>
+__device__ __forceinline__ void tstep_dispatch(const int32_t *p, T *sm, T *scr, void *out, const int tid,
+                                               const int nthr) {
     const int la = p[1], lb = p[2], lc = p[3];
     const int M = p[4], N = p[5], K = p[6];
     const int TM = p[7], TN = p[8], GX = p[9];
     const bool fin = p[10] != 0;
     const int nm = p[11], nn_l = p[12];
-    const int32_t *tcm = p + 13;
-    const int32_t *tcn = p + 13 + 4 * nm;
+    const int32_t *tcm = p + 15;
+    const int32_t *tcn = p + 15 + 4 * nm;
     typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
-    if (la >= 0 && lb >= 0 && (fin || lc >= 0)) {
+    if (PURE || (la >= 0 && lb >= 0 && (fin || lc >= 0))) {
         if (!fin)
-            tstep_sel<BLK, T, T, T>(sm + la, sm + lb, sm + lc, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, T, T>(sm + la, sm + lb, sm + lc, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX, tid, nthr);
         else
-            tstep_sel<BLK, T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
-    } else {
+            tstep_sel<BLK, T, TO, TO>(sm + la, sm + lb, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX, tid,
+                                      nthr);
+    } else if constexpr (!PURE) {
         const T *A = la >= 0 ? sm + la : scr + (-la - 2);
         const T *B = lb >= 0 ? sm + lb : scr + (-lb - 2);
         if (!fin)
             tstep_sel<BLK, T, T, T>(A, B, lc >= 0 ? sm + lc : scr + (-lc - 2), tcm, nm, tcn, nn_l, M, N, K, TM, TN,
-                                    GX);
+                                    GX, tid, nthr);
         else
-            tstep_sel<BLK, T, TO, TO>(A, B, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX);
+            tstep_sel<BLK, T, TO, TO>(A, B, (TO *)out, tcm, nm, tcn, nn_l, M, N, K, TM, TN, GX, tid, nthr);
     }
 }
 
@@ -445,15 +450,15 @@ __device__ __forceinline__ void copy_chunks(const g_uint4 *src, u32x4 *dst, int 
 // The fused kernel.  A workgroup copies its network's program into LDS and
 // interprets it: COPY moves tables or materialised inputs into LDS,
 // STEP / TSTEP contract two values, SYNC ends a phase.
-template <int BLK, typename T, typename TIN, int FM>
-__global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
-                                               void *const *__restrict__ outs, int64_t *__restrict__ stamps,
-                                               void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
+// The interpreter for one network.  PURE: every operand and result lives
+// in LDS (no workspace-operand paths, so a smaller body with less register
+// pressure).
+template <int BLK, typename T, typename TIN, int FM, bool PURE>
+__device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, void *const *__restrict__ outs,
+                                                     int64_t *__restrict__ stamps, void *out1,
+                                                     int64_t *__restrict__ phase_ticks, int max_phases, int64_t t0) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int net = order ? order[blockIdx.x] : (int)blockIdx.x;
     int phase = 0;
-    const FusedDesc d = nets[net];
-    const int64_t t0 = stamps ? (int64_t)wall_clock64() : 0;
     int32_t *img = reinterpret_cast<int32_t *>(smem);
     // program words (a multiple of four) as 16-byte chunks
     copy_chunks<BLK>((const g_uint4 *)d.prog, (u32x4 *)smem, d.prog[0] / 4);
@@ -490,14 +495,19 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
             p += 5;
             continue;
         }
-        const int step_len = op == OP_TSTEP ? 13 + 4 * (p[11] + p[12]) : 15;
+        // A phase: consecutive step ops (independent steps, each run by its
+        // own waves [w0, w0 + nw)), then the copies for the next phase.
+        auto step_length = [](const int32_t *r) { return r[0] == OP_TSTEP ? 15 + 4 * (r[11] + r[12]) : 17; };
+        const int32_t *const steps0 = p;
+        const int32_t *q = p;
+        while (q[0] == OP_STEP || q[0] == OP_TSTEP) q += step_length(q);
+        const int32_t *const copies0 = q;
         // issue the following copies (next phase's tables and operands):
         // each thread stages up to kPrefetch chunks in registers while the
-        // step runs
+        // steps run
         CopyOp cps[4];
         int starts[5] = {0, 0, 0, 0, 0};
         int nc = 0, tot = 0;
-        const int32_t *q = p + step_len;
         while (nc < 4 && q[0] == OP_COPY) {
             cps[nc] = decode_copy(q, gimg, (const unsigned char *)d.scratch);
             starts[nc] = tot;
@@ -532,45 +542,52 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
             dst2 = dst[2];
             dst3 = dst[3];
         }
-        if (op == OP_TSTEP) {
-            tstep_dispatch<BLK, T, FM>(p, sm, scr, out);
-        } else {
-            // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot]
-            const int2 *itab2 = reinterpret_cast<const int2 *>(slots + p[14] * slot_words);
-            const int la = p[1], lb = p[2], lc = p[3];
+        const int wave = threadIdx.x >> 6;
+        for (const int32_t *op_w = steps0; op_w != copies0; op_w += step_length(op_w)) {
+            const int w0 = op_w[0] == OP_TSTEP ? op_w[13] : op_w[15];
+            const int nw = op_w[0] == OP_TSTEP ? op_w[14] : op_w[16];
+            if (wave < w0 || wave >= w0 + nw) continue;  // wave-uniform
+            const int tid = threadIdx.x - 64 * w0, nthr = 64 * nw;
+            if (op_w[0] == OP_TSTEP) {
+                tstep_dispatch<BLK, T, FM, PURE>(op_w, sm, scr, out, tid, nthr);
+                continue;
+            }
+            // OP_STEP: [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot, w0, nw]
+            const int2 *itab2 = reinterpret_cast<const int2 *>(slots + op_w[14] * slot_words);
+            const int la = op_w[1], lb = op_w[2], lc = op_w[3];
             const bool unary = lb == -1;
-            const bool fin = p[13] != 0;
-            const int R = p[12];
+            const bool fin = op_w[13] != 0;
+            const int R = op_w[12];
             typedef typename std::conditional<FM == FM_INTER, T, double>::type TO;
             constexpr bool CMP = (FM == FM_COMP);
-            if (la >= 0 && (unary || lb >= 0) && (fin || lc >= 0)) {
+            if (PURE || (la >= 0 && (unary || lb >= 0) && (fin || lc >= 0))) {
                 const T *A = sm + la;
                 const T *B = unary ? nullptr : sm + lb;
                 if (!fin) {
                     if (unary)
-                        fstep<BLK, T, T, false, true, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, true, T>(A, B, sm + lc, itab2, op_w + 4, R, (T *)red, tid, nthr);
                     else
-                        fstep<BLK, T, T, false, false, T>(A, B, sm + lc, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, false, T>(A, B, sm + lc, itab2, op_w + 4, R, (T *)red, tid, nthr);
                 } else {
                     if (unary)
-                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, op_w + 4, R, (TO *)red, tid, nthr);
                     else
-                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, op_w + 4, R, (TO *)red, tid, nthr);
                 }
-            } else {
+            } else if constexpr (!PURE) {
                 const T *A = la >= 0 ? sm + la : scr + (-la - 2);
                 const T *B = unary ? nullptr : (lb >= 0 ? sm + lb : scr + (-lb - 2));
                 if (!fin) {
                     T *C = lc >= 0 ? sm + lc : scr + (-lc - 2);
                     if (unary)
-                        fstep<BLK, T, T, false, true, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, true, T>(A, B, C, itab2, op_w + 4, R, (T *)red, tid, nthr);
                     else
-                        fstep<BLK, T, T, false, false, T>(A, B, C, itab2, p + 4, R, (T *)red);
+                        fstep<BLK, T, T, false, false, T>(A, B, C, itab2, op_w + 4, R, (T *)red, tid, nthr);
                 } else {
                     if (unary)
-                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, true, TO>(A, B, (TO *)out, itab2, op_w + 4, R, (TO *)red, tid, nthr);
                     else
-                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, p + 4, R, (TO *)red);
+                        fstep<BLK, T, TO, CMP, false, TO>(A, B, (TO *)out, itab2, op_w + 4, R, (TO *)red, tid, nthr);
                 }
             }
         }
@@ -584,7 +601,7 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
             // rare: re-read the copy ops (their decoded form is not kept
             // live across the step) and copy the chunks beyond the staged ones
             int start = 0;
-            for (const int32_t *r = p + step_len; r != q; r += 5) {
+            for (const int32_t *r = copies0; r != q; r += 5) {
                 const CopyOp c = decode_copy(r, gimg, (const unsigned char *)d.scratch);
                 const int skip = max(0, kPrefetch * BLK - start);
                 if (skip < c.n) copy_chunks<BLK>(c.src + skip, lds4 + c.dst + skip, c.n - skip);
@@ -597,6 +614,19 @@ __global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ net
         stamps[2 * net] = t0;
         stamps[2 * net + 1] = (int64_t)wall_clock64();
     }
+}
+
+template <int BLK, typename T, typename TIN, int FM>
+__global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
+                                               void *const *__restrict__ outs, int64_t *__restrict__ stamps,
+                                               void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
+    const int net = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int64_t t0 = stamps ? (int64_t)wall_clock64() : 0;
+    const FusedDesc d = nets[net];
+    if (d.lds_only)
+        fused_body<BLK, T, TIN, FM, true>(d, net, outs, stamps, out1, phase_ticks, max_phases, t0);
+    else
+        fused_body<BLK, T, TIN, FM, false>(d, net, outs, stamps, out1, phase_ticks, max_phases, t0);
 }
 
 template <int BLK, typename T, typename TIN, int FM>
@@ -620,8 +650,8 @@ static hipError_t go_fused(const FusedDesc *nets, const int32_t *order, void *co
 
 template <int BLK>
 hipError_t launch_fused_blk(const FusedDesc *nets, const int32_t *order, void *const *outs, int64_t *stamps,
-                                   void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes,
-                                   int compute, int fm, hipStream_t st) {
+                            void *out1, int64_t *phase_ticks, int max_phases, int n_blocks, int lds_bytes, int compute,
+                            int fm, hipStream_t st) {
 #define HTN_GO(T, TIN, F) go_fused<BLK, T, TIN, F>(nets, order, outs, stamps, out1, phase_ticks, max_phases, n_blocks, lds_bytes, st)
     if (compute == 0) return fm == FM_COMP ? HTN_GO(double, double, FM_COMP) : HTN_GO(double, double, FM_INTER);
     if (compute == 1) {

@@ -70,6 +70,9 @@ struct StepPlan {
     // stride; floor(x / d) = (x * magic) >> 40.
     std::vector<int32_t> c_digits_m, c_digits_n;
     int TM = 1, TN = 1, GX = 16;  // per-thread tile and thread-grid width
+    // Fused kernel: the waves [f_w0, f_w0 + f_nw) of the workgroup run the
+    // step; steps of one phase are independent and run side by side.
+    int f_w0 = 0, f_nw = 1;
     // Fused-program facts (features of the learned cost model).
     int f_phase = -1;           // phase of the fused kernel that runs the step
     int f_spill = 0;            // bit 0: A, bit 1: B, bit 2: C outside LDS
@@ -116,6 +119,9 @@ struct Plan {
     std::vector<StepPlan> steps;     // path steps + optional synthetic final
     std::vector<Value> values;       // indexed by SSA id
     std::vector<int> kernel_steps;   // indices into steps, execution order
+    // fused kernel: groups of independent kernel steps (positions in
+    // kernel_steps) that run side by side in one phase, in phase order
+    std::vector<std::vector<int>> fused_phases;
     std::vector<LoadPlan> loads;     // inputs needing scaling (by first use)
     std::vector<int32_t> tables;     // flat (x, y) pairs
     int final_value = -1;
@@ -132,6 +138,7 @@ struct Plan {
     bool fused_batch_ok = false;  // batches run the net in the fused launch
     bool fused_possible = false;  // program and table slots fit the LDS budget
     bool fused_pure = false;
+    bool fused_lds_only = false;  // every operand and result of every step in LDS
     int64_t fused_lds_bytes = 0;
     int64_t fused_scratch_bytes = 0;
     std::vector<int32_t> program;

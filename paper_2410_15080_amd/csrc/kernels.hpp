@@ -59,6 +59,7 @@ struct FusedDesc {
     // (n_fprep = 0: already done by a separate launch)
     const FPrepEntry *fprep;
     int32_t n_fprep;
+    int32_t lds_only;  // every operand and result of every step in LDS
 };
 // nets[order[b]] is run by workgroup b; outs[net] receives its result.
 // stamps (optional): [2*net] start, [2*net+1] end, 100 MHz ticks.

@@ -576,6 +576,88 @@ void build_plan(Net &n) {
     for (size_t k = 0; k < P.steps.size(); ++k)
         if (!P.steps[k].absorbed) P.kernel_steps.push_back((int)k);
 
+    // Fused-kernel phases.  A step's level is one more than the levels of
+    // the steps producing its operands (inputs: 0); steps of one level are
+    // independent, so up to W = threads / 64 of them share a phase, each on
+    // its own power-of-two number of waves (more waves to more work).
+    {
+        const int W = std::max(1, n.fused_threads / 64);
+        std::vector<int> level_of(P.values.size(), 0);
+        std::vector<std::vector<int>> by_level;
+        for (size_t q = 0; q < P.kernel_steps.size(); ++q) {
+            StepPlan &s = P.steps[P.kernel_steps[q]];
+            int lv = 0;
+            for (int id : {s.a, s.b})
+                if (id >= 0 && !P.values[id].input) lv = std::max(lv, level_of[id]);
+            lv += 1;
+            if (s.c >= 0) level_of[s.c] = lv;
+            if ((int)by_level.size() < lv) by_level.resize(lv);
+            by_level[lv - 1].push_back((int)q);
+        }
+        // Sharing a phase keeps more values live at once; a phase closes
+        // early when its footprint (intermediates carried over from earlier
+        // phases + the phase's loaded inputs and results) would pass ~70 %
+        // of the LDS budget, so that sharing does not push values out of
+        // LDS.
+        const double es = (double)dtype_size(inter_dtype(n.compute));
+        const double budget = 0.7 * (double)n.fused_lds_budget / es;
+        double carry = 0.0;  // intermediates produced and not yet consumed
+        std::vector<std::vector<int>> groups;
+        for (auto &lv : by_level) {
+            std::vector<int> cur;
+            double foot = 0.0, made = 0.0, used = 0.0;
+            auto close = [&]() {
+                if (cur.empty()) return;
+                groups.push_back(cur);
+                carry += made - used;
+                cur.clear();
+                foot = made = used = 0.0;
+            };
+            for (int q : lv) {
+                const StepPlan &s = P.steps[P.kernel_steps[q]];
+                double in_sz = 0.0, inter_sz = 0.0;
+                for (int id : {s.a, s.b})
+                    if (id >= 0) (P.values[id].input ? in_sz : inter_sz) += (double)P.values[id].size;
+                const double out_sz = s.c >= 0 ? (double)P.values[s.c].size : 0.0;
+                if (!cur.empty() && ((int)cur.size() == W || carry + foot + in_sz + out_sz > budget)) close();
+                cur.push_back(q);
+                foot += in_sz + out_sz;
+                made += out_sz;
+                used += inter_sz;
+            }
+            close();
+        }
+        P.fused_phases.clear();
+        for (auto &g : groups) {
+                std::vector<int> ph = g;
+                // waves: one each, then double the busiest while they fit
+                std::vector<int> nw(ph.size(), 1);
+                int used = (int)ph.size();
+                for (;;) {
+                    int best = -1;
+                    double bw = -1.0;
+                    for (size_t j = 0; j < ph.size(); ++j) {
+                        const double w = P.steps[P.kernel_steps[ph[j]]].mults / nw[j];
+                        if (used + nw[j] <= W && w > bw) {
+                            bw = w;
+                            best = (int)j;
+                        }
+                    }
+                    if (best < 0) break;
+                    used += nw[best];
+                    nw[best] *= 2;
+                }
+                int w0 = 0;
+                for (size_t j = 0; j < ph.size(); ++j) {
+                    StepPlan &s = P.steps[P.kernel_steps[ph[j]]];
+                    s.f_w0 = w0;
+                    s.f_nw = nw[j];
+                    w0 += nw[j];
+                }
+                P.fused_phases.push_back(ph);
+            }
+    }
+
     // Layout pass.  Each value is consumed by exactly one kernel step, so its
     // physical label order can be chosen for that consumer: operands of a
     // register-tiled step are laid out [K][M] and [K][N] with the same K
@@ -612,7 +694,7 @@ void build_plan(Net &n) {
         if (!ok) continue;
         if (M.size() > 8 || Nn.size() > 8) continue;  // digit descriptors hold up to 8 labels
         const int64_t mM = (int64_t)prod_dims(n, M), nN = (int64_t)prod_dims(n, Nn);
-        if (mM * nN < n.fused_threads) continue;  // fewer outputs than threads: split the sums instead
+        if (mM * nN < 64 * s.f_nw) continue;  // fewer outputs than threads: split the sums instead
         K = s.sum_labels;
         std::sort(K.begin(), K.end());
         std::sort(M.begin(), M.end());
@@ -679,7 +761,7 @@ void build_plan(Net &n) {
             };
             digits(s.t_gm, cm, s.c_digits_m);
             digits(s.t_gn, cn, s.c_digits_n);
-            choose_tile(s, n.fused_threads);
+            choose_tile(s, 64 * s.f_nw);
             // matrix-core mode (TM = 0): 16x16 blocks, one wave each, when
             // the blocks are mostly filled and the accumulator is the
             // compute type (not an FP64 final sum over FP32 data)
@@ -709,11 +791,12 @@ void build_plan(Net &n) {
         }
         s.n_out = s.n_ohi * s.n_olo;
         s.n_sum = s.n_shi * s.n_slo;
-        // fused kernel: lanes per output
-        const int fth = n.fused_threads;
+        // fused kernel: lanes per output (the whole-workgroup mode needs the
+        // step to own the workgroup: it synchronises all of it)
+        const int fth = 64 * s.f_nw;
         if (s.n_out >= fth) {
             s.r_fused = 1;
-        } else if (s.n_out <= 2 && s.n_sum >= 512 && fth > 64) {
+        } else if (s.n_out <= 2 && s.n_sum >= 512 && fth > 64 && fth == n.fused_threads) {
             s.r_fused = fth;  // whole block per output
         } else {
             int r = std::min<int64_t>(64, pow2floor(fth / s.n_out));
@@ -832,34 +915,34 @@ void build_plan(Net &n) {
     {
         const int64_t es = dtype_size(inter_dtype(n.compute));
         const auto &ks = P.kernel_steps;
-        // step tables, each step's block padded to 16 bytes
+        // step tables: one block per phase (the concatenated tables of its
+        // table-driven steps, each padded to 16 bytes); a step's table
+        // offsets (rel) are relative to its phase's block
+        const auto &phs = P.fused_phases;
         std::vector<int32_t> gtab;
-        std::vector<int64_t> tab_off(ks.size()), tab_words(ks.size());
+        std::vector<int64_t> tab_off(phs.size()), tab_words(phs.size());
         std::vector<std::vector<int32_t>> rel(ks.size());
         int64_t slot_words = 4;
-        for (size_t q = 0; q < ks.size(); ++q) {
-            const StepPlan &s = P.steps[ks[q]];
-            tab_off[q] = (int64_t)gtab.size();
-            auto put_x = [&](int64_t pair_off, int64_t count) {
-                const int32_t o = (int32_t)(gtab.size() - tab_off[q]);
-                for (int64_t e = 0; e < count; ++e) gtab.push_back(P.tables[2 * (pair_off + e)]);
-                return o;
-            };
-            auto put_pairs = [&](int64_t pair_off, int64_t count) {
-                if ((gtab.size() - tab_off[q]) % 2) gtab.push_back(0);
-                const int32_t o = (int32_t)((gtab.size() - tab_off[q]) / 2);
-                for (int64_t e = 0; e < 2 * count; ++e) gtab.push_back(P.tables[2 * pair_off + e]);
-                return o;
-            };
-            if (s.tile) {
-                rel[q] = {0, 0};  // offsets computed from digits: no tables
-            } else {
-                rel[q] = {put_pairs(s.t_ohi, s.n_ohi), put_pairs(s.t_olo, s.n_olo), put_pairs(s.t_shi, s.n_shi),
-                          put_pairs(s.t_slo, s.n_slo)};
+        for (size_t ph = 0; ph < phs.size(); ++ph) {
+            tab_off[ph] = (int64_t)gtab.size();
+            for (int q : phs[ph]) {
+                const StepPlan &s = P.steps[ks[q]];
+                auto put_pairs = [&](int64_t pair_off, int64_t count) {
+                    if ((gtab.size() - tab_off[ph]) % 2) gtab.push_back(0);
+                    const int32_t o = (int32_t)((gtab.size() - tab_off[ph]) / 2);
+                    for (int64_t e = 0; e < 2 * count; ++e) gtab.push_back(P.tables[2 * pair_off + e]);
+                    return o;
+                };
+                if (s.tile) {
+                    rel[q] = {0, 0, 0, 0};  // offsets computed from digits: no tables
+                } else {
+                    rel[q] = {put_pairs(s.t_ohi, s.n_ohi), put_pairs(s.t_olo, s.n_olo), put_pairs(s.t_shi, s.n_shi),
+                              put_pairs(s.t_slo, s.n_slo)};
+                }
+                while (gtab.size() % 4) gtab.push_back(0);
             }
-            while (gtab.size() % 4) gtab.push_back(0);
-            tab_words[q] = (int64_t)gtab.size() - tab_off[q];
-            slot_words = std::max(slot_words, tab_words[q]);
+            tab_words[ph] = (int64_t)gtab.size() - tab_off[ph];
+            slot_words = std::max(slot_words, tab_words[ph]);
         }
         slot_words = (slot_words + 3) / 4 * 4;
 
@@ -919,46 +1002,52 @@ void build_plan(Net &n) {
             std::vector<int32_t> w;
         };
         std::vector<OpRec> seq;
-        auto copies_of_step = [&](size_t q) {
+        auto copies_of_phase = [&](size_t ph) {
             OpRec t;
             t.kind = OP_COPY;
-            t.q = (int)q;
+            t.q = (int)ph;
             // [kind 0: image words, src chunk, chunks, dst chunk]
-            t.w = {OP_COPY, 0, (int32_t)(tab_off[q] / 4), (int32_t)(tab_words[q] / 4), 0};
-            if (tab_words[q] > 0) seq.push_back(t);
-            const StepPlan &s = P.steps[ks[q]];
-            for (int id : {s.a, s.b})
-                if (id >= 0 && P.values[id].input) {
-                    OpRec r;
-                    r.kind = OP_COPY;
-                    r.value = id;
-                    r.w = {OP_COPY, 1, 0, 0, 0};
-                    seq.push_back(r);
-                }
-        };
-        if (!ks.empty()) copies_of_step(0);
-        seq.push_back(OpRec{OP_SYNC, -1, -1, -1, {OP_SYNC}});
-        for (size_t q = 0; q < ks.size(); ++q) {
-            const StepPlan &s = P.steps[ks[q]];
-            OpRec r;
-            r.step = ks[q];
-            r.q = (int)q;
-            const int32_t slot = (int32_t)(q % 2);
-            if (s.tile) {
-                r.kind = OP_TSTEP;
-                // [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, digits of M (4 each), digits of N]
-                r.w = {OP_TSTEP, 0, 0, 0, (int32_t)s.tM, (int32_t)s.tN, (int32_t)s.tK, s.TM, s.TN, s.GX,
-                       s.final_step ? 1 : 0, (int32_t)(s.c_digits_m.size() / 4), (int32_t)(s.c_digits_n.size() / 4)};
-                r.w.insert(r.w.end(), s.c_digits_m.begin(), s.c_digits_m.end());
-                r.w.insert(r.w.end(), s.c_digits_n.begin(), s.c_digits_n.end());
-                (void)slot;
-            } else {
-                r.kind = OP_STEP;
-                r.w = {OP_STEP, 0, 0, 0, (int32_t)s.n_ohi, (int32_t)s.n_olo, (int32_t)s.n_shi, (int32_t)s.n_slo,
-                       rel[q][0], rel[q][1], rel[q][2], rel[q][3], s.r_fused, s.final_step ? 1 : 0, slot};
+            t.w = {OP_COPY, 0, (int32_t)(tab_off[ph] / 4), (int32_t)(tab_words[ph] / 4), 0};
+            if (tab_words[ph] > 0) seq.push_back(t);
+            for (int q : phs[ph]) {
+                const StepPlan &s = P.steps[ks[q]];
+                for (int id : {s.a, s.b})
+                    if (id >= 0 && P.values[id].input) {
+                        OpRec r;
+                        r.kind = OP_COPY;
+                        r.value = id;
+                        r.w = {OP_COPY, 1, 0, 0, 0};
+                        seq.push_back(r);
+                    }
             }
-            seq.push_back(r);
-            if (q + 1 < ks.size()) copies_of_step(q + 1);
+        };
+        if (!phs.empty()) copies_of_phase(0);
+        seq.push_back(OpRec{OP_SYNC, -1, -1, -1, {OP_SYNC}});
+        for (size_t ph = 0; ph < phs.size(); ++ph) {
+            for (int q : phs[ph]) {
+                const StepPlan &s = P.steps[ks[q]];
+                OpRec r;
+                r.step = ks[q];
+                r.q = q;
+                const int32_t slot = (int32_t)(ph % 2);
+                if (s.tile) {
+                    r.kind = OP_TSTEP;
+                    // [a, b, c, M, N, K, TM, TN, GX, final, nm, nn, w0, nw, digits of M (4 each), digits of N]
+                    r.w = {OP_TSTEP, 0, 0, 0, (int32_t)s.tM, (int32_t)s.tN, (int32_t)s.tK, s.TM, s.TN, s.GX,
+                           s.final_step ? 1 : 0, (int32_t)(s.c_digits_m.size() / 4),
+                           (int32_t)(s.c_digits_n.size() / 4), s.f_w0, s.f_nw};
+                    r.w.insert(r.w.end(), s.c_digits_m.begin(), s.c_digits_m.end());
+                    r.w.insert(r.w.end(), s.c_digits_n.begin(), s.c_digits_n.end());
+                } else {
+                    r.kind = OP_STEP;
+                    // [a, b, c, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, final, slot, w0, nw]
+                    r.w = {OP_STEP, 0, 0, 0, (int32_t)s.n_ohi, (int32_t)s.n_olo, (int32_t)s.n_shi, (int32_t)s.n_slo,
+                           rel[q][0], rel[q][1], rel[q][2], rel[q][3], s.r_fused, s.final_step ? 1 : 0, slot,
+                           s.f_w0, s.f_nw};
+                }
+                seq.push_back(r);
+            }
+            if (ph + 1 < phs.size()) copies_of_phase(ph + 1);
             seq.push_back(OpRec{OP_SYNC, -1, -1, -1, {OP_SYNC}});
         }
         int64_t prog_words = 8 + 1;
@@ -998,6 +1087,7 @@ void build_plan(Net &n) {
         int n_ops = 0;
         std::vector<int> pending;
         int phase = 0, last_step = -1;
+        bool lds_only = true;
         for (auto &r : seq) {
             if (r.kind == OP_COPY && r.value >= 0) {
                 const int64_t sz = P.values[r.value].size;
@@ -1025,6 +1115,7 @@ void build_plan(Net &n) {
                 r.w[3] = (int32_t)cl;
                 pending.push_back(s.a);
                 pending.push_back(s.b);
+                if (loc[s.a] < 0 || (s.b >= 0 && loc[s.b] < 0) || (!s.final_step && cl < 0)) lds_only = false;
                 s.f_phase = phase;
                 s.f_spill = (loc[s.a] < 0 ? 1 : 0) | (s.b >= 0 && loc[s.b] < 0 ? 2 : 0) |
                             (!s.final_step && cl < 0 ? 4 : 0);
@@ -1059,6 +1150,7 @@ void build_plan(Net &n) {
         P.program = std::move(prog);
         P.ptr_slots = P.fused_in_ptr_slots;
         P.fused_pure = glb_ff.peak <= inputs_end;
+        P.fused_lds_only = lds_only;
         bool has_mfma = false;
         for (const auto &st : P.steps) has_mfma |= st.mfma != 0;
         // The fused kernel needs its program and table slots in LDS.  Dense
@@ -1092,7 +1184,8 @@ std::string plan_json(const Net &n) {
       << ",\"elem_bytes\":" << dtype_size(inter_dtype(n.compute))
       << ",\"n_absorbed\":" << P.n_absorbed << ",\"fused_ok\":" << (P.fused_ok ? "true" : "false")
       << ",\"fused_batch_ok\":" << (P.fused_batch_ok ? "true" : "false")
-      << ",\"fused_pure\":" << (P.fused_pure ? "true" : "false") << ",\"fused_lds_bytes\":" << P.fused_lds_bytes
+      << ",\"fused_pure\":" << (P.fused_pure ? "true" : "false")
+      << ",\"fused_lds_only\":" << (P.fused_lds_only ? "true" : "false") << ",\"fused_lds_bytes\":" << P.fused_lds_bytes
       << ",\"fused_scratch_bytes\":" << P.fused_scratch_bytes << ",\"ws_bytes\":" << P.ws_bytes
       << ",\"final_value\":" << P.final_value << ",\"n_table_entries\":" << P.tables.size() / 2
       << ",\"steps\":[";

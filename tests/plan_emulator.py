@@ -66,7 +66,21 @@ def _tile_step(tab, s, A, B, out_size):
 OP_END, OP_STEP, OP_SYNC, OP_TSTEP, OP_COPY = 0, 2, 3, 4, 6
 
 
-def run_program(w, prog, n_loads, elem_bytes=8):
+def _check_waves(ranges, threads):
+    """Steps sharing a phase run on disjoint, power-of-two wave ranges inside
+    the workgroup; a whole-workgroup reduction owns the workgroup."""
+    W = threads // 64
+    used = set()
+    for w0, nw, block_mode in ranges:
+        assert nw >= 1 and nw & (nw - 1) == 0 and 0 <= w0 and w0 + nw <= W, (w0, nw, W)
+        waves = set(range(w0, w0 + nw))
+        assert not (waves & used), ranges
+        used |= waves
+        if block_mode:
+            assert nw == W and len(ranges) == 1, ranges
+
+
+def run_program(w, prog, n_loads, elem_bytes=8, threads=None):
     """Interpret the fused path's device image (same encoding the kernels
     read): the prep kernel's load descriptors materialise the inputs into
     the workspace, then the fused program copies and contracts.  LDS and
@@ -122,11 +136,15 @@ def run_program(w, prog, n_loads, elem_bytes=8):
         return ws, -loc - 2
 
     p = 8
+    ranges = []
     while True:
         op = int(prog[p])
         if op == OP_END:
             break
         if op == OP_SYNC:
+            if threads is not None:
+                _check_waves(ranges, threads)
+            ranges = []
             p += 1
             continue
         if op == OP_COPY:
@@ -143,8 +161,10 @@ def run_program(w, prog, n_loads, elem_bytes=8):
             p += 5
             continue
         if op == OP_TSTEP:
-            la, lb, lc, M, N, K, _, _, _, fin, nm, nn = (int(x) for x in prog[p + 1:p + 13])
-            dg = prog[p + 13:p + 13 + 4 * (nm + nn)].reshape(-1, 4)
+            la, lb, lc, M, N, K, _, _, _, fin, nm, nn, w0, nw = (int(x) for x in prog[p + 1:p + 15])
+            assert nw >= 1 and (nw & (nw - 1)) == 0 and w0 >= 0
+            ranges.append((w0, nw, False))
+            dg = prog[p + 15:p + 15 + 4 * (nm + nn)].reshape(-1, 4)
             aa, ao = at(la, K * M)
             ba, bo = at(lb, K * N)
             A = aa[ao:ao + K * M].reshape(K, M)
@@ -172,11 +192,15 @@ def run_program(w, prog, n_loads, elem_bytes=8):
             else:
                 ca, co = at(lc, int(offs.max()) + 1)
                 ca[co + offs] = c
-            p += 13 + 4 * (nm + nn)
+            p += 15 + 4 * (nm + nn)
             continue
         assert op == OP_STEP, op
-        la, lb, lc, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, _, fin, slot = (
-            int(x) for x in prog[p + 1:p + 15])
+        la, lb, lc, n_ohi, n_olo, n_shi, n_slo, t_ohi, t_olo, t_shi, t_slo, R, fin, slot, w0, nw = (
+            int(x) for x in prog[p + 1:p + 17])
+        assert nw >= 1 and (nw & (nw - 1)) == 0 and w0 >= 0
+        if threads is not None:
+            assert R <= 64 or (R == threads and nw == threads // 64), (R, nw, threads)
+        ranges.append((w0, nw, R > 64))
         tab = slots[slot].reshape(-1, 2)
         oa = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 0)
         sa = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 0)
@@ -193,18 +217,18 @@ def run_program(w, prog, n_loads, elem_bytes=8):
         else:
             ca, co = at(lc, c.size)
             ca[co:co + c.size] = c
-        p += 15
+        p += 17
     return result
 
 
-def replay(w, net, executor="steps"):
+def replay(w, net, executor="steps", threads=None):
     """Replay the net's plan on the host.  executor: "steps" (per-step
     kernels, matrix-core steps as packed products) or "fused" (the fused
     kernel's program: tiled steps use their [K][M] x [K][N] view)."""
     plan = json.loads(htn.htn_plan_json(net))
     shape = tuple(w.dims[l] for l in w.out_labels)
     if executor == "program":
-        return run_program(w, plan["program"], len(plan["loads"]), plan["elem_bytes"]).reshape(shape)
+        return run_program(w, plan["program"], len(plan["loads"]), plan["elem_bytes"], threads).reshape(shape)
     tab = htn.htn_plan_tables(net).reshape(-1, 2).astype(np.int64)
     vals = {}
     values = plan["values"]

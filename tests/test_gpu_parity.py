@@ -294,3 +294,12 @@ def test_autotune_picks_a_measured_configuration_and_keeps_results():
         assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref)
         info = htn.htn_get_info(n)
         assert info.fused_lds_bytes <= lds
+
+
+@pytest.mark.parametrize("exec_mode", EXECS)
+def test_edge_case_networks(exec_mode):
+    from edge_cases import edge_networks
+    for name, w in edge_networks(1).items():
+        ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        got = run(w, exec_mode=exec_mode)
+        assert np.abs(got - ref).max() <= 1e-14, name

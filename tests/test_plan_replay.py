@@ -37,7 +37,7 @@ def _check(w, path=None, lds=None, threads=None):
     for ex in ("steps", "fused", "program"):
         if ex == "program" and not plan_possible:
             continue
-        got = replay(w, net, ex)
+        got = replay(w, net, ex, threads=threads or 256)
         assert float(np.abs(got - ref).max()) <= 1e-12 * scale, ex
 
 
@@ -114,3 +114,9 @@ def test_replay_random_batch_networks():
     for w in configs.random_batch(3, n=24, dtype=np.float64):
         if w.input_elements() < 300000:
             _check(w)
+
+
+def test_replay_edge_cases():
+    from edge_cases import edge_networks
+    for name, w in edge_networks().items():
+        _check(w)
