@@ -94,15 +94,15 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     if (R == BLK && nthr == BLK) {
         // whole workgroup per output (tiny outputs, long sums)
         const int dq = BLK / n_slo, dr = BLK - dq * n_slo;
+        const int sh0 = tid / n_slo, sl0 = tid - sh0 * n_slo;
         for (int o = 0; o < n_out; ++o) {
-            const int oh = o / n_olo, ol = o - oh * n_olo;
+            const int oh = o / n_olo, ol = o - oh * n_olo;  // wave-uniform
             const int2 x = toh[oh], y = tol[ol];
             const T *a0 = A + (x.x + y.x);
             const T *b0 = B;
             if constexpr (!UNARY) b0 = B + (x.y + y.y);
             ACC s = 0, c = 0;
-            const int sh = tid / n_slo, sl = tid - sh * n_slo;
-            strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
+            strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh0, sl0, dq, dr, n_shi, n_slo, s, c);
             lane_reduce<COMP>(s, c, 64);
             if ((tid & 63) == 0) {
                 scratch[2 * (tid >> 6)] = s;
@@ -123,12 +123,16 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
     const int groups = nthr >> log2R;
     const int gi = tid >> log2R, sub = tid & (R - 1);
     const int dq = R / n_slo, dr = R - dq * n_slo;
+    // output o = oh * n_olo + ol, advanced by `groups` per pass without a
+    // division (one per thread up front)
+    const int oq = groups / n_olo, orr = groups - oq * n_olo;
+    int oh = gi / n_olo, ol = gi - oh * n_olo;
+    const int sh0 = sub / n_slo, sl0 = sub - sh0 * n_slo;
     for (int o0 = 0; o0 < n_out; o0 += groups) {
         const int o = o0 + gi;
         const bool active = o < n_out;
         ACC s = 0, c = 0;
         if (active) {
-            const int oh = o / n_olo, ol = o - oh * n_olo;
             const int2 x = toh[oh], y = tol[ol];
             const T *a0 = A + (x.x + y.x);
             const T *b0 = B;
@@ -167,12 +171,17 @@ __device__ __forceinline__ void fstep(const T *A, const T *B, TOUT *C, const int
                 }
                 s += (s1 + s2) + s3;
             } else {
-                const int sh = sub / n_slo, sl = sub - sh * n_slo;
-                strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh, sl, dq, dr, n_shi, n_slo, s, c);
+                strided_sum<T, ACC, COMP, UNARY>(a0, b0, tsh, tsl, sh0, sl0, dq, dr, n_shi, n_slo, s, c);
             }
         }
         lane_reduce<COMP>(s, c, R);
         if (active && sub == 0) C[o] = st_cvt<TOUT>(COMP ? s + c : s);
+        oh += oq;
+        ol += orr;
+        if (ol >= n_olo) {
+            ol -= n_olo;
+            ++oh;
+        }
     }
 }
 
