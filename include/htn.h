@@ -263,8 +263,7 @@ void htn_batch_destroy(htn_batch_t batch);
  * multilayer perceptron
  *     h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  y = w3 . h2 + b3,
  * HTN_MODEL_HIDDEN units per hidden layer, FP32 weights and arithmetic, all
- * on the GPU (forward, backward and Adam kernels).  A candidate path's
- * predicted time is the sum of exp(y) over its kernel steps.
+ * on the GPU (forward, backward and Adam kernels).
  *
  * Parameter layout (htn_model_param_count() floats, in this order):
  *     W1 [HIDDEN][FEATURES] (row = hidden unit), b1 [HIDDEN],
@@ -284,8 +283,12 @@ void htn_batch_destroy(htn_batch_t batch);
  *   16 final step  17-19 operand A / operand B / result outside LDS
  *   20 lg(1 + 16-byte chunks the fused kernel copies during the step)
  *   21 fused executor  22 FP64 compute  23 element bytes / 8
+ *   24 lg(threads running the step)  25 steps sharing its phase / 8
+ * A candidate's predicted time sums, over the fused kernel's phases, the
+ * largest exp(y) among the phase's steps (they run side by side), and over
+ * the per-step executor's steps their exp(y).
  * ------------------------------------------------------------------- */
-#define HTN_MODEL_FEATURES 24
+#define HTN_MODEL_FEATURES 26
 #define HTN_MODEL_HIDDEN 64
 typedef struct htn_model *htn_model_t;
 
@@ -335,8 +338,10 @@ htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, i
  * kernel step of each fused net: times[i * capacity + q] for net i and
  * kernel step q < capacity, NaN where the step was not recorded (nets run
  * step by step, steps beyond max_phases).  A fused step's duration is that
- * of its phase (its arithmetic and the copies issued for the next phase),
- * divided equally among the independent steps that share the phase.     */
+ * of its phase (its arithmetic and the copies issued for the next phase);
+ * when independent steps share a phase the duration is recorded for the
+ * one with the most multiplications (the phase waits for the slowest) and
+ * NaN for the others.                                                    */
 htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacity);
 
 /* htn_autotune — pick the fused kernel's workgroup size and LDS budget for

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-F = 24
+F = 26
 H = 64
 
 

@@ -1023,21 +1023,20 @@ htn_status htn_batch_step_times(htn_batch_t b, float *times, int32_t capacity) {
         for (int i : g.idx) {
             const Plan &P = b->nets[i]->plan;
             const int64_t *t = ph.data() + (size_t)i * mp;
-            std::vector<int> per_phase;  // steps sharing each phase
-            for (int k : P.kernel_steps) {
-                const int f = P.steps[k].f_phase;
-                if (f >= 0) {
-                    if ((int)per_phase.size() <= f) per_phase.resize(f + 1, 0);
-                    per_phase[f]++;
-                }
+            std::vector<int> heaviest;  // per phase: position of its step with the most multiplications
+            for (int q = 0; q < (int)P.kernel_steps.size(); ++q) {
+                const int f = P.steps[P.kernel_steps[q]].f_phase;
+                if (f < 0) continue;
+                if ((int)heaviest.size() <= f) heaviest.resize(f + 1, -1);
+                if (heaviest[f] < 0 || P.steps[P.kernel_steps[q]].mults > P.steps[P.kernel_steps[heaviest[f]]].mults)
+                    heaviest[f] = q;
             }
             for (int q = 0; q < (int)P.kernel_steps.size() && q < capacity; ++q) {
                 const int f = P.steps[P.kernel_steps[q]].f_phase;
-                if (f < 0 || f >= mp || t[f] < 0) continue;
+                if (f < 0 || f >= mp || t[f] < 0 || heaviest[f] != q) continue;
                 const int64_t begin = f == 0 ? st[2 * (size_t)i] : t[f - 1];
                 if (begin < 0) continue;
-                // 100 MHz ticks -> us, shared equally by the phase's steps
-                times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f / (float)per_phase[f];
+                times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f;  // 100 MHz ticks -> us
             }
         }
     return HTN_OK;

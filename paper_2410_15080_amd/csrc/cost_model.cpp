@@ -5,8 +5,10 @@
 // a hyper-optimised search (Sec. 4.2; Sec. 6.1, Step 3).  Here every
 // candidate order (FLOP-greedy plus Boltzmann-sampled greedy orders) is
 // planned, each of its kernel steps is described by a feature row, and the
-// model's predicted step times are summed; the fastest predicted candidate
-// wins, FLOP-greedy on ties.
+// model's predicted step times are combined (a fused phase costs its slowest
+// step, phases and per-step launches add up); the fastest predicted
+// candidate wins, FLOP-greedy on ties.
+#include <algorithm>
 #include <cmath>
 
 #include "htn_core.hpp"
@@ -27,6 +29,12 @@ void step_features(const Net &n, std::vector<float> &rows) {
     const Plan &P = n.plan;
     const bool fused = runs_fused(n);
     const int threads = n.fused_threads;
+    std::vector<int> sharing;  // steps per fused phase
+    for (int si : P.kernel_steps) {
+        const int f = std::max(0, P.steps[si].f_phase);
+        if ((int)sharing.size() <= f) sharing.resize(f + 1, 0);
+        sharing[f]++;
+    }
     for (int si : P.kernel_steps) {
         const StepPlan &s = P.steps[si];
         float f[kFeatures] = {0};
@@ -67,6 +75,12 @@ void step_features(const Net &n, std::vector<float> &rows) {
         f[21] = fused ? 1.0f : 0.0f;
         f[22] = n.compute == HTN_F64 ? 1.0f : 0.0f;
         f[23] = (float)dtype_size(inter_dtype(n.compute)) / 8.0f;
+        if (fused) {
+            f[24] = lg(64.0 * s.f_nw);
+            f[25] = (float)sharing[s.f_phase >= 0 ? s.f_phase : 0] / 8.0f;
+        } else {
+            f[24] = lg(256.0);
+        }
         rows.insert(rows.end(), f, f + kFeatures);
     }
 }
@@ -77,6 +91,7 @@ std::vector<std::pair<int, int>> learned_path(const Net &n) {
     Net t = structure_copy(n);
     std::vector<float> rows;
     std::vector<int> owner;  // candidate of each row
+    std::vector<int> group;  // fused phase of each row (-1: per-step executor)
     std::vector<char> ok(cands.size(), 0);
     for (size_t c = 0; c < cands.size(); ++c) {
         t.path = cands[c];
@@ -90,10 +105,29 @@ std::vector<std::pair<int, int>> learned_path(const Net &n) {
         const size_t before = rows.size();
         step_features(t, rows);
         owner.insert(owner.end(), (rows.size() - before) / kFeatures, (int)c);
+        const bool fused = runs_fused(t);
+        for (int si : t.plan.kernel_steps) group.push_back(fused ? t.plan.steps[si].f_phase : -1);
     }
     const std::vector<float> y = model_predict(n.model, rows);
+    // steps sharing a fused phase run side by side: the phase costs its
+    // slowest step (a candidate's rows are contiguous)
     std::vector<double> total(cands.size(), 0.0);
-    for (size_t r = 0; r < owner.size(); ++r) total[owner[r]] += std::exp((double)y[r]);
+    std::vector<double> phase;
+    for (size_t r = 0; r < owner.size();) {
+        size_t e = r;
+        phase.clear();
+        for (; e < owner.size() && owner[e] == owner[r]; ++e) {
+            const double d = std::exp((double)y[e]);
+            if (group[e] < 0) {
+                total[owner[r]] += d;
+                continue;
+            }
+            if ((int)phase.size() <= group[e]) phase.resize(group[e] + 1, 0.0);
+            phase[group[e]] = std::max(phase[group[e]], d);
+        }
+        for (double d : phase) total[owner[r]] += d;
+        r = e;
+    }
     size_t best = 0;
     for (size_t c = 1; c < cands.size(); ++c)
         if (ok[c] && std::isfinite(total[c]) && total[c] < total[best]) best = c;

@@ -1202,7 +1202,7 @@ std::string plan_json(const Net &n) {
         o << ",\"mults\":" << s.mults << ",\"absorbed\":" << (s.absorbed ? "true" : "false")
           << ",\"final\":" << (s.final_step ? "true" : "false") << ",\"synthetic\":" << (s.synthetic ? "true" : "false")
           << ",\"n_out\":" << s.n_out << ",\"n_sum\":" << s.n_sum << ",\"r_fused\":" << s.r_fused
-          << ",\"r_global\":" << s.r_global << ",\"split\":" << s.split_global << ",\"ksplit\":" << s.ksplit << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
+          << ",\"r_global\":" << s.r_global << ",\"split\":" << s.split_global << ",\"ksplit\":" << s.ksplit << ",\"f_phase\":" << s.f_phase << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
           << s.n_slo << "," << s.t_ohi << "," << s.t_olo << "," << s.t_shi << "," << s.t_slo << "],\"pack_a\":["
           << s.pack_a.n_ohi << "," << s.pack_a.n_olo << "," << s.pack_a.t_ohi << "," << s.pack_a.t_olo << "],\"pack_b\":["
           << s.pack_b.n_ohi << "," << s.pack_b.n_olo << "," << s.pack_b.t_ohi << "," << s.pack_b.t_olo

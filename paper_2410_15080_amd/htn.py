@@ -23,7 +23,7 @@ HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
 HTN_PATH_GREEDY, HTN_PATH_LEARNED, HTN_PATH_SAMPLED = -1, -2, -3
 HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
 HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS = 4, 5, 6
-HTN_MODEL_FEATURES, HTN_MODEL_HIDDEN = 24, 64
+HTN_MODEL_FEATURES, HTN_MODEL_HIDDEN = 26, 64
 
 STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
           "HTN_E_DEVICE", "HTN_E_UNSUPPORTED", "HTN_E_STATE"]

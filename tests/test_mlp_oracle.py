@@ -24,9 +24,9 @@ def _params(rng, scale=1.0):
 def test_layout_views_and_count():
     p = np.arange(mlp.param_count(), dtype=np.float64)
     W1, b1, W2, b2, w3, b3 = mlp.unpack(p)
-    assert W1.shape == (64, 24) and W2.shape == (64, 64)
-    assert W1[0, 1] == 1 and b1[0] == 64 * 24 and W2[0, 0] == 64 * 24 + 64
-    assert b3 == mlp.param_count() - 1 == 5824
+    assert W1.shape == (64, 26) and W2.shape == (64, 64)
+    assert W1[0, 1] == 1 and b1[0] == 64 * 26 and W2[0, 0] == 64 * 26 + 64
+    assert b3 == mlp.param_count() - 1 == 5952
 
 
 def test_gradient_matches_central_differences():
@@ -68,7 +68,7 @@ def test_zero_second_layer_disconnects_inputs():
     assert np.ptp(y) == 0.0
     assert y[0] == pytest.approx(w3 @ np.maximum(b2, 0) + b3)
     g = mlp.gradients(p, X, t)
-    assert np.all(g[: 64 * 24 + 64] == 0.0)  # nothing reaches W1, b1
+    assert np.all(g[: 64 * mlp.F + 64] == 0.0)  # nothing reaches W1, b1
 
 
 def test_adam_constant_gradient_closed_form():
