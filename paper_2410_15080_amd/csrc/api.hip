@@ -311,8 +311,12 @@ static void upload_plan(Net &n) {
     D.fprep.clear();
     D.fprep_max = 0;
     for (const LoadPlan &lp : P.loads) {
+        if (lp.desc_word < 0 || lp.desc_word + 7 > (int64_t)P.program.size()) continue;  // no fused image
+        const int32_t rk = P.program[lp.desc_word + 5], ns = P.program[lp.desc_word + 6];
+        const int32_t words = 7 + 2 * ns + rk * (4 + ns);
+        if (words > kern::kFPrepDescMax) throw Error{HTN_E_UNSUPPORTED, "load descriptor too long"};
         for (int64_t e0 = 0; e0 < lp.size; e0 += kern::kFPrepChunk)
-            D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws, (int32_t)e0});
+            D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws, (int32_t)e0, words});
         D.fprep_max = std::max<int>(D.fprep_max, (int)lp.size);
     }
     dfree(D.d_fprep);

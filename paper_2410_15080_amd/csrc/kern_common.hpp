@@ -111,50 +111,60 @@ __device__ __forceinline__ T to_compute(TIN x) {
 //   scale strides)]
 // One wave materialises one entry (a chunk of kFPrepChunk elements of one
 // load); lane = lane index 0..63.  Descriptor words are wave-uniform and
-// read-only: they are read through the constant address space (scalar
-// loads), and the tensors through the global address space.
+// read-only; Words is their view: the constant address space (scalar
+// loads, each digit's words fetched when first needed) or the wave's lanes
+// (one vector load up front, no chain of dependent scalar round trips).
+// The tensors are read through the global address space.
 typedef const int32_t __attribute__((address_space(4))) c_int32;
 
-template <typename T, typename TIN>
-__device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
+template <typename T, typename TIN, typename Words>
+__device__ __forceinline__ void fprep_words(const Words &p, void *ws, int e_first, int lane) {
     typedef const TIN __attribute__((address_space(1))) g_tin;
-    const c_int32 *p = (const c_int32 *)en.desc;
-    const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p[3] << 32) | (uint32_t)p[2]);
-    const int size = p[4], rk = p[5], ns = p[6];
-    const c_int32 *per = p + 7 + 2 * ns;
-    const int W = 4 + ns;
-    auto ptr_at = [&](const c_int32 *w) {
-        return (const g_tin *)(uintptr_t)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]);
+    auto ptr_at = [&](int w) {
+        return (const g_tin *)(uintptr_t)(((uint64_t)(uint32_t)p(w + 1) << 32) | (uint32_t)p(w));
     };
-    const g_tin *src = ptr_at(p);
-    T *o = (T *)en.ws + dst_off;
+    const int64_t dst_off = (int64_t)(((uint64_t)(uint32_t)p(3) << 32) | (uint32_t)p(2));
+    const int size = p(4), rk = p(5), ns = p(6);
+    const int per = 7 + 2 * ns;
+    const int Wd = 4 + ns;
+    const g_tin *src = ptr_at(0);
+    T *o = (T *)ws + dst_off;
     const g_tin *sp[kMaxScalesLoad];
 #pragma unroll
-    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? ptr_at(p + 7 + 2 * q) : nullptr;
-    const int e_end = min(size, en.e0 + kFPrepChunk);
+    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? ptr_at(7 + 2 * q) : nullptr;
+    const int e_end = min(size, e_first + kFPrepChunk);
     // four elements per lane at a time, so their gathers are in flight
     // together
-    for (int e0 = en.e0 + lane; e0 < e_end; e0 += 4 * 64) {
+    for (int e0 = e_first + lane; e0 < e_end; e0 += 4 * 64) {
         int so[4], sc[4][kMaxScalesLoad];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int e = min(e0 + 64 * u, e_end - 1);
-            uint32_t rem = (uint32_t)e;
             so[u] = 0;
 #pragma unroll
             for (int q = 0; q < kMaxScalesLoad; ++q) sc[u][q] = 0;
+        }
+        uint32_t rem[4];
 #pragma unroll
-            for (int k = kMaxRankLoad - 1; k >= 0; --k) {
-                if (k < rk) {
-                    const c_int32 *pk = per + k * W;
-                    const uint64_t magic = ((uint64_t)(uint32_t)pk[2] << 32) | (uint32_t)pk[1];
-                    const uint32_t quo = (uint32_t)(((uint64_t)rem * magic) >> 40);
-                    const int dgt = (int)(rem - quo * (uint32_t)pk[0]);
-                    rem = quo;
-                    so[u] += dgt * pk[3];
+        for (int u = 0; u < 4; ++u) rem[u] = (uint32_t)min(e0 + 64 * u, e_end - 1);
+#pragma unroll
+        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
+            if (k < rk) {
+                const int pk = per + k * Wd;
+                const uint32_t ext = (uint32_t)p(pk);
+                const uint64_t magic = ((uint64_t)(uint32_t)p(pk + 2) << 32) | (uint32_t)p(pk + 1);
+                const int sstr = p(pk + 3);
+                int cstr[kMaxScalesLoad];
+#pragma unroll
+                for (int q = 0; q < kMaxScalesLoad; ++q) cstr[q] = q < ns ? p(pk + 4 + q) : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t quo = (uint32_t)(((uint64_t)rem[u] * magic) >> 40);
+                    const int dgt = (int)(rem[u] - quo * ext);
+                    rem[u] = quo;
+                    so[u] += dgt * sstr;
 #pragma unroll
                     for (int q = 0; q < kMaxScalesLoad; ++q)
-                        if (q < ns) sc[u][q] += dgt * pk[4 + q];
+                        if (q < ns) sc[u][q] += dgt * cstr[q];
                 }
             }
         }
@@ -171,6 +181,27 @@ __device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
         for (int u = 0; u < 4; ++u)
             if (e0 + 64 * u < e_end) o[e0 + 64 * u] = v[u];
     }
+}
+
+// Descriptor read in place through the constant address space.
+struct ConstWords {
+    const c_int32 *p;
+    __device__ __forceinline__ int32_t operator()(int i) const { return p[i]; }
+};
+
+// Descriptor of at most 64 words held across the wave's lanes (word i in
+// lane i), loaded with one vector load; a wave-uniform read is one lane
+// read, with no memory round trip.
+struct LaneWords {
+    int32_t r;
+    __device__ __forceinline__ LaneWords(const int32_t *desc, int n, int lane) : r(lane < n ? desc[lane] : 0) {}
+    __device__ __forceinline__ int32_t operator()(int i) const { return __builtin_amdgcn_readlane(r, i); }
+};
+
+// One entry, descriptor read in place through the constant address space.
+template <typename T, typename TIN>
+__device__ __forceinline__ void fprep_entry(const FPrepEntry &en, int lane) {
+    fprep_words<T, TIN>(ConstWords{(const c_int32 *)en.desc}, en.ws, en.e0, lane);
 }
 
 }  // namespace kern

@@ -219,7 +219,11 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
 // inside their fused workgroup.
 template <typename T, typename TIN>
 __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
-    fprep_entry<T, TIN>(entries[blockIdx.x], threadIdx.x);
+    const FPrepEntry en = entries[blockIdx.x];
+    if (en.n_words <= 64)
+        fprep_words<T, TIN>(LaneWords(en.desc, en.n_words, threadIdx.x), en.ws, en.e0, threadIdx.x);
+    else
+        fprep_entry<T, TIN>(en, threadIdx.x);
 }
 
 // Device clock read into *dst (one thread).

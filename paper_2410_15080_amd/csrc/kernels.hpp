@@ -92,8 +92,11 @@ hipError_t launch_gemm(const void *A, const void *B, void *C, int tin, int tout,
 struct FPrepEntry {
     const int32_t *desc;
     void *ws;
-    int32_t e0;  // first element of this entry's chunk of the load
+    int32_t e0;       // first element of this entry's chunk of the load
+    int32_t n_words;  // descriptor length: 7 + 2 ns + rank (4 + ns)
 };
+// Longest descriptor: 7 + 2 * 8 + 16 * (4 + 8) words.
+constexpr int kFPrepDescMax = 215;
 // Elements per FPrepEntry chunk (one wave each).
 constexpr int kFPrepChunk = 4096;
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st);

@@ -9,8 +9,9 @@
 //
 // Operands are packed K-contiguous by the step's pack kernels, so every
 // lane's MFMA fragment is a contiguous LDS read.  Workgroup tile 128x128,
-// four wave64s each owning a 64x64 sub-tile (4x4 MFMA 16x16 blocks), K
-// staged through double-buffered LDS.  Per input type:
+// four wave64s each owning a 64x64 sub-tile (4x4 MFMA 16x16 blocks), or
+// 64x128 with 32x64 sub-tiles where FP64 accumulators sit beside the FP32
+// ones; K staged through double-buffered LDS.  Per input type:
 //   double : v_mfma_f64_16x16x4_f64,  FP64 accumulation
 //   float  : v_mfma_f32_16x16x4_f32,  FP32 accumulation per K-chunk
 //   bf16   : v_mfma_f32_16x16x32_bf16, FP32 accumulation per K-chunk
@@ -30,7 +31,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int GBM = 128, GBN = 128;
+constexpr int GBN = 128;
 
 template <typename T>
 struct MfmaOp;
@@ -82,14 +83,15 @@ struct MfmaOp<bf16_t> {
     __device__ __forceinline__ static frag ld(const bf16_t *p) { return *(const bf8_t *)p; }
 };
 
-// Load a GBM x BK tile (rows r0.., K-columns k0..) of a [rows][K] operand
+// Load a ROWS x BK tile (rows r0.., K-columns k0..) of a [rows][K] operand
 // into registers: 16 bytes per load, zero outside the matrix.
-template <typename T>
+template <typename T, int ROWS>
 struct TileLoader {
     static constexpr int BK = MfmaOp<T>::BK;
     static constexpr int EPV = 16 / sizeof(T);               // elements per 16B vector
     static constexpr int VPR = BK / EPV;                      // vectors per row
-    static constexpr int NV = GBM * VPR / 256;                // vectors per thread
+    static constexpr int NV = ROWS * VPR / 256;               // vectors per thread
+    static_assert(NV * 256 == ROWS * VPR, "tile rows must fill the workgroup's loads");
     uint4 v[NV];
     // rows of length K (the row stride); columns at or beyond klim read 0
     __device__ __forceinline__ void load(const T *__restrict__ src, int rows, int K, int klim, int r0, int k0) {
@@ -126,36 +128,43 @@ struct TileLoader {
 
 // blockIdx.z = b * ksplit + kz: batch entry b, K range kz (of length kper,
 // a multiple of BK); the output of range kz goes to C + (kz * batch + b) * sC.
-template <typename T, typename TOUT, bool COMBINE64>
+// Each wave owns WI x 4 blocks of 16x16 (the workgroup tile is 32 WI x 128):
+// WI = 4 where the accumulators are the instruction's own; WI = 2 where FP64
+// accumulators are kept beside FP32 ones, so that two waves per SIMD still
+// fit in the register file.
+template <typename T, typename TOUT, bool COMBINE64, int WI>
 __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, TOUT *__restrict__ C,
                                              int M, int N, int K, int64_t sA, int64_t sB, int64_t sC, int kchunk,
                                              int ksplit, int kper, int batch) {
     typedef MfmaOp<T> Op;
     constexpr int BK = Op::BK;
     constexpr int LD = BK + Op::PAD;
-    __shared__ __align__(16) T As[2][GBM * LD];
+    constexpr int TBM = 32 * WI;
+    __shared__ __align__(16) T As[2][TBM * LD];
     __shared__ __align__(16) T Bs[2][GBN * LD];
     const int bz = blockIdx.z / ksplit, kz = blockIdx.z - bz * ksplit;
     const int kbeg = kz * kper, kend = min(K, kbeg + kper);
     A += bz * sA;
     B += bz * sB;
     C += ((int64_t)kz * batch + bz) * sC;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * GBN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (16 * WI), wn = (wave & 1) * 64;
     const int lr = lane & 15, lk = (lane >> 4) * Op::KPL;
 
-    typename Op::acc acc[4][4];
-    d4_t acc64[4][4];
+    typename Op::acc acc[WI][4];
+    d4_t acc64[COMBINE64 ? WI : 1][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = typename Op::acc{0, 0, 0, 0};
-            acc64[i][j] = d4_t{0, 0, 0, 0};
-        }
+        for (int j = 0; j < 4; ++j) acc[i][j] = typename Op::acc{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < (COMBINE64 ? WI : 1); ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc64[i][j] = d4_t{0, 0, 0, 0};
 
-    TileLoader<T> la, lb;
+    TileLoader<T, TBM> la;
+    TileLoader<T, GBN> lb;
     const int nk = (kend - kbeg + BK - 1) / BK;
     la.load(A, M, K, kend, m0, kbeg);
     lb.load(B, N, K, kend, n0, kbeg);
@@ -173,13 +182,13 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
         const T *bs = Bs[cur];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += Op::KI) {
-            typename Op::frag fa[4], fb[4];
+            typename Op::frag fa[WI], fb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = Op::ld(as + (wm + 16 * i + lr) * LD + kk + lk);
+            for (int i = 0; i < WI; ++i) fa[i] = Op::ld(as + (wm + 16 * i + lr) * LD + kk + lk);
 #pragma unroll
             for (int j = 0; j < 4; ++j) fb[j] = Op::ld(bs + (wn + 16 * j + lr) * LD + kk + lk);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WI; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(fa[i], fb[j], acc[i][j]);
         }
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
             since += BK;
             if (since >= kchunk || kt + 1 == nk) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WI; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
     // D block: column lane%16; the row of register r depends on the
     // instruction (Op::row).
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -216,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
                 const int gn = n0 + wn + 16 * j + (lane & 15);
                 if (gm < M && gn < N) {
                     if constexpr (COMBINE64)
-                        C[(int64_t)gm * N + gn] = (TOUT)acc64[i][j][r];
+                        C[(int64_t)gm * N + gn] = (TOUT)acc64[COMBINE64 ? i : 0][j][r];
                     else
                         C[(int64_t)gm * N + gn] = (TOUT)acc[i][j][r];
                 }
@@ -240,10 +249,11 @@ static hipError_t go_gemm(const void *A, const void *B, void *C, int M, int N, i
     const int64_t sA = (int64_t)M * K, sB = (int64_t)N * K, sC = (int64_t)M * N;
     const int kper = ksplit > 1 ? ((K + ksplit - 1) / ksplit + 63) / 64 * 64 : K;
     if (ksplit > 1) ksplit = (K + kper - 1) / kper;
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch * ksplit);
+    constexpr int WI = C64 ? 2 : 4;
+    dim3 grid((N + GBN - 1) / GBN, (M + 32 * WI - 1) / (32 * WI), batch * ksplit);
     TOUT *dst = ksplit > 1 ? (TOUT *)part : (TOUT *)C;
-    hipLaunchKernelGGL((k_gemm<T, TOUT, C64>), grid, dim3(256), 0, st, (const T *)A, (const T *)B, dst, M, N, K, sA,
-                       sB, sC, kchunk, ksplit, kper, batch);
+    hipLaunchKernelGGL((k_gemm<T, TOUT, C64, WI>), grid, dim3(256), 0, st, (const T *)A, (const T *)B, dst, M, N, K,
+                       sA, sB, sC, kchunk, ksplit, kper, batch);
     if (ksplit > 1) {
         const int64_t total = (int64_t)batch * sC;
         const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
