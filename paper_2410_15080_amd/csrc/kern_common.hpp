@@ -117,7 +117,7 @@ __device__ __forceinline__ T to_compute(TIN x) {
 // The tensors are read through the global address space.
 typedef const int32_t __attribute__((address_space(4))) c_int32;
 
-template <typename T, typename TIN, typename Words>
+template <typename T, typename TIN, typename Words, int MR = kMaxRankLoad, int MS = kMaxScalesLoad>
 __device__ __forceinline__ void fprep_words(const Words &p, void *ws, int e_first, int lane) {
     typedef const TIN __attribute__((address_space(1))) g_tin;
     auto ptr_at = [&](int w) {
@@ -129,33 +129,32 @@ __device__ __forceinline__ void fprep_words(const Words &p, void *ws, int e_firs
     const int Wd = 4 + ns;
     const g_tin *src = ptr_at(0);
     T *o = (T *)ws + dst_off;
-    const g_tin *sp[kMaxScalesLoad];
+    const g_tin *sp[MS];
 #pragma unroll
-    for (int q = 0; q < kMaxScalesLoad; ++q) sp[q] = q < ns ? ptr_at(7 + 2 * q) : nullptr;
+    for (int q = 0; q < MS; ++q) sp[q] = q < ns ? ptr_at(7 + 2 * q) : nullptr;
     const int e_end = min(size, e_first + kFPrepChunk);
     // four elements per lane at a time, so their gathers are in flight
-    // together
+    // together; each digit's descriptor words are read once for all four
     for (int e0 = e_first + lane; e0 < e_end; e0 += 4 * 64) {
-        int so[4], sc[4][kMaxScalesLoad];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            so[u] = 0;
-#pragma unroll
-            for (int q = 0; q < kMaxScalesLoad; ++q) sc[u][q] = 0;
-        }
+        int so[4], sc[4][MS];
         uint32_t rem[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rem[u] = (uint32_t)min(e0 + 64 * u, e_end - 1);
+        for (int u = 0; u < 4; ++u) {
+            rem[u] = (uint32_t)min(e0 + 64 * u, e_end - 1);
+            so[u] = 0;
 #pragma unroll
-        for (int k = kMaxRankLoad - 1; k >= 0; --k) {
+            for (int q = 0; q < MS; ++q) sc[u][q] = 0;
+        }
+#pragma unroll
+        for (int k = MR - 1; k >= 0; --k) {
             if (k < rk) {
                 const int pk = per + k * Wd;
                 const uint32_t ext = (uint32_t)p(pk);
                 const uint64_t magic = ((uint64_t)(uint32_t)p(pk + 2) << 32) | (uint32_t)p(pk + 1);
                 const int sstr = p(pk + 3);
-                int cstr[kMaxScalesLoad];
+                int cs[MS];
 #pragma unroll
-                for (int q = 0; q < kMaxScalesLoad; ++q) cstr[q] = q < ns ? p(pk + 4 + q) : 0;
+                for (int q = 0; q < MS; ++q) cs[q] = q < ns ? p(pk + 4 + q) : 0;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const uint32_t quo = (uint32_t)(((uint64_t)rem[u] * magic) >> 40);
@@ -163,8 +162,7 @@ __device__ __forceinline__ void fprep_words(const Words &p, void *ws, int e_firs
                     rem[u] = quo;
                     so[u] += dgt * sstr;
 #pragma unroll
-                    for (int q = 0; q < kMaxScalesLoad; ++q)
-                        if (q < ns) sc[u][q] += dgt * cstr[q];
+                    for (int q = 0; q < MS; ++q) sc[u][q] += dgt * cs[q];
                 }
             }
         }
@@ -172,7 +170,7 @@ __device__ __forceinline__ void fprep_words(const Words &p, void *ws, int e_firs
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = to_compute<T>(src[so[u]]);
 #pragma unroll
-        for (int q = 0; q < kMaxScalesLoad; ++q)
+        for (int q = 0; q < MS; ++q)
             if (q < ns) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v[u] *= to_compute<T>(sp[q][sc[u][q]]);
@@ -194,6 +192,7 @@ struct ConstWords {
 // read, with no memory round trip.
 struct LaneWords {
     int32_t r;
+    __device__ __forceinline__ explicit LaneWords(int32_t word) : r(word) {}
     __device__ __forceinline__ LaneWords(const int32_t *desc, int n, int lane) : r(lane < n ? desc[lane] : 0) {}
     __device__ __forceinline__ int32_t operator()(int i) const { return __builtin_amdgcn_readlane(r, i); }
 };

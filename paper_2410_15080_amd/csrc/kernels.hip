@@ -217,13 +217,26 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
 // Input materialisation for the fused kernel, as its own launch (one wave
 // per entry); used for networks whose inputs are too large to materialise
 // inside their fused workgroup.
+// The digit loop is unrolled to a bound on the rank and the number of
+// scales; small bounds for the common small loads keep the code a wave
+// runs through short (the fully unrolled general form is several times
+// larger and its instruction fetches, not its arithmetic, set the time).
 template <typename T, typename TIN>
 __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
     const FPrepEntry en = entries[blockIdx.x];
-    if (en.n_words <= 64)
-        fprep_words<T, TIN>(LaneWords(en.desc, en.n_words, threadIdx.x), en.ws, en.e0, threadIdx.x);
+    const int lane = threadIdx.x;
+    if (en.n_words > 64) {
+        fprep_entry<T, TIN>(en, lane);
+        return;
+    }
+    const LaneWords p(en.desc, en.n_words, lane);
+    const int rk = p(5), ns = p(6);
+    if (rk <= 4 && ns <= 4)
+        fprep_words<T, TIN, LaneWords, 4, 4>(p, en.ws, en.e0, lane);
+    else if (rk <= 8 && ns <= 8)
+        fprep_words<T, TIN, LaneWords, 8, 8>(p, en.ws, en.e0, lane);
     else
-        fprep_entry<T, TIN>(en, threadIdx.x);
+        fprep_words<T, TIN, LaneWords>(p, en.ws, en.e0, lane);
 }
 
 // Device clock read into *dst (one thread).
