@@ -399,10 +399,20 @@ static void run_mfma_step(Net &n, const StepPlan &s, const void *A, int ta, cons
                           hipStream_t st) {
     DeviceState &D = *n.dev;
     const int tp = n.compute == HTN_BF16 ? 2 : (int)inter_dtype(n.compute);
-    void *pa = (unsigned char *)D.d_ws + s.ws_pa;
-    void *pb = (unsigned char *)D.d_ws + s.ws_pb;
-    HIP_TRY(kern::launch_step(A, ta, nullptr, ta, pa, tp, false, false, D.d_tab, pack_args(s.pack_a), st));
-    HIP_TRY(kern::launch_step(B, tb, nullptr, tb, pb, tp, false, false, D.d_tab, pack_args(s.pack_b), st));
+    // an operand its producer already wrote in packed order is used in place
+    const void *pa = A, *pb = B;
+    if (!(s.pack_a.identity && ta == tp)) {
+        void *w = (unsigned char *)D.d_ws + s.ws_pa;
+        if (s.ws_pa < 0) throw Error{HTN_E_STATE, "packed operand without workspace"};
+        HIP_TRY(kern::launch_step(A, ta, nullptr, ta, w, tp, false, false, D.d_tab, pack_args(s.pack_a), st));
+        pa = w;
+    }
+    if (!(s.pack_b.identity && tb == tp)) {
+        void *w = (unsigned char *)D.d_ws + s.ws_pb;
+        if (s.ws_pb < 0) throw Error{HTN_E_STATE, "packed operand without workspace"};
+        HIP_TRY(kern::launch_step(B, tb, nullptr, tb, w, tp, false, false, D.d_tab, pack_args(s.pack_b), st));
+        pb = w;
+    }
     void *kpart = s.ksplit > 1 ? (unsigned char *)D.d_ws + s.ws_kpart : nullptr;
     HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, s.ksplit, kpart, st));
 }

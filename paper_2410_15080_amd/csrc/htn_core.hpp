@@ -55,6 +55,7 @@ struct StepPlan {
     int64_t gb = 1, gm = 1, gn = 1, gk = 1;   // group extents
     struct Pack {
         int64_t n = 0, n_ohi = 1, n_olo = 1, t_ohi = 0, t_olo = 0, t_one = 0;
+        bool identity = false;  // the operand is already packed (no pack launch)
     } pack_a, pack_b;
     int64_t ws_pa = -1, ws_pb = -1;  // workspace byte offsets of the packed operands
     // Register-tiled steps (tile = 1, fused kernel): a plain GEMM view

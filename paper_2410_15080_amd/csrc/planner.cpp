@@ -675,9 +675,31 @@ void build_plan(Net &n) {
         prod.c_labels = order;
         return true;
     };
+    // An intermediate consumed by a matrix-core step is written by its
+    // producer directly in the packed order [batch][M][K] / [batch][N][K],
+    // so that no pack launch is needed (the element type must also match:
+    // BF16 operands are packed from FP32 intermediates).  Only for networks
+    // above the batch limit of the fused kernel (those run step by step in
+    // every executor choice except an explicit HTN_EXEC_FUSED); below it
+    // the register-tiled layout of the fused kernel keeps precedence.
+    const bool packed_layouts = n.compute != HTN_BF16 && P.mults > n.batch_fused_max_mults;
+    if (packed_layouts)
+        for (int k : P.kernel_steps) {
+            StepPlan &s = P.steps[k];
+            if (!s.mfma) continue;
+            auto packed = [&](const std::vector<int> &mid) {
+                std::vector<int> o = s.g_batch;
+                o.insert(o.end(), mid.begin(), mid.end());
+                o.insert(o.end(), s.g_k.begin(), s.g_k.end());
+                return o;
+            };
+            if (!P.values[s.a].input) set_layout(s.a, packed(s.g_m));
+            if (!P.values[s.b].input) set_layout(s.b, packed(s.g_n));
+        }
     for (int k : P.kernel_steps) {
         StepPlan &s = P.steps[k];
         if (s.b < 0) continue;
+        if (s.mfma && packed_layouts) continue;  // operands keep the packed order
         if (s.final_step && n.final_sum == HTN_SUM_COMPENSATED) continue;
         std::vector<int> al = P.values[s.a].labels, bl = P.values[s.b].labels;
         std::vector<int> K, M, Nn;
@@ -785,9 +807,19 @@ void build_plan(Net &n) {
                 int64_t a, b;
                 group_tables(n, {}, {}, {}, P.tables, a, b, pk.t_one, pk.t_one);
                 pk.n = pk.n_ohi * pk.n_olo;
+                pk.identity = false;
             };
             pack(s.a_labels, sta, s.g_m, s.pack_a);
             pack(s.b_labels, stb, s.g_n, s.pack_b);
+            auto in_order = [&](int v, const std::vector<int> &mid) {
+                if (P.values[v].input || n.compute == HTN_BF16) return false;
+                std::vector<int> o = s.g_batch;
+                o.insert(o.end(), mid.begin(), mid.end());
+                o.insert(o.end(), s.g_k.begin(), s.g_k.end());
+                return P.values[v].labels == o;
+            };
+            s.pack_a.identity = in_order(s.a, s.g_m);
+            s.pack_b.identity = in_order(s.b, s.g_n);
         }
         s.n_out = s.n_ohi * s.n_olo;
         s.n_sum = s.n_shi * s.n_slo;
@@ -870,8 +902,8 @@ void build_plan(Net &n) {
             StepPlan &s = P.steps[k];
             if (!s.final_step) P.ws_off[s.c] = ff.alloc(P.values[s.c].size * es, 256);
             if (s.mfma) {
-                s.ws_pa = ff.alloc(s.pack_a.n * pes, 256);
-                s.ws_pb = ff.alloc(s.pack_b.n * pes, 256);
+                s.ws_pa = s.pack_a.identity ? -1 : ff.alloc(s.pack_a.n * pes, 256);
+                s.ws_pb = s.pack_b.identity ? -1 : ff.alloc(s.pack_b.n * pes, 256);
                 // too few 128x128 output tiles to fill the chip: split K
                 // (ranges of >= 128) into parallel partial products
                 const int64_t tiles = ((s.gm + 127) / 128) * ((s.gn + 127) / 128) * s.gb;
@@ -1206,6 +1238,7 @@ std::string plan_json(const Net &n) {
           << s.n_slo << "," << s.t_ohi << "," << s.t_olo << "," << s.t_shi << "," << s.t_slo << "],\"pack_a\":["
           << s.pack_a.n_ohi << "," << s.pack_a.n_olo << "," << s.pack_a.t_ohi << "," << s.pack_a.t_olo << "],\"pack_b\":["
           << s.pack_b.n_ohi << "," << s.pack_b.n_olo << "," << s.pack_b.t_ohi << "," << s.pack_b.t_olo
+          << "],\"pack_id\":[" << (s.pack_a.identity ? 1 : 0) << "," << (s.pack_b.identity ? 1 : 0)
           << "],\"t_cm\":" << s.t_cm << ",\"t_cn\":" << s.t_cn << ",\"mfma\":" << s.mfma << ",\"gemm\":[" << s.gb << "," << s.gm
           << "," << s.gn << "," << s.gk << "],\"tile\":" << s.tile << ",\"tmnk\":[" << s.tM << "," << s.tN << ","
           << s.tK << "],\"tcfg\":[" << s.TM << "," << s.TN << "," << s.GX << "]}";

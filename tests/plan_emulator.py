@@ -47,8 +47,15 @@ def _generic_step(tab, s, A, B):
 
 def _mfma_step(tab, s, A, B):
     gb, gm, gn, gk = s["gemm"]
-    pa = A[_two_level(tab, s["pack_a"][2], s["pack_a"][3], s["pack_a"][1], gb * gm * gk, 0)]
-    pb = B[_two_level(tab, s["pack_b"][2], s["pack_b"][3], s["pack_b"][1], gb * gn * gk, 0)]
+    ia = _two_level(tab, s["pack_a"][2], s["pack_a"][3], s["pack_a"][1], gb * gm * gk, 0)
+    ib = _two_level(tab, s["pack_b"][2], s["pack_b"][3], s["pack_b"][1], gb * gn * gk, 0)
+    # an operand flagged as already packed is used in place by the library:
+    # its pack must then be the identity permutation
+    for flag, idx, X in zip(s["pack_id"], (ia, ib), (A, B)):
+        if flag:
+            assert idx.size == X.size and np.array_equal(idx, np.arange(X.size)), "pack flagged identity is not"
+    pa = A[ia]
+    pb = B[ib]
     c = np.einsum("bmk,bnk->bmn", pa.reshape(gb, gm, gk), pb.reshape(gb, gn, gk))
     return c.ravel()
 

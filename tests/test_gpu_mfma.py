@@ -104,3 +104,28 @@ def test_split_sum_long_reductions(final_sum, compute):
         absum = oracle.ve_contract([np.abs(t) for t in w.tensors], w.labels, w.dims, w.out_labels)[0]
         bound = 80 * u * np.asarray(absum).max()
         assert float(np.abs(got - ref).max()) <= bound
+
+
+@pytest.mark.parametrize("compute", [htn.HTN_F64, htn.HTN_F32, htn.HTN_BF16])
+def test_gemm_with_more_tiles_than_resident_workgroups(compute):
+    """More output tiles than two per CU, ragged in M, N and K and batched:
+    each workgroup walks several tiles and loads the next tile's first K
+    slice while finishing the current one."""
+    M, N, K, B = 2600, 2050, 24, 2
+    w = _gemm_net(np.random.default_rng(11), M, N, K, B, False)
+    fs = htn.HTN_SUM_PLAIN if compute == htn.HTN_F64 else htn.HTN_SUM_FP64
+    net = create(w, compute=compute, final_sum=fs, storage=htn.HTN_F64, exec_mode=htn.HTN_EXEC_STEPS)
+    step = json.loads(htn.htn_plan_json(net))["steps"][-1]
+    assert step["mfma"] == 1 and step["ksplit"] == 1
+    rows = 128 if compute == htn.HTN_F64 else 64  # workgroup tile rows
+    assert -(-M // rows) * -(-N // 128) * B > 2 * 304  # above two per CU on any current part
+    got = contract(net, (B, M, N))
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    err = float(np.abs(got - (hi + lo)).max())
+    if compute == htn.HTN_F64:
+        bound = K * 2.0 ** -52 * K
+    elif compute == htn.HTN_F32:
+        bound = (K + 2) * U32 * K
+    else:
+        bound = (2 * U16 + (K + 2) * U32) * K
+    assert err <= bound, (err, bound)

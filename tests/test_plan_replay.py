@@ -120,3 +120,16 @@ def test_replay_edge_cases():
     from edge_cases import edge_networks
     for name, w in edge_networks().items():
         _check(w)
+
+
+def test_marginal_operands_written_in_packed_order():
+    """The folds that produce the marginal's GEMM operands write them in the
+    packed [M][K] / [N][K] order, so the matrix-core step needs no pack
+    launch (checked as an identity permutation by the replay)."""
+    import json
+    w = configs.marginal_network(0, out_bits=9)  # 512 x 512 x 256: above the fused batch limit
+    net = htn.htn_create(w.tensors, w.labels, w.dims, w.out_labels)
+    steps = json.loads(htn.htn_plan_json(net))["steps"]
+    gemm = [st for st in steps if st["mfma"]]
+    assert gemm and all(st["pack_id"] == [1, 1] for st in gemm)
+    _check(w)
