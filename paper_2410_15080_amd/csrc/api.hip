@@ -373,7 +373,8 @@ static bool use_fused(const Net &n) {
 
 static void run_fused_single(Net &n, void *out, hipStream_t st) {
     if (!n.dev->fprep_in_kernel)
-        HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, st));
+        HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_max, (int)n.compute, nullptr,
+                                   st));
     HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, nullptr, 0, 1,
                                (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), n.fused_threads, st));
 }
@@ -874,10 +875,17 @@ htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
 // d_stamps.
 static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool events) {
     const size_t n = b->nets.size();
-    HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * n, st));
+    // the run's start clock: written by the first materialisation launch,
+    // or by a launch of its own when there is none
+    int64_t *run_start = b->d_stamps + 2 * n;
+    const bool prep_stamps = !b->groups.empty() && b->groups[0].n_fprep > 0;
+    if (!prep_stamps) HIP_TRY(kern::launch_stamp(run_start, st));
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
-    for (auto &g : b->groups)
-        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, st));
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto &g = b->groups[gi];
+        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, gi == 0 && prep_stamps ? run_start : nullptr,
+                                   st));
+    }
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     if (!b->sides.empty()) {
         HIP_TRY(hipEventRecord(b->ev_fork, st));

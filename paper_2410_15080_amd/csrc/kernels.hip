@@ -222,9 +222,10 @@ hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin
 // runs through short (the fully unrolled general form is several times
 // larger and its instruction fetches, not its arithmetic, set the time).
 template <typename T, typename TIN>
-__global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries) {
-    const FPrepEntry en = entries[blockIdx.x];
+__global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ entries, int64_t *stamp) {
     const int lane = threadIdx.x;
+    if (stamp && blockIdx.x == 0 && lane == 0) *stamp = (int64_t)wall_clock64();
+    const FPrepEntry en = entries[blockIdx.x];
     if (en.n_words > 64) {
         fprep_entry<T, TIN>(en, lane);
         return;
@@ -249,16 +250,17 @@ hipError_t launch_stamp(int64_t *dst, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st) {
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
+                        hipStream_t st) {
     (void)max_size;
     if (n_entries <= 0) return hipSuccess;
     dim3 grid(n_entries);
     if (compute == 0)
-        hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries);
+        hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries, stamp);
     else if (compute == 1)
-        hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries);
+        hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries, stamp);
     else
-        hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries);
+        hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
     return hipGetLastError();
 }
 

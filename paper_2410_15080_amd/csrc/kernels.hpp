@@ -99,7 +99,9 @@ struct FPrepEntry {
 constexpr int kFPrepDescMax = 215;
 // Elements per FPrepEntry chunk (one wave each).
 constexpr int kFPrepChunk = 4096;
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, hipStream_t st);
+// stamp (may be null): the device clock at the start of the first workgroup
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
+                        hipStream_t st);
 
 // Writes the device's constant 100 MHz clock to *dst when the launch runs.
 hipError_t launch_stamp(int64_t *dst, hipStream_t st);
