@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--path", choices=["greedy", "sampled", "learned"], default="sampled")
+    ap.add_argument("--path", choices=["greedy", "sampled", "learned"], default=None,
+                    help="contraction paths (default: sampled for grid and marginal, learned for the random "
+                         "serving batch, greedy for ring)")
     ap.add_argument("--samples", type=int, default=32)
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="measure the fused kernel's workgroup size and LDS budget first "
@@ -257,6 +259,7 @@ def bench_grid(args):
     g_ms, _ = timer.run(lambda: htn.htn_batch_run(b, outs, stream), max(3, args.steps // 2), 2)
     g_res = out.cpu().numpy()
     htn.htn_batch_destroy(b)
+    args.path = args.path or "sampled"
     if args.path != "greedy":
         log(f"planning {args.path} paths")
         nets, _ = make_nets(ws, htn.HTN_F64, htn.HTN_SUM_PLAIN, args, args.path)
@@ -340,12 +343,33 @@ def bench_random(args):
     compute = dtype_code(args.dtype or "f32")
     log(f"generating {n_nets} random networks")
     ws = configs.random_batch(0, n=n_nets, dtype=np.float64)
+    args.path = args.path or "learned"
     nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
     greedy_mults = float(sum(greedy_list))
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))
     in_bytes = sum(i.input_bytes for i in infos)
     tuned = autotune(nets, args, "random")
+
+    def path_leg(path):
+        """The same batch on other paths (same fused configuration), graph
+        launches timed the same way."""
+        pn, _ = make_nets(ws, compute, htn.HTN_SUM_FP64, args, path)
+        if tuned:
+            for n in pn:
+                htn.htn_set_option(n, htn.HTN_OPT_FUSED_THREADS, tuned["threads"])
+                htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, tuned["lds_bytes"])
+        pb, _, pouts, pst = batch_runner(pn, torch.float64, use_graph=True)
+        p_ms, _ = Timer(pst).run(lambda: htn.htn_batch_run(pb, pouts, pst), args.steps, args.warmup)
+        htn.htn_batch_destroy(pb)
+        return {"ms_per_step": round(p_ms, 4), "htns_per_s": round(n_nets / (p_ms * 1e-3), 1),
+                "executed_mults_per_step": float(sum(htn.htn_get_info(n).mults for n in pn))}
+
+    legs = {}
+    for leg in ("greedy", "sampled"):
+        if leg != args.path:
+            log(f"timing the batch on {leg} paths")
+            legs[leg] = path_leg(leg)
     n_fused = sum(1 for n in nets if json.loads(htn.htn_plan_json(n))["fused_batch_ok"])
     b, out, outs, stream = batch_runner(nets, torch.float64, use_graph=True)
     log(f"timing {args.steps} graph launches")
@@ -384,6 +408,9 @@ def bench_random(args):
         "error_vs_oracle": {"networks": int(errs.size),
                             "max_abs_err_over_abs_network": float((errs / np.maximum(bounds, 1e-300)).max())},
         "greedy_mults_per_step": greedy_mults, "executed_mults_per_step": mults,
+        "other_paths": legs,
+        "speedup_vs_flop_greedy": (round(legs["greedy"]["ms_per_step"] / ms_per_step, 3) if "greedy" in legs
+                                   else None),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 5), "traffic": None,
                      "kernel": "graph: k_fused + k_fprep + per-step kernels of the largest networks",
@@ -474,7 +501,9 @@ def bench_ring(args):
     compute = dtype_code(name)
     log(f"generating {n_nets} ring-of-rings networks")
     ws = [configs.ring_of_rings(s) for s in range(n_nets)]
-    path = "greedy" if args.path == "sampled" else args.path
+    # default FLOP-greedy: planning sampled candidates of 64-QT networks
+    # costs ~0.5 s each on the host
+    path = args.path or "greedy"
     nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_COMPENSATED, args, path)
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))

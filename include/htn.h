@@ -230,14 +230,17 @@ htn_status htn_batch_run(htn_batch_t batch, void *const *outs, void *hip_stream)
  * step by clock reads around their kernels.  ticks holds 2*n values.
  * Synchronise the stream of the run first.                                */
 htn_status htn_batch_timestamps(htn_batch_t batch, int64_t *ticks);
-/* Per-phase timing of the fused kernel.  A fused network runs as a sequence
- * of phases separated by workgroup barriers (phase 0 loads the operands of
- * the first step; phase k >= 1 runs kernel step k-1 of the plan and loads
- * the operands of the next).  With max_phases > 0 every run records, for
- * each fused net and each of its first max_phases phases, the clock at the
- * end of the phase.  htn_batch_phase_times writes n * max_phases values
- * ([net][phase], 100 MHz ticks counted from the start of the run; -1
- * for phases not recorded).  Set before a graph is captured.             */
+/* Per-phase timing.  A fused network runs as a sequence of phases
+ * separated by workgroup barriers (phase 0 loads the operands of the first
+ * steps; each later phase runs the kernel steps whose operands are ready,
+ * side by side on their own waves, and loads the operands of the next).
+ * With max_phases > 0 every run records, for each fused net and each of its
+ * first max_phases phases, the clock at the end of the phase; for a net run
+ * step by step, the clock after each of its first max_phases kernel steps
+ * (a clock read enqueued after the step's launches).
+ * htn_batch_phase_times writes n * max_phases values ([net][phase or
+ * step], 100 MHz ticks counted from the start of the run; -1 for entries
+ * not recorded).  Set before a graph is captured.                         */
 htn_status htn_batch_set_phase_timing(htn_batch_t batch, int32_t max_phases);
 htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
 /* Launch timing with HIP events.  With htn_batch_set_event_timing(batch, 1)
@@ -335,13 +338,19 @@ htn_status htn_step_features(htn_net_t net, float *features, int32_t capacity, i
 
 /* htn_batch_step_times — timing collector.  After a run with phase timing
  * on (htn_batch_set_phase_timing), the duration in microseconds of each
- * kernel step of each fused net: times[i * capacity + q] for net i and
- * kernel step q < capacity, NaN where the step was not recorded (nets run
- * step by step, steps beyond max_phases).  A fused step's duration is that
- * of its phase (its arithmetic and the copies issued for the next phase);
- * when independent steps share a phase the duration is recorded for the
- * one with the most multiplications (the phase waits for the slowest) and
- * NaN for the others.                                                    */
+ * kernel step of each net: times[i * capacity + q] for net i and kernel
+ * step q < capacity, NaN where the step was not recorded (steps beyond
+ * max_phases).  A fused step's duration is that of its phase (its
+ * arithmetic and the copies issued for the next phase); when independent
+ * steps share a phase the duration is recorded for the one with the most
+ * multiplications (the phase waits for the slowest) and NaN for the
+ * others.  A step of a net that runs step by step in every batch (its
+ * executor option, or a plan the fused kernel cannot take) lasts from the
+ * previous step's clock read (the net's start stamp for the first step, so
+ * it includes the net's input materialisation) to its own: its launches
+ * and any gap between them.  Nets moved to the per-step executor only for
+ * their size in this batch are not recorded (NaN): their step features
+ * describe the fused executor.                                           */
 htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacity);
 
 /* htn_autotune — pick the fused kernel's workgroup size and LDS budget for

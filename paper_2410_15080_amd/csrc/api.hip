@@ -418,12 +418,17 @@ static void run_mfma_step(Net &n, const StepPlan &s, const void *A, int ta, cons
     HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, s.ksplit, kpart, st));
 }
 
-static void run_steps(Net &n, void *out, hipStream_t st) {
+// ticks (optional): the device clock after each of the first max_ticks
+// kernel steps.
+static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullptr, int max_ticks = 0) {
     DeviceState &D = *n.dev;
     const Plan &P = n.plan;
     const int tin = (int)input_dtype(n.compute), tint = (int)inter_dtype(n.compute);
     if (D.n_prep) HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep, D.prep_max, tin, tint, D.d_tab, st));
+    int q = -1;
     for (int k : P.kernel_steps) {
+        if (ticks && q >= 0 && q < max_ticks) HIP_TRY(kern::launch_stamp(ticks + q, st));
+        ++q;
         const StepPlan &s = P.steps[k];
         auto operand = [&](int id, const void *&ptr, int &t) {
             if (id < 0) {
@@ -476,6 +481,7 @@ static void run_steps(Net &n, void *out, hipStream_t st) {
         }
         HIP_TRY(kern::launch_step(A, ta, B, tb, C, tc, tc == 0, comp, D.d_tab, a, st));
     }
+    if (ticks && q >= 0 && q < max_ticks) HIP_TRY(kern::launch_stamp(ticks + q, st));
 }
 
 static void contract_one(Net &n, void *out, hipStream_t st) {
@@ -899,7 +905,8 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
         const int i = b->step_nets[k];
         hipStream_t ss = b->sides[b->side_of[k]];
         HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * (size_t)i, ss));
-        run_steps(*b->nets[i], outs[i], ss);
+        run_steps(*b->nets[i], outs[i], ss, b->d_phase ? b->d_phase + (size_t)i * b->max_phases : nullptr,
+                  b->max_phases);
         HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * (size_t)i + 1, ss));
     }
     for (size_t q = 0; q < b->sides.size(); ++q) {
@@ -1061,6 +1068,19 @@ htn_status htn_batch_step_times(htn_batch_t b, float *times, int32_t capacity) {
                 times[(size_t)i * capacity + q] = (float)(t[f] - begin) * 0.01f;  // 100 MHz ticks -> us
             }
         }
+    // nets run step by step: the clock after each kernel step (only nets
+    // that run step by step in any batch: a net moved off the fused kernel
+    // for its size in this batch is described by fused-executor features)
+    for (int i : b->step_nets) {
+        if (use_fused_in_batch(*b->nets[i])) continue;
+        const Plan &P = b->nets[i]->plan;
+        const int64_t *t = ph.data() + (size_t)i * mp;
+        for (int q = 0; q < (int)P.kernel_steps.size() && q < capacity && q < mp; ++q) {
+            const int64_t begin = q == 0 ? st[2 * (size_t)i] : t[q - 1];
+            if (t[q] < 0 || begin < 0 || t[q] < begin) continue;
+            times[(size_t)i * capacity + q] = (float)(t[q] - begin) * 0.01f;
+        }
+    }
     return HTN_OK;
     API_GUARD_END
 }

@@ -7,9 +7,12 @@
 // planned, each of its kernel steps is described by a feature row, and the
 // model's predicted step times are combined (a fused phase costs its slowest
 // step, phases and per-step launches add up); the fastest predicted
-// candidate wins, FLOP-greedy on ties.
+// candidate among those within twice the fewest multiplications wins,
+// FLOP-greedy on ties (or the first such candidate when FLOP-greedy itself
+// lies outside that range).
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 #include "htn_core.hpp"
 
@@ -93,6 +96,8 @@ std::vector<std::pair<int, int>> learned_path(const Net &n) {
     std::vector<int> owner;  // candidate of each row
     std::vector<int> group;  // fused phase of each row (-1: per-step executor)
     std::vector<char> ok(cands.size(), 0);
+    std::vector<double> mults(cands.size(), 0.0);
+    double min_mults = std::numeric_limits<double>::infinity();
     for (size_t c = 0; c < cands.size(); ++c) {
         t.path = cands[c];
         try {
@@ -102,6 +107,8 @@ std::vector<std::pair<int, int>> learned_path(const Net &n) {
             continue;           // e.g. above the intermediate cap
         }
         ok[c] = 1;
+        mults[c] = t.plan.mults;
+        min_mults = std::min(min_mults, mults[c]);
         const size_t before = rows.size();
         step_features(t, rows);
         owner.insert(owner.end(), (rows.size() - before) / kFeatures, (int)c);
@@ -128,9 +135,15 @@ std::vector<std::pair<int, int>> learned_path(const Net &n) {
         for (double d : phase) total[owner[r]] += d;
         r = e;
     }
+    // trust region: the model ranks candidates within kTrust times the
+    // fewest multiplications among them (it is trained on paths near the
+    // FLOP optimum and does not extrapolate to far costlier ones)
+    constexpr double kTrust = 2.0;
     size_t best = 0;
     for (size_t c = 1; c < cands.size(); ++c)
-        if (ok[c] && std::isfinite(total[c]) && total[c] < total[best]) best = c;
+        if (ok[c] && mults[c] <= kTrust * min_mults && std::isfinite(total[c]) &&
+            (mults[best] > kTrust * min_mults || total[c] < total[best]))
+            best = c;
     return cands[best];
 }
 

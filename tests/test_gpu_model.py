@@ -139,6 +139,35 @@ def test_step_times_cover_every_fused_step():
         assert htn.htn_step_features(nets[i]).shape == (ki, htn.HTN_MODEL_FEATURES)
 
 
+def test_step_times_cover_nets_run_step_by_step():
+    """Nets forced onto the per-step executor get one duration per kernel
+    step from clock reads between their launches; together they span the
+    net's run."""
+    import torch
+    ws = [configs.grid_network(900 + s) for s in range(6)]
+    nets = [htn.htn_create([torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in w.tensors], w.labels,
+                           w.dims, w.out_labels) for w in ws]
+    for n in nets[:3]:
+        htn.htn_set_option(n, htn.HTN_OPT_EXEC, htn.HTN_EXEC_STEPS)
+    outs = [htn.new_output(n) for n in nets]
+    b = htn.htn_batch_create(nets)
+    htn.htn_batch_set_phase_timing(b, 64)
+    htn.htn_batch_run(b, htn.pointer_array(outs))
+    torch.cuda.synchronize()
+    k = [htn.htn_get_info(n).n_kernel_steps for n in nets]
+    tm = htn.htn_batch_step_times(b, max(k))
+    se = htn.htn_batch_timestamps(b)
+    for i in range(3):
+        rec = tm[i, :k[i]]
+        assert np.all(np.isfinite(rec)) and np.all(rec > 0)
+        assert rec.sum() <= (se[i, 1] - se[i, 0]) * 0.01 + 1e-3
+        assert htn.htn_step_features(nets[i])[:, 21].max() == 0.0  # per-step executor rows
+    import oracle
+    for w, o in zip(ws, outs):
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        assert abs(float(o[0].item()) - (hi + lo)) <= 1e-10 * max(1.0, abs(hi + lo))
+
+
 def _batch_ms(nets, reps=20):
     import torch
     outs = [htn.new_output(n) for n in nets]
