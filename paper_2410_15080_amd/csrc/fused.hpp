@@ -498,14 +498,9 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
             p += 1;
             continue;
         }
-        if (op == OP_COPY) {
-            const CopyOp c = decode_copy(p, gimg, (const unsigned char *)d.scratch);
-            copy_chunks<BLK>(c.src, (u32x4 *)smem + c.dst, c.n);
-            p += 5;
-            continue;
-        }
         // A phase: consecutive step ops (independent steps, each run by its
-        // own waves [w0, w0 + nw)), then the copies for the next phase.
+        // own waves [w0, w0 + nw); none in the first phase, which only loads
+        // operands), then the copies for the next phase.
         auto step_length = [](const int32_t *r) { return r[0] == OP_TSTEP ? 15 + 4 * (r[11] + r[12]) : 17; };
         const int32_t *const steps0 = p;
         const int32_t *q = p;
