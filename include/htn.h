@@ -148,12 +148,12 @@ htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks,
  *                 exp(-(log2 cost - log2 min cost) / T), T cycling through
  *                 0.25, 0.5, 1, 2; deterministic for a given
  *                 HTN_OPT_PATH_SEED.  Never costlier than FLOP-greedy.
- *   HTN_PATH_LEARNED  the candidate (FLOP-greedy plus the sampled paths)
+ *   HTN_PATH_LEARNED  among the candidates (FLOP-greedy plus the sampled
+ *                 paths) within twice the fewest multiplications, the one
  *                 with the lowest total time predicted by the net's cost
  *                 model (htn_set_model); FLOP-greedy when the net has no
- *                 model or when no candidate is predicted faster than
- *                 FLOP-greedy.  Runs the model on the current device and
- *                 waits for it.
+ *                 model, and on ties.  Runs the model on the current device
+ *                 and waits for it.
  * Errors: HTN_E_PATH for a malformed path; HTN_E_OOM if an intermediate
  * exceeds the size cap (htn_set_option HTN_OPT_MAX_INTERMEDIATE).
  * ------------------------------------------------------------------- */
