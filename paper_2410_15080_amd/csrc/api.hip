@@ -436,7 +436,8 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
                 t = tint;
             } else if (P.ws_off[id] >= 0) {
                 ptr = (const unsigned char *)D.d_ws + P.ws_off[id];
-                t = tint;
+                const int pr = P.values[id].producer;
+                t = (!P.values[id].input && pr >= 0 && P.steps[pr].out_bf16) ? (int)HTN_BF16 : tint;
             } else {
                 ptr = D.in[P.values[id].base];
                 t = tin;
@@ -455,7 +456,7 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
             comp = n.final_sum == HTN_SUM_COMPENSATED;
         } else {
             C = (unsigned char *)D.d_ws + P.ws_off[s.c];
-            tc = tint;
+            tc = s.out_bf16 ? (int)HTN_BF16 : tint;
         }
         if (s.mfma) {
             run_mfma_step(n, s, A, ta, B, tb, C, tc, st);

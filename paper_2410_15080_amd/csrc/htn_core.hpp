@@ -29,6 +29,7 @@ struct StepPlan {
     double mults = 0.0;                   // paper's cost of the step
     bool absorbed = false;   // folded into the larger operand's load
     bool final_step = false; // writes the net's output
+    bool out_bf16 = false;   // writes its result as BF16 (a packed matrix-core operand)
     bool synthetic = false;  // added by the planner, not part of the path
     // Kernel geometry (kernel steps only).  Output index o = o_hi*n_olo+o_lo,
     // summed index s = s_hi*n_slo+s_lo.  Each table entry is an (A offset,

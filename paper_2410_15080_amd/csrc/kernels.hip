@@ -153,7 +153,10 @@ static hipError_t step_out(const void *A, const void *B, void *C, int tc, bool c
         if (unary) return go_step<TA, TA, float, float, true, false>(A, B, C, tab, s, st);
         return go_step<TA, TB, float, float, false, false>(A, B, C, tab, s, st);
     }
-    if (tc == 2 && !comp && unary) return go_step<TA, TA, bf16_t, float, true, false>(A, B, C, tab, s, st);
+    if (tc == 2 && !comp) {
+        if (unary) return go_step<TA, TA, bf16_t, float, true, false>(A, B, C, tab, s, st);
+        return go_step<TA, TB, bf16_t, float, false, false>(A, B, C, tab, s, st);
+    }
     return hipErrorInvalidValue;
 }
 

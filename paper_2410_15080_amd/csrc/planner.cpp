@@ -676,13 +676,14 @@ void build_plan(Net &n) {
         return true;
     };
     // An intermediate consumed by a matrix-core step is written by its
-    // producer directly in the packed order [batch][M][K] / [batch][N][K],
-    // so that no pack launch is needed (the element type must also match:
-    // BF16 operands are packed from FP32 intermediates).  Only for networks
-    // above the batch limit of the fused kernel (those run step by step in
-    // every executor choice except an explicit HTN_EXEC_FUSED); below it
-    // the register-tiled layout of the fused kernel keeps precedence.
-    const bool packed_layouts = n.compute != HTN_BF16 && P.mults > n.batch_fused_max_mults;
+    // producer directly in the packed order [batch][M][K] / [batch][N][K]
+    // (as BF16 when the compute type is BF16: the producer rounds where the
+    // pack would have), so that no pack launch is needed.  Only for
+    // networks above the batch limit of the fused kernel (those run step by
+    // step in every executor choice except an explicit HTN_EXEC_FUSED);
+    // below it the register-tiled layout of the fused kernel keeps
+    // precedence.
+    const bool packed_layouts = P.mults > n.batch_fused_max_mults;
     if (packed_layouts)
         for (int k : P.kernel_steps) {
             StepPlan &s = P.steps[k];
@@ -812,7 +813,9 @@ void build_plan(Net &n) {
             pack(s.a_labels, sta, s.g_m, s.pack_a);
             pack(s.b_labels, stb, s.g_n, s.pack_b);
             auto in_order = [&](int v, const std::vector<int> &mid) {
-                if (P.values[v].input || n.compute == HTN_BF16) return false;
+                if (P.values[v].input) return false;
+                const StepPlan &prod = P.steps[P.values[v].producer];
+                if (prod.mfma || prod.final_step || (prod.absorbed && n.compute == HTN_BF16)) return false;
                 std::vector<int> o = s.g_batch;
                 o.insert(o.end(), mid.begin(), mid.end());
                 o.insert(o.end(), s.g_k.begin(), s.g_k.end());
@@ -820,6 +823,10 @@ void build_plan(Net &n) {
             };
             s.pack_a.identity = in_order(s.a, s.g_m);
             s.pack_b.identity = in_order(s.b, s.g_n);
+            if (n.compute == HTN_BF16) {
+                if (s.pack_a.identity) P.steps[P.values[s.a].producer].out_bf16 = true;
+                if (s.pack_b.identity) P.steps[P.values[s.b].producer].out_bf16 = true;
+            }
         }
         s.n_out = s.n_ohi * s.n_olo;
         s.n_sum = s.n_shi * s.n_slo;

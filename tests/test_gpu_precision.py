@@ -81,17 +81,23 @@ def _rounded_bf16(w):
     return out
 
 
+@pytest.mark.parametrize("bits", [8, 9])
 @pytest.mark.parametrize("compute", [htn.HTN_F64, htn.HTN_F32, htn.HTN_BF16])
-def test_marginal_matrix_core_paths(compute):
-    """256 x 256 marginal, K = 256: the last step runs on the matrix cores."""
-    w = configs.marginal_network(5, out_bits=8)
+def test_marginal_matrix_core_paths(compute, bits):
+    """256 x 256 and 512 x 512 marginals, K = 256: the last step runs on the
+    matrix cores; at 512 x 512 (above the fused kernel's batch limit) the
+    folds write the GEMM operands in packed order (BF16: rounded by the
+    fold) and no pack runs."""
+    w = configs.marginal_network(5, out_bits=bits)
     hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
     ref = hi + lo
     fs = htn.HTN_SUM_PLAIN if compute == htn.HTN_F64 else htn.HTN_SUM_FP64
     net = create(w, compute=compute, final_sum=fs, storage=htn.HTN_F64, exec_mode=htn.HTN_EXEC_STEPS)
     plan = json.loads(htn.htn_plan_json(net))
     assert plan["steps"][-1]["mfma"] == 1
-    got = contract(net, (256, 256))
+    assert plan["steps"][-1]["pack_id"] == ([1, 1] if bits == 9 else [0, 0])
+    side = 1 << bits
+    got = contract(net, (side, side))
     err = float(np.abs(got - ref).max())
     absval = _abs_value(w)
     if compute == htn.HTN_F64:
