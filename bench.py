@@ -72,8 +72,8 @@ def parse():
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 21 429.25 x 2048 B, WRITE_SIZE 5 043.6 x 1024 B
-    "k_fused_grid": {"read_bytes": 43_887_104, "write_bytes": 5_164_640, "sources": "860b73e95ece24d1",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 21 374.375 x 2048 B, WRITE_SIZE 5 046.125 x 1024 B
+    "k_fused_grid": {"read_bytes": 43_774_720, "write_bytes": 5_167_232, "sources": "72759d770baef9e7",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
