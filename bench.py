@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--path", choices=["greedy", "sampled", "learned"], default=None,
                     help="contraction paths (default: sampled for grid and marginal, learned for the random "
                          "serving batch, greedy for ring)")
-    ap.add_argument("--samples", type=int, default=32)
+    ap.add_argument("--samples", type=int, default=None,
+                    help="sampled path candidates per network (default: 128 for grid, 32 otherwise)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="measure the fused kernel's workgroup size and LDS budget first "
                          "(auto: on for the random and ring batches)")
@@ -72,8 +73,8 @@ def parse():
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 21 374.375 x 2048 B, WRITE_SIZE 5 046.125 x 1024 B
-    "k_fused_grid": {"read_bytes": 43_774_720, "write_bytes": 5_167_232, "sources": "72759d770baef9e7",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 19 183.25 x 2048 B, WRITE_SIZE 993.1875 x 1024 B
+    "k_fused_grid": {"read_bytes": 39_287_296, "write_bytes": 1_017_024, "sources": "72759d770baef9e7",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
@@ -260,6 +261,7 @@ def bench_grid(args):
     g_res = out.cpu().numpy()
     htn.htn_batch_destroy(b)
     args.path = args.path or "sampled"
+    args.samples = args.samples or 128
     if args.path != "greedy":
         log(f"planning {args.path} paths")
         nets, _ = make_nets(ws, htn.HTN_F64, htn.HTN_SUM_PLAIN, args, args.path)
@@ -324,7 +326,8 @@ def bench_grid(args):
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5),
                      "traffic": measured_traffic("k_fused_grid", runs_ok=(args.lds == 65536 and args.threads == 256
-                                                                           and args.path == "sampled")),
+                                                                           and args.path == "sampled"
+                                                                           and args.samples == 128)),
                      "kernel": "k_fused<256,double,double,0>", "kernel_ms": round(fused_ms, 4),
                      "flops_per_launch": 2.0 * mults, "k_fprep_ms": round(prep_ms, 4),
                      "batch_ms_events": round(kern_ms, 4), "input_bytes": in_bytes},
@@ -344,6 +347,7 @@ def bench_random(args):
     log(f"generating {n_nets} random networks")
     ws = configs.random_batch(0, n=n_nets, dtype=np.float64)
     args.path = args.path or "learned"
+    args.samples = args.samples or 32
     nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
     greedy_mults = float(sum(greedy_list))
     infos = [htn.htn_get_info(n) for n in nets]
@@ -504,6 +508,7 @@ def bench_ring(args):
     # default FLOP-greedy: planning sampled candidates of 64-QT networks
     # costs ~0.5 s each on the host
     path = args.path or "greedy"
+    args.samples = args.samples or 32
     nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_COMPENSATED, args, path)
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))
