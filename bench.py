@@ -60,7 +60,7 @@ def parse():
                     help="contraction paths (default: sampled for grid and marginal, learned for the random "
                          "serving batch, greedy for ring)")
     ap.add_argument("--samples", type=int, default=None,
-                    help="sampled path candidates per network (default: 128 for grid, 32 otherwise)")
+                    help="sampled path candidates per network (default: 128 for grid and random, 32 for ring)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="measure the fused kernel's workgroup size and LDS budget first "
                          "(auto: on for the random and ring batches)")
@@ -347,7 +347,7 @@ def bench_random(args):
     log(f"generating {n_nets} random networks")
     ws = configs.random_batch(0, n=n_nets, dtype=np.float64)
     args.path = args.path or "learned"
-    args.samples = args.samples or 32
+    args.samples = args.samples or 128
     nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
     greedy_mults = float(sum(greedy_list))
     infos = [htn.htn_get_info(n) for n in nets]
