@@ -498,17 +498,16 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
             p += 1;
             continue;
         }
-        // A phase: consecutive step ops (independent steps, each run by its
+        // A phase: the copies for the next phase (tables and operands; they
+        // land after this phase's steps, in regions no step of the phase
+        // touches), then the step ops (independent steps, each run by its
         // own waves [w0, w0 + nw); none in the first phase, which only loads
-        // operands), then the copies for the next phase.
+        // operands).  The copies come first so that their loads are issued
+        // before the steps are decoded: each thread stages up to kPrefetch
+        // chunks in registers while the steps run.
         auto step_length = [](const int32_t *r) { return r[0] == OP_TSTEP ? 15 + 4 * (r[11] + r[12]) : 17; };
-        const int32_t *const steps0 = p;
+        const int32_t *const copies0 = p;
         const int32_t *q = p;
-        while (q[0] == OP_STEP || q[0] == OP_TSTEP) q += step_length(q);
-        const int32_t *const copies0 = q;
-        // issue the following copies (next phase's tables and operands):
-        // each thread stages up to kPrefetch chunks in registers while the
-        // steps run
         CopyOp cps[4];
         int starts[5] = {0, 0, 0, 0, 0};
         int nc = 0, tot = 0;
@@ -546,8 +545,14 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
             dst2 = dst[2];
             dst3 = dst[3];
         }
+        const int32_t *const staged_end = q;  // copy ops [copies0, staged_end) are staged
+        while (q[0] == OP_COPY) q += 5;        // more than four copy ops: copied after the steps
+        const int32_t *const copies_end = q;
+        const int32_t *const steps0 = q;
+        while (q[0] == OP_STEP || q[0] == OP_TSTEP) q += step_length(q);
+        const int32_t *const steps_end = q;
         const int wave = threadIdx.x >> 6;
-        for (const int32_t *op_w = steps0; op_w != copies0; op_w += step_length(op_w)) {
+        for (const int32_t *op_w = steps0; op_w != steps_end; op_w += step_length(op_w)) {
             const int w0 = op_w[0] == OP_TSTEP ? op_w[13] : op_w[15];
             const int nw = op_w[0] == OP_TSTEP ? op_w[14] : op_w[16];
             if (wave < w0 || wave >= w0 + nw) continue;  // wave-uniform
@@ -601,18 +606,19 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
         if (dst1 >= 0) lds4[dst1] = stg1;
         if (dst2 >= 0) lds4[dst2] = stg2;
         if (dst3 >= 0) lds4[dst3] = stg3;
-        if (tot > kPrefetch * BLK) {
+        if (tot > kPrefetch * BLK || copies_end != staged_end) {
             // rare: re-read the copy ops (their decoded form is not kept
-            // live across the step) and copy the chunks beyond the staged ones
+            // live across the step) and copy the chunks beyond the staged
+            // ones, then any copy op past the fourth
             int start = 0;
-            for (const int32_t *r = copies0; r != q; r += 5) {
+            for (const int32_t *r = copies0; r != copies_end; r += 5) {
                 const CopyOp c = decode_copy(r, gimg, (const unsigned char *)d.scratch);
-                const int skip = max(0, kPrefetch * BLK - start);
+                const int skip = r < staged_end ? max(0, kPrefetch * BLK - start) : 0;
                 if (skip < c.n) copy_chunks<BLK>(c.src + skip, lds4 + c.dst + skip, c.n - skip);
                 start += c.n;
             }
         }
-        p = q;
+        p = steps_end;
     }
     if (stamps && threadIdx.x == 0) {
         stamps[2 * net] = t0;
@@ -621,7 +627,7 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
 }
 
 template <int BLK, typename T, typename TIN, int FM>
-__global__ __launch_bounds__(BLK) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2))) void k_fused(const FusedDesc *__restrict__ nets, const int32_t *__restrict__ order,
                                                void *const *__restrict__ outs, int64_t *__restrict__ stamps,
                                                void *out1, int64_t *__restrict__ phase_ticks, int max_phases) {
     const int net = order ? order[blockIdx.x] : (int)blockIdx.x;

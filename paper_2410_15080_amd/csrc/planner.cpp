@@ -1170,8 +1170,25 @@ void build_plan(Net &n) {
             ++n_ops;
         }
         std::vector<int32_t> prog = {0, 0, n_ops, (int32_t)slot0, (int32_t)slot_words, (int32_t)scratch_byte, 0, 0};
-        for (auto &r : seq)
-            if (!(r.kind == OP_COPY && r.w[3] == 0)) prog.insert(prog.end(), r.w.begin(), r.w.end());
+        // within a phase the copies (which land after its steps, into
+        // regions no step of the phase touches) come first, so the kernel
+        // issues their loads before decoding the steps
+        {
+            std::vector<int32_t> steps_of_phase;
+            for (auto &r : seq) {
+                if (r.kind == OP_COPY && r.w[3] == 0) continue;
+                if (r.kind == OP_STEP || r.kind == OP_TSTEP) {
+                    steps_of_phase.insert(steps_of_phase.end(), r.w.begin(), r.w.end());
+                    continue;
+                }
+                if (r.kind == OP_SYNC) {
+                    prog.insert(prog.end(), steps_of_phase.begin(), steps_of_phase.end());
+                    steps_of_phase.clear();
+                }
+                prog.insert(prog.end(), r.w.begin(), r.w.end());
+            }
+            prog.insert(prog.end(), steps_of_phase.begin(), steps_of_phase.end());
+        }
         prog.push_back(OP_END);
         prog.resize(prog_words, 0);
         prog[0] = (int32_t)prog_words;
