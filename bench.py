@@ -73,8 +73,8 @@ def parse():
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 19 183.25 x 2048 B, WRITE_SIZE 993.1875 x 1024 B
-    "k_fused_grid": {"read_bytes": 39_287_296, "write_bytes": 1_017_024, "sources": "72759d770baef9e7",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 19 217.5 x 2048 B, WRITE_SIZE 993.40625 x 1024 B
+    "k_fused_grid": {"read_bytes": 39_357_440, "write_bytes": 1_017_248, "sources": "af6e1d77f20c0f03",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
