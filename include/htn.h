@@ -59,7 +59,7 @@ typedef enum {
     HTN_E_OOM = 5,         /* host/device allocation failed, or a peak
                               intermediate above the configured cap      */
     HTN_E_DEVICE = 6,      /* HIP runtime error                          */
-    HTN_E_UNSUPPORTED = 7, /* valid request this build does not support  */
+    HTN_E_UNSUPPORTED = 7, /* valid request the library does not support  */
     HTN_E_STATE = 8        /* call out of order (e.g. no device data)    */
 } htn_status;
 
