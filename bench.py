@@ -276,6 +276,14 @@ def bench_grid(args):
     prep_ms, fused_ms, runs = htn.htn_batch_launch_ms(b)
     assert runs == args.steps
     got = out.cpu().numpy()
+    eager_ms = ms_per_step
+    # the same batch replayed as a captured HIP graph (the timed line; the
+    # eager run above gives the per-launch event timing)
+    gb, gout, gouts, gstream = batch_runner(nets, torch.float64, use_graph=True)
+    log(f"timing {args.steps} graph launches")
+    ms_per_step, _ = Timer(gstream).run(lambda: htn.htn_batch_run(gb, gouts, gstream), args.steps, args.warmup)
+    assert np.array_equal(gout.cpu().numpy(), got), "graph replay differs from the eager run"
+    htn.htn_batch_destroy(gb)
     errs = []
     for i in range(0, n_nets, max(1, n_nets // 32)):
         ref = oracle_ref(ws[i])
@@ -312,10 +320,11 @@ def bench_grid(args):
         "config": {"workload": "grid4x4_htn_batch", "networks": n_nets, "qts_per_net": 16,
                    "cuts_per_net": 24, "cut_dims": "wire 4 / CZ gate 6, 50/50 by seed",
                    "path": args.path, "path_samples": args.samples,
-                   "executor": "input prep + fused kernel, one workgroup per network",
+                   "executor": "input prep + fused kernel, one workgroup per network, HIP graph",
                    "lds_budget_bytes": args.lds, "threads_per_network": args.threads,
                    "fused_networks": sum(1 for i in infos if i.fused_ok)},
         "htns_per_s": round(htns, 1),
+        "eager_ms_per_step": round(eager_ms, 4),
         "max_rel_err_vs_oracle": float(max(errs)),
         "greedy_mults_per_step": greedy_mults,
         "executed_mults_per_step": mults,
