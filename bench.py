@@ -360,12 +360,19 @@ def bench_random(args):
     ws = configs.random_batch(0, n=n_nets, dtype=np.float64)
     args.path = args.path or "learned"
     args.samples = args.samples or 128
-    nets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
+    # the fused configuration is tuned first (on FLOP-greedy paths) so that
+    # the cost model is trained, and the paths are chosen, under the
+    # configuration the batch then runs with
+    gnets, greedy_list = make_nets(ws, compute, htn.HTN_SUM_FP64, args, "greedy")
+    tuned = autotune(gnets, args, "random")
+    del gnets
+    if tuned:
+        args.threads, args.lds = tuned["threads"], tuned["lds_bytes"]
+    nets, _ = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
     greedy_mults = float(sum(greedy_list))
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))
     in_bytes = sum(i.input_bytes for i in infos)
-    tuned = autotune(nets, args, "random")
 
     def path_leg(path):
         """The same batch on other paths (same fused configuration), graph
