@@ -213,8 +213,8 @@ def train_model(ws, compute, final_sum, args):
     else:
         tws = ws[: min(32, len(ws))]
     tnets, _ = make_nets(tws, compute, final_sum, args, "greedy")
-    X, t = learned.collect_step_timings(tnets, runs=2)
-    model, losses = learned.train_cost_model(X, t, epochs=150, batch=256, lr=2e-3)
+    X, t = learned.collect_step_timings(tnets, runs=4)
+    model, losses = learned.train_cost_model(X, t, epochs=300, batch=256, lr=2e-3)
     log(f"  {X.shape[0]} step timings, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
     return model
 
