@@ -369,6 +369,8 @@ def bench_random(args):
     if tuned:
         args.threads, args.lds = tuned["threads"], tuned["lds_bytes"]
     nets, _ = make_nets(ws, compute, htn.HTN_SUM_FP64, args, args.path)
+    if tuned and args.path != "greedy":
+        tuned = autotune(nets, args, "random")  # again, for the chosen paths
     greedy_mults = float(sum(greedy_list))
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))
