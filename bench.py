@@ -209,7 +209,7 @@ def train_model(ws, compute, final_sum, args):
     if kind == "grid":
         tws = [configs.grid_network(100000 + s) for s in range(128)]
     elif kind == "random_batch":
-        tws = configs.random_batch(100000, n=256)
+        tws = configs.random_batch(100000, n=512)
     else:
         tws = ws[: min(32, len(ws))]
     tnets, _ = make_nets(tws, compute, final_sum, args, "greedy")
