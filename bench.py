@@ -207,7 +207,7 @@ def train_model(ws, compute, final_sum, args):
     log("training the cost model")
     kind = ws[0].meta.get("config")
     if kind == "grid":
-        tws = [configs.grid_network(100000 + s) for s in range(128)]
+        tws = [configs.grid_network(100000 + s) for s in range(512)]
     elif kind == "random_batch":
         tws = configs.random_batch(100000, n=512)
     else:
