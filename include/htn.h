@@ -391,6 +391,65 @@ htn_status htn_plan_json(htn_net_t net, char *buf, int64_t capacity, int64_t *ne
  * htn_plan_json ("t_*" fields) index pairs of this arena.                  */
 htn_status htn_plan_tables(htn_net_t net, int32_t *buf, int64_t capacity, int64_t *needed);
 
+/* ---------------------------------------------------------------------
+ * QPD sampling and h-TN simplification (Sec. 4.3, Fig. 3 (d); Step 1 of
+ * Sec. 6.1).  Each sampled coefficient tensor c (rank 1, length n) is drawn
+ * s_qpd times on its own, index i with probability |c_i| / gamma,
+ * gamma = sum |c_i|; indices drawn zero times are dropped from the CT and
+ * from every QT carrying its label.  Wire-cut tensors are not sampled (all
+ * their terms weigh the same): the caller leaves them out.
+ *
+ * htn_qpd_sample (host) — one CT's draws and estimator weights.
+ *   coeffs[n]     the CT's coefficients (host, FP64, finite, not all 0).
+ *   s_qpd >= 1    number of draws.
+ *   uniforms[s_qpd]  host uniforms in [0, 1), one per draw (the caller's
+ *                 random numbers): draw j goes to the first index i with
+ *                 uniforms[j] < F_i, F_i = (|c_0| + ... + |c_i|) / gamma
+ *                 accumulated left to right in FP64; a draw that rounding
+ *                 puts past F_{n-1} goes to the last non-zero index.
+ *   counts[n]     out: n_i, the draws of index i (they sum to s_qpd).
+ *   weights[n]    out: the unbiased QPD estimator weight of index i,
+ *                 n_i * gamma * sign(c_i) / s_qpd (0 where n_i = 0); its
+ *                 expectation over the draws is c_i.
+ * Errors: HTN_E_ARG for NULL pointers, n < 1, s_qpd < 1, a non-finite
+ * coefficient, all coefficients 0 or a uniform outside [0, 1).
+ * ------------------------------------------------------------------- */
+htn_status htn_qpd_sample(int32_t n, const double *coeffs, int64_t s_qpd, const double *uniforms,
+                          int64_t *counts, double *weights);
+
+/* htn_truncation — one tensor to truncate (all pointers are the caller's).
+ *   src           device, row-major (last axis fastest), extents dims[].
+ *   dst           device, row-major, extent n_kept[a] on axis a (dims[a]
+ *                 where kept[a] is NULL); must not overlap src.
+ *   rank          1..HTN_TRUNC_MAX_RANK.
+ *   kept[a]       host list of the n_kept[a] indices (each in [0, dims[a]),
+ *                 in the order they take in dst) that axis a keeps; NULL
+ *                 keeps the whole axis (n_kept[a] ignored).              */
+#define HTN_TRUNC_MAX_RANK 16
+typedef struct {
+    const void *src;
+    void *dst;
+    int32_t rank;
+    int64_t dims[HTN_TRUNC_MAX_RANK];
+    const int32_t *kept[HTN_TRUNC_MAX_RANK];
+    int32_t n_kept[HTN_TRUNC_MAX_RANK];
+} htn_truncation;
+typedef struct htn_trunc *htn_trunc_t;
+
+/* htn_truncate_create — validate n >= 1 items of element type `dtype` and
+ * upload their gather descriptors to the current device (synchronous).
+ * The src/dst buffers are borrowed: they must stay allocated for the life
+ * of the handle.  Errors: HTN_E_ARG (NULL pointers, bad rank or dtype,
+ * n_kept < 1, an index out of range), HTN_E_UNSUPPORTED (an item with
+ * 2^31 or more elements), HTN_E_OOM, HTN_E_DEVICE.
+ * htn_truncate_run — enqueue the batch's gather (one kernel launch) on
+ * hip_stream (NULL: the default stream); dst[o] = src[the element whose
+ * index on each axis a is kept[a][o_a]].  Bit-exact copies.
+ * htn_truncate_destroy — free the descriptors (NULL is ignored).         */
+htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation *items, htn_dtype dtype);
+htn_status htn_truncate_run(htn_trunc_t t, void *hip_stream);
+void htn_truncate_destroy(htn_trunc_t t);
+
 #ifdef __cplusplus
 }
 #endif

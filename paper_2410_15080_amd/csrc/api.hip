@@ -1460,3 +1460,133 @@ const char *htn_status_string(htn_status s) {
 const char *htn_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// QPD sampling and truncation (Sec. 4.3)
+// ---------------------------------------------------------------------------
+
+struct htn_trunc {
+    int n = 0;
+    int elem_bytes = 8;
+    int64_t n_blocks = 0;
+    kern::TruncItem *d_items = nullptr;
+    int64_t *d_maps = nullptr;
+    ~htn_trunc() {
+        if (d_items) (void)hipFree(d_items);
+        if (d_maps) (void)hipFree(d_maps);
+    }
+};
+
+extern "C" {
+
+htn_status htn_qpd_sample(int32_t n, const double *coeffs, int64_t s_qpd, const double *uniforms, int64_t *counts,
+                          double *weights) {
+    API_GUARD_BEGIN
+    if (n < 1 || s_qpd < 1 || !coeffs || !uniforms || !counts || !weights) return fail(HTN_E_ARG, "bad arguments");
+    double gamma = 0.0;
+    int last = -1;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(coeffs[i])) return fail(HTN_E_ARG, "non-finite coefficient");
+        gamma += std::fabs(coeffs[i]);
+        if (coeffs[i] != 0.0) last = i;
+    }
+    if (last < 0) return fail(HTN_E_ARG, "all coefficients are 0");
+    std::vector<double> cdf((size_t)n);
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        acc += std::fabs(coeffs[i]);
+        cdf[(size_t)i] = acc / gamma;
+    }
+    std::vector<int64_t> c((size_t)n, 0);
+    for (int64_t j = 0; j < s_qpd; ++j) {
+        const double u = uniforms[j];
+        if (!(u >= 0.0 && u < 1.0)) return fail(HTN_E_ARG, "uniform outside [0, 1)");
+        // first i with u < F_i
+        const int i = (int)(std::upper_bound(cdf.begin(), cdf.end(), u) - cdf.begin());
+        ++c[(size_t)std::min(i, last)];
+    }
+    for (int i = 0; i < n; ++i) {
+        counts[i] = c[(size_t)i];
+        const double sg = coeffs[i] > 0.0 ? 1.0 : (coeffs[i] < 0.0 ? -1.0 : 0.0);
+        weights[i] = (double)c[(size_t)i] * gamma * sg / (double)s_qpd;
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation *items, htn_dtype dtype) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !items) return fail(HTN_E_ARG, "bad item list");
+    if (dtype != HTN_F64 && dtype != HTN_F32 && dtype != HTN_BF16) return fail(HTN_E_ARG, "bad dtype");
+    std::vector<kern::TruncItem> h((size_t)n);
+    std::vector<int64_t> maps;
+    int64_t blocks = 0;
+    constexpr int64_t per_block = kern::kTruncThreads * kern::kTruncPerThread;
+    for (int i = 0; i < n; ++i) {
+        const htn_truncation &t = items[i];
+        if (!t.src || !t.dst) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": NULL buffer");
+        if (t.rank < 1 || t.rank > HTN_TRUNC_MAX_RANK) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad rank");
+        kern::TruncItem &k = h[(size_t)i];
+        k = kern::TruncItem{};
+        k.src = t.src;
+        k.dst = t.dst;
+        k.rank = t.rank;
+        k.map_off = (int64_t)maps.size();
+        int64_t stride = 1, n_out = 1;
+        std::vector<int64_t> strides((size_t)t.rank);
+        for (int a = t.rank - 1; a >= 0; --a) {
+            if (t.dims[a] < 1 || t.dims[a] > std::numeric_limits<int32_t>::max())
+                return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad extent");
+            strides[(size_t)a] = stride;
+            if (stride > (int64_t(1) << 40) / t.dims[a]) return fail(HTN_E_UNSUPPORTED, "item too large");
+            stride *= t.dims[a];
+        }
+        for (int a = 0; a < t.rank; ++a) {
+            const int64_t d = t.kept[a] ? t.n_kept[a] : t.dims[a];
+            if (d < 1 || d > t.dims[a]) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad n_kept");
+            k.odim[a] = (int32_t)d;
+            k.moff[a] = (int32_t)(maps.size() - (size_t)k.map_off);
+            for (int64_t x = 0; x < d; ++x) {
+                const int64_t idx = t.kept[a] ? t.kept[a][x] : x;
+                if (idx < 0 || idx >= t.dims[a]) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": kept index out of range");
+                maps.push_back(idx * strides[(size_t)a]);
+            }
+            n_out *= d;
+        }
+        if (n_out >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "item with 2^31 or more elements");
+        k.n_out = n_out;
+        k.block0 = blocks;
+        blocks += (n_out + per_block - 1) / per_block;
+    }
+    if (blocks >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "batch too large");
+    htn_trunc *t = new htn_trunc();
+    t->n = n;
+    t->elem_bytes = dtype_size(dtype);
+    t->n_blocks = blocks;
+    try {
+        HIP_TRY(hipMalloc(&t->d_items, h.size() * sizeof(kern::TruncItem)));
+        HIP_TRY(hipMalloc(&t->d_maps, maps.size() * sizeof(int64_t)));
+        HIP_TRY(hipMemcpy(t->d_items, h.data(), h.size() * sizeof(kern::TruncItem), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t->d_maps, maps.data(), maps.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    } catch (...) {
+        delete t;
+        throw;
+    }
+    *out = t;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_truncate_run(htn_trunc_t t, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!t) return fail(HTN_E_ARG, "handle is NULL");
+    HIP_TRY(kern::launch_truncate(t->d_items, t->n, t->d_maps, t->n_blocks, t->elem_bytes, (hipStream_t)hip_stream));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+void htn_truncate_destroy(htn_trunc_t t) { delete t; }
+
+}  // extern "C"

@@ -109,6 +109,26 @@ hipError_t launch_stamp(int64_t *dst, hipStream_t st);
 // Element-wise dtype conversion on the device.
 hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);
 
+// Truncation gather (qpd.hip).  Item i copies its n_out (< 2^31) output
+// elements from blocks [block0, block0 + ceil(n_out / 1024)); items are
+// sorted by block0.  Axis a of the item reads maps[map_off + moff[a] + d]
+// (kept index d of the axis times its input stride).
+constexpr int kTruncMaxRank = 16;
+constexpr int kTruncThreads = 256;
+constexpr int kTruncPerThread = 4;
+struct TruncItem {
+    const void *src;
+    void *dst;
+    int64_t n_out;
+    int64_t block0;
+    int64_t map_off;
+    int32_t rank;
+    int32_t odim[kTruncMaxRank];
+    int32_t moff[kTruncMaxRank];
+};
+hipError_t launch_truncate(const TruncItem *items, int n_items, const int64_t *maps, int64_t n_blocks, int elem_bytes,
+                           hipStream_t st);
+
 // Cost-model MLP (mlp.hip).  Samples are rows of x ([.][HTN_MODEL_FEATURES]);
 // idx (optional) maps batch position s to its row.  z1, z2, d1, d2 are
 // [n][HTN_MODEL_HIDDEN] work arrays; forward keeps pre-activations in

@@ -45,6 +45,16 @@ class htn_info(ctypes.Structure):
                 ("input_bytes", ctypes.c_int64)]
 
 
+HTN_TRUNC_MAX_RANK = 16
+
+
+class htn_truncation(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("rank", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * HTN_TRUNC_MAX_RANK),
+                ("kept", ctypes.POINTER(ctypes.c_int32) * HTN_TRUNC_MAX_RANK),
+                ("n_kept", ctypes.c_int32 * HTN_TRUNC_MAX_RANK)]
+
+
 _lib = None
 
 
@@ -105,6 +115,11 @@ def load_library():
         "htn_autotune": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P, i32p, i32p, f32p]),
         "htn_batch_set_event_timing": (I32, [P, I32]),
         "htn_batch_launch_ms": (I32, [P, f32p, f32p, i32p]),
+        "htn_qpd_sample": (I32, [I32, ctypes.POINTER(ctypes.c_double), I64, ctypes.POINTER(ctypes.c_double),
+                                 i64p, ctypes.POINTER(ctypes.c_double)]),
+        "htn_truncate_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_truncation), I32]),
+        "htn_truncate_run": (I32, [P, P]),
+        "htn_truncate_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -515,3 +530,69 @@ def htn_batch_step_times(batch: Batch, capacity: int) -> np.ndarray:
     a = np.zeros((len(batch.nets), max(1, capacity)), dtype=np.float32)
     _check(load_library().htn_batch_step_times(batch.handle, _f32p(a), int(capacity)))
     return a[:, :capacity]
+
+
+# ---------------------------------------------------------------------------
+# QPD sampling and truncation (Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def htn_qpd_sample(coeffs, s_qpd: int, uniforms):
+    """(counts int64[n], weights float64[n]) of one CT's s_qpd draws."""
+    lib = load_library()
+    c, cp = _arr(coeffs, np.float64)
+    u, up = _arr(uniforms, np.float64)
+    if u.shape != (int(s_qpd),):
+        raise HtnError(1, "uniforms must hold s_qpd values")
+    counts = np.zeros(c.size, dtype=np.int64)
+    weights = np.zeros(c.size, dtype=np.float64)
+    _check(lib.htn_qpd_sample(int(c.size), cp, int(s_qpd), up,
+                              counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return counts, weights
+
+
+class Trunc:
+    """Handle of htn_truncate_create; keeps the borrowed buffers alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.htn_truncate_destroy(self.handle)
+            self.handle = None
+
+
+def htn_truncate_create(items, dtype=HTN_F64) -> Trunc:
+    """items: (src, dst, dims, kept) per tensor; src/dst device tensors (or
+    pointers), kept[a] a list of indices or None (whole axis)."""
+    lib = load_library()
+    arr = (htn_truncation * len(items))()
+    keep = []
+    for i, (src, dst, dims, kept) in enumerate(items):
+        it = arr[i]
+        it.src = _data_ptr(src) if not isinstance(src, int) else src
+        it.dst = _data_ptr(dst) if not isinstance(dst, int) else dst
+        it.rank = len(dims)
+        for a, d in enumerate(dims):
+            it.dims[a] = int(d)
+            if kept is not None and kept[a] is not None:
+                k, kp = _arr(kept[a], np.int32)
+                keep.append(k)
+                it.kept[a] = kp
+                it.n_kept[a] = int(k.size)
+        keep += [src, dst]
+    h = ctypes.c_void_p()
+    _check(lib.htn_truncate_create(ctypes.byref(h), len(items), arr, int(dtype)))
+    return Trunc(h, keep)
+
+
+def htn_truncate_run(t: Trunc, stream=None) -> None:
+    _check(load_library().htn_truncate_run(t.handle, _stream_ptr(stream)))
+
+
+def htn_truncate_destroy(t: Trunc) -> None:
+    if t.handle:
+        load_library().htn_truncate_destroy(t.handle)
+        t.handle = None

@@ -163,3 +163,22 @@ def test_output_dtype_follows_final_sum():
                               (htn.HTN_BF16, htn.HTN_SUM_FP64, htn.HTN_F64)]:
         net = _host_net(w, compute=compute, final_sum=fs)
         assert htn.htn_get_info(net).out_dtype == want
+
+
+def test_qpd_sampler_host_logic_matches_oracle():
+    # htn_qpd_sample is host code (no device call): draws and weights equal
+    # the oracle's on the same uniforms
+    from oracle import qpd_sampling as qs
+    rng = np.random.default_rng(9)
+    for c in (np.array([0.5, 0.5, 0.5, -0.5, 0.5, -0.5]), np.array([0.0, 2.5, -0.1, 0.0, -3.0])):
+        for s in (1, 5, 4096):
+            u = rng.random(s)
+            n, w = htn.htn_qpd_sample(c, s, u)
+            assert np.array_equal(n, qs.sample_counts(c, s, u))
+            assert np.array_equal(w, qs.estimator_weights(c, n, s))
+
+
+def test_truncation_items_are_validated_before_any_device_call():
+    for kept, dims in (([[0, 6], None], (6, 4)), ([[], None], (6, 4)), ([None, None], (6, 0))):
+        with pytest.raises(htn.HtnError, match="HTN_E_ARG"):
+            htn.htn_truncate_create([(1, 2, dims, kept)], htn.HTN_F64)
