@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["grid", "random", "marginal", "ring"], default="grid")
+    ap.add_argument("--workload", choices=["grid", "random", "marginal", "ring", "qpd"],
+                    default="grid")
     ap.add_argument("--batch", type=int, default=None, help="networks per batch (default per workload)")
     ap.add_argument("--dtype", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--lds", type=int, default=None,
@@ -63,6 +64,8 @@ def parse():
                          "serving batch, greedy for ring)")
     ap.add_argument("--samples", type=int, default=None,
                     help="sampled path candidates per network (default: 128 for grid and random, 32 for ring)")
+    ap.add_argument("--qpd-samples", type=int, default=8,
+                    help="QPD draws per gate-cut CT (qpd workload)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="measure the fused kernel's workgroup size and LDS budget first "
                          "(auto: on for the random and ring batches)")
@@ -347,6 +350,128 @@ def bench_grid(args):
     }
 
 
+# ------------------------------------------------------------------- qpd
+
+def bench_qpd(args):
+    """Grid h-TNs simplified by QPD sampling (Sec. 4.3): every gate-cut CT is
+    drawn --qpd-samples times, its undrawn indices are truncated from the
+    CT and its QTs.  One step = the truncation gather over the whole batch
+    (one launch) + the batch contraction of the simplified networks."""
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    n_nets = args.batch or 1024
+    s_qpd = args.qpd_samples
+    args.lds = args.lds or 81920
+    args.path = args.path or "sampled"
+    args.samples = args.samples or 128
+    dev = torch.device("cuda:0")
+    log(f"generating {n_nets} grid networks, sampling gate cuts with s_QPD = {s_qpd}")
+    ws = [configs.grid_network(s) for s in range(n_nets)]
+    rng = np.random.default_rng(2410)
+    items, nets, src_keep, sampled = [], [], [], []
+    t_sample = 0.0
+    for w in ws:
+        src = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(dev) for t in w.tensors]
+        gate = [i for i, t in enumerate(w.tensors) if w.kinds[i] == "ct" and t.size == 6]
+        kept_of, counts, new = {}, {}, list(src)
+        for c in gate:
+            u = rng.random(s_qpd)
+            t0 = time.perf_counter()
+            n, wts = htn.htn_qpd_sample(w.tensors[c], s_qpd, u)
+            t_sample += time.perf_counter() - t0
+            k = np.nonzero(n)[0]
+            kept_of[w.labels[c][0]] = k
+            counts[c] = n
+            new[c] = torch.from_numpy(wts[k]).to(dev)
+        dims = list(w.dims)
+        for lab, k in kept_of.items():
+            dims[lab] = len(k)
+        for t, ls in enumerate(w.labels):
+            if t in counts or not any(l in kept_of for l in ls):
+                continue
+            dst = torch.empty(tuple(dims[l] for l in ls), dtype=torch.float64, device=dev)
+            items.append((src[t], dst, tuple(w.dims[l] for l in ls), [kept_of.get(l) for l in ls]))
+            new[t] = dst
+        n = htn.htn_create(new, w.labels, dims, [], compute=htn.HTN_F64)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, args.lds)
+        htn.htn_set_option(n, htn.HTN_OPT_FUSED_THREADS, args.threads)
+        nets.append(n)
+        src_keep.append((src, new))
+        sampled.append((gate, [counts[c] for c in gate], dims))
+    tr = htn.htn_truncate_create(items, htn.HTN_F64)
+    trunc_bytes = 2 * 8 * sum(int(np.prod(it[1].shape)) for it in items)
+    stream = torch.cuda.Stream()
+    htn.htn_truncate_run(tr, stream)
+    stream.synchronize()
+    greedy_list = [htn.htn_get_info(n).mults for n in nets]
+    greedy_mults = float(sum(greedy_list))
+    log(f"planning {args.path} paths")
+    for n in nets:
+        htn.htn_set_option(n, htn.HTN_OPT_PATH_SAMPLES, args.samples)
+        htn.htn_set_path(n, htn.HTN_PATH_SAMPLED if args.path == "sampled" else htn.HTN_PATH_GREEDY)
+    infos = [htn.htn_get_info(n) for n in nets]
+    mults = float(sum(i.mults for i in infos))
+    b, out, outs, stream = batch_runner(nets, torch.float64)
+    timer = Timer(stream)
+
+    def step():
+        htn.htn_truncate_run(tr, stream)
+        htn.htn_batch_run(b, outs, stream)
+    log(f"timing {args.steps} steps")
+    ms_per_step, kern_ms = timer.run(step, args.steps, args.warmup,
+                                     after_warmup=lambda: htn.htn_batch_set_event_timing(b, True))
+    prep_ms, fused_ms, runs = htn.htn_batch_launch_ms(b)
+    assert runs == args.steps
+    got = out.cpu().numpy()
+    log("timing the truncation launch alone")
+    _, trunc_ms = Timer(stream).run(lambda: htn.htn_truncate_run(tr, stream), args.steps, args.warmup)
+    # parity on a sample of the networks: the oracle's own draws from the
+    # same counts, truncation and double-double contraction
+    from oracle import qpd_sampling as qs
+    errs, ref_ws = [], []
+    for i in range(0, n_nets, max(1, n_nets // 32)):
+        gate, cnts, dims = sampled[i]
+        rw = qs.truncate(ws[i], gate, cnts, s_qpd)
+        assert rw.dims == dims
+        ref = oracle_ref(rw)
+        errs.append(abs(got[i] - ref) / abs(ref))
+        ref_ws.append(rw)
+    htns = n_nets / (ms_per_step * 1e-3)
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle")
+        cpu = cpu_baseline([qs.truncate(ws[i], *sampled[i][:2], s_qpd) for i in range(min(n_nets, 4096))],
+                           args.cpu_seconds, greedy_list)
+    achieved = 2.0 * mults / (fused_ms * 1e-3) / 1e12
+    tr_gbs = trunc_bytes / (trunc_ms * 1e-3) / 1e9
+    htn.htn_truncate_destroy(tr)
+    return {
+        "metric": METRIC,
+        "value": round(2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
+        "ms_per_step": round(ms_per_step, 4), "dtype": "f64",
+        "config": {"workload": "grid4x4_htn_batch_qpd_sampled", "networks": n_nets, "qts_per_net": 16,
+                   "cuts_per_net": 24, "cut_dims": "wire 4 / CZ gate 6, 50/50 by seed",
+                   "qpd_samples_per_gate_ct": s_qpd, "path": args.path, "path_samples": args.samples,
+                   "executor": "truncation gather + input prep + fused kernel, one workgroup per network",
+                   "lds_budget_bytes": args.lds, "threads_per_network": args.threads},
+        "htns_per_s": round(htns, 1),
+        "max_rel_err_vs_oracle": float(max(errs)),
+        "greedy_mults_per_step": greedy_mults,
+        "executed_mults_per_step": mults,
+        "host_sampling_ms_per_batch": round(t_sample * 1e3, 3),
+        "k_truncate": {"ms": round(trunc_ms, 4), "algorithmic_bytes": trunc_bytes, "items": len(items),
+                       "achieved_gbs": round(tr_gbs, 1), "frac_of_hbm_peak": round(tr_gbs / PEAK["hbm_gbs"], 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5), "traffic": None,
+                     "kernel": f"k_fused<{args.threads},double,double,0>", "kernel_ms": round(fused_ms, 4),
+                     "flops_per_launch": 2.0 * mults, "k_fprep_ms": round(prep_ms, 4),
+                     "batch_ms_events": round(kern_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+
+
 # ---------------------------------------------------------------- random
 
 def bench_random(args):
@@ -578,9 +703,10 @@ def main():
         return 2
     import torch
     torch.cuda.set_device(0)
-    if args.workload != "grid":
+    if args.workload not in ("grid", "qpd"):
         args.lds = args.lds or 65536
-    fn = {"grid": bench_grid, "random": bench_random, "marginal": bench_marginal, "ring": bench_ring}[args.workload]
+    fn = {"grid": bench_grid, "random": bench_random, "marginal": bench_marginal, "ring": bench_ring,
+          "qpd": bench_qpd}[args.workload]
     line = fn(args)
     head = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),

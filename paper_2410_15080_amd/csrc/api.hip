@@ -1470,9 +1470,11 @@ struct htn_trunc {
     int elem_bytes = 8;
     int64_t n_blocks = 0;
     kern::TruncItem *d_items = nullptr;
+    kern::TruncBlock *d_blocks = nullptr;
     int64_t *d_maps = nullptr;
     ~htn_trunc() {
         if (d_items) (void)hipFree(d_items);
+        if (d_blocks) (void)hipFree(d_blocks);
         if (d_maps) (void)hipFree(d_maps);
     }
 };
@@ -1522,8 +1524,9 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
     if (dtype != HTN_F64 && dtype != HTN_F32 && dtype != HTN_BF16) return fail(HTN_E_ARG, "bad dtype");
     std::vector<kern::TruncItem> h((size_t)n);
     std::vector<int64_t> maps;
-    int64_t blocks = 0;
-    constexpr int64_t per_block = kern::kTruncThreads * kern::kTruncPerThread;
+    std::vector<kern::TruncBlock> blocks;
+    constexpr int64_t per_block = kern::kTruncBlockElems;
+    int32_t open_fill = per_block;  // elements in the open packed block (none open)
     for (int i = 0; i < n; ++i) {
         const htn_truncation &t = items[i];
         if (!t.src || !t.dst) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": NULL buffer");
@@ -1557,16 +1560,38 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
         }
         if (n_out >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "item with 2^31 or more elements");
         k.n_out = n_out;
-        k.block0 = blocks;
-        blocks += (n_out + per_block - 1) / per_block;
+        const int64_t mw = (int64_t)maps.size() - k.map_off;  // this item's map entries
+        if (n_out > per_block || mw > kern::kTruncMapLds) {
+            // a larger item (or one whose maps alone fill the LDS share):
+            // 1024-element chunks, one block each
+            k.start = 0;
+            const int32_t words = mw <= kern::kTruncMapLds ? (int32_t)mw : 0;
+            for (int64_t b = 0; b < n_out; b += per_block)
+                blocks.push_back(kern::TruncBlock{i, 1, b, k.map_off, words, 0});
+            open_fill = per_block;
+        } else {
+            // small items share a block while their elements, count and
+            // maps fit
+            if (open_fill + n_out > per_block || blocks.empty() || blocks.back().n_items == kern::kTruncBlockItems ||
+                blocks.back().map_words + mw > kern::kTruncMapLds) {
+                blocks.push_back(kern::TruncBlock{i, 0, 0, k.map_off, 0, 0});
+                open_fill = 0;
+            }
+            k.start = open_fill;
+            ++blocks.back().n_items;
+            blocks.back().map_words += (int32_t)mw;
+            open_fill += (int32_t)n_out;
+        }
+        if ((int64_t)blocks.size() >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "batch too large");
     }
-    if (blocks >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "batch too large");
     htn_trunc *t = new htn_trunc();
     t->n = n;
     t->elem_bytes = dtype_size(dtype);
-    t->n_blocks = blocks;
+    t->n_blocks = (int64_t)blocks.size();
     try {
         HIP_TRY(hipMalloc(&t->d_items, h.size() * sizeof(kern::TruncItem)));
+        HIP_TRY(hipMalloc(&t->d_blocks, blocks.size() * sizeof(kern::TruncBlock)));
+        HIP_TRY(hipMemcpy(t->d_blocks, blocks.data(), blocks.size() * sizeof(kern::TruncBlock), hipMemcpyHostToDevice));
         HIP_TRY(hipMalloc(&t->d_maps, maps.size() * sizeof(int64_t)));
         HIP_TRY(hipMemcpy(t->d_items, h.data(), h.size() * sizeof(kern::TruncItem), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t->d_maps, maps.data(), maps.size() * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -1582,7 +1607,8 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
 htn_status htn_truncate_run(htn_trunc_t t, void *hip_stream) {
     API_GUARD_BEGIN
     if (!t) return fail(HTN_E_ARG, "handle is NULL");
-    HIP_TRY(kern::launch_truncate(t->d_items, t->n, t->d_maps, t->n_blocks, t->elem_bytes, (hipStream_t)hip_stream));
+    HIP_TRY(kern::launch_truncate(t->d_items, t->d_blocks, t->n_blocks, t->d_maps, t->elem_bytes,
+                                  (hipStream_t)hip_stream));
     return HTN_OK;
     API_GUARD_END
 }

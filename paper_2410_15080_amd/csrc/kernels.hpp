@@ -110,24 +110,40 @@ hipError_t launch_stamp(int64_t *dst, hipStream_t st);
 hipError_t launch_convert(const void *src, int ts, void *dst, int td, int64_t n, hipStream_t st);
 
 // Truncation gather (qpd.hip).  Item i copies its n_out (< 2^31) output
-// elements from blocks [block0, block0 + ceil(n_out / 1024)); items are
-// sorted by block0.  Axis a of the item reads maps[map_off + moff[a] + d]
-// (kept index d of the axis times its input stride).
+// elements; axis a of the item reads maps[map_off + moff[a] + d] (kept
+// index d of the axis times its input stride).  A block covers either a
+// run of whole items (n_items >= 1, at most 1024 elements together, item
+// k's elements at block positions [start_k, start_k + n_out_k)) or one
+// 1024-element chunk of a larger item (n_items == 1, elements from base).
 constexpr int kTruncMaxRank = 16;
 constexpr int kTruncThreads = 256;
 constexpr int kTruncPerThread = 4;
+constexpr int kTruncBlockElems = kTruncThreads * kTruncPerThread;
 struct TruncItem {
     const void *src;
     void *dst;
     int64_t n_out;
-    int64_t block0;
     int64_t map_off;
     int32_t rank;
+    int32_t start;
     int32_t odim[kTruncMaxRank];
     int32_t moff[kTruncMaxRank];
 };
-hipError_t launch_truncate(const TruncItem *items, int n_items, const int64_t *maps, int64_t n_blocks, int elem_bytes,
-                           hipStream_t st);
+// A block stages its items (at most kTruncBlockItems) and, when they fit in
+// kTruncMapLds entries (map_words > 0), their maps
+// [map_base, map_base + map_words) in LDS.
+constexpr int kTruncBlockItems = 32;
+constexpr int kTruncMapLds = 1024;
+struct TruncBlock {
+    int32_t item0;
+    int32_t n_items;
+    int64_t base;
+    int64_t map_base;
+    int32_t map_words;
+    int32_t pad;
+};
+hipError_t launch_truncate(const TruncItem *items, const TruncBlock *blocks, int64_t n_blocks, const int64_t *maps,
+                           int elem_bytes, hipStream_t st);
 
 // Cost-model MLP (mlp.hip).  Samples are rows of x ([.][HTN_MODEL_FEATURES]);
 // idx (optional) maps batch position s to its row.  z1, z2, d1, d2 are

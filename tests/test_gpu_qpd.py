@@ -93,6 +93,31 @@ def test_truncate_batch_is_a_bit_exact_gather(dtype):
     htn.htn_truncate_destroy(t)
 
 
+def test_truncate_packs_many_small_items_with_large_ones():
+    # sizes around the 1024-element block: single elements, runs that fill a
+    # block exactly, items one element above and below it, and larger ones
+    torch = _torch()
+    rng = np.random.default_rng(11)
+    shapes = ([(1,)] * 700 + [(32, 32), (1025,), (1023,), (2,), (1024, 1), (3, 7, 5), (2049,), (6, 6, 6, 6)]
+              + [(4, 6)] * 300 + [(1000, 1, 1), (5,)])
+    items, dsts, refs = [], [], []
+    for sh in shapes:
+        kept = [rng.choice(d, size=int(rng.integers(1, d + 1)), replace=False) if d > 1 and rng.random() < 0.7
+                else None for d in sh]
+        a = rng.uniform(-1, 1, sh)
+        ref = _take(a, kept)
+        dst = torch.full(ref.shape, float("nan"), dtype=torch.float64, device="cuda")
+        items.append((torch.from_numpy(a).cuda(), dst, sh, kept))
+        dsts.append(dst)
+        refs.append(ref)
+    t = htn.htn_truncate_create(items, htn.HTN_F64)
+    htn.htn_truncate_run(t)
+    torch.cuda.synchronize()
+    got = torch.cat([d.reshape(-1) for d in dsts]).cpu().numpy()
+    assert np.array_equal(got, np.concatenate([r.reshape(-1) for r in refs]))
+    htn.htn_truncate_destroy(t)
+
+
 def test_truncate_rejects_bad_items():
     torch = _torch()
     a = torch.zeros(6, 4, dtype=torch.float64, device="cuda")
