@@ -81,15 +81,20 @@ TRAFFIC = {
     # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 797.3125 x 2048 B, WRITE_SIZE 213.5 x 1024 B
     "k_fused_grid": {"read_bytes": 38_496_896, "write_bytes": 218_624, "sources": "af6e1d77f20c0f03",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
+    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 476 x 2048 B, WRITE_SIZE 15 552.6 x 1024 B
+    "k_truncate_qpd8": {"read_bytes": 27_598_848, "write_bytes": 15_925_862, "sources": "c89d2a641b3a6971",
+                        "files": ["paper_2410_15080_amd/csrc/qpd.hip", "paper_2410_15080_amd/csrc/api.hip",
+                                  "paper_2410_15080_amd/csrc/kernels.hpp"],
+                        "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
                    "paper_2410_15080_amd/csrc/fused_b256.hip", "paper_2410_15080_amd/csrc/planner.cpp"]
 
 
-def source_digest():
+def source_digest(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in files or TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,7 +102,7 @@ def source_digest():
 
 def measured_traffic(key, runs_ok=True):
     rec = TRAFFIC.get(key)
-    if not rec or not runs_ok or rec["sources"] != source_digest():
+    if not rec or not runs_ok or rec["sources"] != source_digest(rec.get("files")):
         return None
     return {"read_bytes": rec["read_bytes"], "write_bytes": rec["write_bytes"],
             "bytes": rec["read_bytes"] + rec["write_bytes"], "profile": rec["profile"]}
@@ -462,7 +467,8 @@ def bench_qpd(args):
         "executed_mults_per_step": mults,
         "host_sampling_ms_per_batch": round(t_sample * 1e3, 3),
         "k_truncate": {"ms": round(trunc_ms, 4), "algorithmic_bytes": trunc_bytes, "items": len(items),
-                       "achieved_gbs": round(tr_gbs, 1), "frac_of_hbm_peak": round(tr_gbs / PEAK["hbm_gbs"], 4)},
+                       "achieved_gbs": round(tr_gbs, 1), "frac_of_hbm_peak": round(tr_gbs / PEAK["hbm_gbs"], 4),
+                       "traffic": measured_traffic("k_truncate_qpd8", runs_ok=(s_qpd == 8 and n_nets == 1024))},
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5), "traffic": None,
                      "kernel": f"k_fused<{args.threads},double,double,0>", "kernel_ms": round(fused_ms, 4),
