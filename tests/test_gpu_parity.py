@@ -33,13 +33,18 @@ def test_wire_cut_circuit_matches_oracle_and_statevector(exec_mode):
         assert abs(got - full) < 1e-14
 
 
+@pytest.mark.parametrize("gate", ["cz", "rzz"])
 @pytest.mark.parametrize("exec_mode", EXECS)
-def test_gate_cut_circuits(exec_mode):
-    for n_cuts in (1, 2):
-        w, _ = configs.circuit_cut_gates(1, n_cuts)
-        got = float(run(w, exec_mode=exec_mode))
-        ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
-        assert abs(got - float(ref)) <= 1e-13
+def test_gate_cut_circuits(exec_mode, gate):
+    # CZ and parametric RZZ(theta) gate cuts: oracle and uncut statevector
+    for seed in (1, 2):
+        for n_cuts in (1, 2):
+            w, full_ops = configs.circuit_cut_gates(seed, n_cuts, gate=gate)
+            got = float(run(w, exec_mode=exec_mode))
+            ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+            assert abs(got - float(ref)) <= 1e-13
+            full = sv.run_ops(sv.zero_state(4), full_ops, {q: "Z" for q in range(4)})
+            assert abs(got - full) <= 1e-13
 
 
 @pytest.mark.parametrize("exec_mode", EXECS)

@@ -77,6 +77,22 @@ def test_cz_gate_cut_channel_identity():
         assert np.abs(rec - cz @ rho @ cz).max() < 1e-15
 
 
+@pytest.mark.parametrize("theta", [0.0, 0.37, -1.2, np.pi / 2, 2.9, np.pi])
+def test_rzz_gate_cut_channel_identity(theta):
+    """RZZ(theta) rho RZZ(theta)^dag = sum_i c_i(theta) (A_i (x) B_i)(rho)."""
+    u = np.diag(np.exp(-0.5j * theta * np.array([1.0, -1.0, -1.0, 1.0])))
+    c = qpd.rzz_coeffs(theta)
+    assert abs(c.sum() - 1.0) < 1e-15
+    assert abs(np.abs(c).sum() - (1.0 + 2.0 * abs(np.sin(theta)))) < 1e-15  # gamma
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        rho = _rand_rho(rng, 2)
+        rec = np.zeros((4, 4), dtype=complex)
+        for ci, (a, b) in zip(c, qpd.RZZ_INSTANCES):
+            rec += ci * _channel(b, _channel(a, rho, 0), 1)
+        assert np.abs(rec - u @ rho @ u.conj().T).max() < 1e-15
+
+
 # ------------------------------------------------ naive sum vs statevector
 
 @pytest.mark.parametrize("seed", range(4))
@@ -90,10 +106,11 @@ def test_naive_equals_uncut_statevector_wire_cuts(seed):
     assert abs(float(hi) - full) < 1e-14
 
 
+@pytest.mark.parametrize("gate", ["cz", "rzz"])
 @pytest.mark.parametrize("n_cuts", [1, 2])
-def test_naive_equals_uncut_statevector_gate_cuts(n_cuts):
+def test_naive_equals_uncut_statevector_gate_cuts(n_cuts, gate):
     for seed in range(3):
-        net, full_ops = configs.circuit_cut_gates(seed, n_cuts)
+        net, full_ops = configs.circuit_cut_gates(seed, n_cuts, gate=gate)
         full = sv.run_ops(sv.zero_state(4), full_ops, {q: "Z" for q in range(4)})
         got, _ = oracle.naive_contract(net.tensors, net.labels, net.dims, net.out_labels)
         assert abs(float(got) - full) < 1e-14

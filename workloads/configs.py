@@ -130,14 +130,18 @@ def circuit_cut_wires(seed: int) -> Network:
 _INST_U = {"S": sv.S, "Sdg": sv.SDG, "Z": sv.Z, "I": sv.I2}
 
 
-def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3):
-    """4-qubit circuit, halves {q0,q1} | {q2,q3}, crossing CZ(q1,q2) cut.
+def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz"):
+    """4-qubit circuit, halves {q0,q1} | {q2,q3}, crossing gate on (q1,q2) cut.
 
     Returns (network, full_ops).  Each layer: Rz, Ry on every qubit, CZ(0,1),
-    CZ(2,3); the crossing CZ(1,2) follows layers 0..n_cuts-1 and is cut.
+    CZ(2,3); the crossing gate follows layers 0..n_cuts-1 and is cut: CZ, or
+    with gate="rzz" a ZZ rotation RZZ(theta) whose angle per cut is drawn
+    U[-pi, pi) after the layer angles.
     """
     rng = np.random.default_rng(seed)
     ang = rng.uniform(0.0, 2.0 * np.pi, size=(n_layers, 4, 2))
+    thetas = rng.uniform(-np.pi, np.pi, size=n_cuts) if gate == "rzz" else None
+    instances = qpd.RZZ_INSTANCES if gate == "rzz" else qpd.CZ_INSTANCES
     layers = []
     for layer in range(n_layers):
         ops = []
@@ -151,7 +155,7 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3):
     for layer in range(n_layers):
         full += layers[layer]
         if layer < n_cuts:
-            full.append(("cz", 1, 2))
+            full.append(("rzz", 1, 2, thetas[layer]) if gate == "rzz" else ("cz", 1, 2))
 
     def half_ops(side, insts):
         # side 0: global {0,1} -> local {0,1}, cut qubit local 1
@@ -168,7 +172,7 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3):
                     else:
                         out.append(("cz", op[1] - keep[0], op[2] - keep[0]))
             if layer < n_cuts:
-                name = qpd.CZ_INSTANCES[insts[layer]][side]
+                name = instances[insts[layer]][side]
                 if name == "MZ":
                     out.append(("mz", cutq))
                 else:
@@ -182,10 +186,11 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3):
         left[idx] = sv.run_ops(sv.zero_state(2), half_ops(0, idx), {0: "Z", 1: "Z"})
         right[idx] = sv.run_ops(sv.zero_state(2), half_ops(1, idx), {0: "Z", 1: "Z"})
     cut_labels = list(range(n_cuts))
-    tensors = [left, right] + [qpd.CZ_COEFFS.copy() for _ in range(n_cuts)]
+    coeffs = [qpd.rzz_coeffs(t) for t in thetas] if gate == "rzz" else [qpd.CZ_COEFFS.copy()] * n_cuts
+    tensors = [left, right] + [np.array(c) for c in coeffs]
     labels = [cut_labels, cut_labels] + [[l] for l in cut_labels]
     net = Network(tensors, labels, [6] * n_cuts, [], ["qt", "qt"] + ["ct"] * n_cuts,
-                  {"config": "circuit_cut_gates", "seed": seed, "n_cuts": n_cuts})
+                  {"config": "circuit_cut_gates", "seed": seed, "n_cuts": n_cuts, "gate": gate})
     return net, full
 
 

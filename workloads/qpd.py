@@ -46,3 +46,20 @@ PAULI_AS_PREPS = {
     "Y": (("+i", 1.0), ("-i", -1.0)),
 }
 PAULI_ORDER = ("I", "Z", "X", "Y")
+
+
+# Parametric ZZ rotation RZZ(theta) = exp(-i theta/2 Z(x)Z) cut on its two
+# qubits (Sec. 2.1 gate QPD for a two-qubit rotation).  With c = cos(theta/2),
+# s = sin(theta/2):  U rho U^dag = c^2 rho + s^2 ZZ rho ZZ - i c s [ZZ, rho],
+# and the commutator term splits into a signed Z measurement on one qubit
+# and an S or S^dag rotation on the other.  Six instances, in this order:
+#   (I, I; c^2), (Z, Z; s^2), (M_Z, S; cs), (M_Z, S^dag; -cs),
+#   (S, M_Z; cs), (S^dag, M_Z; -cs)
+# so sum c = 1 and gamma = 1 + 2 |sin theta| (3 at theta = pi/2, where the
+# rotation is CZ up to local phases).
+RZZ_INSTANCES = (("I", "I"), ("Z", "Z"), ("MZ", "S"), ("MZ", "Sdg"), ("S", "MZ"), ("Sdg", "MZ"))
+
+
+def rzz_coeffs(theta: float) -> np.ndarray:
+    c, s = np.cos(0.5 * theta), np.sin(0.5 * theta)
+    return np.array([c * c, s * s, c * s, -c * s, c * s, -c * s])

@@ -70,6 +70,14 @@ def apply_cz(psi: np.ndarray, a: int, b: int) -> np.ndarray:
     return out
 
 
+def apply_rzz(psi: np.ndarray, a: int, b: int, theta: float) -> np.ndarray:
+    """exp(-i theta/2 Z_a Z_b): phase exp(-i theta/2) where the bits agree,
+    exp(+i theta/2) where they differ."""
+    idx = np.indices(psi.shape)
+    parity = (idx[a] + idx[b]) % 2
+    return psi * np.where(parity == 0, np.exp(-0.5j * theta), np.exp(0.5j * theta))
+
+
 def project(psi: np.ndarray, q: int, bit: int) -> np.ndarray:
     """Unnormalised projection of qubit q onto |bit>."""
     out = np.zeros_like(psi)
@@ -93,6 +101,7 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
     ops items:
       ("u", q, 2x2 matrix)    unitary on qubit q
       ("cz", a, b)            controlled-Z
+      ("rzz", a, b, theta)    exp(-i theta/2 Z_a Z_b)
       ("mz", q)               signed mid-circuit Z measurement: the result is
                               sum_b (-1)^b <O>_b over the two unnormalised
                               projected branches, each continued to the end.
@@ -103,6 +112,8 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
             psi = apply_1q(psi, op[2], op[1])
         elif kind == "cz":
             psi = apply_cz(psi, op[1], op[2])
+        elif kind == "rzz":
+            psi = apply_rzz(psi, op[1], op[2], op[3])
         elif kind == "mz":
             q = op[1]
             rest = ops[k + 1:]
