@@ -33,10 +33,10 @@ def test_wire_cut_circuit_matches_oracle_and_statevector(exec_mode):
         assert abs(got - full) < 1e-14
 
 
-@pytest.mark.parametrize("gate", ["cz", "rzz"])
+@pytest.mark.parametrize("gate", ["cz", "rzz", "cx"])
 @pytest.mark.parametrize("exec_mode", EXECS)
 def test_gate_cut_circuits(exec_mode, gate):
-    # CZ and parametric RZZ(theta) gate cuts: oracle and uncut statevector
+    # CZ, parametric RZZ(theta) and CX gate cuts: oracle and uncut statevector
     for seed in (1, 2):
         for n_cuts in (1, 2):
             w, full_ops = configs.circuit_cut_gates(seed, n_cuts, gate=gate)

@@ -93,6 +93,20 @@ def test_rzz_gate_cut_channel_identity(theta):
         assert np.abs(rec - u @ rho @ u.conj().T).max() < 1e-15
 
 
+def test_cx_gate_cut_channel_identity():
+    """CX = (I (x) H) CZ (I (x) H): the CZ instances with the target's
+    operation conjugated by H reconstruct CX rho CX."""
+    cx = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=complex)
+    h2 = np.kron(sv.I2, sv.H)
+    rng = np.random.default_rng(6)
+    for _ in range(4):
+        rho = _rand_rho(rng, 2)
+        rec = np.zeros((4, 4), dtype=complex)
+        for c, (a, b) in zip(qpd.CZ_COEFFS, qpd.CZ_INSTANCES):
+            rec += c * h2 @ _channel(b, _channel(a, h2 @ rho @ h2, 0), 1) @ h2
+        assert np.abs(rec - cx @ rho @ cx).max() < 1e-15
+
+
 # ------------------------------------------------ naive sum vs statevector
 
 @pytest.mark.parametrize("seed", range(4))
@@ -106,7 +120,7 @@ def test_naive_equals_uncut_statevector_wire_cuts(seed):
     assert abs(float(hi) - full) < 1e-14
 
 
-@pytest.mark.parametrize("gate", ["cz", "rzz"])
+@pytest.mark.parametrize("gate", ["cz", "rzz", "cx"])
 @pytest.mark.parametrize("n_cuts", [1, 2])
 def test_naive_equals_uncut_statevector_gate_cuts(n_cuts, gate):
     for seed in range(3):

@@ -134,9 +134,11 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str =
     """4-qubit circuit, halves {q0,q1} | {q2,q3}, crossing gate on (q1,q2) cut.
 
     Returns (network, full_ops).  Each layer: Rz, Ry on every qubit, CZ(0,1),
-    CZ(2,3); the crossing gate follows layers 0..n_cuts-1 and is cut: CZ, or
+    CZ(2,3); the crossing gate follows layers 0..n_cuts-1 and is cut: CZ,
     with gate="rzz" a ZZ rotation RZZ(theta) whose angle per cut is drawn
-    U[-pi, pi) after the layer angles.
+    U[-pi, pi) after the layer angles, or with gate="cx" a CX (control q1,
+    target q2): CX = (I (x) H) CZ (I (x) H), so its cut is the CZ cut with
+    each target-side instance operation conjugated by H.
     """
     rng = np.random.default_rng(seed)
     ang = rng.uniform(0.0, 2.0 * np.pi, size=(n_layers, 4, 2))
@@ -155,7 +157,8 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str =
     for layer in range(n_layers):
         full += layers[layer]
         if layer < n_cuts:
-            full.append(("rzz", 1, 2, thetas[layer]) if gate == "rzz" else ("cz", 1, 2))
+            full.append({"rzz": ("rzz", 1, 2, thetas[layer] if thetas is not None else 0.0),
+                         "cx": ("cx", 1, 2)}.get(gate, ("cz", 1, 2)))
 
     def half_ops(side, insts):
         # side 0: global {0,1} -> local {0,1}, cut qubit local 1
@@ -173,10 +176,15 @@ def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str =
                         out.append(("cz", op[1] - keep[0], op[2] - keep[0]))
             if layer < n_cuts:
                 name = instances[insts[layer]][side]
+                conj = gate == "cx" and side == 1  # the CX target's side
+                if conj:
+                    out.append(("u", cutq, sv.H))
                 if name == "MZ":
                     out.append(("mz", cutq))
                 else:
                     out.append(("u", cutq, _INST_U[name]))
+                if conj:
+                    out.append(("u", cutq, sv.H))
         return out
 
     shape = (6,) * n_cuts

@@ -16,6 +16,7 @@ import numpy as np
 
 I2 = np.eye(2, dtype=np.complex128)
 X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
 Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
 Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 S = np.array([[1, 0], [0, 1j]], dtype=np.complex128)
@@ -70,6 +71,17 @@ def apply_cz(psi: np.ndarray, a: int, b: int) -> np.ndarray:
     return out
 
 
+def apply_cx(psi: np.ndarray, c: int, t: int) -> np.ndarray:
+    """Flip qubit t on the amplitudes whose qubit c is 1."""
+    out = psi.copy()
+    idx = [slice(None)] * psi.ndim
+    idx[c] = 1
+    sub = out[tuple(idx)]
+    ax = t if t < c else t - 1
+    out[tuple(idx)] = np.flip(sub, axis=ax)
+    return out
+
+
 def apply_rzz(psi: np.ndarray, a: int, b: int, theta: float) -> np.ndarray:
     """exp(-i theta/2 Z_a Z_b): phase exp(-i theta/2) where the bits agree,
     exp(+i theta/2) where they differ."""
@@ -102,6 +114,7 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
       ("u", q, 2x2 matrix)    unitary on qubit q
       ("cz", a, b)            controlled-Z
       ("rzz", a, b, theta)    exp(-i theta/2 Z_a Z_b)
+      ("cx", c, t)            controlled-X (control c, target t)
       ("mz", q)               signed mid-circuit Z measurement: the result is
                               sum_b (-1)^b <O>_b over the two unnormalised
                               projected branches, each continued to the end.
@@ -114,6 +127,8 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
             psi = apply_cz(psi, op[1], op[2])
         elif kind == "rzz":
             psi = apply_rzz(psi, op[1], op[2], op[3])
+        elif kind == "cx":
+            psi = apply_cx(psi, op[1], op[2])
         elif kind == "mz":
             q = op[1]
             rest = ops[k + 1:]
