@@ -18,6 +18,16 @@ Other workloads (--workload), each printing one JSON line of the same form:
              coefficient fold), FP64 / FP32 / BF16 inputs, FP64 output
   ring       256 ring-of-rings networks (64 QTs, 3-6 cuts each), FP64 / FP32
              / BF16 with a compensated FP64 final sum
+  qpd        the grid batch after QPD sampling of every gate cut (truncation
+             gather + contraction of the simplified networks)
+  copy-calibration  a plain 64 MiB device copy, the reference run that
+             scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes
+
+With the default grid workload (and --configs all) the line also carries
+"configs": every other workload (the 10-qubit circuit's latency, the
+marginal in FP64/FP32/BF16, the ring batch in FP64/FP32/BF16, the random
+serving batch on learned paths, the QPD-sampled grid) in the same form,
+with fewer timed steps and a shorter CPU sample each.
 
 Reported:
   value        GFLOP/s = 2 * (multiplications of the FLOP-greedy paths) / time;
@@ -48,8 +58,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["grid", "random", "marginal", "ring", "qpd"],
+    ap.add_argument("--workload", choices=["grid", "random", "marginal", "ring", "qpd", "copy-calibration"],
                     default="grid")
+    ap.add_argument("--configs", choices=["all", "none"], default="all",
+                    help="with the grid workload: also run every other workload and nest its results "
+                         "under \"configs\" (all, the default) or not (none)")
     ap.add_argument("--batch", type=int, default=None, help="networks per batch (default per workload)")
     ap.add_argument("--dtype", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--lds", type=int, default=None,
@@ -117,29 +130,74 @@ def dtype_code(name):
     return {"f64": htn.HTN_F64, "f32": htn.HTN_F32, "bf16": htn.HTN_BF16}[name]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(ws, seconds, mults):
-    """Time the oracle (FP64 variable elimination) on as many networks as fit
-    in about `seconds`, one network per host thread."""
+    """Time the oracle (FP64 variable elimination) on every host core in the
+    affinity mask, one network per thread: a warm-up pass, then the best of
+    three passes over a sample sized so that one pass takes about seconds/4."""
     import oracle
-    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    cores = max(1, len(os.sched_getaffinity(0)))
     oracle.set_num_threads(1)
 
     def one(w):
-        return float(oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels, mode="f64"))
+        return oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels, mode="f64")
 
-    done = 0
-    t0 = time.perf_counter()
     with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as ex:
-        while time.perf_counter() - t0 < seconds and done < len(ws):
-            chunk = ws[done:done + cores * 4]
-            list(ex.map(one, chunk))
-            done += len(chunk)
-    dt = time.perf_counter() - t0
-    cm = float(sum(mults[:done]))
-    return {"value": 2.0 * cm / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "htns_per_s": done / dt,
-            "sample": f"first {done} of the {len(ws)} networks, FP64 variable elimination, one network per "
-                      f"thread, {dt:.1f} s"}
+        # size the sample: grow it until one pass takes seconds / 4
+        budget = max(0.5, seconds / 4.0)
+        n = min(len(ws), cores)
+        while True:
+            t0 = time.perf_counter()
+            list(ex.map(one, ws[:n]))
+            dt = time.perf_counter() - t0
+            if n >= len(ws) or dt >= budget:
+                break
+            n = min(len(ws), max(n + cores, int(n * min(8.0, 1.2 * budget / max(dt, 1e-3)))))
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            list(ex.map(one, ws[:n]))
+            best = min(best, time.perf_counter() - t0)
+    oracle.set_num_threads(cores)
+    cm = float(sum(mults[:n]))
+    return {"value": 2.0 * cm / best / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "htns_per_s": n / best, "cpu_model": cpu_model(),
+            "sample": f"first {n} of the {len(ws)} networks, FP64 variable elimination, one network per "
+                      f"thread on {cores} threads, best of 3 passes after a warm-up ({best:.2f} s per pass)"}
+
+
+def roofline(flops, nbytes, seconds, flop_peak_tf, unit_peak_name, **extra):
+    """Both roofline fractions of a kernel from its algorithmic flops and HBM
+    bytes per launch and its launch duration; the bound is the unit the
+    arithmetic intensity points at (flops / bytes against the ridge
+    peak_flops / peak_bandwidth), and the reported fraction is that unit's."""
+    fps = flops / seconds / 1e12
+    bps = nbytes / seconds / 1e9
+    ridge = flop_peak_tf * 1e12 / (PEAK["hbm_gbs"] * 1e9)
+    intensity = flops / nbytes if nbytes else float("inf")
+    f_frac = fps / flop_peak_tf
+    b_frac = bps / PEAK["hbm_gbs"]
+    if intensity < ridge:
+        r = {"bound": "hbm", "achieved": round(bps, 2), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+             "frac": round(b_frac, 5)}
+    else:
+        r = {"bound": unit_peak_name, "achieved": round(fps, 4), "peak": flop_peak_tf, "unit": "TFLOP/s",
+             "frac": round(f_frac, 5)}
+    r.update({"intensity_flop_per_byte": round(intensity, 3), "ridge_flop_per_byte": round(ridge, 3),
+              "flop_frac": round(f_frac, 5), "hbm_frac": round(b_frac, 5), "algorithmic_flops": flops,
+              "algorithmic_bytes": nbytes})
+    r.update(extra)
+    return r
 
 
 def oracle_ref(w):
@@ -313,17 +371,21 @@ def bench_grid(args):
             for n, o in zip(pnets, pouts):
                 htn.htn_contract(n, o, stream)
         log(f"timing plain per-network path on {n_plain} networks")
-        p_ms, _ = Timer(stream).run(plain_all, 1, 1)
+        p_ms = median_wall_ms(plain_all, stream, reps=7, warmup=1)
         pv = np.array([float(o.item()) for o in pouts])
         plain = {"htns_per_s": n_plain / (p_ms * 1e-3), "gflops": 2.0 * sum(pm) / (p_ms * 1e-3) / 1e9,
-                 "networks": n_plain, "path": "flop-greedy",
+                 "networks": n_plain, "path": "flop-greedy", "timing": "median of 7 passes after a warm-up",
+                 "ms_per_pass": round(p_ms, 3),
                  "max_abs_diff_vs_batched": float(np.abs(pv - got[:n_plain]).max())}
 
+    log("timing one network alone (latency)")
+    single = single_latency(ws[0], args)
     cpu = None
     if not args.no_cpu:
         log("timing CPU oracle")
         cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
-    achieved = 2.0 * mults / (fused_ms * 1e-3) / 1e12
+    traffic = measured_traffic("k_fused_grid", runs_ok=(args.lds == 81920 and args.threads == 256
+                                                       and args.path == "sampled" and args.samples == 128))
     return {
         "metric": METRIC,
         "value": round(2.0 * greedy_mults / (ms_per_step * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
@@ -343,16 +405,67 @@ def bench_grid(args):
                                 "gflops": round(2.0 * greedy_mults / (g_ms * 1e-3) / 1e9, 3)},
         "plain_fp64_path": plain,
         "speedup_vs_plain_fp64": (htns / plain["htns_per_s"]) if plain else None,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5),
-                     "traffic": measured_traffic("k_fused_grid", runs_ok=(args.lds == 81920 and args.threads == 256
-                                                                           and args.path == "sampled"
-                                                                           and args.samples == 128)),
-                     "kernel": "k_fused<256,double,double,0>", "kernel_ms": round(fused_ms, 4),
-                     "flops_per_launch": 2.0 * mults, "k_fprep_ms": round(prep_ms, 4),
-                     "batch_ms_events": round(kern_ms, 4), "input_bytes": in_bytes},
+        "single_network": single,
+        # k_fused: executed flops of the sampled paths; algorithmic bytes =
+        # the batch's inputs read once plus one FP64 result per network
+        "roofline": roofline(2.0 * mults, in_bytes + 8 * n_nets, fused_ms * 1e-3, PEAK["f64_valu"], "alu",
+                             traffic=traffic, kernel="k_fused<256,double,double,0>", kernel_ms=round(fused_ms, 4),
+                             k_fprep_ms=round(prep_ms, 4), batch_ms_events=round(kern_ms, 4),
+                             input_bytes=in_bytes),
         "cpu_baseline": cpu,
     }
+
+
+def median_wall_ms(fn, stream, reps=7, warmup=1):
+    """Median wall time of `reps` calls of fn, each bracketed by stream
+    synchronisation (for host-bound launch sequences)."""
+    import numpy as np
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            fn()
+    stream.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            fn()
+        stream.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def single_latency(w, args, reps=50):
+    """One grid network contracted on its own (htn_contract, fused executor,
+    sampled path): median HIP-event latency of `reps` calls after a warm-up,
+    and the same through the per-step executor on the FLOP-greedy path."""
+    import numpy as np
+    import torch
+    from paper_2410_15080_amd import htn
+    dev = torch.device("cuda:0")
+    ts = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(dev) for t in w.tensors]
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    res = {}
+    for name, exec_mode, path in (("fused_sampled", htn.HTN_EXEC_FUSED, htn.HTN_PATH_SAMPLED),
+                                  ("steps_greedy", htn.HTN_EXEC_STEPS, htn.HTN_PATH_GREEDY)):
+        n = htn.htn_create(ts, w.labels, w.dims, w.out_labels)
+        htn.htn_set_option(n, htn.HTN_OPT_PATH_SAMPLES, 128)
+        htn.htn_set_path(n, path)
+        htn.htn_set_option(n, htn.HTN_OPT_EXEC, exec_mode)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                htn.htn_contract(n, out, stream)
+            stream.synchronize()
+            for a, b in ev:
+                a.record(stream)
+                htn.htn_contract(n, out, stream)
+                b.record(stream)
+        stream.synchronize()
+        res[name + "_us"] = round(1e3 * float(np.median([a.elapsed_time(b) for a, b in ev])), 2)
+    res["timing"] = f"median of {reps} HIP-event intervals on the launch stream"
+    return res
 
 
 # ------------------------------------------------------------------- qpd
@@ -418,6 +531,7 @@ def bench_qpd(args):
         htn.htn_set_path(n, htn.HTN_PATH_SAMPLED if args.path == "sampled" else htn.HTN_PATH_GREEDY)
     infos = [htn.htn_get_info(n) for n in nets]
     mults = float(sum(i.mults for i in infos))
+    in_bytes = sum(i.input_bytes for i in infos)
     b, out, outs, stream = batch_runner(nets, torch.float64)
     timer = Timer(stream)
 
@@ -449,7 +563,6 @@ def bench_qpd(args):
         log("timing CPU oracle")
         cpu = cpu_baseline([qs.truncate(ws[i], *sampled[i][:2], s_qpd) for i in range(min(n_nets, 4096))],
                            args.cpu_seconds, greedy_list)
-    achieved = 2.0 * mults / (fused_ms * 1e-3) / 1e12
     tr_gbs = trunc_bytes / (trunc_ms * 1e-3) / 1e9
     htn.htn_truncate_destroy(tr)
     return {
@@ -469,11 +582,10 @@ def bench_qpd(args):
         "k_truncate": {"ms": round(trunc_ms, 4), "algorithmic_bytes": trunc_bytes, "items": len(items),
                        "achieved_gbs": round(tr_gbs, 1), "frac_of_hbm_peak": round(tr_gbs / PEAK["hbm_gbs"], 4),
                        "traffic": measured_traffic("k_truncate_qpd8", runs_ok=(s_qpd == 8 and n_nets == 1024))},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["f64_valu"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_valu"], 5), "traffic": None,
-                     "kernel": f"k_fused<{args.threads},double,double,0>", "kernel_ms": round(fused_ms, 4),
-                     "flops_per_launch": 2.0 * mults, "k_fprep_ms": round(prep_ms, 4),
-                     "batch_ms_events": round(kern_ms, 4)},
+        "roofline": roofline(2.0 * mults, in_bytes + 8 * n_nets, fused_ms * 1e-3, PEAK["f64_valu"], "alu",
+                             traffic=None, kernel=f"k_fused<{args.threads},double,double,0>",
+                             kernel_ms=round(fused_ms, 4), k_fprep_ms=round(prep_ms, 4),
+                             batch_ms_events=round(kern_ms, 4)),
         "cpu_baseline": cpu,
     }
 
@@ -549,7 +661,6 @@ def bench_random(args):
     if not args.no_cpu:
         log("timing CPU oracle")
         cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
-    achieved = 2.0 * mults / (kern_ms * 1e-3) / 1e12
     peak = PEAK["f32_valu"] if compute != htn.HTN_F64 else PEAK["f64_valu"]
     return {
         "metric": METRIC,
@@ -567,11 +678,9 @@ def bench_random(args):
         "other_paths": legs,
         "speedup_vs_flop_greedy": (round(legs["greedy"]["ms_per_step"] / ms_per_step, 3) if "greedy" in legs
                                    else None),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 5), "traffic": None,
-                     "kernel": "graph: k_fused + k_fprep + per-step kernels of the largest networks",
-                     "kernel_ms": round(kern_ms, 4), "input_bytes": in_bytes,
-                     "hbm_gbs_on_inputs": round(in_bytes / (kern_ms * 1e-3) / 1e9, 2)},
+        "roofline": roofline(2.0 * mults, in_bytes + 8 * n_nets, kern_ms * 1e-3, peak, "alu", traffic=None,
+                             kernel="graph: k_fprep + k_fused + per-step kernels of the largest networks",
+                             kernel_ms=round(kern_ms, 4), input_bytes=in_bytes),
         "cpu_baseline": cpu,
     }
 
@@ -610,22 +719,22 @@ def bench_marginal(args):
     gflop = 2.0 * greedy[0] / 1e9
     mf = 2.0 * float(np.prod(gemm[0]["gemm"])) / 1e9 if gemm else gflop
     peak = {"f64": PEAK["f64_mfma"], "f32": PEAK["f32_mfma"], "bf16": PEAK["bf16_mfma"]}[name]
-    achieved = mf / (kern_ms * 1e-3) / 1e3
     out_bytes = 4096 * 4096 * 8
+    in_bytes = htn.htn_get_info(net).input_bytes
     cpu = None
     if not args.no_cpu:
-        # oracle: the naive sum on a block of outputs, scaled per output
+        # the oracle (FP64 variable elimination) on whole rows R[x1, :], each
+        # row the network with x1 fixed, scaled from the rows timed to all
         log("timing CPU oracle")
-        blk = 8
-        ts = [w.tensors[0][..., :blk], w.tensors[1][..., :blk]] + list(w.tensors[2:])
-        dims = list(w.dims)
-        dims[2 * c] = dims[2 * c + 1] = blk
-        t0 = time.perf_counter()
-        oracle.naive_contract(ts, w.labels, dims, w.out_labels)
-        dt = (time.perf_counter() - t0) * (4096 / blk) ** 2
-        cpu = {"value": gflop / dt, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-               "sample": f"naive knitting sum on an {blk}x{blk} output block, scaled to 4096x4096 "
-                         f"(extrapolated: {dt:.0f} s)"}
+        from workloads.network import Network
+        rows = []
+        for x1 in range(4096):
+            ts = [w.tensors[0][..., x1], w.tensors[1]] + list(w.tensors[2:])
+            ls = [w.labels[0][:c], w.labels[1]] + list(w.labels[2:])
+            rows.append(Network(ts, ls, w.dims, [w.labels[1][c]], w.kinds, {}))
+        cpu = cpu_baseline(rows, args.cpu_seconds, [greedy[0] / 4096.0] * 4096)
+        cpu["htns_per_s"] = cpu["htns_per_s"] / 4096.0
+        cpu["sample"] = "rows of the marginal (one network per row, x1 fixed): " + cpu["sample"]
     return {
         "metric": METRIC,
         "value": round(gflop / (ms * 1e-3), 3), "unit": "GFLOP/s", "ms_per_step": round(ms, 4), "dtype": name,
@@ -634,13 +743,11 @@ def bench_marginal(args):
         "htns_per_s": round(1.0 / (ms * 1e-3), 2),
         "sum_minus_one": float(R.sum() - 1.0),
         "max_abs_err_sampled": float(max(errs)),
-        "roofline": {"bound": "mfma" if name != "bf16" else "hbm",
-                     "achieved": round(achieved if name != "bf16" else out_bytes / (kern_ms * 1e-3) / 1e9, 3),
-                     "peak": peak if name != "bf16" else PEAK["hbm_gbs"],
-                     "unit": "TFLOP/s" if name != "bf16" else "GB/s",
-                     "frac": round(achieved / peak if name != "bf16" else out_bytes / (kern_ms * 1e-3) / 1e9
-                                   / PEAK["hbm_gbs"], 4),
-                     "traffic": None, "kernel": "k_gemm (+ pack and fold steps)", "kernel_ms": round(kern_ms, 4)},
+        # the whole contraction (coefficient fold, packs and the GEMM) timed as
+        # one: the GEMM's flops over the inputs read once and the FP64
+        # result written once
+        "roofline": roofline(mf * 1e9, in_bytes + out_bytes, kern_ms * 1e-3, peak, "mfma", traffic=None,
+                             kernel="whole contraction: fold + pack + k_gemm", kernel_ms=round(kern_ms, 4)),
         "cpu_baseline": cpu,
     }
 
@@ -683,7 +790,7 @@ def bench_ring(args):
     if not args.no_cpu:
         log("timing CPU oracle")
         cpu = cpu_baseline(ws, args.cpu_seconds, greedy_list)
-    gbs = in_bytes / (kern_ms * 1e-3) / 1e9
+    peak = PEAK["f64_valu"] if compute == htn.HTN_F64 else PEAK["f32_valu"]
     return {
         "metric": METRIC,
         "value": round(2.0 * float(sum(greedy_list)) / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s",
@@ -694,11 +801,120 @@ def bench_ring(args):
         "max_rel_err_vs_oracle": float(max(rel)), "median_rel_err_vs_oracle": float(np.median(rel)),
         "max_abs_err_over_abs_network": float(max(over_abs)),
         "greedy_mults_per_step": float(sum(greedy_list)), "executed_mults_per_step": mults,
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                     "frac": round(gbs / PEAK["hbm_gbs"], 5), "traffic": None, "input_bytes": in_bytes,
-                     "kernel": "graph: k_fprep + k_fused", "kernel_ms": round(kern_ms, 4)},
+        "roofline": roofline(2.0 * mults, in_bytes + 8 * n_nets, kern_ms * 1e-3, peak, "alu", traffic=None,
+                             kernel="graph: k_fprep + k_fused + per-step kernels", kernel_ms=round(kern_ms, 4),
+                             input_bytes=in_bytes),
         "cpu_baseline": cpu,
     }
+
+
+# ---------------------------------------------------------------- circuit
+
+def bench_circuit(args):
+    """The 10-qubit circuit cut by two wire cuts into three subcircuits (QTs
+    [4], [4, 4], [4] from an exact statevector): latency of one contraction
+    (both executors) and its error against the uncut circuit's statevector."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2410_15080_amd import htn
+    from workloads import configs
+    from workloads import statevector as sv
+    w = configs.circuit_cut_wires(0)
+    full = sv.run_ops(sv.zero_state(10), configs.circuit1_full_ops(0), {q: "Z" for q in range(10)})
+    ts = [torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in w.tensors]
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    res = {}
+    for name, mode in (("fused", htn.HTN_EXEC_FUSED), ("steps", htn.HTN_EXEC_STEPS)):
+        n = htn.htn_create(ts, w.labels, w.dims, w.out_labels)
+        htn.htn_set_option(n, htn.HTN_OPT_EXEC, mode)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                htn.htn_contract(n, out, stream)
+            for a, b in ev:
+                a.record(stream)
+                htn.htn_contract(n, out, stream)
+                b.record(stream)
+        stream.synchronize()
+        res[name] = {"latency_us": round(1e3 * float(np.median([a.elapsed_time(b) for a, b in ev])), 2),
+                     "abs_err_vs_statevector": abs(float(out.item()) - full)}
+    ref, nterms = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    t0 = time.perf_counter()
+    for _ in range(1000):
+        oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    naive_us = (time.perf_counter() - t0) * 1e3
+    return {"workload": "circuit10_two_wire_cuts", "qts": "[4], [4,4], [4]", "executors": res,
+            "statevector_value": full, "oracle_naive_value": float(ref), "oracle_terms": nterms,
+            "cpu_baseline": {"value": round(naive_us, 3), "unit": "us per network", "cores": 1, "kind": "oracle",
+                             "sample": "naive knitting sum, mean of 1000 calls (includes ctypes marshalling)"}}
+
+
+def copy_calibration(args):
+    """Plain device-to-device copy of 64 MiB, three launches: the reference
+    run for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes
+    (bytes per counter unit = bytes copied / counter reading)."""
+    import torch
+    n = 64 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {n * 8} bytes per launch, 3 launches")
+    return None
+
+
+def sub_args(args, **kw):
+    """Arguments of a nested configuration run: the defaults of its own
+    workload, fewer timed steps, a shorter CPU sample."""
+    a = argparse.Namespace(**vars(args))
+    a.batch = None
+    a.lds = None
+    a.threads = 256
+    a.path = None
+    a.samples = None
+    a.dtype = None
+    a.autotune = "auto"
+    a.steps = max(5, min(args.steps, 10))
+    a.warmup = max(2, min(args.warmup, 3))
+    a.cpu_seconds = min(args.cpu_seconds, 6.0)
+    a.no_plain = True
+    for k, v in kw.items():
+        setattr(a, k, v)
+    if a.workload not in ("grid", "qpd"):
+        a.lds = a.lds or 65536
+    return a
+
+
+NESTED = (("circuit10", "circuit", {}),
+          ("marginal_f64", "marginal", {"dtype": "f64"}),
+          ("marginal_f32", "marginal", {"dtype": "f32"}),
+          ("marginal_bf16", "marginal", {"dtype": "bf16"}),
+          ("ring_f64", "ring", {"dtype": "f64"}),
+          ("ring_f32", "ring", {"dtype": "f32"}),
+          ("ring_bf16", "ring", {"dtype": "bf16"}),
+          ("random_f32_learned", "random", {"dtype": "f32"}),
+          ("qpd_grid_s8", "qpd", {}))
+
+
+def run_nested(args):
+    """Every other workload, each in the same form as its own line, nested
+    under the headline line's "configs"."""
+    fns = {"circuit": bench_circuit, "random": bench_random, "marginal": bench_marginal, "ring": bench_ring,
+           "qpd": bench_qpd}
+    out = {}
+    for key, wl, kw in NESTED:
+        log(f"--- nested configuration {key}")
+        t0 = time.perf_counter()
+        a = sub_args(args, workload=wl, **kw)
+        r = fns[wl](a)
+        r.pop("metric", None)
+        r["steps"], r["warmup"] = a.steps, a.warmup
+        r["run_s"] = round(time.perf_counter() - t0, 1)
+        out[key] = r
+    return out
 
 
 def main():
@@ -711,9 +927,14 @@ def main():
     torch.cuda.set_device(0)
     if args.workload not in ("grid", "qpd"):
         args.lds = args.lds or 65536
+    if args.workload == "copy-calibration":
+        copy_calibration(args)
+        return 0
     fn = {"grid": bench_grid, "random": bench_random, "marginal": bench_marginal, "ring": bench_ring,
           "qpd": bench_qpd}[args.workload]
     line = fn(args)
+    if args.workload == "grid" and args.configs == "all":
+        line["configs"] = run_nested(args)
     head = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": line.pop("dtype"),

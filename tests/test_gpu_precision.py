@@ -68,8 +68,15 @@ def test_grid_bf16_within_bound(exec_mode):
         net = create(w, compute=htn.HTN_BF16, final_sum=htn.HTN_SUM_COMPENSATED, storage=htn.HTN_F64,
                      exec_mode=exec_mode)
         got = float(contract(net, ()))
-        bound = (_gamma(_n_roundings(net), U32) + 16 * U16) * float(_abs_value(w))
+        xabs = float(_abs_value(w))
+        bound = (_gamma(_n_roundings(net), U32) + 16 * U16) * xabs
         assert abs(got - ref) <= bound, (seed, got, ref, bound)
+        # against the input-rounding-only error (the oracle on BF16-rounded
+        # inputs): at most twice it, plus the FP32 arithmetic term, since a
+        # scalar's input-rounding error can cancel to almost nothing
+        rin = oracle.ve_contract(_rounded_bf16(w), w.labels, w.dims, w.out_labels, mode="f64")
+        e_in = abs(float(rin) - ref)
+        assert abs(got - ref) <= 2.0 * e_in + _gamma(_n_roundings(net), U32) * xabs, (seed, got, ref, e_in)
 
 
 def _rounded_bf16(w):
@@ -111,6 +118,9 @@ def test_marginal_matrix_core_paths(compute, bits):
         e_in = float(np.abs(rin - ref).max())
         assert err <= float((_gamma(300, U32) + 4 * U16) * absval.max()), err
         print(f"bf16 marginal: gpu max-abs {err:.3e}, input-rounding-only {e_in:.3e}")
+        # the GPU error stays within twice the error that rounding the inputs
+        # alone causes (the extra rounding is that of the folded operand)
+        assert err <= 2.0 * e_in, (err, e_in)
         # sanity check only: BF16 rounding of the folded operand moves the
         # sum (its first-order bound, 3 * 2^-9 * (sum |c_w|)^4, is vacuous)
         assert abs(got.sum() - 1.0) <= 1e-2
@@ -129,3 +139,119 @@ def test_ring_of_rings_precisions():
         u = 2.0 ** -53 if compute == htn.HTN_F64 else U32
         bound = (_gamma(_n_roundings(net), u) + 64 * u_in) * absval
         assert abs(got - ref) <= bound, (compute, got, ref, bound)
+
+
+def _oracle_pool(fn, items):
+    """fn over items on the host cores, one oracle thread each."""
+    import concurrent.futures
+    import os
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    oracle.set_num_threads(1)
+    try:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as ex:
+            return list(ex.map(fn, items))
+    finally:
+        oracle.set_num_threads(cores)
+
+
+@pytest.mark.parametrize("final_sum", [htn.HTN_SUM_FP64, htn.HTN_SUM_COMPENSATED])
+def test_random_serving_batch_f32_with_fp64_final_sum(final_sum):
+    """The serving batch at its stated precision: FP32 inputs, intermediates
+    and accumulation, the final signed sum in FP64 (or compensated FP64),
+    every network of a 128-network random batch (including the two heaviest,
+    which run step by step beside the fused launch), eager and graph runs,
+    against the double-double oracle under the first-order bound
+    gamma(n, 2^-24) * X_abs (the entries are FP32 values, so the inputs
+    carry no rounding)."""
+    import torch
+    ws = configs.random_batch(3, n=128, dtype=np.float32)
+    nets = [create(w, compute=htn.HTN_F32, final_sum=final_sum, storage=htn.HTN_F32) for w in ws]
+    stepped = [i for i, n in enumerate(nets) if not json.loads(htn.htn_plan_json(n))["fused_batch_ok"]]
+    assert len(stepped) >= 2
+
+    def refs(w):
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ahi, alo = oracle.ve_contract([np.abs(t) for t in w.tensors], w.labels, w.dims, w.out_labels)
+        return float(hi) + float(lo), float(ahi) + float(alo)
+
+    ref = _oracle_pool(refs, ws)
+    outs = [htn.new_output(n) for n in nets]
+    assert all(o.dtype == torch.float64 for o in outs)
+    b = htn.htn_batch_create(nets)
+    stream = torch.cuda.Stream()
+    for graph in (False, True, True):
+        htn.htn_batch_set_graph(b, graph)
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            htn.htn_batch_run(b, htn.pointer_array(outs), stream)
+        stream.synchronize()
+        for i, (w, n, o) in enumerate(zip(ws, nets, outs)):
+            x, xabs = ref[i]
+            bound = _gamma(_n_roundings(n), U32) * xabs
+            assert abs(float(o.item()) - x) <= bound, (graph, i, float(o.item()), x, bound)
+
+
+def _marginal_slices(w, rows, cols, tensors=None):
+    """Oracle values of full rows R[x1, :] and full columns R[:, x2] of the
+    marginal, each as the contraction of the network with one output label
+    fixed (double-double variable elimination on the sliced QT)."""
+    c = 4
+    ts0 = w.tensors if tensors is None else tensors
+
+    def row(x1):
+        ts = [ts0[0][..., x1], ts0[1]] + list(ts0[2:])
+        ls = [w.labels[0][:c], w.labels[1]] + list(w.labels[2:])
+        hi, lo = oracle.ve_contract(ts, ls, w.dims, [w.labels[1][c]])
+        return hi + lo
+
+    def col(x2):
+        ts = [ts0[0], ts0[1][..., x2]] + list(ts0[2:])
+        ls = [w.labels[0], w.labels[1][:c]] + list(w.labels[2:])
+        hi, lo = oracle.ve_contract(ts, ls, w.dims, [w.labels[0][c]])
+        return hi + lo
+
+    return _oracle_pool(row, rows), _oracle_pool(col, cols)
+
+
+@pytest.mark.parametrize("compute", [htn.HTN_F64, htn.HTN_F32, htn.HTN_BF16])
+def test_marginal_4096_every_output_tile(compute):
+    """The full-size 4096 x 4096 marginal (K = 256 on the matrix cores) in
+    each precision, FP64 output: one full row in every 128-row block and one
+    full column in every 128-column block (so every 128 x 128 output tile is
+    checked on a whole row segment and a whole column segment) against the
+    oracle, element by element; plus the sum invariant sum R = 1.
+    FP64: 1e-12 relative + 1e-17.  FP32: (gamma(300, 2^-24) + 2 2^-24) times
+    the |entries| contraction.  BF16: at most twice the error of the oracle
+    run on the BF16-rounded inputs (the input-rounding-only error), max-abs
+    over the checked entries."""
+    w = configs.marginal_network(0, out_bits=12)
+    rng = np.random.default_rng(41)
+    rows = [128 * i + int(rng.integers(0, 128)) for i in range(32)]
+    cols = [128 * j + int(rng.integers(0, 128)) for j in range(32)]
+    fs = htn.HTN_SUM_PLAIN if compute == htn.HTN_F64 else htn.HTN_SUM_FP64
+    net = create(w, compute=compute, final_sum=fs, storage=htn.HTN_F64, exec_mode=htn.HTN_EXEC_STEPS)
+    got = contract(net, (4096, 4096))
+    ref_r, ref_c = _marginal_slices(w, rows, cols)
+    got_r = np.stack([got[x, :] for x in rows])
+    got_c = np.stack([got[:, x] for x in cols])
+    ref_r, ref_c = np.stack(ref_r), np.stack(ref_c)
+    err = max(float(np.abs(got_r - ref_r).max()), float(np.abs(got_c - ref_c).max()))
+    if compute == htn.HTN_F64:
+        assert np.all(np.abs(got_r - ref_r) <= 1e-17 + 1e-12 * np.abs(ref_r))
+        assert np.all(np.abs(got_c - ref_c) <= 1e-17 + 1e-12 * np.abs(ref_c))
+        assert abs(got.sum() - 1.0) < 1e-9
+    elif compute == htn.HTN_F32:
+        aw = [np.abs(t) for t in w.tensors]
+        abs_r, abs_c = _marginal_slices(w, rows, cols, tensors=aw)
+        bound_r = (_gamma(300, U32) + 2 * U32) * np.stack(abs_r)
+        bound_c = (_gamma(300, U32) + 2 * U32) * np.stack(abs_c)
+        assert np.all(np.abs(got_r - ref_r) <= bound_r)
+        assert np.all(np.abs(got_c - ref_c) <= bound_c)
+        assert abs(got.sum() - 1.0) < 1e-6
+    else:
+        rin_r, rin_c = _marginal_slices(w, rows, cols, tensors=_rounded_bf16(w))
+        e_in = max(float(np.abs(np.stack(rin_r) - ref_r).max()), float(np.abs(np.stack(rin_c) - ref_c).max()))
+        print(f"bf16 4096 marginal: gpu max-abs {err:.3e}, input-rounding-only {e_in:.3e}")
+        assert err <= 2.0 * e_in, (err, e_in)
