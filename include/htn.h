@@ -369,6 +369,40 @@ htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacit
 htn_status htn_autotune(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream,
                         int32_t *best_threads, int32_t *best_lds_bytes, float *best_ms);
 
+/* ---------------------------------------------------------------------
+ * htn_contract_noalloc — htn_contract for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *
+ * It runs the per-step executor (as with HTN_EXEC_STEPS: one launch that
+ * applies absorbed coefficient tensors, then one kernel sequence per
+ * pairwise step) and writes the result to out_device (caller-owned device
+ * memory, as for htn_contract), asynchronously on hip_stream.  The
+ * executor's workspace (materialised inputs, intermediates, split-sum and
+ * split-K partials) lives in a library-wide device array of
+ * HTN_NOALLOC_SCRATCH_BYTES bytes.  Each device holds its own copy from
+ * the library's load until the process ends.  The array is shared by every
+ * call on that device and keeps the last call's contents.  Calls that
+ * overlap on one device, on any streams, therefore race: serialise them.
+ * No kernel of the executor needs the workspace cleared first.
+ *
+ * Preconditions: the net's device state (input copies, step tables, load
+ * descriptors) has been set up on the current device by an htn_contract
+ * call after the net's last htn_create, htn_set_path, htn_set_option or
+ * htn_update_data.
+ * Errors (all reported before anything is enqueued):
+ *   HTN_E_ARG          NULL net or out_device.
+ *   HTN_E_UNSUPPORTED  the net's per-step workspace (htn_info.workspace_bytes)
+ *                      exceeds HTN_NOALLOC_SCRATCH_BYTES.
+ *   HTN_E_STATE        the device state is missing or stale, or it lives on
+ *                      another device.
+ *   HTN_E_DEVICE       a HIP error while resolving the array's address
+ *                      (first call on a device) or enqueueing.
+ * ------------------------------------------------------------------- */
+#define HTN_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+htn_status htn_contract_noalloc(htn_net_t net, void *out_device, void *hip_stream);
+
 /* htn_update_data — replace the tensor values (same structure and path).
  * Same data / data_on_device semantics as htn_create.                     */
 htn_status htn_update_data(htn_net_t net, const void *const *data, int32_t data_on_device);

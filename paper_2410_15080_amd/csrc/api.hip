@@ -285,7 +285,7 @@ static void upload_plan(Net &n) {
         kern::PrepDesc q;
         std::memset(&q, 0, sizeof(q));
         q.src = D.in[lp.base];
-        q.dst = (unsigned char *)D.d_ws + P.ws_off[lp.value];
+        q.dst_off = P.ws_off[lp.value];
         q.size = (int32_t)lp.size;
         q.ns = (int32_t)lp.scales.size();
         for (int k = 0; k < q.ns; ++k) {
@@ -397,34 +397,37 @@ static kern::StepArgs pack_args(const StepPlan::Pack &pk) {
 
 // Matrix-core step: pack both operands K-contiguous, then one GEMM launch.
 static void run_mfma_step(Net &n, const StepPlan &s, const void *A, int ta, const void *B, int tb, void *C, int tc,
-                          hipStream_t st) {
+                          unsigned char *ws, hipStream_t st) {
     DeviceState &D = *n.dev;
     const int tp = n.compute == HTN_BF16 ? 2 : (int)inter_dtype(n.compute);
     // an operand its producer already wrote in packed order is used in place
     const void *pa = A, *pb = B;
     if (!(s.pack_a.identity && ta == tp)) {
-        void *w = (unsigned char *)D.d_ws + s.ws_pa;
+        void *w = ws + s.ws_pa;
         if (s.ws_pa < 0) throw Error{HTN_E_STATE, "packed operand without workspace"};
         HIP_TRY(kern::launch_step(A, ta, nullptr, ta, w, tp, false, false, D.d_tab, pack_args(s.pack_a), st));
         pa = w;
     }
     if (!(s.pack_b.identity && tb == tp)) {
-        void *w = (unsigned char *)D.d_ws + s.ws_pb;
+        void *w = ws + s.ws_pb;
         if (s.ws_pb < 0) throw Error{HTN_E_STATE, "packed operand without workspace"};
         HIP_TRY(kern::launch_step(B, tb, nullptr, tb, w, tp, false, false, D.d_tab, pack_args(s.pack_b), st));
         pb = w;
     }
-    void *kpart = s.ksplit > 1 ? (unsigned char *)D.d_ws + s.ws_kpart : nullptr;
+    void *kpart = s.ksplit > 1 ? ws + s.ws_kpart : nullptr;
     HIP_TRY(kern::launch_gemm(pa, pb, C, tp, tc, (int)s.gm, (int)s.gn, (int)s.gk, (int)s.gb, 64, s.ksplit, kpart, st));
 }
 
 // ticks (optional): the device clock after each of the first max_ticks
-// kernel steps.
-static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullptr, int max_ticks = 0) {
+// kernel steps.  ws: the workspace (the net's own when NULL; at least
+// plan.ws_bytes bytes).
+static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullptr, int max_ticks = 0,
+                      void *ws_base = nullptr) {
     DeviceState &D = *n.dev;
     const Plan &P = n.plan;
+    unsigned char *ws = (unsigned char *)(ws_base ? ws_base : D.d_ws);
     const int tin = (int)input_dtype(n.compute), tint = (int)inter_dtype(n.compute);
-    if (D.n_prep) HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep, D.prep_max, tin, tint, D.d_tab, st));
+    if (D.n_prep) HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep, D.prep_max, tin, tint, D.d_tab, ws, st));
     int q = -1;
     for (int k : P.kernel_steps) {
         if (ticks && q >= 0 && q < max_ticks) HIP_TRY(kern::launch_stamp(ticks + q, st));
@@ -435,7 +438,7 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
                 ptr = nullptr;
                 t = tint;
             } else if (P.ws_off[id] >= 0) {
-                ptr = (const unsigned char *)D.d_ws + P.ws_off[id];
+                ptr = ws + P.ws_off[id];
                 const int pr = P.values[id].producer;
                 t = (!P.values[id].input && pr >= 0 && P.steps[pr].out_bf16) ? (int)HTN_BF16 : tint;
             } else {
@@ -455,11 +458,11 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
             tc = n.final_sum == HTN_SUM_PLAIN ? tint : 0;
             comp = n.final_sum == HTN_SUM_COMPENSATED;
         } else {
-            C = (unsigned char *)D.d_ws + P.ws_off[s.c];
+            C = ws + P.ws_off[s.c];
             tc = s.out_bf16 ? (int)HTN_BF16 : tint;
         }
         if (s.mfma) {
-            run_mfma_step(n, s, A, ta, B, tb, C, tc, st);
+            run_mfma_step(n, s, A, ta, B, tb, C, tc, ws, st);
             continue;
         }
         kern::StepArgs a;
@@ -478,7 +481,7 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
         if (s.split_global > 1) {
             a.split = s.split_global;
             a.chunk = (s.n_sum + s.split_global - 1) / s.split_global;
-            a.part = (double *)((unsigned char *)D.d_ws + s.ws_part);
+            a.part = (double *)(ws + s.ws_part);
         }
         HIP_TRY(kern::launch_step(A, ta, B, tb, C, tc, tc == 0, comp, D.d_tab, a, st));
     }
@@ -690,6 +693,50 @@ htn_status htn_contract(htn_net_t net, void *out_device, void *hip_stream) {
     if (!net || !out_device) return fail(HTN_E_ARG, "NULL argument");
     ensure_device(*net);
     contract_one(*net, out_device, (hipStream_t)hip_stream);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+}  // extern "C"
+
+// Workspace of htn_contract_noalloc: one array per device (each device holds
+// its own copy from the library's load until the process ends), shared by
+// every call on that device.  Host code never uses the array's name as an
+// address: the device address comes from hipGetSymbolAddress, resolved once
+// per device with that device current.
+static __device__ __align__(256) unsigned char scratch[HTN_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static void *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw Error{HTN_E_DEVICE, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error{HTN_E_DEVICE, "hipGetSymbolAddress returned NULL"};
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" {
+
+htn_status htn_contract_noalloc(htn_net_t net, void *out_device, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!net || !out_device) return fail(HTN_E_ARG, "NULL argument");
+    if (net->plan.ws_bytes > (int64_t)HTN_NOALLOC_SCRATCH_BYTES)
+        return fail(HTN_E_UNSUPPORTED, "the per-step workspace needs " + std::to_string(net->plan.ws_bytes) +
+                                           " bytes, above the " + std::to_string((int64_t)HTN_NOALLOC_SCRATCH_BYTES) +
+                                           "-byte allocation-free workspace");
+    if (!net->dev || net->data_dirty || net->dev->plan_uploaded != net->plan_version)
+        return fail(HTN_E_STATE, "device state of the net is not set up: call htn_contract once after the last "
+                                 "htn_create, htn_set_path, htn_set_option or htn_update_data");
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != net->dev->device) return fail(HTN_E_STATE, "net was set up on another device");
+    run_steps(*net, out_device, (hipStream_t)hip_stream, nullptr, 0, scratch_address(cur));
     return HTN_OK;
     API_GUARD_END
 }

@@ -179,10 +179,11 @@ hipError_t launch_step(const void *A, int ta, const void *B, int tb, void *C, in
 // ------------------------------------------------------------------ k_prep
 
 template <typename TIN, typename TI>
-__global__ __launch_bounds__(kBlk) void k_prep(const PrepDesc *__restrict__ descs, const int2 *__restrict__ tab) {
+__global__ __launch_bounds__(kBlk) void k_prep(const PrepDesc *__restrict__ descs, const int2 *__restrict__ tab,
+                                                unsigned char *__restrict__ ws) {
     const PrepDesc &q = descs[blockIdx.y];
     const TIN *src = (const TIN *)q.src;
-    TI *dst = (TI *)q.dst;
+    TI *dst = (TI *)(ws + q.dst_off);
     const int ns = q.ns;
     for (int e = blockIdx.x * kBlk + threadIdx.x; e < q.size; e += gridDim.x * kBlk) {
         int se = e;
@@ -201,17 +202,17 @@ __global__ __launch_bounds__(kBlk) void k_prep(const PrepDesc *__restrict__ desc
 }
 
 hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin, int tinter, const int2 *tab,
-                       hipStream_t st) {
+                       void *ws, hipStream_t st) {
     if (n_desc <= 0) return hipSuccess;
     int bx = (max_size + kBlk * 4 - 1) / (kBlk * 4);
     bx = bx < 1 ? 1 : (bx > 4096 ? 4096 : bx);
     dim3 grid(bx, n_desc);
     if (tin == 0 && tinter == 0)
-        hipLaunchKernelGGL((k_prep<double, double>), grid, dim3(kBlk), 0, st, d_desc, tab);
+        hipLaunchKernelGGL((k_prep<double, double>), grid, dim3(kBlk), 0, st, d_desc, tab, (unsigned char *)ws);
     else if (tin == 1 && tinter == 1)
-        hipLaunchKernelGGL((k_prep<float, float>), grid, dim3(kBlk), 0, st, d_desc, tab);
+        hipLaunchKernelGGL((k_prep<float, float>), grid, dim3(kBlk), 0, st, d_desc, tab, (unsigned char *)ws);
     else if (tin == 2 && tinter == 1)
-        hipLaunchKernelGGL((k_prep<bf16_t, float>), grid, dim3(kBlk), 0, st, d_desc, tab);
+        hipLaunchKernelGGL((k_prep<bf16_t, float>), grid, dim3(kBlk), 0, st, d_desc, tab, (unsigned char *)ws);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

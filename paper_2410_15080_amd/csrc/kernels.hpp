@@ -38,15 +38,16 @@ hipError_t launch_step(const void *A, int ta, const void *B, int tb, void *C, in
 constexpr int kMaxScalesDev = 16;
 struct PrepDesc {
     const void *src;   // input in its device dtype
-    void *dst;         // intermediate-dtype copy
+    int64_t dst_off;   // byte offset of its intermediate-dtype copy in the workspace
     int32_t size;
     int32_t ns;
     const void *sp[kMaxScalesDev];
     int32_t thi[kMaxScalesDev], tlo[kMaxScalesDev], nlo[kMaxScalesDev];
     int32_t sthi, stlo, snlo;  // source gather table (snlo = 0: same layout)
 };
+// ws: the workspace the copies are written to (base of dst_off).
 hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin, int tinter, const int2 *tab,
-                       hipStream_t st);
+                       void *ws, hipStream_t st);
 
 // Fused whole-network kernel.
 struct FPrepEntry;

@@ -86,6 +86,7 @@ def load_library():
         "htn_set_option": (I32, [P, I32, I64]),
         "htn_get_info": (I32, [P, ctypes.POINTER(htn_info)]),
         "htn_contract": (I32, [P, P, P]),
+        "htn_contract_noalloc": (I32, [P, P, P]),
         "htn_contract_batch": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P]),
         "htn_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
         "htn_batch_set_graph": (I32, [P, I32]),
@@ -300,6 +301,13 @@ def htn_get_info(net: Net) -> htn_info:
 
 def htn_contract(net: Net, out, stream=None) -> None:
     _check(load_library().htn_contract(net.handle, ctypes.c_void_p(_data_ptr(out)), _stream_ptr(stream)))
+
+
+HTN_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def htn_contract_noalloc(net: Net, out, stream=None) -> None:
+    _check(load_library().htn_contract_noalloc(net.handle, ctypes.c_void_p(_data_ptr(out)), _stream_ptr(stream)))
 
 
 def pointer_array(outs):

@@ -182,3 +182,19 @@ def test_truncation_items_are_validated_before_any_device_call():
     for kept, dims in (([[0, 6], None], (6, 4)), ([[], None], (6, 4)), ([None, None], (6, 0))):
         with pytest.raises(htn.HtnError, match="HTN_E_ARG"):
             htn.htn_truncate_create([(1, 2, dims, kept)], htn.HTN_F64)
+
+
+def test_noalloc_rejects_a_workspace_above_its_limit_on_the_host():
+    """Three 4096 x 4096 matrices in a chain: the per-step workspace holds a
+    128 MiB intermediate, above the allocation-free limit; the call fails on
+    the host before touching a device."""
+    import numpy as np
+    from paper_2410_15080_amd import htn
+    d = 4096
+    ts = [np.zeros((d, d)), np.zeros((d, d)), np.zeros((d, d))]
+    net = htn.htn_create(ts, [[0, 1], [1, 2], [2, 3]], [d, d, d, d], [0, 3])
+    info = htn.htn_get_info(net)
+    assert info.workspace_bytes > htn.HTN_NOALLOC_SCRATCH_BYTES
+    with pytest.raises(htn.HtnError) as e:
+        htn.htn_contract_noalloc(net, np.zeros(1))  # rejected before the output is used
+    assert e.value.name == "HTN_E_UNSUPPORTED"
