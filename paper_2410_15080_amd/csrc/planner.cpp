@@ -105,7 +105,12 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
     struct Cand {
         double cost, os;
         int i, j;
+        int absorb;  // 1: an input scaled by another input (a1 absorption)
     };
+    // ids holding an input (possibly with absorbed factors): absorbing one
+    // into another is a scaling of a load, not a kernel step
+    std::vector<char> is_input(2 * N, 0);
+    for (int i = 0; i < N; ++i) is_input[i] = 1;
     std::vector<Cand> cands;
     auto eval = [&](int i, int j, Cand &c, std::vector<int> *kept_out) {
         std::vector<int> u = sorted_union(lab[i], lab[j]);
@@ -121,6 +126,35 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
             }
         }
         c.os = os;
+        // absorption: both are inputs, one label set holds the other, and no
+        // label of extent above 1 is summed
+        c.absorb = 0;
+        if (is_input[i] && is_input[j] &&
+            (std::includes(lab[i].begin(), lab[i].end(), lab[j].begin(), lab[j].end()) ||
+             std::includes(lab[j].begin(), lab[j].end(), lab[i].begin(), lab[i].end()))) {
+            c.absorb = 1;
+            for (int l : u) {
+                const int r = ref[l] - (int)contains(lab[i], l) - (int)contains(lab[j], l);
+                if (!is_out[l] && r <= 0 && n.dims[l] > 1) c.absorb = 0;
+            }
+        }
+    };
+    auto take = [&](int i, int j) {
+        Cand c;
+        std::vector<int> kept;
+        eval(i, j, c, &kept);
+        tot += c.cost;
+        pk = std::max(pk, c.os);
+        path.push_back({i, j});
+        for (int l : lab[i]) ref[l]--;
+        for (int l : lab[j]) ref[l]--;
+        alive[i] = alive[j] = 0;
+        lab[next] = kept;
+        for (int l : kept) ref[l]++;
+        alive[next] = 1;
+        is_input[next] = is_input[i] && is_input[j] && c.absorb;
+        ++next;
+        --n_alive;
     };
     while (n_alive > 1) {
         for (auto &h : holders) h.clear();
@@ -140,6 +174,7 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
         // the same pair can appear under several shared labels
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) {
             if (a.cost != b.cost) return a.cost < b.cost;
+            if (a.absorb != b.absorb) return a.absorb > b.absorb;
             if (a.os != b.os) return a.os < b.os;
             if (a.i != b.i) return a.i < b.i;
             return a.j < b.j;
@@ -158,6 +193,12 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
         } else if (!rng || cands.size() == 1) {
             bi = cands[0].i;
             bj = cands[0].j;
+        } else if (std::any_of(cands.begin(), cands.end(), [](const Cand &c) { return c.absorb; })) {
+            // sampled orders make every absorption (a normalisation of the
+            // network, never a choice of order) before drawing a step
+            const Cand &c = *std::find_if(cands.begin(), cands.end(), [](const Cand &x) { return x.absorb; });
+            bi = c.i;
+            bj = c.j;
         } else {
             const double lmin = std::log2(cands[0].cost);
             double wsum = 0.0;
@@ -172,20 +213,7 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
             bi = cands[k].i;
             bj = cands[k].j;
         }
-        Cand c;
-        std::vector<int> kept;
-        eval(bi, bj, c, &kept);
-        tot += c.cost;
-        pk = std::max(pk, c.os);
-        path.push_back({bi, bj});
-        for (int l : lab[bi]) ref[l]--;
-        for (int l : lab[bj]) ref[l]--;
-        alive[bi] = alive[bj] = 0;
-        lab[next] = kept;
-        for (int l : kept) ref[l]++;
-        alive[next] = 1;
-        ++next;
-        --n_alive;
+        take(bi, bj);
     }
     if (total) *total = tot;
     if (peak) *peak = pk;
@@ -468,6 +496,10 @@ void build_plan(Net &n) {
         v.base = i;
         for (int l : v.labels) ref[l]++;
     }
+    // input values whose data went into another value's load (absorbed or
+    // moved); the others are loaded by their own consumer and may carry
+    // further folded factors
+    std::vector<char> folded(N + path.size() + 1, 0);
     for (size_t t = 0; t < path.size(); ++t) {
         const int i = path[t].first, j = path[t].second, c = N + (int)t;
         const Value A = P.values[i], B = P.values[j];
@@ -488,11 +520,75 @@ void build_plan(Net &n) {
         s.mults = prod_dims(n, u);
         P.mults += s.mults;
         const bool last = (t + 1 == path.size());
+        // Summing a label of extent 1 changes no value and no layout: such a
+        // label may stay on a value (it is summed by a later step at no cost).
+        bool sums_trivial = true;
+        for (int l : sums) sums_trivial = sums_trivial && n.dims[l] == 1;
+        // An input operand whose labels the other operand (an intermediate)
+        // carries -- a coefficient tensor, or a scalar factor such as a CT
+        // truncated to one kept index -- multiplies the network entry-wise:
+        // it is applied exactly once by folding it into the load of an input
+        // that carries every one of its labels of extent above 1 (any input
+        // for a scalar), and the intermediate's producer writes this step's
+        // result directly.  Loads happen before any label is summed, so the
+        // order of the path does not matter.
+        auto sub_of = [&](const Value &x, const Value &y) {
+            for (int l : x.labels)
+                if (!contains(y.labels, l) && !std::binary_search(sums.begin(), sums.end(), l)) return false;
+            return true;
+        };
+        int scl = -1, oth = -1;
+        if (sums_trivial && A.input != B.input && !last) {
+            scl = A.input ? i : j;
+            oth = scl == i ? j : i;
+            if (!sub_of(P.values[scl], P.values[oth])) scl = -1;
+        }
+        if (scl >= 0) {
+            const Value &S = P.values[scl];
+            int carrier = -1;
+            for (int k = 0; k < c; ++k) {
+                const Value &K = P.values[k];
+                if (!K.input || folded[k] || k == scl) continue;
+                if (K.scales.size() + 1 + S.scales.size() > (size_t)kMaxScales) continue;
+                bool carries = true;
+                for (int l : S.labels) carries = carries && (n.dims[l] == 1 || contains(K.labels, l));
+                if (!carries) continue;
+                if (carrier < 0 || (P.values[carrier].size == 1 && K.size > 1)) carrier = k;
+            }
+            if (carrier >= 0) {
+                P.values[carrier].scales.push_back(S.base);
+                for (int x : S.scales) P.values[carrier].scales.push_back(x);
+                folded[scl] = 1;
+                Value &C = P.values[c];
+                C = P.values[oth];
+                P.steps[C.producer].c = c;
+                s.absorbed = true;
+                s.c_labels = C.labels;
+                P.n_absorbed++;
+                for (int l : kept_set) ref[l]++;
+                s.final_step = false;
+                P.steps.push_back(s);
+                continue;
+            }
+        }
         // Absorption: both operands are (possibly already scaled) inputs, one
-        // label set contains the other and nothing is summed, so the result
-        // is the larger input scaled entry-wise by the smaller one.
+        // label set contains the other (or the smaller is a scalar whose
+        // labels the larger carries or this step sums) and nothing of extent
+        // above 1 is summed, so the result is the larger input scaled
+        // entry-wise by the smaller one.
         int tgt = -1, sml = -1;
-        if (A.input && B.input && sums.empty()) {
+        if (A.input && B.input && sums_trivial && (A.size == 1) != (B.size == 1)) {
+            // a scalar factor: its labels all have extent 1 (carried by the
+            // other operand or summed here)
+            tgt = A.size == 1 ? j : i;
+            sml = tgt == i ? j : i;
+            bool carried = true;
+            for (int l : P.values[sml].labels)
+                carried = carried && (contains(P.values[tgt].labels, l) || std::binary_search(sums.begin(), sums.end(), l));
+            if (!carried || P.values[tgt].scales.size() + 1 + P.values[sml].scales.size() > (size_t)kMaxScales)
+                tgt = -1;
+        }
+        if (tgt < 0 && A.input && B.input && sums_trivial) {
             bool b_in_a = std::includes(sa.begin(), sa.end(), sb.begin(), sb.end());
             bool a_in_b = std::includes(sb.begin(), sb.end(), sa.begin(), sa.end());
             if (b_in_a && (!a_in_b || A.size >= B.size)) {
@@ -508,6 +604,7 @@ void build_plan(Net &n) {
         Value &C = P.values[c];
         if (tgt >= 0) {
             s.absorbed = true;
+            folded[tgt] = folded[sml] = 1;
             C = P.values[tgt];
             C.scales.push_back(P.values[sml].base);
             for (int x : P.values[sml].scales) C.scales.push_back(x);

@@ -79,23 +79,28 @@ def test_replay_random_networks():
         _check(_random_network(rng))
 
 
+def _random_path(w, rng):
+    """A uniformly random order of steps between tensors sharing a label."""
+    live = {i: set(ls) for i, ls in enumerate(w.labels)}
+    nxt = len(w.labels)
+    path = []
+    while len(live) > 1:
+        ids = sorted(live)
+        pairs = [(a, b) for ai, a in enumerate(ids) for b in ids[ai + 1:] if live[a] & live[b]]
+        a, b = rng.choice(pairs)
+        if rng.random() < 0.5:
+            a, b = b, a
+        path.append((a, b))
+        live[nxt] = live.pop(a) | live.pop(b)
+        nxt += 1
+    return path
+
+
 def test_replay_random_paths():
     rng = random.Random(7)
     w = configs.grid_network(4)
     for _ in range(8):
-        live = {i: set(ls) for i, ls in enumerate(w.labels)}
-        nxt = len(w.labels)
-        path = []
-        while len(live) > 1:
-            ids = sorted(live)
-            pairs = [(a, b) for ai, a in enumerate(ids) for b in ids[ai + 1:] if live[a] & live[b]]
-            a, b = rng.choice(pairs)
-            if rng.random() < 0.5:
-                a, b = b, a
-            path.append((a, b))
-            live[nxt] = live.pop(a) | live.pop(b)
-            nxt += 1
-        _check(w, path)
+        _check(w, _random_path(w, rng))
 
 
 def test_replay_small_lds_budgets_spill():
@@ -133,3 +138,34 @@ def test_marginal_operands_written_in_packed_order():
     gemm = [st for st in steps if st["mfma"]]
     assert gemm and all(st["pack_id"] == [1, 1] for st in gemm)
     _check(w)
+
+
+def _qpd_grid(seed, s_qpd):
+    """A grid network after QPD sampling of its gate cuts (oracle draws)."""
+    from oracle import qpd_sampling as qs
+    w = configs.grid_network(seed)
+    rng = np.random.default_rng(1000 + seed)
+    gate = [i for i, t in enumerate(w.tensors) if w.kinds[i] == "ct" and t.size == 6]
+    counts = [qs.sample_counts(w.tensors[c], s_qpd, rng.random(s_qpd)) for c in gate]
+    return qs.truncate(w, gate, counts, s_qpd)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_one_draw_per_gate_cut_folds_scalar_factors(seed):
+    """With one draw per gate cut every sampled label keeps one index, so each
+    gate CT is a single number: the planner folds these scalar factors into
+    input loads on any path, and the 16 QTs take 15 kernel steps (none for
+    a coefficient tensor); the replayed plans equal the oracle."""
+    w = _qpd_grid(seed, 1)
+    for path in (htn.HTN_PATH_GREEDY, htn.HTN_PATH_SAMPLED):
+        net = htn.htn_create(w.tensors, w.labels, w.dims, w.out_labels)
+        htn.htn_set_option(net, htn.HTN_OPT_PATH_SAMPLES, 64)
+        htn.htn_set_path(net, path)
+        info = htn.htn_get_info(net)
+        assert info.n_kernel_steps == 15, (path, info.n_kernel_steps)
+        assert info.n_absorbed == len(w.tensors) - 16
+    _check(w)
+    _check(w, path=htn.htn_get_path(net)[0])
+    rng = random.Random(seed)
+    for _ in range(4):
+        _check(w, path=_random_path(w, rng))
