@@ -142,3 +142,107 @@ def test_grid_estimate_converges():
         vals.append(_einsum(qs.truncate(net, gate, cnts, s)))
     vals = np.array(vals)
     assert abs(vals.mean() - exact) < 5 * vals.std(ddof=1) / np.sqrt(len(vals)) + 1e-12
+
+
+# --------------------------------------------------------------------------
+# Fusion of the CTs between the same tensors before sampling (Sec. 4.3,
+# Sec. 6.1 Step 1)
+# --------------------------------------------------------------------------
+
+def _double_bond(seed: int) -> Network:
+    """QTs A[g0, g1, w] and B[w, g1, x, g0] joined by two CZ gate cuts
+    (labels 0, 1: dim 6) and one wire cut (label 2: dim 4); B also meets C
+    over a third gate cut (label 3).  The parallel gate cuts are listed out
+    of label order in B, so the mode merge has to permute."""
+    rng = np.random.default_rng(seed)
+    dims = [6, 6, 4, 6]
+    labels = [[0, 1, 2], [2, 1, 3, 0], [3], [0], [1], [2], [3]]
+    tensors = [rng.uniform(-1, 1, [dims[l] for l in ls]) for ls in labels[:3]]
+    tensors += [qpd.CZ_COEFFS.copy(), qpd.CZ_COEFFS.copy(), qpd.WIRE_PAULI.copy(), qpd.CZ_COEFFS.copy()]
+    return Network(tensors, labels, dims, [], ["qt"] * 3 + ["ct"] * 4)
+
+
+def test_parallel_groups_pair_the_cts_between_the_same_tensors():
+    net = _double_bond(0)
+    assert qs.parallel_groups(net, [3, 4, 6]) == [[3, 4], [6]]
+
+
+def test_fusion_leaves_the_value_unchanged():
+    # the fused network is an equivalent form: same contraction value, on a
+    # hand-made double bond (modes out of order) and on ring-of-rings
+    # networks with bond multiplicities 1-3
+    import oracle
+    for seed in range(4):
+        net = _double_bond(seed)
+        f, fids = qs.fuse_parallel(net, qs.parallel_groups(net, [3, 4, 6]))
+        assert f.dims[0] == 36 and f.dims[1] == 1 and len(f.tensors) == len(net.tensors) - 1
+        assert f.labels[1] == [2, 0, 3]      # B's two gate modes merged where the first of them stood
+        assert abs(_einsum(f) - _einsum(net)) <= 1e-13 * max(1.0, abs(_einsum(net)))
+    for seed in range(2):
+        w = configs.ring_of_rings(seed)
+        gate = [i for i, k in enumerate(w.kinds) if k == "ct" and w.tensors[i].size == 6]
+        groups = qs.parallel_groups(w, gate)
+        assert any(len(g) >= 2 for g in groups)
+        f, _ = qs.fuse_parallel(w, groups)
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        fh, fl = oracle.ve_contract(f.tensors, f.labels, f.dims, f.out_labels)
+        ref = float(hi) + float(lo)
+        assert abs(float(fh) + float(fl) - ref) <= 1e-12 * abs(ref)
+
+
+def test_fused_ct_is_the_tensor_product():
+    # one-hot vectors fuse to the one-hot of the row-major pair index (first
+    # CT slowest); k CZ cuts fuse to gamma = 3^k (the 9^k = gamma^(2k)
+    # sampling overhead of Sec. 2.1) with coefficients still summing to 1
+    dims = [6, 6, 6]
+    e = [np.eye(6)[2], np.eye(6)[5], np.eye(6)[1]]
+    labels = [[0, 1, 2], [0], [1], [2]]
+    net = Network([np.zeros((6, 6, 6))] + e, labels, dims, [])
+    f, fids = qs.fuse_parallel(net, [[1, 2, 3]])
+    assert f.tensors[fids[0]].shape == (216,)
+    assert np.flatnonzero(f.tensors[fids[0]]).tolist() == [2 * 36 + 5 * 6 + 1]
+    for k in (1, 2, 3):
+        net = Network([np.zeros((6,) * k)] + [qpd.CZ_COEFFS.copy() for _ in range(k)],
+                      [list(range(k))] + [[i] for i in range(k)], [6] * k, [])
+        f, fids = qs.fuse_parallel(net, [list(range(1, k + 1))])
+        c = f.tensors[fids[0]]
+        assert abs(np.abs(c).sum() - 3.0 ** k) < 1e-12 and abs(c.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("s_qpd", [1, 2])
+def test_fused_sampling_expectation_is_exact(s_qpd):
+    # every multinomial outcome of the draws on the fused 36-entry CT and
+    # on the single CT of the third cut, weighted by its probability
+    net = _double_bond(7)
+    exact = _einsum(net)
+    groups = qs.parallel_groups(net, [3, 4, 6])
+    f, fids = qs.fuse_parallel(net, groups)
+    p0 = np.abs(f.tensors[fids[0]]) / np.abs(f.tensors[fids[0]]).sum()
+    p1 = np.abs(f.tensors[fids[1]]) / np.abs(f.tensors[fids[1]]).sum()
+    expect, total_p = 0.0, 0.0
+    for n0 in _compositions(s_qpd, 36):
+        for n1 in _compositions(s_qpd, 6):
+            pr = _pmf(n0, p0) * _pmf(n1, p1)
+            total_p += pr
+            t = qs.truncate(f, fids, [n0, n1], s_qpd)
+            # drawn pairs are kept jointly: at most s_QPD of the 36
+            assert t.dims[0] <= s_qpd
+            expect += pr * _einsum(t)
+    assert abs(total_p - 1.0) < 1e-12
+    assert abs(expect - exact) <= 1e-12 * max(1.0, abs(exact))
+
+
+def test_simplify_keeps_drawn_pairs_of_the_original_modes():
+    # one draw lands on pair (i, j) (and the third cut on k): the simplified
+    # A is A[i, j, :] and B is B[:, j, k, i], with the fused CT's weight
+    # gamma_f sign(c_i c_j), gamma_f = 9
+    net = _double_bond(3)
+    u = [np.array([0.5]), np.array([0.1])]
+    simp, fused, fids, counts = qs.simplify(net, [3, 4, 6], 1, u)
+    f = int(np.flatnonzero(counts[0])[0])
+    k = int(np.flatnonzero(counts[1])[0])      # the third cut's drawn index
+    i, j = divmod(f, 6)
+    assert np.array_equal(simp.tensors[0].reshape(-1), net.tensors[0][i, j, :])
+    assert np.array_equal(simp.tensors[1][:, 0, 0], net.tensors[1][:, j, k, i])
+    c = qpd.CZ_COEFFS
+    assert abs(simp.tensors[fids[0]][0] - 9.0 * np.sign(c[i] * c[j])) < 1e-15
