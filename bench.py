@@ -471,10 +471,11 @@ def single_latency(w, args, reps=50):
 # ------------------------------------------------------------------- qpd
 
 def bench_qpd(args):
-    """Grid h-TNs simplified by QPD sampling (Sec. 4.3): every gate-cut CT is
-    drawn --qpd-samples times, its undrawn indices are truncated from the
-    CT and its QTs.  One step = the truncation gather over the whole batch
-    (one launch) + the batch contraction of the simplified networks."""
+    """Grid h-TNs simplified by QPD sampling (Sec. 4.3): the gate-cut CTs
+    between the same QTs are fused (none on a grid: one cut per edge), each
+    CT is drawn --qpd-samples times, undrawn indices are truncated from the
+    CT and its QTs.  One step = the gather over the whole batch (one
+    launch) + the batch contraction of the simplified networks."""
     import numpy as np
     import torch
     from paper_2410_15080_amd import htn
@@ -486,6 +487,7 @@ def bench_qpd(args):
     args.samples = args.samples or 128
     dev = torch.device("cuda:0")
     log(f"generating {n_nets} grid networks, sampling gate cuts with s_QPD = {s_qpd}")
+    from paper_2410_15080_amd import qpd as lq
     ws = [configs.grid_network(s) for s in range(n_nets)]
     rng = np.random.default_rng(2410)
     items, nets, src_keep, sampled = [], [], [], []
@@ -493,32 +495,17 @@ def bench_qpd(args):
     for w in ws:
         src = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(dev) for t in w.tensors]
         gate = [i for i, t in enumerate(w.tensors) if w.kinds[i] == "ct" and t.size == 6]
-        kept_of, counts, new = {}, {}, list(src)
-        for c in gate:
-            u = rng.random(s_qpd)
-            t0 = time.perf_counter()
-            n, wts = htn.htn_qpd_sample(w.tensors[c], s_qpd, u)
-            t_sample += time.perf_counter() - t0
-            k = np.nonzero(n)[0]
-            kept_of[w.labels[c][0]] = k
-            counts[c] = n
-            new[c] = torch.from_numpy(wts[k]).to(dev)
-        dims = list(w.dims)
-        for lab, k in kept_of.items():
-            dims[lab] = len(k)
-        for t, ls in enumerate(w.labels):
-            if t in counts or not any(l in kept_of for l in ls):
-                continue
-            dst = torch.empty(tuple(dims[l] for l in ls), dtype=torch.float64, device=dev)
-            items.append((src[t], dst, tuple(w.dims[l] for l in ls), [kept_of.get(l) for l in ls]))
-            new[t] = dst
-        n = htn.htn_create(new, w.labels, dims, [], compute=htn.HTN_F64)
+        uniforms = [rng.random(s_qpd) for _ in lq.parallel_groups(w.labels, gate)]
+        t0 = time.perf_counter()
+        simp = lq.simplify(src, w.labels, w.dims, w.out_labels, gate, s_qpd, uniforms, items, device=dev)
+        t_sample += time.perf_counter() - t0
+        n = htn.htn_create(simp.tensors, simp.labels, simp.dims, simp.out_labels, compute=htn.HTN_F64)
         htn.htn_set_option(n, htn.HTN_OPT_FUSED_LDS_BYTES, args.lds)
         htn.htn_set_option(n, htn.HTN_OPT_FUSED_THREADS, args.threads)
         nets.append(n)
-        src_keep.append((src, new))
-        sampled.append((gate, [counts[c] for c in gate], dims))
-    tr = htn.htn_truncate_create(items, htn.HTN_F64)
+        src_keep.append((src, simp))
+        sampled.append((gate, uniforms, simp.dims))
+    tr = htn.htn_gather_create(items, htn.HTN_F64)
     trunc_bytes = 2 * 8 * sum(int(np.prod(it[1].shape)) for it in items)
     stream = torch.cuda.Stream()
     htn.htn_truncate_run(tr, stream)
@@ -549,19 +536,18 @@ def bench_qpd(args):
     # parity on a sample of the networks: the oracle's own draws from the
     # same counts, truncation and double-double contraction
     from oracle import qpd_sampling as qs
-    errs, ref_ws = [], []
+    errs = []
     for i in range(0, n_nets, max(1, n_nets // 32)):
-        gate, cnts, dims = sampled[i]
-        rw = qs.truncate(ws[i], gate, cnts, s_qpd)
+        gate, uniforms, dims = sampled[i]
+        rw = qs.simplify(ws[i], gate, s_qpd, uniforms)[0]
         assert rw.dims == dims
         ref = oracle_ref(rw)
         errs.append(abs(got[i] - ref) / abs(ref))
-        ref_ws.append(rw)
     htns = n_nets / (ms_per_step * 1e-3)
     cpu = None
     if not args.no_cpu:
         log("timing CPU oracle")
-        cpu = cpu_baseline([qs.truncate(ws[i], *sampled[i][:2], s_qpd) for i in range(min(n_nets, 4096))],
+        cpu = cpu_baseline([qs.simplify(ws[i], sampled[i][0], s_qpd, sampled[i][1])[0] for i in range(n_nets)],
                            args.cpu_seconds, greedy_list)
     tr_gbs = trunc_bytes / (trunc_ms * 1e-3) / 1e9
     htn.htn_truncate_destroy(tr)

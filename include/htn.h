@@ -484,6 +484,60 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
 htn_status htn_truncate_run(htn_trunc_t t, void *hip_stream);
 void htn_truncate_destroy(htn_trunc_t t);
 
+/* ---------------------------------------------------------------------
+ * Fusion of the CTs between the same QTs before sampling (Sec. 4.3;
+ * Step 1 of Sec. 6.1): the CTs on parallel cuts between two QTs become one
+ * CT, their tensor product, on one fused index, and each QT carrying their
+ * indices has those modes merged into that one mode.  The fused network
+ * contracts to the same value; its fused CT is then sampled as a whole
+ * (htn_qpd_sample), so pairs of terms are drawn jointly.
+ *
+ * htn_qpd_fuse (host) — fused[f] = coeffs[0][i_0] * ... * coeffs[n-1][i_{n-1}]
+ * with f row-major over (i_0, ..., i_{n-1}) (i_0 slowest).
+ *   n >= 1 tensors; dims[k] >= 1 their lengths; coeffs[k] host FP64 arrays;
+ *   fused: host array of prod(dims) values (caller-owned).
+ * Errors: HTN_E_ARG (NULL pointers, n < 1, a length < 1), HTN_E_UNSUPPORTED
+ * (2^31 or more fused entries).
+ * ------------------------------------------------------------------- */
+htn_status htn_qpd_fuse(int32_t n, const int32_t *dims, const double *const *coeffs, double *fused);
+
+/* htn_gather — one tensor to gather with merged (fused) axes and kept
+ * indices, the QT side of the fusion and truncation (all pointers the
+ * caller's).
+ *   src, dst      device; src row-major with extents dims[0..rank-1]; dst
+ *                 row-major over the output axes; must not overlap.
+ *   rank          input rank, 1..HTN_TRUNC_MAX_RANK.
+ *   out_rank      output rank, 1..rank.
+ *   n_axes[o]     number of input axes merged into output axis o (>= 1;
+ *                 they sum to rank).
+ *   axes          the input axes, output axis by output axis (n_axes[0]
+ *                 for axis 0, then axis 1's, ...): a permutation of
+ *                 0..rank-1.  Output axis o's index is row-major over its
+ *                 input axes in the order listed (the first slowest).
+ *   kept[o]       host list of the n_kept[o] indices of output axis o that
+ *                 dst keeps, in dst order (NULL: all of them).
+ * dst[o_0, ..., o_{out_rank-1}] = src[the element whose merged index on
+ * each output axis o is kept[o][o_o]].  Bit-exact copies.
+ * htn_gather_create — validate n >= 1 items of element type dtype and
+ * upload their gather descriptors (synchronous); the handle is run and
+ * destroyed with htn_truncate_run / htn_truncate_destroy (one launch for
+ * the batch).  Errors: HTN_E_ARG (NULL buffers, bad rank/out_rank/n_axes,
+ * axes not a permutation, a kept index out of range), HTN_E_UNSUPPORTED
+ * (an item or a merged axis with 2^31 or more elements), HTN_E_OOM,
+ * HTN_E_DEVICE.                                                           */
+typedef struct {
+    const void *src;
+    void *dst;
+    int32_t rank;
+    int64_t dims[HTN_TRUNC_MAX_RANK];
+    int32_t out_rank;
+    int32_t n_axes[HTN_TRUNC_MAX_RANK];
+    int32_t axes[HTN_TRUNC_MAX_RANK];
+    const int32_t *kept[HTN_TRUNC_MAX_RANK];
+    int32_t n_kept[HTN_TRUNC_MAX_RANK];
+} htn_gather;
+htn_status htn_gather_create(htn_trunc_t *out, int32_t n, const htn_gather *items, htn_dtype dtype);
+
 #ifdef __cplusplus
 }
 #endif

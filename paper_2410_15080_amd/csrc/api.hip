@@ -1563,49 +1563,43 @@ htn_status htn_qpd_sample(int32_t n, const double *coeffs, int64_t s_qpd, const 
     API_GUARD_END
 }
 
-htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation *items, htn_dtype dtype) {
-    API_GUARD_BEGIN
-    if (!out) return fail(HTN_E_ARG, "out is NULL");
-    *out = nullptr;
-    if (n < 1 || !items) return fail(HTN_E_ARG, "bad item list");
-    if (dtype != HTN_F64 && dtype != HTN_F32 && dtype != HTN_BF16) return fail(HTN_E_ARG, "bad dtype");
+}  // extern "C"
+
+// One gather item: dst[o] = src[sum over output axes a of offs[a][digit_a(o)]]
+// with output digits row-major over the output axes.
+struct GatherSpec {
+    const void *src = nullptr;
+    void *dst = nullptr;
+    std::vector<std::vector<int64_t>> offs;  // per output axis: input offset of each index
+};
+
+// Packs the items into gather blocks and uploads their descriptors (the
+// launch layout of k_truncate: runs of small items per block, 1024-element
+// chunks of larger ones).
+static htn_trunc *build_gather(const std::vector<GatherSpec> &items, htn_dtype dtype) {
+    const int n = (int)items.size();
     std::vector<kern::TruncItem> h((size_t)n);
     std::vector<int64_t> maps;
     std::vector<kern::TruncBlock> blocks;
     constexpr int64_t per_block = kern::kTruncBlockElems;
     int32_t open_fill = per_block;  // elements in the open packed block (none open)
     for (int i = 0; i < n; ++i) {
-        const htn_truncation &t = items[i];
-        if (!t.src || !t.dst) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": NULL buffer");
-        if (t.rank < 1 || t.rank > HTN_TRUNC_MAX_RANK) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad rank");
+        const GatherSpec &g = items[(size_t)i];
         kern::TruncItem &k = h[(size_t)i];
         k = kern::TruncItem{};
-        k.src = t.src;
-        k.dst = t.dst;
-        k.rank = t.rank;
+        k.src = g.src;
+        k.dst = g.dst;
+        k.rank = (int32_t)g.offs.size();
         k.map_off = (int64_t)maps.size();
-        int64_t stride = 1, n_out = 1;
-        std::vector<int64_t> strides((size_t)t.rank);
-        for (int a = t.rank - 1; a >= 0; --a) {
-            if (t.dims[a] < 1 || t.dims[a] > std::numeric_limits<int32_t>::max())
-                return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad extent");
-            strides[(size_t)a] = stride;
-            if (stride > (int64_t(1) << 40) / t.dims[a]) return fail(HTN_E_UNSUPPORTED, "item too large");
-            stride *= t.dims[a];
-        }
-        for (int a = 0; a < t.rank; ++a) {
-            const int64_t d = t.kept[a] ? t.n_kept[a] : t.dims[a];
-            if (d < 1 || d > t.dims[a]) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad n_kept");
-            k.odim[a] = (int32_t)d;
+        int64_t n_out = 1;
+        for (size_t a = 0; a < g.offs.size(); ++a) {
+            k.odim[a] = (int32_t)g.offs[a].size();
             k.moff[a] = (int32_t)(maps.size() - (size_t)k.map_off);
-            for (int64_t x = 0; x < d; ++x) {
-                const int64_t idx = t.kept[a] ? t.kept[a][x] : x;
-                if (idx < 0 || idx >= t.dims[a]) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": kept index out of range");
-                maps.push_back(idx * strides[(size_t)a]);
-            }
-            n_out *= d;
+            maps.insert(maps.end(), g.offs[a].begin(), g.offs[a].end());
+            n_out *= (int64_t)g.offs[a].size();
         }
-        if (n_out >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "item with 2^31 or more elements");
+        if (n_out >= (int64_t(1) << 31))
+            throw Error{HTN_E_UNSUPPORTED, "item " + std::to_string(i) + " has 2^31 or more elements"};
         k.n_out = n_out;
         const int64_t mw = (int64_t)maps.size() - k.map_off;  // this item's map entries
         if (n_out > per_block || mw > kern::kTruncMapLds) {
@@ -1629,7 +1623,7 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
             blocks.back().map_words += (int32_t)mw;
             open_fill += (int32_t)n_out;
         }
-        if ((int64_t)blocks.size() >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "batch too large");
+        if ((int64_t)blocks.size() >= (int64_t(1) << 31)) throw Error{HTN_E_UNSUPPORTED, "batch too large"};
     }
     htn_trunc *t = new htn_trunc();
     t->n = n;
@@ -1646,7 +1640,134 @@ htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation
         delete t;
         throw;
     }
-    *out = t;
+    return t;
+}
+
+// Row-major strides of an item's input axes; throws on bad extents.
+static std::vector<int64_t> gather_strides(int i, int rank, const int64_t *dims) {
+    std::vector<int64_t> strides((size_t)rank);
+    int64_t stride = 1;
+    for (int a = rank - 1; a >= 0; --a) {
+        if (dims[a] < 1 || dims[a] > std::numeric_limits<int32_t>::max())
+            throw Error{HTN_E_ARG, "item " + std::to_string(i) + ": bad extent"};
+        strides[(size_t)a] = stride;
+        if (stride > (int64_t(1) << 40) / dims[a]) throw Error{HTN_E_UNSUPPORTED, "item too large"};
+        stride *= dims[a];
+    }
+    return strides;
+}
+
+extern "C" {
+
+htn_status htn_truncate_create(htn_trunc_t *out, int32_t n, const htn_truncation *items, htn_dtype dtype) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !items) return fail(HTN_E_ARG, "bad item list");
+    if (dtype != HTN_F64 && dtype != HTN_F32 && dtype != HTN_BF16) return fail(HTN_E_ARG, "bad dtype");
+    std::vector<GatherSpec> specs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const htn_truncation &t = items[i];
+        if (!t.src || !t.dst) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": NULL buffer");
+        if (t.rank < 1 || t.rank > HTN_TRUNC_MAX_RANK) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad rank");
+        const auto strides = gather_strides(i, t.rank, t.dims);
+        GatherSpec &g = specs[(size_t)i];
+        g.src = t.src;
+        g.dst = t.dst;
+        g.offs.resize((size_t)t.rank);
+        for (int a = 0; a < t.rank; ++a) {
+            const int64_t d = t.kept[a] ? t.n_kept[a] : t.dims[a];
+            if (d < 1 || d > t.dims[a]) return fail(HTN_E_ARG, "item " + std::to_string(i) + ": bad n_kept");
+            for (int64_t x = 0; x < d; ++x) {
+                const int64_t idx = t.kept[a] ? t.kept[a][x] : x;
+                if (idx < 0 || idx >= t.dims[a])
+                    return fail(HTN_E_ARG, "item " + std::to_string(i) + ": kept index out of range");
+                g.offs[(size_t)a].push_back(idx * strides[(size_t)a]);
+            }
+        }
+    }
+    *out = build_gather(specs, dtype);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_gather_create(htn_trunc_t *out, int32_t n, const htn_gather *items, htn_dtype dtype) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !items) return fail(HTN_E_ARG, "bad item list");
+    if (dtype != HTN_F64 && dtype != HTN_F32 && dtype != HTN_BF16) return fail(HTN_E_ARG, "bad dtype");
+    std::vector<GatherSpec> specs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const htn_gather &t = items[i];
+        const std::string it = "item " + std::to_string(i) + ": ";
+        if (!t.src || !t.dst) return fail(HTN_E_ARG, it + "NULL buffer");
+        if (t.rank < 1 || t.rank > HTN_TRUNC_MAX_RANK) return fail(HTN_E_ARG, it + "bad rank");
+        if (t.out_rank < 1 || t.out_rank > t.rank) return fail(HTN_E_ARG, it + "bad out_rank");
+        const auto strides = gather_strides(i, t.rank, t.dims);
+        std::vector<char> seen((size_t)t.rank, 0);
+        int used = 0;
+        GatherSpec &g = specs[(size_t)i];
+        g.src = t.src;
+        g.dst = t.dst;
+        g.offs.resize((size_t)t.out_rank);
+        for (int o = 0; o < t.out_rank; ++o) {
+            const int na = t.n_axes[o];
+            if (na < 1 || used + na > t.rank) return fail(HTN_E_ARG, it + "bad n_axes");
+            int64_t ext = 1;
+            std::vector<int> ax((size_t)na);
+            for (int k = 0; k < na; ++k) {
+                const int a = t.axes[used + k];
+                if (a < 0 || a >= t.rank || seen[(size_t)a]) return fail(HTN_E_ARG, it + "axes is not a permutation");
+                seen[(size_t)a] = 1;
+                ax[(size_t)k] = a;
+                ext *= t.dims[a];
+                if (ext >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, it + "fused axis too long");
+            }
+            used += na;
+            const int64_t d = t.kept[o] ? t.n_kept[o] : ext;
+            if (d < 1 || d > ext) return fail(HTN_E_ARG, it + "bad n_kept");
+            for (int64_t x = 0; x < d; ++x) {
+                int64_t f = t.kept[o] ? t.kept[o][x] : x;
+                if (f < 0 || f >= ext) return fail(HTN_E_ARG, it + "kept index out of range");
+                // the fused index, row-major over the axes (first slowest)
+                int64_t off = 0;
+                for (int k = na - 1; k >= 0; --k) {
+                    const int64_t e = t.dims[ax[(size_t)k]];
+                    off += (f % e) * strides[(size_t)ax[(size_t)k]];
+                    f /= e;
+                }
+                g.offs[(size_t)o].push_back(off);
+            }
+        }
+        if (used != t.rank) return fail(HTN_E_ARG, it + "axes must list every input axis once");
+    }
+    *out = build_gather(specs, dtype);
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_qpd_fuse(int32_t n, const int32_t *dims, const double *const *coeffs, double *fused) {
+    API_GUARD_BEGIN
+    if (n < 1 || !dims || !coeffs || !fused) return fail(HTN_E_ARG, "bad arguments");
+    int64_t total = 1;
+    for (int k = 0; k < n; ++k) {
+        if (dims[k] < 1 || !coeffs[k]) return fail(HTN_E_ARG, "bad coefficient tensor " + std::to_string(k));
+        total *= dims[k];
+        if (total >= (int64_t(1) << 31)) return fail(HTN_E_UNSUPPORTED, "fused tensor too long");
+    }
+    // the tensor product, one factor at a time: index row-major over the
+    // tensors in the order given (the first slowest)
+    fused[0] = 1.0;
+    int64_t len = 1;
+    for (int k = 0; k < n; ++k) {
+        const int64_t d = dims[k];
+        for (int64_t f = len - 1; f >= 0; --f) {
+            const double v = fused[f];
+            for (int64_t x = d - 1; x >= 0; --x) fused[f * d + x] = v * coeffs[k][x];
+        }
+        len *= d;
+    }
     return HTN_OK;
     API_GUARD_END
 }

@@ -55,6 +55,14 @@ class htn_truncation(ctypes.Structure):
                 ("n_kept", ctypes.c_int32 * HTN_TRUNC_MAX_RANK)]
 
 
+class htn_gather(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("rank", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * HTN_TRUNC_MAX_RANK), ("out_rank", ctypes.c_int32),
+                ("n_axes", ctypes.c_int32 * HTN_TRUNC_MAX_RANK), ("axes", ctypes.c_int32 * HTN_TRUNC_MAX_RANK),
+                ("kept", ctypes.POINTER(ctypes.c_int32) * HTN_TRUNC_MAX_RANK),
+                ("n_kept", ctypes.c_int32 * HTN_TRUNC_MAX_RANK)]
+
+
 _lib = None
 
 
@@ -121,6 +129,9 @@ def load_library():
         "htn_truncate_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_truncation), I32]),
         "htn_truncate_run": (I32, [P, P]),
         "htn_truncate_destroy": (None, [P]),
+        "htn_qpd_fuse": (I32, [I32, i32p, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.POINTER(ctypes.c_double)]),
+        "htn_gather_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_gather), I32]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -604,3 +615,46 @@ def htn_truncate_destroy(t: Trunc) -> None:
     if t.handle:
         load_library().htn_truncate_destroy(t.handle)
         t.handle = None
+
+
+def htn_qpd_fuse(coeffs):
+    """Tensor product of the CTs `coeffs` (row-major, first slowest)."""
+    lib = load_library()
+    arrs = [np.ascontiguousarray(c, dtype=np.float64).reshape(-1) for c in coeffs]
+    d, dp = _arr([a.size for a in arrs], np.int32)
+    dpp = ctypes.POINTER(ctypes.c_double)
+    ptrs = (dpp * len(arrs))(*[a.ctypes.data_as(dpp) for a in arrs])
+    out = np.zeros(int(np.prod([a.size for a in arrs])), dtype=np.float64)
+    _check(lib.htn_qpd_fuse(len(arrs), dp, ptrs, out.ctypes.data_as(dpp)))
+    return out
+
+
+def htn_gather_create(items, dtype=HTN_F64) -> Trunc:
+    """items: (src, dst, dims, groups, kept) per tensor: groups[o] lists the
+    input axes merged into output axis o (first slowest), kept[o] its kept
+    indices or None (all)."""
+    lib = load_library()
+    arr = (htn_gather * len(items))()
+    keep = []
+    for i, (src, dst, dims, groups, kept) in enumerate(items):
+        it = arr[i]
+        it.src = _data_ptr(src) if not isinstance(src, int) else src
+        it.dst = _data_ptr(dst) if not isinstance(dst, int) else dst
+        it.rank = len(dims)
+        for a, d in enumerate(dims):
+            it.dims[a] = int(d)
+        it.out_rank = len(groups)
+        flat = [a for g in groups for a in g]
+        for k, a in enumerate(flat):
+            it.axes[k] = int(a)
+        for o, g in enumerate(groups):
+            it.n_axes[o] = len(g)
+            if kept is not None and kept[o] is not None:
+                k, kp = _arr(kept[o], np.int32)
+                keep.append(k)
+                it.kept[o] = kp
+                it.n_kept[o] = int(k.size)
+        keep += [src, dst]
+    h = ctypes.c_void_p()
+    _check(lib.htn_gather_create(ctypes.byref(h), len(items), arr, int(dtype)))
+    return Trunc(h, keep)

@@ -184,3 +184,98 @@ def test_sampled_grid_networks_match_oracle(s_qpd):
     for o, ref in zip(outs, refs):
         got = float(o.cpu().numpy()[0])
         assert rel_err(got, float(ref)) < 1e-10, (got, ref)
+
+
+# --------------------------------------------------------------------------
+# Fusion of the CTs between the same QTs before sampling (Sec. 4.3)
+# --------------------------------------------------------------------------
+
+def test_fuse_matches_the_oracle_tensor_product():
+    from workloads.network import Network
+    rng = np.random.default_rng(5)
+    for dims in ([6], [6, 6], [4, 6, 6], [2, 3, 5, 7]):
+        cs = [rng.uniform(-1, 1, d) for d in dims]
+        got = htn.htn_qpd_fuse(cs)
+        net = Network([np.zeros(dims)] + cs, [list(range(len(dims)))] + [[k] for k in range(len(dims))],
+                      list(dims), [])
+        f, fids = qs.fuse_parallel(net, [list(range(1, len(dims) + 1))])
+        assert np.array_equal(got, f.tensors[fids[0]])
+
+
+def test_gather_merges_and_permutes_axes_bit_exactly():
+    torch = _torch()
+    rng = np.random.default_rng(2)
+    items, refs = [], []
+    for dims, groups, kept in (([4, 6, 3], [[1], [0, 2]], [None, [0, 5, 11]]),
+                               ([6, 6, 4, 6], [[2], [3, 1], [0]], [None, [35, 0, 7], [1, 4]]),
+                               ([5, 7], [[0, 1]], [None]),
+                               ([3, 4, 5, 6, 2], [[4, 0], [2], [1, 3]], [[5, 1], None, list(range(0, 24, 5))])):
+        src = rng.uniform(-1, 1, dims)
+        # the reference: permute the axes into group order, merge each group
+        x = np.transpose(src, [a for g in groups for a in g]).reshape([int(np.prod([dims[a] for a in g]))
+                                                                       for g in groups])
+        for o, k in enumerate(kept):
+            if k is not None:
+                x = np.take(x, k, axis=o)
+        d_src = torch.from_numpy(src).cuda()
+        dst = torch.empty(x.shape, dtype=torch.float64, device="cuda")
+        items.append((d_src, dst, dims, groups, kept))
+        refs.append(x)
+    g = htn.htn_gather_create(items, htn.HTN_F64)
+    htn.htn_truncate_run(g)
+    torch.cuda.synchronize()
+    for (_, dst, _, _, _), x in zip(items, refs):
+        assert np.array_equal(dst.cpu().numpy(), x)
+
+
+def _fused_case(w, seed, s_qpd):
+    """Library and oracle simplification of one network on the same
+    uniforms; returns the library's Simplified and the oracle's network."""
+    from paper_2410_15080_amd import qpd as lq
+    torch = _torch()
+    gate = [i for i, k in enumerate(w.kinds) if k == "ct" and w.tensors[i].size == 6]
+    n_groups = len(qs.parallel_groups(w, gate))
+    rng = np.random.default_rng(seed)
+    uniforms = [rng.random(s_qpd) for _ in range(n_groups)]
+    ts = to_device(w)
+    items = []
+    lib = lq.simplify(ts, w.labels, w.dims, w.out_labels, gate, s_qpd, uniforms, items)
+    ref, _, _, counts = qs.simplify(w, gate, s_qpd, uniforms)
+    for a, b in zip(lib.counts, counts):
+        assert np.array_equal(a, b)
+    return lib, ref, items
+
+
+@pytest.mark.parametrize("s_qpd", [1, 2, 8])
+def test_fused_sampling_on_multi_bond_networks_matches_oracle(s_qpd):
+    """Ring-of-rings networks (bond multiplicities 1-3) and random networks
+    with multi-edges: the library fuses the CTs between the same QTs, draws
+    the fused CTs, gathers every QT in one launch (bit-exact against the
+    oracle's merged and truncated tensors) and contracts the simplified
+    network to the oracle's value within 1e-10 relative (FP64)."""
+    torch = _torch()
+    cases = [configs.ring_of_rings(s) for s in range(2)]
+    cases += [w for w in configs.random_batch(9, n=40, dtype=np.float64)
+              if any(len(g) > 1 for g in qs.parallel_groups(
+                  w, [i for i, k in enumerate(w.kinds) if k == "ct" and w.tensors[i].size == 6]))][:6]
+    assert len(cases) >= 6
+    simp, refs, items = [], [], []
+    for k, w in enumerate(cases):
+        lib, ref, its = _fused_case(w, 100 * s_qpd + k, s_qpd)
+        simp.append(lib)
+        refs.append(ref)
+        items += its
+    g = htn.htn_gather_create([it for it in items], htn.HTN_F64)
+    htn.htn_truncate_run(g)
+    torch.cuda.synchronize()
+    for lib, ref in zip(simp, refs):
+        assert lib.dims == ref.dims and lib.labels == ref.labels
+        for a, b in zip(lib.tensors, ref.tensors):
+            assert np.array_equal(a.cpu().numpy(), b)
+        net = htn.htn_create(lib.tensors, lib.labels, lib.dims, lib.out_labels)
+        out = htn.new_output(net)
+        htn.htn_contract(net, out)
+        torch.cuda.synchronize()
+        hi, lo = oracle.ve_contract(ref.tensors, ref.labels, ref.dims, ref.out_labels)
+        x = float(hi) + float(lo)
+        assert abs(float(out.item()) - x) <= 1e-10 * abs(x) + 1e-300, (float(out.item()), x)
