@@ -40,6 +40,7 @@
 #ifndef HTN_H
 #define HTN_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -219,9 +220,22 @@ htn_status htn_contract_batch(int32_t n, const htn_net_t *nets, void *const *out
 /* Reusable batch: plans the combined launch once.  The nets must outlive
  * the batch and keep their paths.  htn_batch_run may capture its launches
  * in a HIP graph (htn_batch_set_graph) and replay it on later calls with
- * the same outs.                                                          */
+ * the same outs.
+ * htn_batch_set_graph: use_graph 0 runs eagerly; 1 makes the next run on a
+ * non-NULL stream run eagerly once and capture a graph, replayed by later
+ * runs with the same outs and stream.  If the capture fails (the stream
+ * cannot be captured, a launch is refused while capturing, the graph does
+ * not instantiate), the stream is taken out of capture mode, the partial
+ * graph is freed and every later run is eager; the run that tried still
+ * computed its results.  HTN_GRAPH_FORCE_FAILURE behaves as 1 but fails the
+ * capture on purpose after recording, so callers can test that path.
+ * htn_batch_graph_state: *state = 0 (eager: graphs off or not yet
+ * captured), 1 (a captured graph is replayed) or 2 (a capture failed: eager
+ * from then on; htn_last_error() then describes the failure).             */
+#define HTN_GRAPH_FORCE_FAILURE 2
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets);
 htn_status htn_batch_set_graph(htn_batch_t batch, int32_t use_graph);
+htn_status htn_batch_graph_state(htn_batch_t batch, int32_t *state);
 htn_status htn_batch_run(htn_batch_t batch, void *const *outs, void *hip_stream);
 /* Per-net start and completion times of the last run: ticks[2*i] and
  * ticks[2*i+1], in ticks of the device's constant 100 MHz clock counted
@@ -368,6 +382,25 @@ htn_status htn_batch_step_times(htn_batch_t batch, float *times, int32_t capacit
  * settings and HTN_E_UNSUPPORTED is returned.                             */
 htn_status htn_autotune(int32_t n, const htn_net_t *nets, void *const *outs, void *hip_stream,
                         int32_t *best_threads, int32_t *best_lds_bytes, float *best_ms);
+
+/* ---------------------------------------------------------------------
+ * htn_set_allocator — device memory allocator of the library (process
+ * wide): every device buffer it allocates from then on (net workspaces,
+ * input copies, step tables and descriptors, batch and model buffers)
+ * comes from alloc(bytes, ctx), which must return memory of at least
+ * `bytes` bytes on the current device, aligned to 256 bytes, or NULL
+ * (reported as HTN_E_OOM by the call that needed it).  A buffer is
+ * released with the free routine of the allocator that made it, so the
+ * allocator may be changed at any time; free(ptr, ctx) is called when the
+ * library no longer uses ptr (after the caller has synchronised the
+ * streams of work that used it, e.g. before htn_destroy).  This lets the
+ * caller route the library's memory through its own pool (e.g. PyTorch's
+ * caching allocator).  Both NULL: back to hipMalloc / hipFree.
+ * Errors: HTN_E_ARG if exactly one of alloc and free_fn is NULL.
+ * ------------------------------------------------------------------- */
+typedef void *(*htn_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*htn_free_fn)(void *ptr, void *ctx);
+htn_status htn_set_allocator(htn_alloc_fn alloc, htn_free_fn free_fn, void *ctx);
 
 /* ---------------------------------------------------------------------
  * htn_contract_noalloc — htn_contract for callers that cannot allocate

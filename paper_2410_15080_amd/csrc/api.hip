@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "htn.h"
@@ -100,6 +101,9 @@ struct htn_batch {
     int64_t *d_stamps = nullptr;
     std::vector<void *> outs_uploaded;
     bool use_graph = false;
+    bool force_capture_failure = false;  // host-forced: the capture fails (tests the fallback)
+    bool graph_failed = false;           // a capture failed: runs stay eager
+    std::string graph_error;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -131,17 +135,63 @@ static constexpr double kStragglerFactor = 4.0;
 
 // ------------------------------------------------------------- helpers
 
+// Device memory of the library: hipMalloc/hipFree, or the caller's
+// allocator (htn_set_allocator).  Each block remembers the free routine of
+// the allocator that made it, so changing the allocator later is safe.
+namespace {
+struct AllocHook {
+    htn_alloc_fn alloc = nullptr;
+    htn_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocHook g_hook;
+std::unordered_map<void *, AllocHook> g_hooked;  // blocks made by a caller allocator
+}  // namespace
+
 static void dfree(void *p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        auto it = g_hooked.find(p);
+        if (it != g_hooked.end()) {
+            h = it->second;
+            g_hooked.erase(it);
+        }
+    }
+    if (h.free)
+        h.free(p, h.ctx);
+    else
+        (void)hipFree(p);
+}
+
+static void *dalloc_bytes(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        h = g_hook;
+    }
+    if (h.alloc) {
+        void *p = h.alloc(bytes, h.ctx);
+        if (!p) throw Error{HTN_E_OOM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        g_hooked[p] = h;
+        return p;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{HTN_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    }
+    return p;
 }
 
 template <typename T>
 static T *dalloc(size_t count) {
-    void *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) throw Error{HTN_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e)};
-    return (T *)p;
+    return (T *)dalloc_bytes(count * sizeof(T));
 }
 
 static float bf16_bits_to_f32(uint16_t h) {
@@ -723,6 +773,17 @@ static void *scratch_address(int dev) {
 
 extern "C" {
 
+htn_status htn_set_allocator(htn_alloc_fn alloc, htn_free_fn free_fn, void *ctx) {
+    API_GUARD_BEGIN
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(HTN_E_ARG, "give both alloc and free, or neither");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_hook.alloc = alloc;
+    g_hook.free = free_fn;
+    g_hook.ctx = alloc ? ctx : nullptr;
+    return HTN_OK;
+    API_GUARD_END
+}
+
 htn_status htn_contract_noalloc(htn_net_t net, void *out_device, void *hip_stream) {
     API_GUARD_BEGIN
     if (!net || !out_device) return fail(HTN_E_ARG, "NULL argument");
@@ -916,7 +977,24 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
 htn_status htn_batch_set_graph(htn_batch_t b, int32_t use_graph) {
     API_GUARD_BEGIN
     if (!b) return fail(HTN_E_ARG, "batch is NULL");
+    if (use_graph < 0 || use_graph > HTN_GRAPH_FORCE_FAILURE) return fail(HTN_E_ARG, "bad graph mode");
     b->use_graph = use_graph != 0;
+    b->force_capture_failure = use_graph == HTN_GRAPH_FORCE_FAILURE;
+    b->graph_failed = false;
+    b->graph_error.clear();
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_graph_state(htn_batch_t b, int32_t *state) {
+    API_GUARD_BEGIN
+    if (!b || !state) return fail(HTN_E_ARG, "NULL argument");
+    if (b->graph_failed) {
+        *state = 2;
+        g_err = b->graph_error;
+    } else {
+        *state = b->gexec ? 1 : 0;
+    }
     return HTN_OK;
     API_GUARD_END
 }
@@ -963,6 +1041,38 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
     }
 }
 
+// Records the batch's launches on st into a HIP graph and instantiates it.
+// Any failure (the stream cannot be captured, a launch refused inside the
+// capture, instantiation) leaves st out of capture mode, frees what was
+// built and marks the batch to run eagerly from then on.
+static void capture_batch(htn_batch *b, void *const *outs, hipStream_t st) {
+    auto give_up = [&](const std::string &why) {
+        b->graph_failed = true;
+        b->graph_error = "graph capture failed, running eagerly: " + why;
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        (void)hipGetLastError();
+    };
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return give_up(std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    std::string why;
+    try {
+        batch_enqueue(b, outs, st, false);
+        if (b->force_capture_failure) why = "capture failure forced by the caller";
+    } catch (const Error &err) {
+        why = err.msg;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (why.empty() && e != hipSuccess) why = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+    b->graph = g;
+    if (!why.empty()) return give_up(why);
+    e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return give_up(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+}
+
 htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
     API_GUARD_BEGIN
     if (!b || !outs) return fail(HTN_E_ARG, "NULL argument");
@@ -979,7 +1089,7 @@ htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
         HIP_TRY(hipMemcpy(b->d_outs, ov.data(), n * sizeof(void *), hipMemcpyHostToDevice));
         b->outs_uploaded = ov;
     }
-    if (b->use_graph && st != nullptr) {
+    if (b->use_graph && st != nullptr && !b->graph_failed) {
         if (b->gexec && (b->graph_outs != ov || b->graph_stream != st)) {
             (void)hipGraphExecDestroy(b->gexec);
             (void)hipGraphDestroy(b->graph);
@@ -988,19 +1098,11 @@ htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
         }
         if (!b->gexec) {
             batch_enqueue(b, outs, st, false);  // first run eagerly (also sets kernel attributes)
-            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            try {
-                batch_enqueue(b, outs, st, false);
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(st, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
+            capture_batch(b, outs, st);          // on failure: later runs stay eager
+            if (!b->graph_failed) {
+                b->graph_outs = ov;
+                b->graph_stream = st;
             }
-            HIP_TRY(hipStreamEndCapture(st, &b->graph));
-            HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
-            b->graph_outs = ov;
-            b->graph_stream = st;
             return HTN_OK;
         }
         HIP_TRY(hipGraphLaunch(b->gexec, st));
@@ -1520,9 +1622,9 @@ struct htn_trunc {
     kern::TruncBlock *d_blocks = nullptr;
     int64_t *d_maps = nullptr;
     ~htn_trunc() {
-        if (d_items) (void)hipFree(d_items);
-        if (d_blocks) (void)hipFree(d_blocks);
-        if (d_maps) (void)hipFree(d_maps);
+        dfree(d_items);
+        dfree(d_blocks);
+        dfree(d_maps);
     }
 };
 
@@ -1630,10 +1732,10 @@ static htn_trunc *build_gather(const std::vector<GatherSpec> &items, htn_dtype d
     t->elem_bytes = dtype_size(dtype);
     t->n_blocks = (int64_t)blocks.size();
     try {
-        HIP_TRY(hipMalloc(&t->d_items, h.size() * sizeof(kern::TruncItem)));
-        HIP_TRY(hipMalloc(&t->d_blocks, blocks.size() * sizeof(kern::TruncBlock)));
+        t->d_items = dalloc<kern::TruncItem>(h.size());
+        t->d_blocks = dalloc<kern::TruncBlock>(blocks.size());
         HIP_TRY(hipMemcpy(t->d_blocks, blocks.data(), blocks.size() * sizeof(kern::TruncBlock), hipMemcpyHostToDevice));
-        HIP_TRY(hipMalloc(&t->d_maps, maps.size() * sizeof(int64_t)));
+        t->d_maps = dalloc<int64_t>(maps.size());
         HIP_TRY(hipMemcpy(t->d_items, h.data(), h.size() * sizeof(kern::TruncItem), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t->d_maps, maps.data(), maps.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     } catch (...) {

@@ -98,6 +98,8 @@ def load_library():
         "htn_contract_batch": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P]),
         "htn_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
         "htn_batch_set_graph": (I32, [P, I32]),
+        "htn_batch_graph_state": (I32, [P, i32p]),
+        "htn_set_allocator": (I32, [P, P, P]),
         "htn_batch_run": (I32, [P, ctypes.POINTER(P), P]),
         "htn_batch_timestamps": (I32, [P, i64p]),
         "htn_batch_destroy": (None, [P]),
@@ -353,8 +355,64 @@ def htn_batch_create(nets) -> Batch:
     return Batch(h, list(nets))
 
 
-def htn_batch_set_graph(batch: Batch, use_graph: bool) -> None:
-    _check(load_library().htn_batch_set_graph(batch.handle, 1 if use_graph else 0))
+def htn_batch_set_graph(batch: Batch, use_graph) -> None:
+    """use_graph: False/0, True/1, or HTN_GRAPH_FORCE_FAILURE."""
+    _check(load_library().htn_batch_set_graph(batch.handle, int(use_graph)))
+
+
+HTN_GRAPH_FORCE_FAILURE = 2
+
+
+def htn_batch_graph_state(batch: Batch) -> int:
+    """0 eager, 1 replaying a captured graph, 2 capture failed (eager)."""
+    st = ctypes.c_int32()
+    _check(load_library().htn_batch_graph_state(batch.handle, ctypes.byref(st)))
+    return int(st.value)
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None  # keeps the installed callbacks alive
+
+
+def htn_set_allocator(alloc, free) -> None:
+    """Install Python callables alloc(nbytes) -> int address (0 on failure)
+    and free(address) as the library's device allocator; (None, None)
+    restores hipMalloc / hipFree."""
+    global _allocator_refs
+    lib = load_library()
+    if alloc is None and free is None:
+        _check(lib.htn_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+
+    def _a(nbytes, ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:
+            return None
+
+    def _f(ptr, ctx):
+        free(int(ptr))
+
+    refs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib.htn_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p),
+                                 None))
+    _allocator_refs = refs
+
+
+def use_torch_allocator() -> None:
+    """Route the library's device memory through PyTorch's caching allocator
+    (on the current device and stream)."""
+    import torch
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(n)
+
+    def free(p):
+        torch.cuda.caching_allocator_delete(p)
+
+    htn_set_allocator(alloc, free)
 
 
 def htn_batch_run(batch: Batch, outs, stream=None) -> None:

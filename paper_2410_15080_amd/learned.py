@@ -78,3 +78,41 @@ def predict_log_us(model, features):
     htn.htn_model_forward(model, x, y)
     torch.cuda.synchronize()
     return y.cpu().numpy()
+
+
+def save_model(model, path):
+    """Write the model's parameters (htn_model_get_params) to an .npz file."""
+    np.savez(path, params=htn.htn_model_get_params(model), features=htn.HTN_MODEL_FEATURES,
+             hidden=htn.HTN_MODEL_HIDDEN)
+
+
+def load_model(path, seed=0):
+    """A model on the current device with the parameters saved by save_model
+    (a file of another feature or hidden-layer size is refused)."""
+    with np.load(path, allow_pickle=False) as f:
+        if int(f["features"]) != htn.HTN_MODEL_FEATURES or int(f["hidden"]) != htn.HTN_MODEL_HIDDEN:
+            raise ValueError("model file has another shape")
+        params = f["params"]
+    m = htn.htn_model_create(seed)
+    htn.htn_model_set_params(m, params)
+    return m
+
+
+def save_autotune(path, threads, lds_bytes, ms, workload):
+    """Record an htn_autotune choice (JSON) for reuse by later runs."""
+    import json
+    with open(path, "w") as f:
+        json.dump({"workload": workload, "threads": int(threads), "lds_bytes": int(lds_bytes), "ms": float(ms)}, f)
+
+
+def load_autotune(path, workload):
+    """(threads, lds_bytes) of a saved choice for `workload`, or None."""
+    import json
+    import os
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("workload") != workload:
+        return None
+    return int(rec["threads"]), int(rec["lds_bytes"])

@@ -198,3 +198,12 @@ def test_noalloc_rejects_a_workspace_above_its_limit_on_the_host():
     with pytest.raises(htn.HtnError) as e:
         htn.htn_contract_noalloc(net, np.zeros(1))  # rejected before the output is used
     assert e.value.name == "HTN_E_UNSUPPORTED"
+
+
+def test_allocator_hook_arguments_are_checked_on_the_host():
+    import ctypes
+    from paper_2410_15080_amd import htn
+    lib = htn.load_library()
+    fn = htn.ALLOC_FN(lambda n, c: None)
+    assert lib.htn_set_allocator(ctypes.cast(fn, ctypes.c_void_p), None, None) == 1  # HTN_E_ARG
+    assert lib.htn_set_allocator(None, None, None) == 0

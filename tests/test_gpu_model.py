@@ -263,3 +263,23 @@ def test_learned_path_without_model_is_greedy():
     g = htn.htn_get_path(n)
     htn.htn_set_path(n, htn.HTN_PATH_LEARNED)
     assert htn.htn_get_path(n) == g
+
+
+def test_model_and_autotune_choice_persist(tmp_path):
+    from paper_2410_15080_amd import learned
+    import torch
+    m = htn.htn_model_create(11)
+    p = htn.htn_model_get_params(m)
+    learned.save_model(m, str(tmp_path / "m.npz"))
+    m2 = learned.load_model(str(tmp_path / "m.npz"))
+    assert np.array_equal(htn.htn_model_get_params(m2), p)
+    x = torch.rand(32, htn.HTN_MODEL_FEATURES, device="cuda")
+    y1 = torch.empty(32, device="cuda")
+    y2 = torch.empty(32, device="cuda")
+    htn.htn_model_forward(m, x, y1)
+    htn.htn_model_forward(m2, x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    learned.save_autotune(str(tmp_path / "t.json"), 256, 65536, 0.5, "grid")
+    assert learned.load_autotune(str(tmp_path / "t.json"), "grid") == (256, 65536)
+    assert learned.load_autotune(str(tmp_path / "t.json"), "ring") is None

@@ -330,3 +330,85 @@ def test_edge_case_networks(exec_mode):
         ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
         got = run(w, exec_mode=exec_mode)
         assert np.abs(got - ref).max() <= 1e-14, name
+
+
+def test_torch_allocator_holds_the_library_memory():
+    """With PyTorch's caching allocator installed, a net's device buffers
+    (input copies, tables, workspace) are counted by torch and returned when
+    the net is destroyed; results are unchanged."""
+    import torch
+    w = configs.grid_network(21)
+    ref = float(run(w, exec_mode=htn.HTN_EXEC_STEPS))
+    htn.use_torch_allocator()
+    try:
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated()
+        net = create(w, exec_mode=htn.HTN_EXEC_STEPS, on_device=False)  # host data: copied into library memory
+        out = htn.new_output(net)
+        htn.htn_contract(net, out)
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated() - before
+        ws = htn.htn_get_info(net).workspace_bytes
+        assert held >= ws + htn.htn_get_info(net).input_bytes, (held, ws)
+        assert float(out.item()) == ref
+        del out
+        htn.htn_destroy(net)
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == before
+    finally:
+        htn.htn_set_allocator(None, None)
+
+
+def test_failing_allocator_reports_oom_and_the_net_recovers():
+    import torch
+    w = configs.grid_network(22)
+    net = create(w, exec_mode=htn.HTN_EXEC_STEPS, on_device=False)
+    out = htn.new_output(net)
+    htn.htn_set_allocator(lambda n: 0, lambda p: None)
+    try:
+        with pytest.raises(htn.HtnError) as e:
+            htn.htn_contract(net, out)
+        assert e.value.name == "HTN_E_OOM"
+    finally:
+        htn.htn_set_allocator(None, None)
+    htn.htn_contract(net, out)
+    torch.cuda.synchronize()
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    assert abs(float(out.item()) - (hi + lo)) <= REL_F64 * abs(hi + lo)
+
+
+def test_failed_graph_capture_falls_back_to_stream_launches():
+    """A capture forced to fail leaves the stream usable, the batch runs
+    eagerly from then on with the same results, and the state says so; a
+    later graph request captures normally."""
+    import torch
+    ws = [configs.grid_network(300 + s) for s in range(16)] + configs.random_batch(5, n=16, dtype=np.float64)
+    nets = [create(w) for w in ws]
+    outs = [htn.new_output(n) for n in nets]
+    ptrs = htn.pointer_array(outs)
+    refs = []
+    for w in ws:
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        refs.append(float(hi) + float(lo))
+    b = htn.htn_batch_create(nets)
+    stream = torch.cuda.Stream()
+    for mode, state in ((htn.HTN_GRAPH_FORCE_FAILURE, 2), (1, 1)):
+        htn.htn_batch_set_graph(b, mode)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                htn.htn_batch_run(b, ptrs, stream)
+            stream.synchronize()
+            for i, (o, ref) in enumerate(zip(outs, refs)):
+                assert abs(float(o.item()) - ref) <= REL_F64 * abs(ref) + 1e-300, (mode, rep, i)
+            assert htn.htn_batch_graph_state(b) == state
+        if state == 2:
+            assert "forced" in htn.htn_last_error()
+        # the stream is not left capturing
+        x = torch.ones(4, device="cuda")
+        with torch.cuda.stream(stream):
+            y = x * 2
+        stream.synchronize()
+        assert float(y.sum()) == 8.0
