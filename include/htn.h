@@ -176,8 +176,27 @@ typedef enum {
                                       0: VALU only */
     HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
     HTN_OPT_PATH_SEED = 5,         /* seed of the path sampler (default 0) */
-    HTN_OPT_FUSED_THREADS = 6      /* threads per network in the fused kernel: 64, 256 (default) or 512 */
+    HTN_OPT_FUSED_THREADS = 6,     /* threads per network in the fused kernel: 64, 256 (default) or 512 */
+    HTN_OPT_SLICE = 7              /* 0 (default): a path whose largest intermediate exceeds
+                                      HTN_OPT_MAX_INTERMEDIATE is HTN_E_OOM.  1: slicing (see below) */
 } htn_option;
+
+/* Slicing under the intermediate cap (HTN_OPT_SLICE = 1).  Contraction
+ * orders are chosen by cost (Sec. 4.2; Sec. 6.1 Step 3 uses hyper-optimised
+ * search, which slices); when the largest intermediate of the net's path
+ * (every step's result) exceeds HTN_OPT_MAX_INTERMEDIATE, summed labels are
+ * fixed one at a time -- each time the one that leaves the smallest largest
+ * intermediate (fewer slices, then the lower label id, on ties) -- until the
+ * path fits; at most 65536 slices, else HTN_E_OOM.  A slice is the network
+ * with those labels fixed to one value each; htn_contract cuts every
+ * input's slices out of its device copy (one gather launch), contracts the
+ * slices as one batch (same path, each slice a network of its own) and
+ * sums their results in FP64 (compensated under HTN_SUM_COMPENSATED) in
+ * slice order.  htn_info.mults counts every slice, htn_info.peak_elements
+ * is one slice's largest intermediate, htn_info.n_slices the slice count.
+ * A sliced net cannot join a batch (htn_batch_create: HTN_E_UNSUPPORTED) or
+ * htn_contract_noalloc.  htn_get_slicing lists the sliced labels (in slice
+ * order: the first slowest).                                              */
 
 htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value);
 
@@ -194,9 +213,15 @@ typedef struct {
     double peak_elements;   /* largest intermediate                          */
     int64_t workspace_bytes;/* device workspace of the per-step executor     */
     int64_t input_bytes;    /* bytes of the inputs in compute storage        */
+    int64_t n_slices;       /* slices contracted (1: not sliced)             */
 } htn_info;
 
 htn_status htn_get_info(htn_net_t net, htn_info *info);
+
+/* htn_get_slicing — the sliced labels of the current plan: *n_labels
+ * receives their count, labels (if non-NULL) the first min(capacity,
+ * *n_labels) of them, *n_slices (if non-NULL) the number of slices.     */
+htn_status htn_get_slicing(htn_net_t net, int32_t *n_labels, int32_t *labels, int32_t capacity, int64_t *n_slices);
 
 /* ---------------------------------------------------------------------
  * htn_contract — contract the net into out_device (caller-owned device

@@ -13,6 +13,9 @@ Contents
                    open output labels for marginal distributions.
   ve_contract      variable elimination, double-double (reference) or FP64
                    (timed CPU baseline) (C).
+  sliced_contract  the sum over every assignment of chosen labels of the
+                   network with those labels fixed (the slices a sliced
+                   contraction sums).
   path_cost        the paper's postprocessing cost of a pairwise contraction
                    order: multiplications per step = product of the
                    extents of the union of both operands' labels
@@ -121,6 +124,39 @@ def ve_contract(tensors, labels, dims, out_labels=(), mode="dd"):
     if mode == "dd":
         return hi.reshape(shape), lo.reshape(shape)
     return hi.reshape(shape)
+
+
+def sliced_contract(tensors, labels, dims, out_labels, sliced):
+    """The network's value as the sum of its slices: for every assignment
+    of the labels in `sliced` (none of them an output label), the network
+    with those labels fixed (every tensor carrying one takes that index),
+    contracted by ve_contract in double-double; the slices' hi and lo parts
+    are summed with math.fsum (correctly rounded).  Returns an FP64 array."""
+    import itertools
+    import math
+    vals = []
+    for assign in itertools.product(*[range(dims[l]) for l in sliced]):
+        fixed = dict(zip(sliced, assign))
+        ts, ls = [], []
+        for t, lab in zip(tensors, labels):
+            a = np.asarray(t, dtype=np.float64)
+            keep = []
+            for ax in range(len(lab) - 1, -1, -1):
+                if lab[ax] in fixed:
+                    a = np.take(a, fixed[lab[ax]], axis=ax)
+                else:
+                    keep.append(lab[ax])
+            ts.append(np.ascontiguousarray(a).reshape([dims[l] for l in reversed(keep)]) if keep
+                      else np.array([float(a)]))
+            ls.append(list(reversed(keep)) if keep else [len(dims)])
+        d = list(dims) + [1]
+        hi, lo = ve_contract(ts, ls, d, out_labels)
+        vals.append((np.asarray(hi), np.asarray(lo)))
+    shape = vals[0][0].shape
+    out = np.zeros(shape)
+    for idx in np.ndindex(*shape) if shape else [()]:
+        out[idx] = math.fsum([float(h[idx]) for h, _ in vals] + [float(l[idx]) for _, l in vals])
+    return out
 
 
 def contract_net(net, mode="dd"):

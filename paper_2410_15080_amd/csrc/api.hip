@@ -66,8 +66,12 @@ struct DeviceState {
     int fprep_max = 0;
     bool fprep_in_kernel = false;  // the fused workgroup materialises its inputs
     int plan_uploaded = -1;
+    struct SliceRun *slices = nullptr;  // a sliced net's slice networks (built at first use)
 };
 }  // namespace htn
+
+static void free_slices(htn::DeviceState &D);
+static void run_sliced(htn::Net &n, void *out, hipStream_t st);
 
 // A network contracted on its own (htn_contract, fused) whose inputs total
 // at most this many elements materialises them inside its workgroup, which
@@ -244,6 +248,7 @@ static void release_inputs(Net &n) {
 
 static void release_device(Net &n) {
     if (!n.dev) return;
+    free_slices(*n.dev);
     release_inputs(n);
     DeviceState &D = *n.dev;
     dfree(D.d_inptrs);
@@ -279,6 +284,7 @@ static void set_data(Net &n, const void *const *data, int on_device) {
 static void upload_inputs(Net &n) {
     DeviceState &D = *n.dev;
     const htn_dtype tin = input_dtype(n.compute);
+    free_slices(D);  // slice networks read the inputs' device copies
     release_inputs(n);
     D.in.assign(n.n_t, nullptr);
     D.own.assign(n.n_t, 0);
@@ -396,7 +402,8 @@ static void ensure_device(Net &n) {
         if (cur != n.dev->device) throw Error{HTN_E_STATE, "net was first used on another device"};
     }
     if (n.data_dirty) upload_inputs(n);
-    if (n.dev->plan_uploaded != n.plan_version) upload_plan(n);
+    // a sliced net runs its slice networks, never its own plan
+    if (n.n_slices == 1 && n.dev->plan_uploaded != n.plan_version) upload_plan(n);
 }
 
 static int final_mode(const Net &n) {
@@ -539,7 +546,9 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
 }
 
 static void contract_one(Net &n, void *out, hipStream_t st) {
-    if (use_fused(n))
+    if (n.n_slices > 1)
+        run_sliced(n, out, st);
+    else if (use_fused(n))
         run_fused_single(n, out, st);
     else
         run_steps(n, out, st);
@@ -548,7 +557,7 @@ static void contract_one(Net &n, void *out, hipStream_t st) {
 static void replan(Net &n) {
     auto old_path = n.path;
     try {
-        build_plan(n);
+        plan_net(n);
     } catch (...) {
         n.path = old_path;
         throw;
@@ -598,7 +607,7 @@ htn_status htn_create(htn_net_t *out, int32_t n_tensors, const int32_t *ranks, c
         set_data(*n, data, data_on_device);
         n->path = greedy_path(*n);
         n->path_kind = HTN_PATH_GREEDY;
-        build_plan(*n);
+        plan_net(*n);
     } catch (...) {
         delete n;
         throw;
@@ -633,7 +642,7 @@ htn_status htn_set_path(htn_net_t net, int32_t n_steps, const int32_t *ssa_pairs
         } else {
             return fail(HTN_E_ARG, "unknown path selector");
         }
-        build_plan(*net);
+        plan_net(*net);
     } catch (...) {
         net->path = old;
         net->path_kind = old_kind;
@@ -696,6 +705,19 @@ htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
         case HTN_OPT_PATH_SEED:
             net->path_seed = (uint64_t)value;
             return HTN_OK;
+        case HTN_OPT_SLICE: {
+            if (value != 0 && value != 1) return fail(HTN_E_ARG, "slicing is 0 (off) or 1 (on)");
+            const int old = net->slice_mode;
+            net->slice_mode = (int)value;
+            try {
+                replan(*net);
+            } catch (...) {
+                net->slice_mode = old;
+                replan(*net);
+                throw;
+            }
+            return HTN_OK;
+        }
         case HTN_OPT_FUSED_THREADS: {
             if (value != 64 && value != 256 && value != 512)
                 return fail(HTN_E_ARG, "fused threads must be 64, 256 or 512");
@@ -728,12 +750,24 @@ htn_status htn_get_info(htn_net_t net, htn_info *info) {
     info->n_absorbed = P.n_absorbed;
     info->fused_ok = P.fused_ok ? 1 : 0;
     info->fused_lds_bytes = (int32_t)P.fused_lds_bytes;
-    info->mults = P.mults;
+    info->mults = P.mults * (double)net->n_slices;
     info->peak_elements = P.peak;
+    info->n_slices = net->n_slices;
     info->workspace_bytes = P.ws_bytes;
     int64_t ib = 0;
     for (int i = 0; i < net->n_t; ++i) ib += net->sizes[i] * dtype_size(input_dtype(net->compute));
     info->input_bytes = ib;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_get_slicing(htn_net_t net, int32_t *n_labels, int32_t *labels, int32_t capacity, int64_t *n_slices) {
+    API_GUARD_BEGIN
+    if (!net || !n_labels || capacity < 0) return fail(HTN_E_ARG, "bad arguments");
+    *n_labels = (int32_t)net->sliced.size();
+    if (labels)
+        for (int k = 0; k < (int)net->sliced.size() && k < capacity; ++k) labels[k] = net->sliced[k];
+    if (n_slices) *n_slices = net->n_slices;
     return HTN_OK;
     API_GUARD_END
 }
@@ -787,6 +821,7 @@ htn_status htn_set_allocator(htn_alloc_fn alloc, htn_free_fn free_fn, void *ctx)
 htn_status htn_contract_noalloc(htn_net_t net, void *out_device, void *hip_stream) {
     API_GUARD_BEGIN
     if (!net || !out_device) return fail(HTN_E_ARG, "NULL argument");
+    if (net->n_slices > 1) return fail(HTN_E_UNSUPPORTED, "a sliced net allocates its slice networks");
     if (net->plan.ws_bytes > (int64_t)HTN_NOALLOC_SCRATCH_BYTES)
         return fail(HTN_E_UNSUPPORTED, "the per-step workspace needs " + std::to_string(net->plan.ws_bytes) +
                                            " bytes, above the " + std::to_string((int64_t)HTN_NOALLOC_SCRATCH_BYTES) +
@@ -899,6 +934,8 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
         const double straggler = std::max(kStragglerFloor, kStragglerFactor * fused_total / (2.0 * cus));
         for (int i = 0; i < n; ++i) {
             Net &net = *nets[i];
+            if (net.n_slices > 1)
+                throw Error{HTN_E_UNSUPPORTED, "net " + std::to_string(i) + " is sliced: contract it with htn_contract"};
             ensure_device(net);
             b->versions.push_back(net.plan_version);
             desc[i] = fused_desc(*net.dev, false, net.plan.fused_lds_only);
@@ -1886,3 +1923,141 @@ htn_status htn_truncate_run(htn_trunc_t t, void *hip_stream) {
 void htn_truncate_destroy(htn_trunc_t t) { delete t; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Sliced networks: every slice (the network with its sliced labels fixed) is
+// a network of its own; one gather launch cuts every input's slices out of
+// its device copy, the slices run as one batch, and a last launch sums their
+// results in FP64.
+// ---------------------------------------------------------------------------
+
+namespace htn {
+struct SliceRun {
+    int version = -1;           // plan version it was built for
+    htn_trunc *gather = nullptr;
+    void *buf = nullptr;        // slice inputs: [slice][sliced input][elements]
+    void *parts = nullptr;      // slice results: [slice][output elements]
+    std::vector<htn_net *> subs;
+    htn_batch *batch = nullptr;
+    std::vector<void *> outs;
+};
+}  // namespace htn
+
+static void free_slices(DeviceState &D) {
+    SliceRun *r = D.slices;
+    if (!r) return;
+    D.slices = nullptr;
+    if (r->batch) htn_batch_destroy(r->batch);
+    for (htn_net *m : r->subs) htn_destroy(m);
+    delete r->gather;
+    dfree(r->buf);
+    dfree(r->parts);
+    delete r;
+}
+
+static void build_slices(Net &n) {
+    DeviceState &D = *n.dev;
+    const htn_dtype tin = input_dtype(n.compute);
+    const int es = dtype_size(tin);
+    const std::vector<int64_t> sd = sliced_dims(n);
+    const int64_t S = n.n_slices;
+    std::vector<char> is_sliced(n.dims.size(), 0);
+    for (int l : n.sliced) is_sliced[l] = 1;
+    // per slice: each input that carries a sliced label gets its own copy
+    std::vector<int64_t> soff(n.n_t, -1), ssize(n.n_t, 1);
+    int64_t per = 0;
+    for (int i = 0; i < n.n_t; ++i) {
+        bool carries = false;
+        for (int l : n.labels[i]) {
+            ssize[i] *= sd[l];
+            carries = carries || is_sliced[l];
+        }
+        if (carries) {
+            soff[i] = per;
+            per += (ssize[i] * es + 255) / 256 * 256;
+        }
+    }
+    auto *r = new SliceRun();
+    D.slices = r;  // freed by free_slices on any failure below
+    if (per > 0) r->buf = dalloc_bytes((size_t)(S * per));
+    std::vector<GatherSpec> specs;
+    std::vector<int64_t> val(n.dims.size(), 0);
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t rem = s;  // the slice's label values, row-major over n.sliced (first slowest)
+        for (int k = (int)n.sliced.size() - 1; k >= 0; --k) {
+            val[n.sliced[k]] = rem % n.dims[n.sliced[k]];
+            rem /= n.dims[n.sliced[k]];
+        }
+        for (int i = 0; i < n.n_t; ++i) {
+            if (soff[i] < 0) continue;
+            GatherSpec g;
+            g.src = D.in[i];
+            g.dst = (unsigned char *)r->buf + s * per + soff[i];
+            const auto &ls = n.labels[i];
+            int64_t stride = 1;
+            g.offs.resize(ls.size());
+            for (int a = (int)ls.size() - 1; a >= 0; --a) {
+                const int l = ls[a];
+                if (is_sliced[l])
+                    g.offs[a].push_back(val[l] * stride);
+                else
+                    for (int64_t x = 0; x < n.dims[l]; ++x) g.offs[a].push_back(x * stride);
+                stride *= n.dims[l];
+            }
+            specs.push_back(std::move(g));
+        }
+    }
+    if (!specs.empty()) r->gather = build_gather(specs, tin);
+    int64_t out_elems = 1;
+    for (int l : n.out_labels) out_elems *= n.dims[l];
+    const int oes = dtype_size(out_dtype(n));
+    r->parts = dalloc_bytes((size_t)(S * out_elems * oes));
+    for (int64_t s = 0; s < S; ++s) {
+        auto *m = new htn_net;
+        r->subs.push_back(m);
+        Net &t = *m;
+        t = structure_copy(n);
+        t.dims = sd;
+        for (int i = 0; i < t.n_t; ++i) t.sizes[i] = ssize[i];
+        t.slice_mode = 0;
+        t.storage = tin;
+        t.data_on_device = true;
+        t.user_ptrs.resize(t.n_t);
+        t.host.assign(t.n_t, {});
+        for (int i = 0; i < t.n_t; ++i)
+            t.user_ptrs[i] = soff[i] >= 0 ? (const void *)((unsigned char *)r->buf + s * per + soff[i]) : D.in[i];
+        t.data_dirty = true;
+        t.path = n.path;
+        t.path_kind = 0;
+        build_plan(t);
+        r->outs.push_back((unsigned char *)r->parts + s * out_elems * oes);
+    }
+    htn_batch_t b = nullptr;
+    if (htn_batch_create(&b, (int32_t)S, (const htn_net_t *)r->subs.data()) != HTN_OK)
+        throw Error{HTN_E_DEVICE, std::string("slice batch: ") + htn_last_error()};
+    r->batch = b;
+    r->version = n.plan_version;
+}
+
+static void run_sliced(Net &n, void *out, hipStream_t st) {
+    DeviceState &D = *n.dev;
+    if (D.slices && D.slices->version != n.plan_version) free_slices(D);
+    if (!D.slices) {
+        try {
+            build_slices(n);
+        } catch (...) {
+            free_slices(D);
+            throw;
+        }
+    }
+    SliceRun &r = *D.slices;
+    if (r.gather)
+        HIP_TRY(kern::launch_truncate(r.gather->d_items, r.gather->d_blocks, r.gather->n_blocks, r.gather->d_maps,
+                                      r.gather->elem_bytes, st));
+    if (htn_batch_run(r.batch, r.outs.data(), st) != HTN_OK)
+        throw Error{HTN_E_DEVICE, std::string("slice batch: ") + htn_last_error()};
+    int64_t out_elems = 1;
+    for (int l : n.out_labels) out_elems *= n.dims[l];
+    HIP_TRY(kern::launch_slice_sum(r.parts, (int)n.n_slices, out_elems, out, out_dtype(n) == HTN_F64 ? 0 : 1,
+                                   n.final_sum == HTN_SUM_COMPENSATED, st));
+}

@@ -170,6 +170,7 @@ struct Net {
     double fused_max_mults = 67108864.0;        // AUTO runs larger spilled nets step by step
     double batch_fused_max_mults = 33554432.0;  // batch limit for nets with matrix-core steps
     int allow_mfma = 1;
+    int slice_mode = 0;         // 1: slice summed labels until the path fits max_intermediate
     int path_samples = 32;      // sampled-greedy candidates
     uint64_t path_seed = 0;
     // data
@@ -182,6 +183,10 @@ struct Net {
     int path_kind = HTN_PATH_GREEDY;
     Plan plan;
     int plan_version = 0;
+    // slicing: labels fixed per slice (row-major over this list, first
+    // slowest) and the number of slices; plan then describes one slice
+    std::vector<int> sliced;
+    int64_t n_slices = 1;
     DeviceState *dev = nullptr;
     struct htn_model *model = nullptr;  // cost model of HTN_PATH_LEARNED (borrowed)
 };
@@ -216,6 +221,13 @@ std::vector<std::pair<int, int>> learned_path(const Net &n);  // throws Error
 std::vector<float> model_predict(struct htn_model *m, const std::vector<float> &x);
 void check_path(const Net &n, const std::vector<std::pair<int, int>> &p);  // throws Error
 void build_plan(Net &n);                                     // throws Error
+// build_plan, slicing summed labels first when slice_mode is on and the
+// path's largest intermediate exceeds max_intermediate (throws Error)
+void plan_net(Net &n);
+// Extents of a sliced network: every sliced label has extent 1.
+std::vector<int64_t> sliced_dims(const Net &n);
+// Largest intermediate (elements) of the net's path under the given extents.
+double path_peak(const Net &n, const std::vector<int64_t> &dims);
 std::string plan_json(const Net &n);
 
 }  // namespace htn

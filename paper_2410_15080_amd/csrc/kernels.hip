@@ -7,11 +7,13 @@
 //           single-operand summed label and outer product.  R lanes
 //           cooperate on one output and reduce with cross-lane shuffles.
 //  k_prep   applies coefficient tensors folded into an input (entry-wise
-//           scaling, Sec. 4.3's fusion of CTs into the QTs they join) and
+//           scaling: a coefficient vector on a cut index is a diagonal
+//           scaling of a QT carrying that index, absorbed at load time) and
 //           converts to the intermediate type.
 //  k_fprep  materialises the inputs of fused networks (layout change and
 //           coefficient scaling) into their workspaces.
 //  The fused whole-network kernel lives in fused.hpp / fused_b*.hip.
+#include <algorithm>
 #include <type_traits>
 
 #include "kern_common.hpp"
@@ -247,6 +249,39 @@ __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ ent
 // Device clock read into *dst (one thread).
 __global__ void k_stamp(int64_t *dst) {
     if (threadIdx.x == 0) *dst = (int64_t)wall_clock64();
+}
+
+// ------------------------------------------------------------- k_slice_sum
+
+// out[e] = sum over slices k (in order) of parts[k * n + e], accumulated in
+// FP64 (Neumaier-compensated when COMP), stored in the output type.
+template <typename T, bool COMP>
+__global__ __launch_bounds__(kBlk) void k_slice_sum(const T *__restrict__ parts, int n_slices, int64_t n,
+                                                    T *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlk + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlk) {
+        double s = 0.0, c = 0.0;
+        for (int k = 0; k < n_slices; ++k) accum<COMP>(s, c, (double)parts[(int64_t)k * n + e]);
+        out[e] = (T)(COMP ? s + c : s);
+    }
+}
+
+hipError_t launch_slice_sum(const void *parts, int n_slices, int64_t n, void *out, int tout, bool comp,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlk - 1) / kBlk, 8192);
+    const dim3 grid((unsigned)blocks), block(kBlk);
+    if (tout == 0 && comp)
+        hipLaunchKernelGGL((k_slice_sum<double, true>), grid, block, 0, st, (const double *)parts, n_slices, n,
+                           (double *)out);
+    else if (tout == 0)
+        hipLaunchKernelGGL((k_slice_sum<double, false>), grid, block, 0, st, (const double *)parts, n_slices, n,
+                           (double *)out);
+    else if (tout == 1)
+        hipLaunchKernelGGL((k_slice_sum<float, false>), grid, block, 0, st, (const float *)parts, n_slices, n,
+                           (float *)out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_stamp(int64_t *dst, hipStream_t st) {

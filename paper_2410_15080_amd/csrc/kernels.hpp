@@ -104,6 +104,11 @@ constexpr int kFPrepChunk = 4096;
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
                         hipStream_t st);
 
+// Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
+// in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.
+hipError_t launch_slice_sum(const void *parts, int n_slices, int64_t n, void *out, int tout, bool comp,
+                            hipStream_t st);
+
 // Writes the device's constant 100 MHz clock to *dst when the launch runs.
 hipError_t launch_stamp(int64_t *dst, hipStream_t st);
 

@@ -271,6 +271,7 @@ Net structure_copy(const Net &n) {
     t.allow_mfma = n.allow_mfma;
     t.path_samples = n.path_samples;
     t.path_seed = n.path_seed;
+    t.slice_mode = n.slice_mode;
     return t;
 }
 
@@ -1326,6 +1327,113 @@ static void json_ints(std::ostringstream &o, const std::vector<int> &v) {
     o << "[";
     for (size_t k = 0; k < v.size(); ++k) o << (k ? "," : "") << v[k];
     o << "]";
+}
+
+double path_peak(const Net &n, const std::vector<int64_t> &dims) {
+    const int N = n.n_t;
+    std::vector<int> ref(dims.size(), 0);
+    std::vector<char> is_out(dims.size(), 0);
+    for (int l : n.out_labels) is_out[l] = 1;
+    std::vector<std::vector<int>> lab(N + n.path.size());
+    for (int i = 0; i < N; ++i) {
+        lab[i] = n.labels[i];
+        std::sort(lab[i].begin(), lab[i].end());
+        for (int l : lab[i]) ref[l]++;
+    }
+    // inputs and inputs scaled by absorbed ones are loads, not intermediates
+    std::vector<char> input(N + n.path.size(), 0);
+    for (int i = 0; i < N; ++i) input[i] = 1;
+    double peak = 0.0;
+    for (size_t t = 0; t < n.path.size(); ++t) {
+        const int i = n.path[t].first, j = n.path[t].second;
+        const auto &a = lab[i], &b = lab[j];
+        std::vector<int> u = sorted_union(a, b), kept;
+        for (int l : a) ref[l]--;
+        for (int l : b) ref[l]--;
+        double sz = 1.0;
+        bool sums = false;
+        for (int l : u)
+            if (is_out[l] || ref[l] > 0) {
+                kept.push_back(l);
+                sz *= (double)dims[l];
+            } else if (dims[l] > 1) {
+                sums = true;
+            }
+        for (int l : kept) ref[l]++;
+        const bool absorption = input[i] && input[j] && !sums &&
+                                (std::includes(a.begin(), a.end(), b.begin(), b.end()) ||
+                                 std::includes(b.begin(), b.end(), a.begin(), a.end()));
+        input[N + t] = absorption;
+        if (!absorption) peak = std::max(peak, sz);
+        lab[N + t] = kept;
+    }
+    return peak;
+}
+
+std::vector<int64_t> sliced_dims(const Net &n) {
+    std::vector<int64_t> d = n.dims;
+    for (int l : n.sliced) d[l] = 1;
+    return d;
+}
+
+// Slicing (for a path whose largest intermediate exceeds the cap): fix
+// summed labels one at a time, each time the label that leaves the smallest
+// largest intermediate (fewer slices, then the lower id, on ties), until
+// the path fits.  Every slice is the network with those labels fixed; the
+// slices' results sum to the network's value.
+void plan_net(Net &n) {
+    if (!n.slice_mode || path_peak(n, n.dims) <= (double)n.max_intermediate) {
+        build_plan(n);
+        n.sliced.clear();
+        n.n_slices = 1;
+        return;
+    }
+    constexpr int64_t kMaxSlices = 65536;
+    std::vector<char> is_out(n.dims.size(), 0), used(n.dims.size(), 0);
+    for (int l : n.out_labels) is_out[l] = 1;
+    for (const auto &ls : n.labels)
+        for (int l : ls) used[l] = 1;
+    std::vector<int64_t> dims = n.dims;
+    std::vector<int> sliced;
+    int64_t slices = 1;
+    double peak = path_peak(n, dims);
+    while (peak > (double)n.max_intermediate) {
+        int best = -1;
+        double best_peak = 0.0;
+        for (int l = 0; l < (int)dims.size(); ++l) {
+            if (is_out[l] || !used[l] || dims[l] <= 1) continue;
+            if (slices * dims[l] > kMaxSlices) continue;
+            const int64_t keep = dims[l];
+            dims[l] = 1;
+            const double pk = path_peak(n, dims);
+            dims[l] = keep;
+            if (best < 0 || pk < best_peak || (pk == best_peak && dims[l] < dims[best])) {
+                best = l;
+                best_peak = pk;
+            }
+        }
+        if (best < 0 || best_peak >= peak)
+            throw make_err(HTN_E_OOM, "no slicing of at most " + std::to_string(kMaxSlices) +
+                                          " slices brings the largest intermediate under the cap " +
+                                          std::to_string(n.max_intermediate));
+        slices *= dims[best];
+        dims[best] = 1;
+        sliced.push_back(best);
+        peak = best_peak;
+    }
+    Net t = structure_copy(n);
+    t.dims = dims;
+    for (int i = 0; i < t.n_t; ++i) {
+        int64_t sz = 1;
+        for (int l : t.labels[i]) sz *= t.dims[l];
+        t.sizes[i] = sz;
+    }
+    t.path = n.path;
+    build_plan(t);
+    n.plan = std::move(t.plan);
+    n.sliced = sliced;
+    n.n_slices = slices;
+    n.plan_version++;
 }
 
 std::string plan_json(const Net &n) {

@@ -22,7 +22,7 @@ HTN_SUM_PLAIN, HTN_SUM_FP64, HTN_SUM_COMPENSATED = 0, 1, 2
 HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
 HTN_PATH_GREEDY, HTN_PATH_LEARNED, HTN_PATH_SAMPLED = -1, -2, -3
 HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
-HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS = 4, 5, 6
+HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS, HTN_OPT_SLICE = 4, 5, 6, 7
 HTN_MODEL_FEATURES, HTN_MODEL_HIDDEN = 26, 64
 
 STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
@@ -42,7 +42,7 @@ class htn_info(ctypes.Structure):
                 ("n_absorbed", ctypes.c_int32), ("fused_ok", ctypes.c_int32),
                 ("fused_lds_bytes", ctypes.c_int32), ("mults", ctypes.c_double),
                 ("peak_elements", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("input_bytes", ctypes.c_int64)]
+                ("input_bytes", ctypes.c_int64), ("n_slices", ctypes.c_int64)]
 
 
 HTN_TRUNC_MAX_RANK = 16
@@ -93,6 +93,7 @@ def load_library():
         "htn_get_path": (I32, [P, i32p, i32p, I32, ctypes.POINTER(ctypes.c_double)]),
         "htn_set_option": (I32, [P, I32, I64]),
         "htn_get_info": (I32, [P, ctypes.POINTER(htn_info)]),
+        "htn_get_slicing": (I32, [P, i32p, i32p, I32, i64p]),
         "htn_contract": (I32, [P, P, P]),
         "htn_contract_noalloc": (I32, [P, P, P]),
         "htn_contract_batch": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P]),
@@ -310,6 +311,17 @@ def htn_get_info(net: Net) -> htn_info:
     info = htn_info()
     _check(load_library().htn_get_info(net.handle, ctypes.byref(info)))
     return info
+
+
+def htn_get_slicing(net: Net):
+    """(sliced labels, number of slices) of the current plan."""
+    lib = load_library()
+    n = ctypes.c_int32()
+    s = ctypes.c_int64()
+    buf = np.zeros(64, dtype=np.int32)
+    _check(lib.htn_get_slicing(net.handle, ctypes.byref(n), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 64,
+                               ctypes.byref(s)))
+    return [int(x) for x in buf[: n.value]], int(s.value)
 
 
 def htn_contract(net: Net, out, stream=None) -> None:

@@ -412,3 +412,83 @@ def test_failed_graph_capture_falls_back_to_stream_launches():
             y = x * 2
         stream.synchronize()
         assert float(y.sum()) == 8.0
+
+
+def _sliced(w, div, compute=htn.HTN_F64, final_sum=htn.HTN_SUM_PLAIN):
+    net = create(w, compute=compute, final_sum=final_sum, storage=htn.HTN_F64)
+    peak = htn.htn_get_info(net).peak_elements
+    cap = max(1, int(peak // div))
+    htn.htn_set_option(net, htn.HTN_OPT_SLICE, 1)
+    htn.htn_set_option(net, htn.HTN_OPT_MAX_INTERMEDIATE, cap)
+    info = htn.htn_get_info(net)
+    labels, n_slices = htn.htn_get_slicing(net)
+    assert n_slices > 1 and labels and info.n_slices == n_slices and info.peak_elements <= cap
+    return net, labels
+
+
+@pytest.mark.parametrize("compute,final_sum", [(htn.HTN_F64, htn.HTN_SUM_PLAIN),
+                                               (htn.HTN_F64, htn.HTN_SUM_COMPENSATED),
+                                               (htn.HTN_F32, htn.HTN_SUM_FP64)])
+def test_sliced_contraction_matches_oracle(compute, final_sum):
+    """Nets whose path exceeds an intermediate cap: the library slices summed
+    labels until the path fits, contracts every slice (one batch) and sums
+    them in FP64.  FP64 within 1e-10 relative of the oracle (scalars) or
+    1e-14 absolute (marginal entries); FP32 within gamma(300, 2^-24) times
+    the |entries| contraction.  The oracle's own slice sum over the same
+    labels equals the unsliced value."""
+    import torch
+    cases = [(configs.grid_network(3), 20), (configs.ring_of_rings(0), 3),
+             (configs.marginal_network(1, out_bits=4), 16)]
+    for w, div in cases:
+        net, labels = _sliced(w, div, compute, final_sum)
+        shape = tuple(w.dims[l] for l in w.out_labels)
+        got = contract(net, shape)
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = hi + lo
+        if compute == htn.HTN_F64:
+            if shape:
+                assert np.abs(got - ref).max() <= 1e-14, labels
+            else:
+                assert abs(float(got) - float(ref)) <= REL_F64 * abs(float(ref)), (labels, float(got), float(ref))
+        else:
+            ahi, alo = oracle.ve_contract([np.abs(t) for t in w.tensors], w.labels, w.dims, w.out_labels)
+            u = 2.0 ** -24
+            assert np.all(np.abs(got - ref) <= (300 * u / (1 - 300 * u)) * (ahi + alo)), labels
+        if compute == htn.HTN_F64 and final_sum == htn.HTN_SUM_PLAIN and len(labels) <= 3:
+            sl = oracle.sliced_contract(w.tensors, w.labels, w.dims, w.out_labels, labels)
+            assert np.abs(sl - ref).max() <= 1e-13 * max(1.0, float(np.abs(ref).max()))
+
+
+def test_sliced_net_is_refused_by_batches_and_noalloc_but_contracts_again():
+    import torch
+    w = configs.grid_network(8)
+    net, _ = _sliced(w, 10)
+    with pytest.raises(htn.HtnError) as e:
+        htn.htn_batch_create([net])
+    assert e.value.name == "HTN_E_UNSUPPORTED"
+    out = htn.new_output(net)
+    htn.htn_contract(net, out)
+    torch.cuda.synchronize()
+    with pytest.raises(htn.HtnError) as e:
+        htn.htn_contract_noalloc(net, out)
+    assert e.value.name == "HTN_E_UNSUPPORTED"
+    a = float(out.item())
+    # new data, same structure: the slices are cut again from the new inputs
+    w2 = configs.grid_network(8)
+    w2.tensors = [t * 2.0 if k == 0 else t for k, t in enumerate(w2.tensors)]
+    htn.htn_update_data(net, [torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in w2.tensors])
+    htn.htn_contract(net, out)
+    torch.cuda.synchronize()
+    assert abs(float(out.item()) - 2.0 * a) <= 1e-13 * abs(a)
+    # slicing off while the cap still binds is refused (and changes nothing)
+    with pytest.raises(htn.HtnError) as e:
+        htn.htn_set_option(net, htn.HTN_OPT_SLICE, 0)
+    assert e.value.name == "HTN_E_OOM"
+    assert htn.htn_get_slicing(net)[1] > 1
+    # lift the cap (the path then fits: no slices), then slicing off
+    htn.htn_set_option(net, htn.HTN_OPT_MAX_INTERMEDIATE, 2 ** 31 - 1)
+    htn.htn_set_option(net, htn.HTN_OPT_SLICE, 0)
+    assert htn.htn_get_slicing(net) == ([], 1)
+    htn.htn_contract(net, out)
+    torch.cuda.synchronize()
+    assert abs(float(out.item()) - 2.0 * a) <= 1e-13 * abs(a)

@@ -290,3 +290,23 @@ def test_worked_example_costs():
     n_c = nv["gate_terms"] ** nv["n_gate_cuts"] * nv["wire_terms"] ** nv["n_wire_cuts"]
     assert n_c == nv["expected_C"]
     assert oracle.naive_pp_cost(n_c, nv["s"], nv["n_g"]) == nv["expected_cost"]
+
+
+def test_slices_sum_to_the_network():
+    """Fixing summed labels to each of their values and adding the slices
+    gives the network's value (for scalars and open outputs)."""
+    import itertools
+    rng = np.random.default_rng(17)
+    w = configs.grid_network(6, rows=2, cols=3)
+    hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+    for sliced in ([0], [0, 4], [1, 2, 6]):
+        got = oracle.sliced_contract(w.tensors, w.labels, w.dims, w.out_labels, sliced)
+        assert abs(float(got) - (float(hi) + float(lo))) <= 1e-15 * max(1.0, abs(float(hi)))
+    m = configs.marginal_network(2, out_bits=3, n_cuts=2)
+    ref = oracle.naive_contract(m.tensors, m.labels, m.dims, m.out_labels)[0]
+    got = oracle.sliced_contract(m.tensors, m.labels, m.dims, m.out_labels, [0, 3])
+    assert np.abs(got - ref).max() <= 1e-15
+    # a single slice is a slice: fixing a label of a two-tensor product
+    a, b = rng.uniform(-1, 1, (3, 4)), rng.uniform(-1, 1, (4, 5))
+    got = oracle.sliced_contract([a, b], [[0, 1], [1, 2]], [3, 4, 5], [0, 2], [1])
+    assert np.abs(got - a @ b).max() <= 1e-14
