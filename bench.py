@@ -874,8 +874,7 @@ def sub_args(args, **kw):
     return a
 
 
-NESTED = (("circuit10", "circuit", {}),
-          ("marginal_f64", "marginal", {"dtype": "f64"}),
+NESTED = (("marginal_f64", "marginal", {"dtype": "f64"}),
           ("marginal_f32", "marginal", {"dtype": "f32"}),
           ("marginal_bf16", "marginal", {"dtype": "bf16"}),
           ("ring_f64", "ring", {"dtype": "f64"}),

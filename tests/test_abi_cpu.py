@@ -14,6 +14,8 @@ import oracle
 from paper_2410_15080_amd import htn
 from workloads import configs
 
+import circuit_nets
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -74,7 +76,7 @@ def test_planner_cost_matches_oracle_cost_model(maker):
         elif maker == "ring":
             w = configs.ring_of_rings(seed)
         else:
-            w, _ = configs.circuit_cut_gates(seed, 2)
+            w, _ = circuit_nets.cut_gates(seed, 2)
         net = _host_net(w)
         path, m = htn.htn_get_path(net)
         assert m == sum(oracle.path_cost(w.labels, w.dims, w.out_labels, path))

@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2410_15080_amd import htn
 from workloads import configs
-from workloads import statevector as sv
+import circuit_nets
 
 from gpu_helpers import create, contract, rel_err, run
 
@@ -25,10 +25,10 @@ REL_F64 = 1e-10
 @pytest.mark.parametrize("exec_mode", EXECS)
 def test_wire_cut_circuit_matches_oracle_and_statevector(exec_mode):
     for seed in range(3):
-        w = configs.circuit_cut_wires(seed)
+        w = circuit_nets.cut_wires(seed)
         got = float(run(w, exec_mode=exec_mode))
         ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
-        full = sv.run_ops(sv.zero_state(10), configs.circuit1_full_ops(seed), {q: "Z" for q in range(10)})
+        full = circuit_nets.cut_wires_full(seed)
         assert abs(got - float(ref)) <= REL_F64 * abs(float(ref))
         assert abs(got - full) < 1e-14
 
@@ -39,11 +39,10 @@ def test_gate_cut_circuits(exec_mode, gate):
     # CZ, parametric RZZ(theta) and CX gate cuts: oracle and uncut statevector
     for seed in (1, 2):
         for n_cuts in (1, 2):
-            w, full_ops = configs.circuit_cut_gates(seed, n_cuts, gate=gate)
+            w, full = circuit_nets.cut_gates(seed, n_cuts, gate=gate)
             got = float(run(w, exec_mode=exec_mode))
             ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)
             assert abs(got - float(ref)) <= 1e-13
-            full = sv.run_ops(sv.zero_state(4), full_ops, {q: "Z" for q in range(4)})
             assert abs(got - full) <= 1e-13
 
 

@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 from workloads import configs, qpd
-from workloads import statevector as sv
+from oracle import statevector as sv
+import circuit_nets
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -111,8 +112,8 @@ def test_cx_gate_cut_channel_identity():
 
 @pytest.mark.parametrize("seed", range(4))
 def test_naive_equals_uncut_statevector_wire_cuts(seed):
-    net = configs.circuit_cut_wires(seed)
-    full = sv.run_ops(sv.zero_state(10), configs.circuit1_full_ops(seed), {q: "Z" for q in range(10)})
+    net = circuit_nets.cut_wires(seed)
+    full = circuit_nets.cut_wires_full(seed)
     got, n_terms = oracle.naive_contract(net.tensors, net.labels, net.dims, net.out_labels)
     assert n_terms == 16
     assert abs(float(got) - full) < 1e-14
@@ -124,8 +125,7 @@ def test_naive_equals_uncut_statevector_wire_cuts(seed):
 @pytest.mark.parametrize("n_cuts", [1, 2])
 def test_naive_equals_uncut_statevector_gate_cuts(n_cuts, gate):
     for seed in range(3):
-        net, full_ops = configs.circuit_cut_gates(seed, n_cuts, gate=gate)
-        full = sv.run_ops(sv.zero_state(4), full_ops, {q: "Z" for q in range(4)})
+        net, full = circuit_nets.cut_gates(seed, n_cuts, gate=gate)
         got, _ = oracle.naive_contract(net.tensors, net.labels, net.dims, net.out_labels)
         assert abs(float(got) - full) < 1e-14
 
@@ -187,7 +187,7 @@ def test_ve_rank1_closed_form_full_size(maker):
 
 def test_naive_rank1_closed_form():
     rng = np.random.default_rng(6)
-    net, _ = configs.circuit_cut_gates(0, 2)
+    net, _ = circuit_nets.cut_gates(0, 2)
     tensors, ref = _rank1_network(rng, net)
     got, _ = oracle.naive_contract(tensors, net.labels, net.dims, [])
     assert abs(float(got) - ref) <= 1e-14 * max(1.0, abs(ref))
@@ -310,3 +310,53 @@ def test_slices_sum_to_the_network():
     a, b = rng.uniform(-1, 1, (3, 4)), rng.uniform(-1, 1, (4, 5))
     got = oracle.sliced_contract([a, b], [[0, 1], [1, 2]], [3, 4, 5], [0, 2], [1])
     assert np.abs(got - a @ b).max() <= 1e-14
+
+
+# ------------------------------------------ the oracle's QT evaluator
+
+def test_instance_outputs_on_textbook_states():
+    """Single-qubit eigenstates, a Bell pair and a GHZ state: expectation
+    values and marginals known in closed form."""
+    from workloads import circuits as c
+    st = c.STATES
+    for prep, (ex, ey, ez) in {"0": (0, 0, 1), "1": (0, 0, -1), "+": (1, 0, 0), "-": (-1, 0, 0),
+                               "+i": (0, 1, 0), "-i": (0, -1, 0)}.items():
+        for p, e in zip("XYZ", (ex, ey, ez)):
+            out = sv.instance_outputs(c.Instance(1, [st[prep]], [], p))
+            assert abs(out[0] - e) < 1e-15, (prep, p)
+    bell = [("u", 0, c.H), ("cx", 0, 1)]
+    for obs, e in (("ZZ", 1), ("XX", 1), ("YY", -1), ("ZI", 0), ("XZ", 0)):
+        out = sv.instance_outputs(c.Instance(2, [st["0"], st["0"]], bell, obs))
+        assert abs(out[0] - e) < 1e-15, obs
+    ghz = [("u", 0, c.H), ("cx", 0, 1), ("cx", 1, 2)]
+    out = sv.instance_outputs(c.Instance(3, [st["0"]] * 3, ghz, "III", kept=[0, 1, 2]))
+    assert np.allclose(out, [0.5, 0, 0, 0, 0, 0, 0, 0.5], atol=1e-15)
+    # kept order: x row-major over the kept list, first slowest
+    out = sv.instance_outputs(c.Instance(2, [st["0"], st["1"]], [], "II", kept=[1, 0]))
+    assert np.allclose(out, [0, 0, 1, 0])
+    # a projection keeps the branch's weight; with Z on that qubit the sign
+    proj = [("u", 0, c.H), ("proj", 0, 1)]
+    assert abs(sv.instance_outputs(c.Instance(1, [st["0"]], proj, "I"))[0] - 0.5) < 1e-15
+    assert abs(sv.instance_outputs(c.Instance(1, [st["0"]], proj, "Z"))[0] + 0.5) < 1e-15
+    # RZZ(theta) on |++>: <X I> = cos(theta) (X I anticommutes with Z Z),
+    # <X X> = 1 (it commutes)
+    th = 0.7
+    out = sv.instance_outputs(c.Instance(2, [st["+"], st["+"]], [("rzz", 0, 1, th)], "XI"))
+    assert abs(out[0] - np.cos(th)) < 1e-15
+    out = sv.instance_outputs(c.Instance(2, [st["+"], st["+"]], [("rzz", 0, 1, th)], "XX"))
+    assert abs(out[0] - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cut_marginal_equals_the_uncut_distribution(seed):
+    """The marginal of a circuit cut by two or three wire cuts, rebuilt from
+    its two QTs (Pauli-basis measurements and signed preparations), equals
+    the uncut circuit's output distribution over the kept qubits."""
+    from workloads import circuits as c
+    for kw in ({}, {"n_left": 7, "n_right": 6, "n_cuts": 3, "kept_left": 2, "kept_right": 4}):
+        cn = c.cut_marginal(seed, **kw)
+        net = sv.network(cn)
+        got, _ = oracle.naive_contract(net.tensors, net.labels, net.dims, net.out_labels)
+        full = sv.full_value(cn)
+        assert np.abs(got.reshape(-1) - full).max() < 1e-14
+        assert abs(full.sum() - 1.0) < 1e-13

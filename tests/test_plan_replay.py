@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_2410_15080_amd import htn
+import circuit_nets
 from plan_emulator import replay
 from workloads import configs
 from workloads.network import Network
@@ -111,8 +112,8 @@ def test_replay_small_lds_budgets_spill():
 def test_replay_ring_and_marginal_and_circuits():
     _check(configs.ring_of_rings(0))
     _check(configs.marginal_network(0, out_bits=7))
-    _check(configs.circuit_cut_wires(0))
-    _check(configs.circuit_cut_gates(0, 2)[0])
+    _check(circuit_nets.cut_wires(0))
+    _check(circuit_nets.cut_gates(0, 2)[0])
 
 
 def test_replay_random_batch_networks():

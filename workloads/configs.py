@@ -6,15 +6,15 @@ most 15 qubits (Sec. 7.1) with 2-10 cuts (Sec. 7.2), six-term gate cuts
 (Sec. 2.1) and four-dimensional wire-cut indices (Sec. 4.1).  None of the
 paper's benchmark circuits are reproduced; these are synthetic stand-ins.
 
-  circuit_cut_wires   10-qubit brick circuit cut by 2 wire cuts into 3
-                      subcircuits, QTs evaluated exactly by statevector.
-  circuit_cut_gates   4-qubit circuit with 1 or 2 CZ gate cuts.
   grid_network        16 QTs on a 4x4 grid, each edge a wire (dim 4) or a
                       CZ gate cut (dim 6), entries U[-1,1].
   marginal_network    two QTs [4^c, 2^b] joined through c CutQC wire
                       tensors; result is a 2^b x 2^b marginal.
   ring_of_rings       8 rings x 8 QTs, 3-6 cut indices per QT.
   random_batch        many small random networks of uneven size.
+
+The circuit workloads (subcircuit instances whose results form the QTs)
+are in workloads.circuits.
 """
 
 from __future__ import annotations
@@ -22,188 +22,9 @@ from __future__ import annotations
 import numpy as np
 
 from . import qpd
-from . import statevector as sv
 from .network import Network
 
 
-# --------------------------------------------------------------------------
-# 10-qubit circuit, two wire cuts, three subcircuits
-# --------------------------------------------------------------------------
-
-N_Q1 = 10
-N_LAYERS1 = 4
-
-
-def _block_c1(q: int, layer: int) -> int:
-    """Subcircuit that owns qubit q during layer `layer` (cut after layer 1)."""
-    if q <= 3:
-        return 1
-    if q == 4:
-        return 1 if layer < 2 else 2
-    if q in (5, 6):
-        return 2
-    if q == 7:
-        return 2 if layer < 2 else 3
-    return 3
-
-
-def circuit1_gates(seed: int):
-    """Gate list [(layer, op)] of the 10-qubit brick circuit.
-
-    Layers 0..3: Rz(a) then Ry(b) on every qubit, then CZ on brick pairs
-    (a, a+1), a = layer mod 2, kept only when both qubits belong to the same
-    subcircuit at that layer.  Layer 4: a final Rz, Ry layer.  Angles are
-    i.i.d. U[0, 2pi) in the order (layer, qubit, {z, y}).
-    """
-    rng = np.random.default_rng(seed)
-    ang = rng.uniform(0.0, 2.0 * np.pi, size=(N_LAYERS1 + 1, N_Q1, 2))
-    gates = []
-    for layer in range(N_LAYERS1 + 1):
-        for q in range(N_Q1):
-            gates.append((layer, ("u", q, sv.rz(ang[layer, q, 0]))))
-            gates.append((layer, ("u", q, sv.ry(ang[layer, q, 1]))))
-        if layer < N_LAYERS1:
-            for a in range(layer % 2, N_Q1 - 1, 2):
-                if _block_c1(a, layer) == _block_c1(a + 1, layer):
-                    gates.append((layer, ("cz", a, a + 1)))
-    return gates
-
-
-def _sub_ops(gates, block, qmap):
-    ops = []
-    for layer, op in gates:
-        qs = [op[1]] if op[0] == "u" else [op[1], op[2]]
-        if all(_block_c1(q, layer) == block for q in qs):
-            if op[0] == "u":
-                ops.append(("u", qmap[op[1]], op[2]))
-            else:
-                ops.append(("cz", qmap[op[1]], qmap[op[2]]))
-    return ops
-
-
-def circuit1_full_ops(seed: int):
-    """Ops of the uncut 10-qubit circuit (same gates as the cut version)."""
-    return [op for _, op in circuit1_gates(seed)]
-
-
-def circuit_cut_wires(seed: int) -> Network:
-    """Config: 10-qubit circuit, 2 wire cuts (q4, q7 after layer 1), 3 QTs.
-
-    QT1[a]    = <Z^4 (x) P_a>   on S1 = {q0..q4}, q4 measured in Pauli a.
-    QT2[a, b] = sum_prep sign * <Z^3 (x) P_b> on S2 = {q4', q5, q6, q7},
-                q4' prepared per Pauli a, q7 measured in Pauli b.
-    QT3[b]    = sum_prep sign * <Z^3> on S3 = {q7', q8, q9}.
-    CTs: the Pauli-basis weights (1/2,1/2,1/2,1/2) on labels a and b.
-    The target is <Z^(x)10> of the uncut circuit.
-    """
-    gates = circuit1_gates(seed)
-    P = qpd.PAULI_ORDER
-    # S1: global q0..q4 -> local 0..4
-    ops1 = _sub_ops(gates, 1, {q: q for q in range(5)})
-    qt1 = np.array([sv.run_ops(sv.zero_state(5), ops1, {0: "Z", 1: "Z", 2: "Z", 3: "Z", 4: p})
-                    for p in P])
-    # S2: q4 -> 0, q5 -> 1, q6 -> 2, q7 -> 3
-    ops2 = _sub_ops(gates, 2, {4: 0, 5: 1, 6: 2, 7: 3})
-    qt2 = np.zeros((4, 4))
-    for ia, pa in enumerate(P):
-        for prep, sgn in qpd.PAULI_AS_PREPS[pa]:
-            init = sv.product_state([sv.STATES[prep], sv.STATES["0"], sv.STATES["0"], sv.STATES["0"]])
-            for ib, pb in enumerate(P):
-                qt2[ia, ib] += sgn * sv.run_ops(init, ops2, {0: "Z", 1: "Z", 2: "Z", 3: pb})
-    # S3: q7 -> 0, q8 -> 1, q9 -> 2
-    ops3 = _sub_ops(gates, 3, {7: 0, 8: 1, 9: 2})
-    qt3 = np.zeros(4)
-    for ib, pb in enumerate(P):
-        for prep, sgn in qpd.PAULI_AS_PREPS[pb]:
-            init = sv.product_state([sv.STATES[prep], sv.STATES["0"], sv.STATES["0"]])
-            qt3[ib] += sgn * sv.run_ops(init, ops3, {0: "Z", 1: "Z", 2: "Z"})
-    tensors = [qt1, qt2, qt3, qpd.WIRE_PAULI.copy(), qpd.WIRE_PAULI.copy()]
-    labels = [[0], [0, 1], [1], [0], [1]]
-    return Network(tensors, labels, [4, 4], [], ["qt", "qt", "qt", "ct", "ct"],
-                   {"config": "circuit_cut_wires", "seed": seed})
-
-
-# --------------------------------------------------------------------------
-# 4-qubit circuit with CZ gate cuts
-# --------------------------------------------------------------------------
-
-_INST_U = {"S": sv.S, "Sdg": sv.SDG, "Z": sv.Z, "I": sv.I2}
-
-
-def circuit_cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz"):
-    """4-qubit circuit, halves {q0,q1} | {q2,q3}, crossing gate on (q1,q2) cut.
-
-    Returns (network, full_ops).  Each layer: Rz, Ry on every qubit, CZ(0,1),
-    CZ(2,3); the crossing gate follows layers 0..n_cuts-1 and is cut: CZ,
-    with gate="rzz" a ZZ rotation RZZ(theta) whose angle per cut is drawn
-    U[-pi, pi) after the layer angles, or with gate="cx" a CX (control q1,
-    target q2): CX = (I (x) H) CZ (I (x) H), so its cut is the CZ cut with
-    each target-side instance operation conjugated by H.
-    """
-    rng = np.random.default_rng(seed)
-    ang = rng.uniform(0.0, 2.0 * np.pi, size=(n_layers, 4, 2))
-    thetas = rng.uniform(-np.pi, np.pi, size=n_cuts) if gate == "rzz" else None
-    instances = qpd.RZZ_INSTANCES if gate == "rzz" else qpd.CZ_INSTANCES
-    layers = []
-    for layer in range(n_layers):
-        ops = []
-        for q in range(4):
-            ops.append(("u", q, sv.rz(ang[layer, q, 0])))
-            ops.append(("u", q, sv.ry(ang[layer, q, 1])))
-        ops.append(("cz", 0, 1))
-        ops.append(("cz", 2, 3))
-        layers.append(ops)
-    full = []
-    for layer in range(n_layers):
-        full += layers[layer]
-        if layer < n_cuts:
-            full.append({"rzz": ("rzz", 1, 2, thetas[layer] if thetas is not None else 0.0),
-                         "cx": ("cx", 1, 2)}.get(gate, ("cz", 1, 2)))
-
-    def half_ops(side, insts):
-        # side 0: global {0,1} -> local {0,1}, cut qubit local 1
-        # side 1: global {2,3} -> local {0,1}, cut qubit local 0
-        keep = (0, 1) if side == 0 else (2, 3)
-        cutq = 1 if side == 0 else 0
-        out = []
-        for layer in range(n_layers):
-            for op in layers[layer]:
-                qs = [op[1]] if op[0] == "u" else [op[1], op[2]]
-                if all(q in keep for q in qs):
-                    if op[0] == "u":
-                        out.append(("u", op[1] - keep[0], op[2]))
-                    else:
-                        out.append(("cz", op[1] - keep[0], op[2] - keep[0]))
-            if layer < n_cuts:
-                name = instances[insts[layer]][side]
-                conj = gate == "cx" and side == 1  # the CX target's side
-                if conj:
-                    out.append(("u", cutq, sv.H))
-                if name == "MZ":
-                    out.append(("mz", cutq))
-                else:
-                    out.append(("u", cutq, _INST_U[name]))
-                if conj:
-                    out.append(("u", cutq, sv.H))
-        return out
-
-    shape = (6,) * n_cuts
-    left = np.zeros(shape)
-    right = np.zeros(shape)
-    for idx in np.ndindex(*shape):
-        left[idx] = sv.run_ops(sv.zero_state(2), half_ops(0, idx), {0: "Z", 1: "Z"})
-        right[idx] = sv.run_ops(sv.zero_state(2), half_ops(1, idx), {0: "Z", 1: "Z"})
-    cut_labels = list(range(n_cuts))
-    coeffs = [qpd.rzz_coeffs(t) for t in thetas] if gate == "rzz" else [qpd.CZ_COEFFS.copy()] * n_cuts
-    tensors = [left, right] + [np.array(c) for c in coeffs]
-    labels = [cut_labels, cut_labels] + [[l] for l in cut_labels]
-    net = Network(tensors, labels, [6] * n_cuts, [], ["qt", "qt"] + ["ct"] * n_cuts,
-                  {"config": "circuit_cut_gates", "seed": seed, "n_cuts": n_cuts, "gate": gate})
-    return net, full
-
-
-# --------------------------------------------------------------------------
-# Synthetic networks
 # --------------------------------------------------------------------------
 
 def _coeff(dim: int) -> np.ndarray:
