@@ -596,6 +596,70 @@ typedef struct {
 } htn_gather;
 htn_status htn_gather_create(htn_trunc_t *out, int32_t n, const htn_gather *items, htn_dtype dtype);
 
+/* ---------------------------------------------------------------------
+ * QT evaluator (Sec. 6.2; Step 2 of Sec. 6.1): exact statevector
+ * simulation of subcircuit instances on the GPU, and the assembly of
+ * quantum-tensor entries from their results.  A QT entry is a signed
+ * combination of instance results (one instance per QPD term of the cuts
+ * it touches; a signed mid-circuit Z measurement is two instances, one per
+ * projection, entering with signs +1 and -1; a Pauli operator injected at a
+ * cut is the signed sum of two eigenstate preparations).
+ *
+ * An instance: n_qubits (1..HTN_SV_MAX_QUBITS) in a product state
+ * (init[4q..4q+3] = re, im of <0|q>, re, im of <1|q>, host FP64), then
+ * n_ops ops in order, then the measurement of a Pauli observable
+ * (observable[q] in 'I', 'X', 'Y', 'Z') with the kept qubits kept[0..n_kept)
+ * (observable 'I' there) read out in the computational basis:
+ *     out[x] = Re <psi| O (x) |x><x|_kept |psi>,  x < 2^n_kept,
+ * x row-major over the kept qubits (kept[0] slowest), every other qubit
+ * summed.  Ops (htn_sv_op):
+ *   HTN_SV_U1    q0: 2x2 unitary m = (re, im) of u00, u01, u10, u11
+ *   HTN_SV_CZ    q0, q1 (distinct)
+ *   HTN_SV_CX    control q0, target q1
+ *   HTN_SV_RZZ   exp(-i m[0]/2 Z_q0 Z_q1)
+ *   HTN_SV_PROJ  projection of q0 onto |q1> (q1 = 0 or 1), unnormalised
+ * Instance outputs are numbered consecutively (instance 0's first).
+ * Assembly: entry e = sum over t in [entry_start[e], entry_start[e+1]) of
+ * term_coef[t] * output[term_output[t]], in that order, in FP64.
+ * States of up to 12 qubits are simulated in LDS, larger ones (up to 24) in
+ * device memory owned by the handle.
+ *
+ * htn_qt_eval_create — validate and upload (synchronous).  Host arrays are
+ *   copied.  Errors: HTN_E_ARG (qubit counts, NULL data, observable
+ *   letters, kept qubits out of range, repeated or not 'I', op kinds and
+ *   qubits, projection bits, entry_start not starting at 0 or decreasing,
+ *   term outputs out of range), HTN_E_OOM, HTN_E_DEVICE.
+ * htn_qt_eval_run — enqueue on hip_stream: the instances (one launch, one
+ *   workgroup each) and the assembly (one launch) into entries (device,
+ *   n_entries FP64 values).  outputs (device, n_outputs FP64 values) may be
+ *   NULL; otherwise the raw instance outputs are written there.
+ * htn_qt_eval_info — the handle's output and entry counts.
+ * ------------------------------------------------------------------- */
+#define HTN_SV_MAX_QUBITS 24
+typedef enum { HTN_SV_U1 = 0, HTN_SV_CZ = 1, HTN_SV_CX = 2, HTN_SV_RZZ = 3, HTN_SV_PROJ = 4 } htn_sv_kind;
+typedef struct {
+    int32_t kind;
+    int32_t q0, q1;
+    int32_t pad;
+    double m[8];
+} htn_sv_op;
+typedef struct {
+    int32_t n_qubits;
+    const double *init;
+    int32_t n_ops;
+    const htn_sv_op *ops;
+    const char *observable;
+    int32_t n_kept;
+    const int32_t *kept;
+} htn_sv_instance;
+typedef struct htn_qteval *htn_qteval_t;
+htn_status htn_qt_eval_create(htn_qteval_t *out, int32_t n_instances, const htn_sv_instance *instances,
+                              int64_t n_entries, const int64_t *entry_start, const int64_t *term_output,
+                              const double *term_coef);
+htn_status htn_qt_eval_run(htn_qteval_t q, double *entries, double *outputs, void *hip_stream);
+htn_status htn_qt_eval_info(htn_qteval_t q, int64_t *n_outputs, int64_t *n_entries);
+void htn_qt_eval_destroy(htn_qteval_t q);
+
 #ifdef __cplusplus
 }
 #endif

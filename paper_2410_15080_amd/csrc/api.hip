@@ -2061,3 +2061,161 @@ static void run_sliced(Net &n, void *out, hipStream_t st) {
     HIP_TRY(kern::launch_slice_sum(r.parts, (int)n.n_slices, out_elems, out, out_dtype(n) == HTN_F64 ? 0 : 1,
                                    n.final_sum == HTN_SUM_COMPENSATED, st));
 }
+
+// ---------------------------------------------------------------------------
+// QT evaluator (Sec. 6.2)
+// ---------------------------------------------------------------------------
+
+struct htn_qteval {
+    int n_inst = 0;
+    int64_t n_outputs = 0, n_entries = 0;
+    kern::SvInst *d_insts = nullptr;
+    kern::SvOp *d_ops = nullptr;
+    double2 *d_state = nullptr;
+    double *d_outs = nullptr;
+    int64_t *d_start = nullptr, *d_term = nullptr;
+    double *d_coef = nullptr;
+    ~htn_qteval() {
+        dfree(d_insts);
+        dfree(d_ops);
+        dfree(d_state);
+        dfree(d_outs);
+        dfree(d_start);
+        dfree(d_term);
+        dfree(d_coef);
+    }
+};
+
+extern "C" {
+
+htn_status htn_qt_eval_create(htn_qteval_t *out, int32_t n_instances, const htn_sv_instance *instances,
+                              int64_t n_entries, const int64_t *entry_start, const int64_t *term_output,
+                              const double *term_coef) {
+    API_GUARD_BEGIN
+    if (!out) return fail(HTN_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_instances < 1 || !instances) return fail(HTN_E_ARG, "bad instance list");
+    if (n_entries < 0 || (n_entries > 0 && !entry_start)) return fail(HTN_E_ARG, "bad entry list");
+    std::vector<kern::SvInst> hi((size_t)n_instances);
+    std::vector<kern::SvOp> hops;
+    int64_t n_out = 0, n_state = 0;
+    for (int i = 0; i < n_instances; ++i) {
+        const htn_sv_instance &x = instances[i];
+        const std::string it = "instance " + std::to_string(i) + ": ";
+        if (x.n_qubits < 1 || x.n_qubits > HTN_SV_MAX_QUBITS) return fail(HTN_E_ARG, it + "bad qubit count");
+        if (!x.init || !x.observable || (x.n_ops > 0 && !x.ops) || x.n_ops < 0) return fail(HTN_E_ARG, it + "NULL data");
+        if (x.n_kept < 0 || x.n_kept > x.n_qubits || (x.n_kept > 0 && !x.kept)) return fail(HTN_E_ARG, it + "bad kept list");
+        kern::SvInst &k = hi[(size_t)i];
+        std::memset(&k, 0, sizeof(k));
+        const int n = x.n_qubits;
+        k.n = n;
+        k.n_ops = x.n_ops;
+        k.n_kept = x.n_kept;
+        k.op_off = (int64_t)hops.size();
+        k.out_off = n_out;
+        for (int q = 0; q < n; ++q) {
+            for (int c = 0; c < 4; ++c) k.init[q][c] = x.init[4 * q + c];
+            const int64_t bit = int64_t(1) << (n - 1 - q);
+            switch (x.observable[q]) {
+                case 'I': break;
+                case 'X': k.xmask |= bit; break;
+                case 'Y': k.xmask |= bit; k.zymask |= bit; ++k.n_y; break;
+                case 'Z': k.zymask |= bit; break;
+                default: return fail(HTN_E_ARG, it + "observable must be I, X, Y or Z per qubit");
+            }
+        }
+        for (int j = 0; j < x.n_kept; ++j) {
+            const int q = x.kept[j];
+            if (q < 0 || q >= n || x.observable[q] != 'I') return fail(HTN_E_ARG, it + "kept qubit out of range or not I");
+            for (int j2 = 0; j2 < j; ++j2)
+                if (x.kept[j2] == q) return fail(HTN_E_ARG, it + "kept qubit repeated");
+            k.kept[j] = q;
+        }
+        for (int j = 0; j < x.n_ops; ++j) {
+            const htn_sv_op &o = x.ops[j];
+            const bool two = o.kind == HTN_SV_CZ || o.kind == HTN_SV_CX || o.kind == HTN_SV_RZZ;
+            if (o.kind < HTN_SV_U1 || o.kind > HTN_SV_PROJ) return fail(HTN_E_ARG, it + "bad op kind");
+            if (o.q0 < 0 || o.q0 >= n) return fail(HTN_E_ARG, it + "op qubit out of range");
+            if (two && (o.q1 < 0 || o.q1 >= n || o.q1 == o.q0)) return fail(HTN_E_ARG, it + "bad second qubit");
+            if (o.kind == HTN_SV_PROJ && o.q1 != 0 && o.q1 != 1) return fail(HTN_E_ARG, it + "projection bit not 0/1");
+            kern::SvOp d;
+            d.kind = o.kind;
+            d.q0 = o.q0;
+            d.q1 = o.q1;
+            d.pad = 0;
+            for (int c = 0; c < 8; ++c) d.m[c] = o.m[c];
+            hops.push_back(d);
+        }
+        n_out += int64_t(1) << x.n_kept;
+        if (n > kern::kSvLdsQubits) {
+            k.state_off = n_state;
+            n_state += int64_t(1) << n;
+        } else {
+            k.state_off = -1;
+        }
+    }
+    if (n_entries > 0) {
+        if (entry_start[0] != 0) return fail(HTN_E_ARG, "entry_start[0] must be 0");
+        for (int64_t e = 0; e < n_entries; ++e)
+            if (entry_start[e + 1] < entry_start[e]) return fail(HTN_E_ARG, "entry_start must not decrease");
+        const int64_t n_terms = entry_start[n_entries];
+        if (n_terms > 0 && (!term_output || !term_coef)) return fail(HTN_E_ARG, "NULL terms");
+        for (int64_t t = 0; t < n_terms; ++t)
+            if (term_output[t] < 0 || term_output[t] >= n_out) return fail(HTN_E_ARG, "term output out of range");
+    }
+    auto *q = new htn_qteval();
+    try {
+        q->n_inst = n_instances;
+        q->n_outputs = n_out;
+        q->n_entries = n_entries;
+        q->d_insts = dalloc<kern::SvInst>(hi.size());
+        HIP_TRY(hipMemcpy(q->d_insts, hi.data(), hi.size() * sizeof(kern::SvInst), hipMemcpyHostToDevice));
+        q->d_ops = dalloc<kern::SvOp>(std::max<size_t>(1, hops.size()));
+        if (!hops.empty())
+            HIP_TRY(hipMemcpy(q->d_ops, hops.data(), hops.size() * sizeof(kern::SvOp), hipMemcpyHostToDevice));
+        if (n_state > 0) q->d_state = dalloc<double2>((size_t)n_state);
+        q->d_outs = dalloc<double>((size_t)n_out);
+        if (n_entries > 0) {
+            const int64_t n_terms = entry_start[n_entries];
+            q->d_start = dalloc<int64_t>((size_t)n_entries + 1);
+            HIP_TRY(hipMemcpy(q->d_start, entry_start, ((size_t)n_entries + 1) * 8, hipMemcpyHostToDevice));
+            q->d_term = dalloc<int64_t>(std::max<int64_t>(1, n_terms));
+            q->d_coef = dalloc<double>(std::max<int64_t>(1, n_terms));
+            if (n_terms > 0) {
+                HIP_TRY(hipMemcpy(q->d_term, term_output, (size_t)n_terms * 8, hipMemcpyHostToDevice));
+                HIP_TRY(hipMemcpy(q->d_coef, term_coef, (size_t)n_terms * 8, hipMemcpyHostToDevice));
+            }
+        }
+    } catch (...) {
+        delete q;
+        throw;
+    }
+    *out = q;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_qt_eval_run(htn_qteval_t q, double *entries, double *outputs, void *hip_stream) {
+    API_GUARD_BEGIN
+    if (!q) return fail(HTN_E_ARG, "handle is NULL");
+    if (q->n_entries > 0 && !entries) return fail(HTN_E_ARG, "entries is NULL");
+    const hipStream_t st = (hipStream_t)hip_stream;
+    double *outs = outputs ? outputs : q->d_outs;
+    HIP_TRY(kern::launch_sv_eval(q->d_insts, q->n_inst, q->d_ops, q->d_state, outs, st));
+    HIP_TRY(kern::launch_qt_assemble(q->d_start, q->d_term, q->d_coef, q->n_entries, outs, entries, st));
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_qt_eval_info(htn_qteval_t q, int64_t *n_outputs, int64_t *n_entries) {
+    API_GUARD_BEGIN
+    if (!q) return fail(HTN_E_ARG, "handle is NULL");
+    if (n_outputs) *n_outputs = q->n_outputs;
+    if (n_entries) *n_entries = q->n_entries;
+    return HTN_OK;
+    API_GUARD_END
+}
+
+void htn_qt_eval_destroy(htn_qteval_t q) { delete q; }
+
+}  // extern "C"

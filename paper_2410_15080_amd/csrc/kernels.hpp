@@ -104,6 +104,28 @@ constexpr int kFPrepChunk = 4096;
 hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
                         hipStream_t st);
 
+// QT evaluator (qteval.hip): statevector instances, one workgroup each.
+constexpr int kSvMaxQubits = 24;
+constexpr int kSvLdsQubits = 12;  // states of at most this many qubits live in LDS
+enum SvKind { SV_U1 = 0, SV_CZ = 1, SV_CX = 2, SV_RZZ = 3, SV_PROJ = 4 };
+struct SvOp {
+    int32_t kind, q0, q1, pad;  // PROJ: q1 = the bit kept
+    double m[8];                // U1: u00, u01, u10, u11 as (re, im); RZZ: m[0] = theta
+};
+struct SvInst {
+    int32_t n, n_ops, n_kept, n_y;  // n_y: qubits measured in Y
+    int64_t op_off;                 // first op
+    int64_t out_off;                // first output (2^n_kept of them)
+    int64_t state_off;              // offset (amplitudes) in the global state buffer; -1: LDS
+    int64_t xmask, zymask;          // amplitude-index bits of X|Y qubits and of Z|Y qubits
+    int32_t kept[kSvMaxQubits];
+    double init[kSvMaxQubits][4];   // (re0, im0, re1, im1) per qubit
+};
+hipError_t launch_sv_eval(const SvInst *insts, int n_insts, const SvOp *ops, double2 *gstate, double *outs,
+                          hipStream_t st);
+hipError_t launch_qt_assemble(const int64_t *start, const int64_t *term_out, const double *coef, int64_t n_entries,
+                              const double *outs, double *entries, hipStream_t st);
+
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.
 hipError_t launch_slice_sum(const void *parts, int n_slices, int64_t n, void *out, int tout, bool comp,

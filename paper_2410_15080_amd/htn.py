@@ -63,6 +63,20 @@ class htn_gather(ctypes.Structure):
                 ("n_kept", ctypes.c_int32 * HTN_TRUNC_MAX_RANK)]
 
 
+HTN_SV_U1, HTN_SV_CZ, HTN_SV_CX, HTN_SV_RZZ, HTN_SV_PROJ = 0, 1, 2, 3, 4
+
+
+class htn_sv_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("m", ctypes.c_double * 8)]
+
+
+class htn_sv_instance(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("init", ctypes.POINTER(ctypes.c_double)), ("n_ops", ctypes.c_int32),
+                ("ops", ctypes.POINTER(htn_sv_op)), ("observable", ctypes.c_char_p), ("n_kept", ctypes.c_int32),
+                ("kept", ctypes.POINTER(ctypes.c_int32))]
+
+
 _lib = None
 
 
@@ -135,6 +149,11 @@ def load_library():
         "htn_qpd_fuse": (I32, [I32, i32p, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
                                ctypes.POINTER(ctypes.c_double)]),
         "htn_gather_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_gather), I32]),
+        "htn_qt_eval_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_sv_instance), I64, i64p, i64p,
+                                     ctypes.POINTER(ctypes.c_double)]),
+        "htn_qt_eval_run": (I32, [P, P, P, P]),
+        "htn_qt_eval_info": (I32, [P, i64p, i64p]),
+        "htn_qt_eval_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -728,3 +747,58 @@ def htn_gather_create(items, dtype=HTN_F64) -> Trunc:
     h = ctypes.c_void_p()
     _check(lib.htn_gather_create(ctypes.byref(h), len(items), arr, int(dtype)))
     return Trunc(h, keep)
+
+
+class QtEval:
+    """Handle of htn_qt_eval_create."""
+
+    def __init__(self, handle, n_outputs, n_entries):
+        self.handle, self.n_outputs, self.n_entries = handle, n_outputs, n_entries
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.htn_qt_eval_destroy(self.handle)
+            self.handle = None
+
+
+def htn_qt_eval_create(instances, entry_start, term_output, term_coef) -> QtEval:
+    """instances: (n_qubits, init [n][4] float64, ops [(kind, q0, q1, m8)],
+    observable str, kept list) tuples; entry CSR as numpy arrays."""
+    lib = load_library()
+    arr = (htn_sv_instance * len(instances))()
+    keep = []
+    for i, (n, init, ops, obs, kept) in enumerate(instances):
+        it = arr[i]
+        it.n_qubits = int(n)
+        a, ap = _arr(np.asarray(init, dtype=np.float64).reshape(-1), np.float64)
+        keep.append(a)
+        it.init = ap
+        oa = (htn_sv_op * max(1, len(ops)))()
+        for j, (kind, q0, q1, m) in enumerate(ops):
+            oa[j].kind, oa[j].q0, oa[j].q1 = int(kind), int(q0), int(q1)
+            for c in range(8):
+                oa[j].m[c] = float(m[c])
+        keep.append(oa)
+        it.n_ops = len(ops)
+        it.ops = oa
+        ob = obs.encode()
+        keep.append(ob)
+        it.observable = ob
+        k, kp = _arr(list(kept) or [0], np.int32)
+        keep.append(k)
+        it.n_kept = len(kept)
+        it.kept = kp
+    st, sp = _arr(entry_start, np.int64)
+    to, tp = _arr(term_output if len(term_output) else [0], np.int64)
+    tc, cp = _arr(term_coef if len(term_coef) else [0.0], np.float64)
+    h = ctypes.c_void_p()
+    _check(lib.htn_qt_eval_create(ctypes.byref(h), len(instances), arr, len(entry_start) - 1, sp, tp, cp))
+    n_out, n_ent = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.htn_qt_eval_info(h, ctypes.byref(n_out), ctypes.byref(n_ent)))
+    return QtEval(h, int(n_out.value), int(n_ent.value))
+
+
+def htn_qt_eval_run(q: QtEval, entries, outputs=None, stream=None) -> None:
+    _check(load_library().htn_qt_eval_run(q.handle, ctypes.c_void_p(_data_ptr(entries)),
+                                          ctypes.c_void_p(_data_ptr(outputs)) if outputs is not None else None,
+                                          _stream_ptr(stream)))

@@ -209,3 +209,22 @@ def test_allocator_hook_arguments_are_checked_on_the_host():
     fn = htn.ALLOC_FN(lambda n, c: None)
     assert lib.htn_set_allocator(ctypes.cast(fn, ctypes.c_void_p), None, None) == 1  # HTN_E_ARG
     assert lib.htn_set_allocator(None, None, None) == 0
+
+
+def test_qt_evaluator_validates_on_the_host():
+    from paper_2410_15080_amd import htn
+    init = np.array([[1.0, 0.0, 0.0, 0.0]] * 2)
+    bad = [
+        [(2, init, [], "ZQ", [])],                         # observable letter
+        [(2, init, [], "ZI", [0])],                        # kept qubit not I
+        [(2, init, [(htn.HTN_SV_CZ, 0, 0, [0] * 8)], "ZZ", [])],  # CZ on one qubit
+        [(2, init, [(htn.HTN_SV_PROJ, 0, 2, [0] * 8)], "ZZ", [])],  # projection bit
+        [(25, np.zeros((25, 4)), [], "I" * 25, [])],       # too many qubits
+    ]
+    for insts in bad:
+        with pytest.raises(htn.HtnError) as e:
+            htn.htn_qt_eval_create(insts, np.array([0, 1]), np.array([0]), np.array([1.0]))
+        assert e.value.name == "HTN_E_ARG"
+    with pytest.raises(htn.HtnError) as e:   # term output beyond the outputs
+        htn.htn_qt_eval_create([(2, init, [], "ZZ", [])], np.array([0, 1]), np.array([1]), np.array([1.0]))
+    assert e.value.name == "HTN_E_ARG"
