@@ -174,7 +174,6 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
         // the same pair can appear under several shared labels
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) {
             if (a.cost != b.cost) return a.cost < b.cost;
-            if (a.absorb != b.absorb) return a.absorb > b.absorb;
             if (a.os != b.os) return a.os < b.os;
             if (a.i != b.i) return a.i < b.i;
             return a.j < b.j;
@@ -191,14 +190,17 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
             bi = std::min(sz[0].second, sz[1].second);
             bj = std::max(sz[0].second, sz[1].second);
         } else if (!rng || cands.size() == 1) {
-            bi = cands[0].i;
-            bj = cands[0].j;
-        } else if (std::any_of(cands.begin(), cands.end(), [](const Cand &c) { return c.absorb; })) {
-            // sampled orders make every absorption (a normalisation of the
-            // network, never a choice of order) before drawing a step
-            const Cand &c = *std::find_if(cands.begin(), cands.end(), [](const Cand &x) { return x.absorb; });
-            bi = c.i;
-            bj = c.j;
+            // among the cheapest pairs an absorption goes first
+            const Cand *c = &cands[0];
+            for (const Cand &x : cands) {
+                if (x.cost != cands[0].cost) break;
+                if (x.absorb) {
+                    c = &x;
+                    break;
+                }
+            }
+            bi = c->i;
+            bj = c->j;
         } else {
             const double lmin = std::log2(cands[0].cost);
             double wsum = 0.0;
@@ -210,6 +212,16 @@ static std::vector<std::pair<int, int>> greedy_core(const Net &n, Rng *rng, doub
             double r = rng->uniform() * wsum;
             size_t k = 0;
             while (k + 1 < cands.size() && r >= wts[k]) r -= wts[k++];
+            // a drawn step that ties with an absorption defers to it (an
+            // absorption is a scaling of a load, never a kernel step)
+            if (!cands[k].absorb)
+                for (const Cand &x : cands) {
+                    if (x.cost > cands[k].cost) break;
+                    if (x.cost == cands[k].cost && x.absorb) {
+                        k = (size_t)(&x - cands.data());
+                        break;
+                    }
+                }
             bi = cands[k].i;
             bj = cands[k].j;
         }
@@ -525,14 +537,16 @@ void build_plan(Net &n) {
         // label may stay on a value (it is summed by a later step at no cost).
         bool sums_trivial = true;
         for (int l : sums) sums_trivial = sums_trivial && n.dims[l] == 1;
-        // An input operand whose labels the other operand (an intermediate)
-        // carries -- a coefficient tensor, or a scalar factor such as a CT
-        // truncated to one kept index -- multiplies the network entry-wise:
-        // it is applied exactly once by folding it into the load of an input
-        // that carries every one of its labels of extent above 1 (any input
-        // for a scalar), and the intermediate's producer writes this step's
-        // result directly.  Loads happen before any label is summed, so the
-        // order of the path does not matter.
+        // A scalar factor (an input of one element, such as a CT truncated
+        // to one kept index) that meets an intermediate multiplies the whole
+        // network: it is applied exactly once by folding it into the load of
+        // an input (loads happen before any label is summed, so the order of
+        // the path does not matter), and the intermediate's producer writes
+        // this step's result directly.  Larger coefficient tensors that meet
+        // an intermediate stay kernel steps: folding them would force the
+        // carrier input, often loaded straight from its tensor, through the
+        // materialisation launch (measured slower on grid batches); path
+        // selection absorbs them first instead.
         auto sub_of = [&](const Value &x, const Value &y) {
             for (int l : x.labels)
                 if (!contains(y.labels, l) && !std::binary_search(sums.begin(), sums.end(), l)) return false;
@@ -542,7 +556,7 @@ void build_plan(Net &n) {
         if (sums_trivial && A.input != B.input && !last) {
             scl = A.input ? i : j;
             oth = scl == i ? j : i;
-            if (!sub_of(P.values[scl], P.values[oth])) scl = -1;
+            if (!sub_of(P.values[scl], P.values[oth]) || P.values[scl].size != 1) scl = -1;
         }
         if (scl >= 0) {
             const Value &S = P.values[scl];
