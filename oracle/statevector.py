@@ -39,6 +39,12 @@ def apply_1q(psi: np.ndarray, u: np.ndarray, q: int) -> np.ndarray:
     return np.moveaxis(out, 0, q)
 
 
+def apply_2q(psi: np.ndarray, u: np.ndarray, a: int, b: int) -> np.ndarray:
+    """4x4 unitary u on qubits (a, b) (a the slower index of u)."""
+    out = np.tensordot(np.asarray(u).reshape(2, 2, 2, 2), psi, axes=([2, 3], [a, b]))
+    return np.moveaxis(out, [0, 1], [a, b])
+
+
 def apply_cz(psi: np.ndarray, a: int, b: int) -> np.ndarray:
     out = psi.copy()
     idx = [slice(None)] * psi.ndim
@@ -92,6 +98,7 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
       ("cz", a, b)            controlled-Z
       ("rzz", a, b, theta)    exp(-i theta/2 Z_a Z_b)
       ("cx", c, t)            controlled-X (control c, target t)
+      ("u2", a, b, 4x4)       two-qubit unitary on (a, b), a the slower index
       ("mz", q)               signed mid-circuit Z measurement: the result is
                               sum_b (-1)^b <O>_b over the two unnormalised
                               projected branches, each continued to the end.
@@ -106,6 +113,8 @@ def run_ops(psi: np.ndarray, ops, observable: dict) -> float:
             psi = apply_rzz(psi, op[1], op[2], op[3])
         elif kind == "cx":
             psi = apply_cx(psi, op[1], op[2])
+        elif kind == "u2":
+            psi = apply_2q(psi, op[3], op[1], op[2])
         elif kind == "mz":
             q = op[1]
             rest = ops[k + 1:]

@@ -33,12 +33,13 @@ def test_wire_cut_circuit_matches_oracle_and_statevector(exec_mode):
         assert abs(got - full) < 1e-14
 
 
-@pytest.mark.parametrize("gate", ["cz", "rzz", "cx"])
+@pytest.mark.parametrize("gate", ["cz", "rzz", "cx", "general"])
 @pytest.mark.parametrize("exec_mode", EXECS)
 def test_gate_cut_circuits(exec_mode, gate):
-    # CZ, parametric RZZ(theta) and CX gate cuts: oracle and uncut statevector
+    # CZ, parametric RZZ(theta), CX and general (KAK) two-qubit gate cuts:
+    # oracle and uncut statevector
     for seed in (1, 2):
-        for n_cuts in (1, 2):
+        for n_cuts in ((1,) if gate == "general" else (1, 2)):
             w, full = circuit_nets.cut_gates(seed, n_cuts, gate=gate)
             got = float(run(w, exec_mode=exec_mode))
             ref, _ = oracle.naive_contract(w.tensors, w.labels, w.dims, w.out_labels)

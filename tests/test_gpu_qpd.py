@@ -279,3 +279,32 @@ def test_fused_sampling_on_multi_bond_networks_matches_oracle(s_qpd):
         hi, lo = oracle.ve_contract(ref.tensors, ref.labels, ref.dims, ref.out_labels)
         x = float(hi) + float(lo)
         assert abs(float(out.item()) - x) <= 1e-10 * abs(x) + 1e-300, (float(out.item()), x)
+
+
+@pytest.mark.parametrize("s_qpd", [1, 4, 64])
+def test_general_gate_cuts_fuse_their_three_rotations_before_sampling(s_qpd):
+    """A general two-qubit gate cut is three rotation cuts between the same
+    two QTs: the library fuses their CTs into one 216-entry CT, draws it
+    jointly, gathers the QTs (bit-exact against the oracle) and contracts
+    them to the oracle's value of the simplified network (FP64, 1e-10)."""
+    torch = _torch()
+    import circuit_nets
+    for seed in (1, 2, 3):
+        for n_cuts in (1,):
+            w, _ = circuit_nets.cut_gates(seed, n_cuts, gate="general")
+            gate = [i for i, k in enumerate(w.kinds) if k == "ct"]
+            groups = qs.parallel_groups(w, gate)
+            assert [len(g) for g in groups] == [3 * n_cuts]  # all rotations join the same two QTs
+            lib, ref, items = _fused_case(w, 7 * s_qpd + seed, s_qpd)
+            g = htn.htn_gather_create(items, htn.HTN_F64)
+            htn.htn_truncate_run(g)
+            torch.cuda.synchronize()
+            for a, b in zip(lib.tensors, ref.tensors):
+                assert np.array_equal(a.cpu().numpy(), b)
+            net = htn.htn_create(lib.tensors, lib.labels, lib.dims, lib.out_labels)
+            out = htn.new_output(net)
+            htn.htn_contract(net, out)
+            torch.cuda.synchronize()
+            hi, lo = oracle.ve_contract(ref.tensors, ref.labels, ref.dims, ref.out_labels)
+            x = float(hi) + float(lo)
+            assert abs(float(out.item()) - x) <= 1e-10 * abs(x) + 1e-300

@@ -73,6 +73,7 @@ def test_instance_outputs_match_oracle(sizes):
 def _workloads():
     ws = [c.cut_wires(s) for s in range(2)]
     ws += [c.cut_gates(s, k, gate=g) for s in (1, 2) for k in (1, 2) for g in ("cz", "rzz", "cx")]
+    ws += [c.cut_gates(s, 1, gate="general") for s in (1, 2, 3)]
     ws += [c.cut_marginal(0), c.cut_marginal(1, n_left=7, n_right=6, n_cuts=3, kept_left=2, kept_right=4)]
     return ws
 

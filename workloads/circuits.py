@@ -237,11 +237,35 @@ def cut_wires(seed: int) -> CircuitNetwork:
 _INST_U = {"S": S, "Sdg": SDG, "Z": Z, "I": I2}
 
 
+def random_u2(rng) -> np.ndarray:
+    """A random single-qubit unitary Rz Ry Rz with angles U[0, 2pi)."""
+    a, b, c = rng.uniform(0.0, 2.0 * np.pi, size=3)
+    return rz(a) @ ry(b) @ rz(c)
+
+
+PAULI_M = {"X": X, "Y": Y, "Z": Z}
+# V with V Z V^dag = P, per KAK axis
+KAK_V = {"X": H, "Y": S @ H, "Z": I2}
+
+
+def kak_gate(a1, a2, b1, b2, t):
+    """The 4x4 unitary (A1 (x) A2) exp(i sum_k t_k P_k (x) P_k) (B1 (x) B2)
+    (first qubit the slower index), P_k = X, Y, Z."""
+    r = np.eye(4, dtype=np.complex128)
+    for p, tk in zip(qpd.KAK_AXES, t):
+        pp = np.kron(PAULI_M[p], PAULI_M[p])
+        r = r @ (np.cos(tk) * np.eye(4) + 1j * np.sin(tk) * pp)
+    return np.kron(a1, a2) @ r @ np.kron(b1, b2)
+
+
 def cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz") -> CircuitNetwork:
     """4-qubit circuit, halves {q0,q1} | {q2,q3}, crossing gate on (q1,q2) cut.
 
     Each layer: Rz, Ry on every qubit, CZ(0,1), CZ(2,3); the crossing gate
-    follows layers 0..n_cuts-1 and is cut: CZ; with gate="rzz" a ZZ rotation
+    follows layers 0..n_cuts-1 and is cut: CZ; with gate="general" a random
+    two-qubit gate in KAK form (random single-qubit unitaries around
+    exp(i (a XX + b YY + c ZZ)), a, b, c U[-pi/2, pi/2)), cut as three
+    rotation cuts (three cut indices per gate); with gate="rzz" a ZZ rotation
     RZZ(theta) whose angle per cut is drawn U[-pi, pi) after the layer
     angles; with gate="cx" a CX (control q1, target q2): CX = (I (x) H) CZ
     (I (x) H), so its cut is the CZ cut with each target-side instance
@@ -252,7 +276,13 @@ def cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz") -
     rng = np.random.default_rng(seed)
     ang = rng.uniform(0.0, 2.0 * np.pi, size=(n_layers, 4, 2))
     thetas = rng.uniform(-np.pi, np.pi, size=n_cuts) if gate == "rzz" else None
-    instances = qpd.RZZ_INSTANCES if gate == "rzz" else qpd.CZ_INSTANCES
+    kak = None
+    if gate == "general":
+        # per cut: A1, A2, B1, B2 and the three rotation angles U[-pi/2, pi/2)
+        kak = [(random_u2(rng), random_u2(rng), random_u2(rng), random_u2(rng),
+                rng.uniform(-np.pi / 2, np.pi / 2, size=3)) for _ in range(n_cuts)]
+    instances = qpd.RZZ_INSTANCES if gate in ("rzz", "general") else qpd.CZ_INSTANCES
+    per_cut = 3 if gate == "general" else 1  # cut indices per crossing gate
     layers = []
     for layer in range(n_layers):
         ops = []
@@ -266,8 +296,11 @@ def cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz") -
     for layer in range(n_layers):
         full += layers[layer]
         if layer < n_cuts:
-            full.append({"rzz": ("rzz", 1, 2, thetas[layer] if thetas is not None else 0.0),
-                         "cx": ("cx", 1, 2)}.get(gate, ("cz", 1, 2)))
+            if gate == "general":
+                full.append(("u2", 1, 2, kak_gate(*kak[layer])))
+            else:
+                full.append({"rzz": ("rzz", 1, 2, thetas[layer] if thetas is not None else 0.0),
+                             "cx": ("cx", 1, 2)}.get(gate, ("cz", 1, 2)))
 
     def half_ops(side, insts):
         # side 0: global {0,1} -> local {0,1}, cut qubit local 1
@@ -283,7 +316,17 @@ def cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz") -
                         out.append(("u", op[1] - keep[0], op[2]))
                     else:
                         out.append(("cz", op[1] - keep[0], op[2] - keep[0]))
-            if layer < n_cuts:
+            if layer < n_cuts and gate == "general":
+                a1, a2, b1, b2, t = kak[layer]
+                out.append(("u", cutq, b1 if side == 0 else b2))
+                for k, p in enumerate(qpd.KAK_AXES):
+                    v = KAK_V[p]
+                    name = instances[insts[per_cut * layer + k]][side]
+                    out.append(("u", cutq, v.conj().T))
+                    out.append(("mz", cutq) if name == "MZ" else ("u", cutq, _INST_U[name]))
+                    out.append(("u", cutq, v))
+                out.append(("u", cutq, a1 if side == 0 else a2))
+            elif layer < n_cuts:
                 name = instances[insts[layer]][side]
                 conj = gate == "cx" and side == 1  # the CX target's side
                 if conj:
@@ -296,17 +339,22 @@ def cut_gates(seed: int, n_cuts: int = 1, n_layers: int = 3, gate: str = "cz") -
                     out.append(("u", cutq, H))
         return out
 
-    shape = (6,) * n_cuts
+    shape = (6,) * (n_cuts * per_cut)
     zero = STATES["0"]
     left, right = _Builder(shape), _Builder(shape)
     for e, idx in enumerate(np.ndindex(*shape)):
         left.add(e, 2, [zero, zero], half_ops(0, idx), "ZZ", 1.0)
         right.add(e, 2, [zero, zero], half_ops(1, idx), "ZZ", 1.0)
-    cut_labels = list(range(n_cuts))
-    coeffs = [qpd.rzz_coeffs(t) for t in thetas] if gate == "rzz" else [qpd.CZ_COEFFS.copy()] * n_cuts
+    cut_labels = list(range(n_cuts * per_cut))
+    if gate == "general":
+        coeffs = [qpd.kak_coeffs(t) for g in kak for t in g[4]]
+    elif gate == "rzz":
+        coeffs = [qpd.rzz_coeffs(t) for t in thetas]
+    else:
+        coeffs = [qpd.CZ_COEFFS.copy()] * n_cuts
     return CircuitNetwork([left.spec(), right.spec()] + [np.array(c) for c in coeffs],
-                          [cut_labels, cut_labels] + [[l] for l in cut_labels], [6] * n_cuts, [],
-                          ["qt", "qt"] + ["ct"] * n_cuts, full, 4, "ZZZZ", [],
+                          [cut_labels, cut_labels] + [[l] for l in cut_labels], [6] * len(cut_labels), [],
+                          ["qt", "qt"] + ["ct"] * len(cut_labels), full, 4, "ZZZZ", [],
                           {"config": "circuit_cut_gates", "seed": seed, "n_cuts": n_cuts, "gate": gate})
 
 

@@ -63,3 +63,18 @@ RZZ_INSTANCES = (("I", "I"), ("Z", "Z"), ("MZ", "S"), ("MZ", "Sdg"), ("S", "MZ")
 def rzz_coeffs(theta: float) -> np.ndarray:
     c, s = np.cos(0.5 * theta), np.sin(0.5 * theta)
     return np.array([c * c, s * s, c * s, -c * s, c * s, -c * s])
+
+
+# General two-qubit gates (Sec. 2.1 gate QPD for an arbitrary two-qubit
+# gate): in the KAK form U = (A1 (x) A2) exp(i (a XX + b YY + c ZZ)) (B1 (x) B2)
+# the three rotations commute, and exp(i t P(x)P) = (V (x) V) RZZ(-2t) (V (x) V)^dag
+# with V Z V^dag = P (V = H for X, S H for Y, I for Z).  Each rotation is cut
+# with the six RZZ instances, every instance operation conjugated by V on
+# its qubit: three cut indices of dimension 6 per gate (216 terms), weights
+# rzz_coeffs(-2t) each, gamma = prod (1 + 2 |sin 2t|).
+KAK_AXES = ("X", "Y", "Z")
+
+
+def kak_coeffs(t: float) -> np.ndarray:
+    """QPD weights of the rotation exp(i t P(x)P) (any Pauli P)."""
+    return rzz_coeffs(-2.0 * t)
