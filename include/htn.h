@@ -177,8 +177,11 @@ typedef enum {
     HTN_OPT_PATH_SAMPLES = 4,      /* sampled candidates of HTN_PATH_SAMPLED/LEARNED (default 32) */
     HTN_OPT_PATH_SEED = 5,         /* seed of the path sampler (default 0) */
     HTN_OPT_FUSED_THREADS = 6,     /* threads per network in the fused kernel: 64, 256 (default) or 512 */
-    HTN_OPT_SLICE = 7              /* 0 (default): a path whose largest intermediate exceeds
+    HTN_OPT_SLICE = 7,             /* 0 (default): a path whose largest intermediate exceeds
                                       HTN_OPT_MAX_INTERMEDIATE is HTN_E_OOM.  1: slicing (see below) */
+    HTN_OPT_QUEUE = 8              /* batches: 0 (default) a net run step by step goes to the batch's
+                                      work queue; 1 the net always does (even one the fused kernel
+                                      could take); 2 never (one launch per step, on side streams) */
 } htn_option;
 
 /* Slicing under the intermediate cap (HTN_OPT_SLICE = 1).  Contraction
@@ -290,6 +293,23 @@ htn_status htn_batch_phase_times(htn_batch_t batch, int64_t *ticks);
  * last read, and their count; then starts a new tally.  Any argument but
  * the batch may be NULL.                                                  */
 htn_status htn_batch_set_event_timing(htn_batch_t batch, int32_t on);
+/* Work queue of a batch (Sec. 6.1 Step 4 contracts a network step by step;
+ * a batch runs the steps of all its step-by-step networks in one launch).
+ * Networks too large for one fused workgroup (HTN_OPT_QUEUE, above) have
+ * their input materialisations and every block of every step cut into
+ * tasks, listed in dependency order; the resident workgroups of one
+ * persistent launch take the tasks in list order and each waits (bounded)
+ * until the steps it reads are complete.  Each network's intermediates get
+ * their own device buffer for the batch's lifetime (no reuse between
+ * steps), allocated at htn_batch_create.  A network whose matrix-core
+ * steps use another input/output type pair than the first such network's,
+ * and every step-by-step network while phase timing is on, runs with one
+ * launch per step instead.  Runs of one batch must not overlap.
+ * htn_batch_queue_info (waits for the device): *n_nets networks and
+ * *n_tasks tasks in the queue; *error = 1 if a task of any run since the
+ * last call gave up waiting (never for a consistent queue; the flag is then
+ * cleared).  Any pointer may be NULL.                                     */
+htn_status htn_batch_queue_info(htn_batch_t batch, int32_t *n_nets, int32_t *n_tasks, int32_t *error);
 htn_status htn_batch_launch_ms(htn_batch_t batch, float *prep_ms, float *fused_ms, int32_t *runs);
 void htn_batch_destroy(htn_batch_t batch);
 

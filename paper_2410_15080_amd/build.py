@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhtn.so")
 
-SOURCES = ["api.hip", "kernels.hip", "fused_b64.hip", "fused_b256.hip", "fused_b512.hip", "mfma.hip", "mlp.hip", "qpd.hip", "qteval.hip",
+SOURCES = ["api.hip", "kernels.hip", "fused_b64.hip", "fused_b256.hip", "fused_b512.hip", "mfma.hip", "mlp.hip", "qpd.hip", "qteval.hip", "queue.hip",
            "planner.cpp", "cost_model.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <limits>
 #include <mutex>
@@ -14,6 +15,7 @@
 #include "htn.h"
 #include "htn_core.hpp"
 #include "kernels.hpp"
+#include "mfma_dev.hpp"
 
 using namespace htn;
 
@@ -66,6 +68,7 @@ struct DeviceState {
     int fprep_max = 0;
     bool fprep_in_kernel = false;  // the fused workgroup materialises its inputs
     int plan_uploaded = -1;
+    int64_t uploads = 0;  // input and plan uploads so far (a batch holds the addresses of one)
     struct SliceRun *slices = nullptr;  // a sliced net's slice networks (built at first use)
 };
 }  // namespace htn
@@ -100,6 +103,19 @@ struct htn_batch {
     std::vector<int> versions;
     std::vector<Group> groups;
     std::vector<int> step_nets;
+    std::vector<int64_t> uploads;  // each net's DeviceState::uploads at creation
+    // Work queue of the step-by-step nets (in_queue[k]: step_nets[k] is in
+    // it); it runs on its own side stream when the batch has a fused launch.
+    struct Queue {
+        kern::QItem *d_items = nullptr;
+        kern::QTask *d_tasks = nullptr;
+        int32_t *d_counters = nullptr, *d_init = nullptr, *d_ctrl = nullptr;
+        void *d_ws = nullptr;
+        int n_items = 0, n_tasks = 0, n_nets = 0, gk = 0, lds = 0, n_blocks = 0;
+        hipStream_t stream = nullptr;
+        hipEvent_t ev_join = nullptr;
+    } q;
+    std::vector<char> in_queue;
     kern::FusedDesc *d_desc = nullptr;
     void **d_outs = nullptr;
     int64_t *d_stamps = nullptr;
@@ -309,6 +325,7 @@ static void upload_inputs(Net &n) {
     HIP_TRY(hipMemcpy(D.d_inptrs, D.in.data(), sizeof(void *) * n.n_t, hipMemcpyHostToDevice));
     n.data_dirty = false;
     D.plan_uploaded = -1;  // prep descriptors hold input pointers
+    ++D.uploads;
 }
 
 static void upload_plan(Net &n) {
@@ -390,6 +407,7 @@ static void upload_plan(Net &n) {
     D.d_fdesc = dalloc<kern::FusedDesc>(1);
     HIP_TRY(hipMemcpy(D.d_fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
     D.plan_uploaded = n.plan_version;
+    ++D.uploads;
 }
 
 static void ensure_device(Net &n) {
@@ -718,6 +736,10 @@ htn_status htn_set_option(htn_net_t net, htn_option opt, int64_t value) {
             }
             return HTN_OK;
         }
+        case HTN_OPT_QUEUE:
+            if (value < 0 || value > 2) return fail(HTN_E_ARG, "queue mode is 0 (auto), 1 (always) or 2 (never)");
+            net->queue_mode = (int)value;
+            return HTN_OK;
         case HTN_OPT_FUSED_THREADS: {
             if (value != 64 && value != 256 && value != 512)
                 return fail(HTN_E_ARG, "fused threads must be 64, 256 or 512");
@@ -889,6 +911,15 @@ static void batch_free(htn_batch *b) {
         dfree(g.d_order);
         dfree(g.d_fprep);
     }
+    dfree(b->q.d_items);
+    dfree(b->q.d_tasks);
+    dfree(b->q.d_counters);
+    dfree(b->q.d_init);
+    dfree(b->q.d_ctrl);
+    dfree(b->q.d_ws);
+    if (b->q.ev_join) (void)hipEventDestroy(b->q.ev_join);
+    if (b->q.stream) (void)hipStreamDestroy(b->q.stream);
+    b->q = htn_batch::Queue{};
     dfree(b->d_desc);
     dfree(b->d_outs);
     dfree(b->d_stamps);
@@ -911,6 +942,312 @@ static hipEvent_t next_event(htn_batch *b) {
         b->ev_pool.push_back(e);
     }
     return b->ev_pool[b->ev_used++];
+}
+
+// ------------------------------------------------------------ work queue
+
+namespace {
+// Items of the work queue under construction.  Buffers in the queue's
+// workspace are recorded as byte offsets (off: A, B, C, s.part; -1 where
+// the field holds a device address already) and patched once the
+// workspace is allocated.
+struct QBuild {
+    std::vector<kern::QItem> items;
+    std::vector<std::array<int64_t, 4>> off;
+    std::vector<int> level;
+    int64_t ws = 0;
+    int gk = 0;  // GEMM kind of the queue (0: no GEMM items yet)
+    int64_t take(int64_t bytes) {
+        const int64_t o = ws;
+        ws += (std::max<int64_t>(bytes, 1) + 255) / 256 * 256;
+        return o;
+    }
+    int add(kern::QItem it, std::array<int64_t, 4> o) {
+        int lvl = 0;
+        for (int d : {it.dep0, it.dep1})
+            if (d >= 0) lvl = std::max(lvl, level[d] + 1);
+        items.push_back(it);
+        off.push_back(o);
+        level.push_back(lvl);
+        return (int)items.size() - 1;
+    }
+};
+}  // namespace
+
+static kern::QItem q_item(int kind, int net, const Net &n) {
+    kern::QItem it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = kind;
+    it.dep0 = it.dep1 = -1;
+    it.net = net;
+    it.tab = n.dev->d_tab;
+    it.units_per_task = 1;
+    return it;
+}
+
+// Blocks of a table-driven step per task: about 256 dependent terms per
+// thread, but at least min(blocks, 256) tasks so that one step spreads
+// over the chip.
+static int q_step_blocks_per_task(const kern::StepArgs &a, int64_t n_sum, int64_t blocks) {
+    const int64_t chunk = a.split > 1 ? a.chunk : n_sum;
+    const int64_t per_thread = std::max<int64_t>(1, (chunk + a.R - 1) / a.R);
+    const int64_t by_work = std::max<int64_t>(1, 256 / per_thread);
+    const int64_t by_spread = std::max<int64_t>(1, (blocks + 255) / 256);
+    return (int)std::max<int64_t>(1, std::min<int64_t>({by_work, by_spread, 64}));
+}
+
+// Appends the items of net `bi` of the batch; false (nothing appended) if
+// it has no kernel step or a matrix-core step of another GEMM kind than the
+// queue's.
+static bool queue_net(QBuild &Q, Net &n, int bi) {
+    const Plan &P = n.plan;
+    DeviceState &D = *n.dev;
+    if (P.kernel_steps.empty()) return false;
+    const int tin = (int)input_dtype(n.compute), tint = (int)inter_dtype(n.compute);
+    const int64_t es = dtype_size(inter_dtype(n.compute));
+    const int tp = n.compute == HTN_BF16 ? 2 : tint;  // packed GEMM operand type
+    const int64_t pes = dtype_size((htn_dtype)tp);
+    auto result_type = [&](const StepPlan &s) {
+        return s.final_step ? (n.final_sum == HTN_SUM_PLAIN ? tint : 0) : (s.out_bf16 ? 2 : tint);
+    };
+    int gk = Q.gk;
+    for (int k : P.kernel_steps) {
+        const StepPlan &s = P.steps[k];
+        if (!s.mfma) continue;
+        const int g = kern::queue_gemm_kind(tp, result_type(s));
+        if (g < 0 || (gk != 0 && g != gk)) return false;
+        gk = g;
+    }
+    Q.gk = gk;
+    const size_t first = Q.items.size();
+    std::vector<int> prod(P.values.size(), -1);      // item that completes each value
+    std::vector<int64_t> voff(P.values.size(), -1);  // its workspace offset
+    // input materialisations, in the order of the net's prep descriptors
+    int j = 0;
+    for (const LoadPlan &lp : P.loads) {
+        if (!lp.needs_copy()) continue;
+        kern::QItem it = q_item(kern::QI_LOAD, bi, n);
+        it.ta = tin;
+        it.tc = tint;
+        it.prep = D.d_prep + j++;
+        it.n_units = (lp.size + 255) / 256;
+        it.units_per_task = 16;
+        voff[lp.value] = Q.take(lp.size * es);
+        prod[lp.value] = Q.add(it, {-1, -1, voff[lp.value], -1});
+    }
+    if (j != D.n_prep) throw Error{HTN_E_STATE, "queue: prep descriptors out of step with the plan"};
+    // operand id -> (device address or workspace offset, dtype, producer)
+    struct Opd {
+        const void *ptr = nullptr;
+        int64_t off = -1;
+        int t = 0, dep = -1;
+    };
+    auto operand = [&](int id) {
+        Opd o;
+        if (id < 0) return o;
+        const Value &v = P.values[id];
+        o.dep = prod[id];
+        if (v.input && voff[id] < 0) {
+            o.ptr = D.in[v.base];
+            o.t = tin;
+        } else {
+            if (voff[id] < 0) throw Error{HTN_E_STATE, "queue: operand without a buffer"};
+            o.off = voff[id];
+            o.t = (!v.input && v.producer >= 0 && P.steps[v.producer].out_bf16) ? 2 : tint;
+        }
+        return o;
+    };
+    auto set_ab = [](kern::QItem &it, std::array<int64_t, 4> &o, const Opd &a, const Opd &b) {
+        it.A = a.ptr;
+        o[0] = a.off;
+        it.B = b.ptr;
+        o[1] = b.off;
+        it.dep0 = a.dep;
+        it.dep1 = b.dep;
+    };
+    int last = -1;
+    for (int k : P.kernel_steps) {
+        const StepPlan &s = P.steps[k];
+        const Opd A = operand(s.a), B = operand(s.b);
+        const int tc = result_type(s);
+        const bool comp = s.final_step && n.final_sum == HTN_SUM_COMPENSATED;
+        int64_t coff = -1;
+        if (!s.final_step) coff = voff[s.c] = Q.take(P.values[s.c].size * es);
+        const int out_flags = s.final_step ? (kern::QF_OUT | kern::QF_LAST) : 0;
+        if (s.mfma) {
+            auto pack = [&](const Opd &x, const StepPlan::Pack &pk) {
+                if (pk.identity && x.t == tp) return x;
+                kern::QItem it = q_item(kern::QI_STEP, bi, n);
+                std::array<int64_t, 4> o{-1, -1, -1, -1};
+                set_ab(it, o, x, Opd{});
+                it.ta = x.t;
+                it.tb = x.t;
+                it.tc = tp;
+                it.unary = 1;
+                it.s = pack_args(pk);
+                it.n_units = (pk.n + kBlock - 1) / kBlock;
+                it.units_per_task = q_step_blocks_per_task(it.s, 1, it.n_units);
+                Opd r;
+                r.off = o[2] = Q.take(pk.n * pes);
+                r.t = tp;
+                r.dep = Q.add(it, o);
+                return r;
+            };
+            const Opd pa = pack(A, s.pack_a), pb = pack(B, s.pack_b);
+            int ks = s.ksplit, kper = 0;
+            kern::gemm_ksplit((int)s.gk, ks, kper);
+            const int wi = (gk == 2 || gk == 4) ? 2 : 4;
+            kern::QItem it = q_item(kern::QI_GEMM, bi, n);
+            std::array<int64_t, 4> o{-1, -1, -1, -1};
+            set_ab(it, o, pa, pb);
+            it.ta = tp;
+            it.tb = tp;
+            it.tc = tc;
+            it.M = (int)s.gm;
+            it.N = (int)s.gn;
+            it.K = (int)s.gk;
+            it.batch = (int)s.gb;
+            it.kchunk = 64;
+            it.ksplit = ks;
+            it.kper = kper;
+            it.tiles_m = (int)((s.gm + 32 * wi - 1) / (32 * wi));
+            it.tiles_n = (int)((s.gn + 127) / 128);
+            it.n_units = (int64_t)it.tiles_m * it.tiles_n * it.batch * ks;
+            const int64_t total = s.gb * s.gm * s.gn;
+            if (ks > 1) {
+                o[2] = Q.take(ks * total * (tc == 0 ? 8 : 4));
+                const int64_t part_off = o[2];
+                const int g = Q.add(it, o);
+                kern::QItem ksum = q_item(kern::QI_KSUM, bi, n);
+                ksum.tc = tc;
+                ksum.ksplit = ks;
+                ksum.total = total;
+                ksum.dep0 = g;
+                ksum.flags = out_flags;
+                ksum.n_units = (total + 255) / 256;
+                ksum.units_per_task = 16;
+                last = Q.add(ksum, {part_off, -1, coff, -1});
+            } else {
+                it.flags = out_flags;
+                o[2] = coff;
+                last = Q.add(it, o);
+            }
+        } else {
+            kern::QItem it = q_item(kern::QI_STEP, bi, n);
+            std::array<int64_t, 4> o{-1, -1, -1, -1};
+            set_ab(it, o, A, B);
+            it.ta = A.t;
+            it.tb = s.b < 0 ? A.t : B.t;
+            it.tc = tc;
+            it.comp = comp ? 1 : 0;
+            it.unary = s.b < 0 ? 1 : 0;
+            kern::StepArgs &a = it.s;
+            a.n_ohi = (int32_t)s.n_ohi;
+            a.n_olo = (int32_t)s.n_olo;
+            a.n_shi = (int32_t)s.n_shi;
+            a.n_slo = (int32_t)s.n_slo;
+            a.t_ohi = (int32_t)s.t_ohi;
+            a.t_olo = (int32_t)s.t_olo;
+            a.t_shi = (int32_t)s.t_shi;
+            a.t_slo = (int32_t)s.t_slo;
+            a.R = s.r_global;
+            a.log2R = 0;
+            while ((1 << a.log2R) < a.R) ++a.log2R;
+            a.n_out = s.n_out;
+            a.split = 1;
+            a.chunk = 0;
+            a.part = nullptr;
+            if (s.split_global > 1) {
+                a.split = s.split_global;
+                a.chunk = (s.n_sum + s.split_global - 1) / s.split_global;
+                o[3] = Q.take(s.n_out * s.split_global * 16);
+            }
+            it.n_units = (s.n_out * a.R * a.split + kBlock - 1) / kBlock;
+            it.units_per_task = q_step_blocks_per_task(a, s.n_sum, it.n_units);
+            if (a.split > 1) {
+                const int g = Q.add(it, o);
+                kern::QItem fin = q_item(kern::QI_FINISH, bi, n);
+                fin.tc = tc;
+                fin.comp = it.comp;
+                fin.s = a;
+                fin.dep0 = g;
+                fin.flags = out_flags;
+                fin.n_units = (s.n_out + 3) / 4;
+                fin.units_per_task = 16;
+                last = Q.add(fin, {-1, -1, coff, o[3]});
+            } else {
+                it.flags = out_flags;
+                o[2] = coff;
+                last = Q.add(it, o);
+            }
+        }
+        if (!s.final_step) prod[s.c] = last;
+    }
+    if (last < 0 || !(Q.items[last].flags & kern::QF_OUT)) {
+        Q.items.resize(first);
+        Q.off.resize(first);
+        Q.level.resize(first);
+        throw Error{HTN_E_STATE, "queue: the last kernel step does not write the output"};
+    }
+    return true;
+}
+
+// Orders the items by dependency level (a task's producers all come
+// earlier), cuts them into tasks, allocates the workspace and uploads.
+static void queue_upload(htn_batch *b, QBuild &Q) {
+    htn_batch::Queue &q = b->q;
+    const int ni = (int)Q.items.size();
+    std::vector<int> order(ni), pos(ni);
+    for (int i = 0; i < ni; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return Q.level[x] < Q.level[y]; });
+    for (int i = 0; i < ni; ++i) pos[order[i]] = i;
+    q.d_ws = Q.ws > 0 ? dalloc_bytes((size_t)Q.ws) : nullptr;
+    unsigned char *ws = (unsigned char *)q.d_ws;
+    std::vector<kern::QItem> items(ni);
+    std::vector<int32_t> init(ni);
+    std::vector<kern::QTask> tasks;
+    std::vector<char> seen(b->nets.size(), 0);
+    for (int i = 0; i < ni; ++i) {
+        kern::QItem it = Q.items[order[i]];
+        const auto &o = Q.off[order[i]];
+        if (o[0] >= 0) it.A = ws + o[0];
+        if (o[1] >= 0) it.B = ws + o[1];
+        if (o[2] >= 0) it.C = ws + o[2];
+        if (o[3] >= 0) it.s.part = (double *)(ws + o[3]);
+        if (it.dep0 >= 0) it.dep0 = pos[it.dep0];
+        if (it.dep1 >= 0) it.dep1 = pos[it.dep1];
+        if (it.dep0 >= i || it.dep1 >= i) throw Error{HTN_E_STATE, "queue: dependency listed after its consumer"};
+        if (!seen[it.net]) {
+            it.flags |= kern::QF_FIRST;
+            seen[it.net] = 1;
+        }
+        const int64_t nt = (it.n_units + it.units_per_task - 1) / it.units_per_task;
+        if (nt < 1 || nt > (int64_t(1) << 30) || (int64_t)tasks.size() + nt > (int64_t(1) << 30))
+            throw Error{HTN_E_UNSUPPORTED, "queue: too many tasks"};
+        it.n_tasks = (int32_t)nt;
+        init[i] = (int32_t)nt;
+        for (int64_t t = 0; t < nt; ++t) tasks.push_back(kern::QTask{i, (int32_t)t});
+        items[i] = it;
+    }
+    q.n_items = ni;
+    q.n_tasks = (int)tasks.size();
+    q.gk = Q.gk;
+    q.lds = kern::queue_gemm_lds(Q.gk);
+    q.d_items = dalloc<kern::QItem>(ni);
+    HIP_TRY(hipMemcpy(q.d_items, items.data(), ni * sizeof(kern::QItem), hipMemcpyHostToDevice));
+    q.d_tasks = dalloc<kern::QTask>(tasks.size());
+    HIP_TRY(hipMemcpy(q.d_tasks, tasks.data(), tasks.size() * sizeof(kern::QTask), hipMemcpyHostToDevice));
+    q.d_init = dalloc<int32_t>(ni);
+    HIP_TRY(hipMemcpy(q.d_init, init.data(), ni * 4, hipMemcpyHostToDevice));
+    q.d_counters = dalloc<int32_t>(ni);
+    HIP_TRY(hipMemcpy(q.d_counters, init.data(), ni * 4, hipMemcpyHostToDevice));
+    std::vector<int32_t> ctrl(kern::QC_WORDS, 0);
+    q.d_ctrl = dalloc<int32_t>(kern::QC_WORDS);
+    HIP_TRY(hipMemcpy(q.d_ctrl, ctrl.data(), kern::QC_WORDS * 4, hipMemcpyHostToDevice));
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    q.n_blocks = (int)std::min<int64_t>(q.n_tasks, (int64_t)kern::queue_blocks_per_cu(q.gk, q.lds) * cus);
 }
 
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
@@ -938,8 +1275,9 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
                 throw Error{HTN_E_UNSUPPORTED, "net " + std::to_string(i) + " is sliced: contract it with htn_contract"};
             ensure_device(net);
             b->versions.push_back(net.plan_version);
+            b->uploads.push_back(net.dev->uploads);
             desc[i] = fused_desc(*net.dev, false, net.plan.fused_lds_only);
-            if (!use_fused_in_batch(net) || net.plan.mults > straggler) {
+            if (net.queue_mode == 1 || !use_fused_in_batch(net) || net.plan.mults > straggler) {
                 b->step_nets.push_back(i);
                 continue;
             }
@@ -990,6 +1328,23 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
                 const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
                 b->side_of.push_back(q);
                 load[q] += nets[i]->plan.mults;
+            }
+            // the work queue takes every step-by-step net it can
+            QBuild Q;
+            b->in_queue.assign(b->step_nets.size(), 0);
+            for (size_t k = 0; k < b->step_nets.size(); ++k) {
+                Net &net = *nets[b->step_nets[k]];
+                if (net.queue_mode != 2 && queue_net(Q, net, b->step_nets[k])) {
+                    b->in_queue[k] = 1;
+                    ++b->q.n_nets;
+                }
+            }
+            if (!Q.items.empty()) {
+                queue_upload(b, Q);
+                if (!b->groups.empty()) {
+                    HIP_TRY(hipStreamCreateWithFlags(&b->q.stream, hipStreamNonBlocking));
+                    HIP_TRY(hipEventCreateWithFlags(&b->q.ev_join, hipEventDisableTiming));
+                }
             }
             HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
             for (int q = 0; q < ns; ++q) {
@@ -1048,7 +1403,11 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
     // or by a launch of its own when there is none
     int64_t *run_start = b->d_stamps + 2 * n;
     const bool prep_stamps = !b->groups.empty() && b->groups[0].n_fprep > 0;
-    if (!prep_stamps) HIP_TRY(kern::launch_stamp(run_start, st));
+    // the queue (not while per-step phase clocks are asked for); alone, it
+    // stamps the run's start itself
+    const bool use_queue = b->q.n_tasks > 0 && !b->d_phase;
+    const bool queue_alone = use_queue && b->groups.empty();
+    if (!prep_stamps && !queue_alone) HIP_TRY(kern::launch_stamp(run_start, st));
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto &g = b->groups[gi];
@@ -1064,7 +1423,20 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
         HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
                                    (int)g.idx.size(), g.lds, g.compute, g.fm, g.threads, st));
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
+    if (use_queue) {
+        const htn_batch::Queue &q = b->q;
+        hipStream_t qs = queue_alone ? st : q.stream;
+        if (!queue_alone) HIP_TRY(hipStreamWaitEvent(qs, b->ev_fork, 0));
+        HIP_TRY(kern::launch_queue(q.d_items, q.d_tasks, q.n_tasks, q.d_init, q.d_counters, q.n_items, q.d_ctrl,
+                                   b->d_outs, b->d_stamps, queue_alone ? run_start : nullptr, q.gk, q.lds,
+                                   q.n_blocks, qs));
+        if (!queue_alone) {
+            HIP_TRY(hipEventRecord(q.ev_join, qs));
+            HIP_TRY(hipStreamWaitEvent(st, q.ev_join, 0));
+        }
+    }
     for (size_t k = 0; k < b->step_nets.size(); ++k) {
+        if (use_queue && b->in_queue[k]) continue;
         const int i = b->step_nets[k];
         hipStream_t ss = b->sides[b->side_of[k]];
         HIP_TRY(kern::launch_stamp(b->d_stamps + 2 * (size_t)i, ss));
@@ -1116,7 +1488,8 @@ htn_status htn_batch_run(htn_batch_t b, void *const *outs, void *hip_stream) {
     const int n = (int)b->nets.size();
     for (int i = 0; i < n; ++i) {
         if (!outs[i]) return fail(HTN_E_ARG, "outs[" + std::to_string(i) + "] is NULL");
-        if (b->nets[i]->plan_version != b->versions[i] || b->nets[i]->data_dirty)
+        if (b->nets[i]->plan_version != b->versions[i] || b->nets[i]->data_dirty ||
+            b->nets[i]->dev->uploads != b->uploads[i])
             return fail(HTN_E_STATE, "net " + std::to_string(i) + " changed after htn_batch_create");
     }
     hipStream_t st = (hipStream_t)hip_stream;
@@ -1266,6 +1639,28 @@ htn_status htn_batch_step_times(htn_batch_t b, float *times, int32_t capacity) {
             const int64_t begin = q == 0 ? st[2 * (size_t)i] : t[q - 1];
             if (t[q] < 0 || begin < 0 || t[q] < begin) continue;
             times[(size_t)i * capacity + q] = (float)(t[q] - begin) * 0.01f;
+        }
+    }
+    return HTN_OK;
+    API_GUARD_END
+}
+
+htn_status htn_batch_queue_info(htn_batch_t b, int32_t *n_nets, int32_t *n_tasks, int32_t *error) {
+    API_GUARD_BEGIN
+    if (!b) return fail(HTN_E_ARG, "batch is NULL");
+    if (n_nets) *n_nets = b->q.n_nets;
+    if (n_tasks) *n_tasks = b->q.n_tasks;
+    if (error) {
+        *error = 0;
+        if (b->q.d_ctrl) {
+            HIP_TRY(hipDeviceSynchronize());
+            int32_t e = 0;
+            HIP_TRY(hipMemcpy(&e, b->q.d_ctrl + kern::QC_ERR, 4, hipMemcpyDeviceToHost));
+            *error = e;
+            if (e) {
+                const int32_t zero = 0;
+                HIP_TRY(hipMemcpy(b->q.d_ctrl + kern::QC_ERR, &zero, 4, hipMemcpyHostToDevice));
+            }
         }
     }
     return HTN_OK;

@@ -171,6 +171,7 @@ struct Net {
     double batch_fused_max_mults = 33554432.0;  // batch limit for nets with matrix-core steps
     int allow_mfma = 1;
     int slice_mode = 0;         // 1: slice summed labels until the path fits max_intermediate
+    int queue_mode = 0;         // batches: 0 step-by-step nets in the work queue, 1 always, 2 never
     int path_samples = 32;      // sampled-greedy candidates
     uint64_t path_seed = 0;
     // data

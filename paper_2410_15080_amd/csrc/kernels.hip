@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "kern_common.hpp"
+#include "step_dev.hpp"
 
 namespace htn {
 namespace kern {
@@ -25,106 +26,14 @@ namespace kern {
 template <typename TA, typename TB, typename TC, typename ACC, bool UNARY, bool COMP>
 __global__ __launch_bounds__(kBlk) void k_step(const TA *__restrict__ A, const TB *__restrict__ B, TC *__restrict__ C,
                                               const int2 *__restrict__ tab, StepArgs s) {
-    const int64_t gt = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int64_t grp = gt >> s.log2R;
-    const int64_t o = s.split > 1 ? grp / s.split : grp;
-    const int jc = (int)(grp - o * s.split);  // chunk of the summed range (split > 1)
-    const int sub = (int)(gt & (s.R - 1));
-    const bool active = o < s.n_out;
-    ACC acc = 0, cmp = 0;
-    if (active && s.split > 1) {
-        const int oh = (int)(o / s.n_olo);
-        const int ol = (int)(o - (int64_t)oh * s.n_olo);
-        const int2 x = tab[s.t_ohi + oh], y = tab[s.t_olo + ol];
-        const TA *a0 = A + (x.x + y.x);
-        const TB *b0 = B;
-        if constexpr (!UNARY) b0 = B + (x.y + y.y);
-        const int2 *th = tab + s.t_shi;
-        const int2 *tl = tab + s.t_slo;
-        const int64_t n_sum = (int64_t)s.n_shi * s.n_slo;
-        int64_t e = (int64_t)jc * s.chunk + sub;
-        const int64_t e_end = min(n_sum, (int64_t)(jc + 1) * s.chunk);
-        int sh = (int)(e / s.n_slo);
-        int sl = (int)(e - (int64_t)sh * s.n_slo);
-        const int dq = s.R / s.n_slo, dr = s.R - dq * s.n_slo;
-        for (; e < e_end; e += s.R) {
-            const int2 h = th[sh], l = tl[sl];
-            ACC p = Ld<ACC, TA>::get(a0 + h.x + l.x);
-            if constexpr (!UNARY) p *= Ld<ACC, TB>::get(b0 + h.y + l.y);
-            accum<COMP>(acc, cmp, p);
-            sh += dq;
-            sl += dr;
-            if (sl >= s.n_slo) {
-                sl -= s.n_slo;
-                ++sh;
-            }
-        }
-    } else if (active) {
-        const int oh = (int)(o / s.n_olo);
-        const int ol = (int)(o - (int64_t)oh * s.n_olo);
-        const int2 x = tab[s.t_ohi + oh], y = tab[s.t_olo + ol];
-        const TA *a0 = A + (x.x + y.x);
-        const TB *b0 = B;
-        if constexpr (!UNARY) b0 = B + (x.y + y.y);
-        const int2 *th = tab + s.t_shi;
-        const int2 *tl = tab + s.t_slo;
-        if (s.R == 1) {
-            for (int sh = 0; sh < s.n_shi; ++sh) {
-                const int2 h = th[sh];
-                const TA *a1 = a0 + h.x;
-                const TB *b1 = b0;
-                if constexpr (!UNARY) b1 = b0 + h.y;
-                for (int sl = 0; sl < s.n_slo; ++sl) {
-                    const int2 l = tl[sl];
-                    ACC p = Ld<ACC, TA>::get(a1 + l.x);
-                    if constexpr (!UNARY) p *= Ld<ACC, TB>::get(b1 + l.y);
-                    accum<COMP>(acc, cmp, p);
-                }
-            }
-        } else {
-            const int dq = s.R / s.n_slo, dr = s.R - dq * s.n_slo;
-            int sh = sub / s.n_slo;
-            int sl = sub - sh * s.n_slo;
-            while (sh < s.n_shi) {
-                const int2 h = th[sh], l = tl[sl];
-                ACC p = Ld<ACC, TA>::get(a0 + h.x + l.x);
-                if constexpr (!UNARY) p *= Ld<ACC, TB>::get(b0 + h.y + l.y);
-                accum<COMP>(acc, cmp, p);
-                sh += dq;
-                sl += dr;
-                if (sl >= s.n_slo) {
-                    sl -= s.n_slo;
-                    ++sh;
-                }
-            }
-        }
-    }
-    lane_reduce<COMP>(acc, cmp, s.R);
-    if (active && sub == 0) {
-        if (s.split > 1) {
-            double *q = s.part + 2 * (o * s.split + jc);
-            q[0] = (double)acc;
-            q[1] = COMP ? (double)cmp : 0.0;
-        } else {
-            C[o] = st_cvt<TC>(COMP ? acc + cmp : acc);
-        }
-    }
+    step_block<TA, TB, TC, ACC, UNARY, COMP>(A, B, C, tab, s, blockIdx.x);
 }
 
-// Second pass of a split sum: one wave per output combines its `split`
-// partial (sum, compensation) pairs, lanes striding over them, then a
-// fixed shuffle tree.
+// Second pass of a split sum: one wave per output.
 template <typename TC, bool COMP>
 __global__ __launch_bounds__(64) void k_split_finish(const double *__restrict__ part, TC *__restrict__ C,
                                                     int split) {
-    const int64_t o = blockIdx.x;
-    double sum = 0.0, cmp = 0.0;
-    for (int j = threadIdx.x; j < split; j += 64) {
-        const double *q = part + 2 * (o * split + j);
-        combine<COMP>(sum, cmp, q[0], q[1]);
-    }
-    lane_reduce<COMP>(sum, cmp, 64);
-    if (threadIdx.x == 0) C[o] = st_cvt<TC>(COMP ? sum + cmp : sum);
+    split_finish_one<TC, COMP>(part, C, split, blockIdx.x, threadIdx.x);
 }
 
 template <typename TA, typename TB, typename TC, typename ACC, bool U, bool CMP>
@@ -184,23 +93,9 @@ template <typename TIN, typename TI>
 __global__ __launch_bounds__(kBlk) void k_prep(const PrepDesc *__restrict__ descs, const int2 *__restrict__ tab,
                                                 unsigned char *__restrict__ ws) {
     const PrepDesc &q = descs[blockIdx.y];
-    const TIN *src = (const TIN *)q.src;
     TI *dst = (TI *)(ws + q.dst_off);
-    const int ns = q.ns;
-    for (int e = blockIdx.x * kBlk + threadIdx.x; e < q.size; e += gridDim.x * kBlk) {
-        int se = e;
-        if (q.snlo > 0) {
-            const int eh = e / q.snlo;
-            se = tab[q.sthi + eh].x + tab[q.stlo + (e - eh * q.snlo)].x;
-        }
-        TI v = Ld<TI, TIN>::get(src + se);
-        for (int k = 0; k < ns; ++k) {
-            const int eh = e / q.nlo[k];
-            const int el = e - eh * q.nlo[k];
-            v *= Ld<TI, TIN>::get((const TIN *)q.sp[k] + tab[q.thi[k] + eh].x + tab[q.tlo[k] + el].x);
-        }
-        dst[e] = v;
-    }
+    for (int e = blockIdx.x * kBlk + threadIdx.x; e < q.size; e += gridDim.x * kBlk)
+        dst[e] = prep_value<TIN, TI>(q, tab, e);
 }
 
 hipError_t launch_prep(const PrepDesc *d_desc, int n_desc, int max_size, int tin, int tinter, const int2 *tab,

@@ -126,6 +126,58 @@ hipError_t launch_sv_eval(const SvInst *insts, int n_insts, const SvOp *ops, dou
 hipError_t launch_qt_assemble(const int64_t *start, const int64_t *term_out, const double *coef, int64_t n_entries,
                               const double *outs, double *entries, hipStream_t st);
 
+// Persistent work queue (queue.hip).  Items are the units of a network's
+// per-step plan: an input materialisation (LOAD), a table-driven step or an
+// operand pack (STEP; with split sums its partials), the second pass of a
+// split sum (FINISH), a matrix-core product (GEMM) and the sum of its split-K
+// partial products (KSUM).  An item is cut into tasks of units_per_task
+// units (LOAD and KSUM: 256 elements; STEP: one 256-thread block of the
+// per-step kernel's grid; FINISH: 4 outputs; GEMM: one output tile).
+enum QItemKind { QI_LOAD = 0, QI_STEP = 1, QI_FINISH = 2, QI_GEMM = 3, QI_KSUM = 4 };
+enum QItemFlags { QF_FIRST = 1, QF_LAST = 2, QF_OUT = 4 };
+struct QItem {
+    int32_t kind;
+    int32_t ta, tb, tc;     // dtype codes: operands and result (GEMM: ta packed inputs)
+    int32_t comp, unary;    // Neumaier-compensated FP64 result; single-operand step
+    int32_t dep0, dep1;     // items whose tasks must all be done first (-1: none)
+    int32_t net;            // batch index of the network
+    int32_t flags;          // QF_FIRST: the network's first item (start stamp); QF_LAST:
+                            // completes it (end stamp); QF_OUT: C is outs[net]
+    int32_t units_per_task;
+    int32_t n_tasks;
+    int64_t n_units;
+    const void *A, *B;      // operands (LOAD: unused; KSUM: partial products in A)
+    void *C;                // result
+    const int2 *tab;        // the network's offset tables
+    const PrepDesc *prep;   // LOAD: the materialisation descriptor (dst_off unused)
+    StepArgs s;             // STEP and FINISH geometry
+    int32_t M, N, K, batch, kchunk, ksplit, kper, tiles_m, tiles_n;  // GEMM; KSUM: ksplit
+    int64_t total;          // KSUM: elements of one partial product
+};
+struct QTask {
+    int32_t item, task;
+};
+// Control words of a queue: next task, error flag, exited workgroups.
+enum { QC_NEXT = 0, QC_ERR = 1, QC_EXITED = 2, QC_WORDS = 4 };
+// GEMM kind of a queue kernel for packed inputs of dtype tin and results of
+// dtype tout (1..5; -1: no such product), its dynamic LDS bytes, and the
+// resident workgroups per compute unit of the queue kernel of kind gk
+// (0: no GEMM items).
+int queue_gemm_kind(int tin, int tout);
+int queue_gemm_lds(int gk);
+int queue_blocks_per_cu(int gk, int lds_bytes);
+// Runs the queue in one launch of n_blocks workgroups.  counters[i] must
+// hold items[i].n_tasks and ctrl[QC_NEXT], ctrl[QC_EXITED] zero at launch;
+// the last workgroup to finish restores them from init, so the next launch
+// starts clean.  ctrl[QC_ERR] is set to 1 if a task gave up waiting for a
+// dependency (it never does on a queue listed in dependency order).
+// stamps (optional): [2 net] start, [2 net + 1] end of each network, device
+// clock; run_start (optional): clock at the start of the launch.  gk: the
+// GEMM kind of every GEMM item (0 if there are none).
+hipError_t launch_queue(const QItem *items, const QTask *tasks, int n_tasks, const int32_t *init, int32_t *counters,
+                        int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps, int64_t *run_start, int gk,
+                        int lds_bytes, int n_blocks, hipStream_t st);
+
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.
 hipError_t launch_slice_sum(const void *parts, int n_slices, int64_t n, void *out, int tout, bool comp,

@@ -23,109 +23,10 @@
 #include <climits>
 
 #include "kernels.hpp"
+#include "mfma_dev.hpp"
 
 namespace htn {
 namespace kern {
-
-typedef uint16_t bf16_t;
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-
-constexpr int GBN = 128;
-
-template <typename T>
-struct MfmaOp;
-
-template <>
-struct MfmaOp<double> {
-    typedef double frag;
-    typedef d4_t acc;
-    static constexpr int KI = 4;   // K per instruction
-    static constexpr int KPL = 1;  // K values per lane
-    static constexpr int BK = 16;
-    static constexpr int PAD = 1;
-    // output block: lane holds rows lane/16 + 4*r (interleaved)
-    __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ __forceinline__ static frag ld(const double *p) { return *p; }
-};
-
-template <>
-struct MfmaOp<float> {
-    typedef float frag;
-    typedef f4_t acc;
-    static constexpr int KI = 4;
-    static constexpr int KPL = 1;
-    static constexpr int BK = 32;
-    static constexpr int PAD = 1;
-    // output block: lane holds rows 4*(lane/16) + r (blocked)
-    __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ __forceinline__ static frag ld(const float *p) { return *p; }
-};
-
-template <>
-struct MfmaOp<bf16_t> {
-    typedef bf8_t frag;
-    typedef f4_t acc;
-    static constexpr int KI = 32;
-    static constexpr int KPL = 8;
-    static constexpr int BK = 64;
-    static constexpr int PAD = 8;
-    __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-    __device__ __forceinline__ static acc mma(frag a, frag b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-    __device__ __forceinline__ static frag ld(const bf16_t *p) { return *(const bf8_t *)p; }
-};
-
-// Load a ROWS x BK tile (rows r0.., K-columns k0..) of a [rows][K] operand
-// into registers: 16 bytes per load, zero outside the matrix.
-template <typename T, int ROWS>
-struct TileLoader {
-    static constexpr int BK = MfmaOp<T>::BK;
-    static constexpr int EPV = 16 / sizeof(T);               // elements per 16B vector
-    static constexpr int VPR = BK / EPV;                      // vectors per row
-    static constexpr int NV = ROWS * VPR / 256;               // vectors per thread
-    static_assert(NV * 256 == ROWS * VPR, "tile rows must fill the workgroup's loads");
-    uint4 v[NV];
-    // rows of length K (the row stride); columns at or beyond klim read 0
-    __device__ __forceinline__ void load(const T *__restrict__ src, int rows, int K, int klim, int r0, int k0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int idx = threadIdx.x + i * 256;
-            const int r = idx / VPR, c = (idx % VPR) * EPV;
-            const int gr = r0 + r, gk = k0 + c;
-            if (gr < rows && gk + EPV <= klim && ((K % EPV) == 0)) {
-                v[i] = *(const uint4 *)(src + (int64_t)gr * K + gk);
-            } else {
-                T tmp[EPV];
-#pragma unroll
-                for (int e = 0; e < EPV; ++e) {
-                    const bool ok = gr < rows && gk + e < klim;
-                    tmp[e] = ok ? src[(int64_t)gr * K + gk + e] : T(0);
-                }
-                v[i] = *(const uint4 *)tmp;
-            }
-        }
-    }
-    __device__ __forceinline__ void store(T *lds) const {
-        constexpr int LD = BK + MfmaOp<T>::PAD;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int idx = threadIdx.x + i * 256;
-            const int r = idx / VPR, c = (idx % VPR) * EPV;
-            const T *tv = (const T *)&v[i];
-#pragma unroll
-            for (int e = 0; e < EPV; ++e) lds[r * LD + c + e] = tv[e];
-        }
-    }
-};
 
 // Output tiles t = ((b * ksplit + kz) * tiles_m + tm) * tiles_n + tn: batch
 // entry b, K range kz (of length kper, a multiple of BK), tile row tm and
@@ -293,8 +194,8 @@ template <typename T, typename TOUT, bool C64>
 static hipError_t go_gemm(const void *A, const void *B, void *C, int M, int N, int K, int batch, int kchunk,
                           int ksplit, void *part, hipStream_t st) {
     const int64_t sA = (int64_t)M * K, sB = (int64_t)N * K, sC = (int64_t)M * N;
-    const int kper = ksplit > 1 ? ((K + ksplit - 1) / ksplit + 63) / 64 * 64 : K;
-    if (ksplit > 1) ksplit = (K + kper - 1) / kper;
+    int kper = 0;
+    gemm_ksplit(K, ksplit, kper);
     constexpr int WI = C64 ? 2 : 4;
     const int tiles_n = (N + GBN - 1) / GBN, tiles_m = (M + 32 * WI - 1) / (32 * WI);
     const int64_t n_tiles = (int64_t)tiles_n * tiles_m * batch * ksplit;

@@ -284,6 +284,7 @@ Net structure_copy(const Net &n) {
     t.path_samples = n.path_samples;
     t.path_seed = n.path_seed;
     t.slice_mode = n.slice_mode;
+    t.queue_mode = n.queue_mode;
     return t;
 }
 

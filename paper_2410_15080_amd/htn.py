@@ -22,7 +22,7 @@ HTN_SUM_PLAIN, HTN_SUM_FP64, HTN_SUM_COMPENSATED = 0, 1, 2
 HTN_EXEC_AUTO, HTN_EXEC_STEPS, HTN_EXEC_FUSED = 0, 1, 2
 HTN_PATH_GREEDY, HTN_PATH_LEARNED, HTN_PATH_SAMPLED = -1, -2, -3
 HTN_OPT_EXEC, HTN_OPT_MAX_INTERMEDIATE, HTN_OPT_FUSED_LDS_BYTES, HTN_OPT_MFMA = 0, 1, 2, 3
-HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS, HTN_OPT_SLICE = 4, 5, 6, 7
+HTN_OPT_PATH_SAMPLES, HTN_OPT_PATH_SEED, HTN_OPT_FUSED_THREADS, HTN_OPT_SLICE, HTN_OPT_QUEUE = 4, 5, 6, 7, 8
 HTN_MODEL_FEATURES, HTN_MODEL_HIDDEN = 26, 64
 
 STATUS = ["HTN_OK", "HTN_E_ARG", "HTN_E_LABEL", "HTN_E_SHAPE", "HTN_E_PATH", "HTN_E_OOM",
@@ -141,6 +141,7 @@ def load_library():
         "htn_autotune": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), P, i32p, i32p, f32p]),
         "htn_batch_set_event_timing": (I32, [P, I32]),
         "htn_batch_launch_ms": (I32, [P, f32p, f32p, i32p]),
+        "htn_batch_queue_info": (I32, [P, i32p, i32p, i32p]),
         "htn_qpd_sample": (I32, [I32, ctypes.POINTER(ctypes.c_double), I64, ctypes.POINTER(ctypes.c_double),
                                  i64p, ctypes.POINTER(ctypes.c_double)]),
         "htn_truncate_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(htn_truncation), I32]),
@@ -479,6 +480,14 @@ def htn_batch_launch_ms(batch: Batch):
     k = ctypes.c_int32()
     _check(load_library().htn_batch_launch_ms(batch.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(k)))
     return float(a.value), float(b.value), int(k.value)
+
+
+def htn_batch_queue_info(batch: Batch):
+    """(networks in the batch's work queue, tasks, error flag); waits for
+    the device and clears the flag."""
+    a, t, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().htn_batch_queue_info(batch.handle, ctypes.byref(a), ctypes.byref(t), ctypes.byref(e)))
+    return int(a.value), int(t.value), int(e.value)
 
 
 def htn_batch_destroy(batch: Batch) -> None:

@@ -143,6 +143,10 @@ def test_structural_errors():
     _expect("HTN_E_PATH", htn.htn_set_path, net, [(0, 1), (2, 0)])
     _expect("HTN_E_ARG", htn.htn_set_path, net, -7)
     _expect("HTN_E_ARG", htn.htn_set_option, net, htn.HTN_OPT_EXEC, 9)
+    _expect("HTN_E_ARG", htn.htn_set_option, net, htn.HTN_OPT_QUEUE, 3)
+    _expect("HTN_E_ARG", htn.htn_set_option, net, htn.HTN_OPT_QUEUE, -1)
+    for mode in (0, 1, 2):
+        htn.htn_set_option(net, htn.HTN_OPT_QUEUE, mode)
     # a failed call leaves the previous path in place
     htn.htn_set_path(net, [(1, 0)])
     _expect("HTN_E_PATH", htn.htn_set_path, net, [(1, 1)])
