@@ -180,8 +180,10 @@ typedef enum {
     HTN_OPT_SLICE = 7,             /* 0 (default): a path whose largest intermediate exceeds
                                       HTN_OPT_MAX_INTERMEDIATE is HTN_E_OOM.  1: slicing (see below) */
     HTN_OPT_QUEUE = 8              /* batches: 0 (default) a net run step by step goes to the batch's
-                                      work queue; 1 the net always does (even one the fused kernel
-                                      could take); 2 never (one launch per step, on side streams) */
+                                      work queue if its kernel steps are small (mean below 2^19
+                                      multiplications), else one launch per step; 1 the net always
+                                      goes to the queue (even one the fused kernel could take);
+                                      2 never (one launch per step, on side streams) */
 } htn_option;
 
 /* Slicing under the intermediate cap (HTN_OPT_SLICE = 1).  Contraction
@@ -297,9 +299,10 @@ htn_status htn_batch_set_event_timing(htn_batch_t batch, int32_t on);
  * a batch runs the steps of all its step-by-step networks in one launch).
  * Networks too large for one fused workgroup (HTN_OPT_QUEUE, above) have
  * their input materialisations and every block of every step cut into
- * tasks, listed in dependency order; the resident workgroups of one
- * persistent launch take the tasks in list order and each waits (bounded)
- * until the steps it reads are complete.  Each network's intermediates get
+ * tasks, listed in dependency order; each network is assigned to one XCD
+ * (heaviest first, to the least loaded), and the resident workgroups of
+ * one persistent launch take the tasks of their own XCD in list order, each
+ * waiting (bounded) until the steps it reads are complete.  Each network's intermediates get
  * their own device buffer for the batch's lifetime (no reuse between
  * steps), allocated at htn_batch_create.  A network whose matrix-core
  * steps use another input/output type pair than the first such network's,
@@ -307,8 +310,9 @@ htn_status htn_batch_set_event_timing(htn_batch_t batch, int32_t on);
  * launch per step instead.  Runs of one batch must not overlap.
  * htn_batch_queue_info (waits for the device): *n_nets networks and
  * *n_tasks tasks in the queue; *error = 1 if a task of any run since the
- * last call gave up waiting (never for a consistent queue; the flag is then
- * cleared).  Any pointer may be NULL.                                     */
+ * last call gave up waiting, 2 if some XCD's tasks were left untaken
+ * (neither happens for a consistent queue; the flag is then cleared).
+ * Any pointer may be NULL.                                     */
 htn_status htn_batch_queue_info(htn_batch_t batch, int32_t *n_nets, int32_t *n_tasks, int32_t *error);
 htn_status htn_batch_launch_ms(htn_batch_t batch, float *prep_ms, float *fused_ms, int32_t *runs);
 void htn_batch_destroy(htn_batch_t batch);

@@ -109,11 +109,11 @@ struct htn_batch {
     struct Queue {
         kern::QItem *d_items = nullptr;
         kern::QTask *d_tasks = nullptr;
-        int32_t *d_counters = nullptr, *d_init = nullptr, *d_ctrl = nullptr;
+        int32_t *d_counters = nullptr, *d_init = nullptr, *d_ctrl = nullptr, *d_qinfo = nullptr;
         void *d_ws = nullptr;
-        int n_items = 0, n_tasks = 0, n_nets = 0, gk = 0, lds = 0, n_blocks = 0;
+        int n_items = 0, n_tasks = 0, n_nets = 0, gk = 0, lds = 0, n_blocks = 0, n_sub = 0;
         hipStream_t stream = nullptr;
-        hipEvent_t ev_join = nullptr;
+        hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     } q;
     std::vector<char> in_queue;
     kern::FusedDesc *d_desc = nullptr;
@@ -916,8 +916,10 @@ static void batch_free(htn_batch *b) {
     dfree(b->q.d_counters);
     dfree(b->q.d_init);
     dfree(b->q.d_ctrl);
+    dfree(b->q.d_qinfo);
     dfree(b->q.d_ws);
     if (b->q.ev_join) (void)hipEventDestroy(b->q.ev_join);
+    if (b->q.ev_fork) (void)hipEventDestroy(b->q.ev_fork);
     if (b->q.stream) (void)hipStreamDestroy(b->q.stream);
     b->q = htn_batch::Queue{};
     dfree(b->d_desc);
@@ -954,7 +956,8 @@ namespace {
 struct QBuild {
     std::vector<kern::QItem> items;
     std::vector<std::array<int64_t, 4>> off;
-    std::vector<int> level;
+    std::vector<int> level, sub;  // dependency level and sub-queue (XCD) of each item
+    int cur_sub = 0;               // sub-queue of the net being added
     int64_t ws = 0;
     int gk = 0;  // GEMM kind of the queue (0: no GEMM items yet)
     int64_t take(int64_t bytes) {
@@ -969,6 +972,7 @@ struct QBuild {
         items.push_back(it);
         off.push_back(o);
         level.push_back(lvl);
+        sub.push_back(cur_sub);
         return (int)items.size() - 1;
     }
 };
@@ -985,15 +989,25 @@ static kern::QItem q_item(int kind, int net, const Net &n) {
     return it;
 }
 
-// Blocks of a table-driven step per task: about 256 dependent terms per
-// thread, but at least min(blocks, 256) tasks so that one step spreads
-// over the chip.
-static int q_step_blocks_per_task(const kern::StepArgs &a, int64_t n_sum, int64_t blocks) {
+// Task sizes of the work queue: each task carries about kQTaskWork operand
+// reads (or element writes), and one item is cut into at most
+// kQMaxItemTasks tasks: a task's fixed cost (taking it, waiting, one
+// device-scope acquire and release) is then small against its work.
+static constexpr int64_t kQTaskWork = int64_t(1) << 14;
+static constexpr int64_t kQMaxItemTasks = 1024;
+
+static int64_t q_units_per_task(int64_t units, int64_t work_per_unit) {
+    const int64_t work = units * std::max<int64_t>(1, work_per_unit);
+    const int64_t tasks = std::min<int64_t>(kQMaxItemTasks, std::max<int64_t>(1, work / kQTaskWork));
+    return std::max<int64_t>(1, (units + tasks - 1) / tasks);
+}
+
+// Blocks of a table-driven step per task (operand reads per block: 256
+// threads, each summing its share of the summed range).
+static int64_t q_step_blocks_per_task(const kern::StepArgs &a, int64_t n_sum, int64_t blocks) {
     const int64_t chunk = a.split > 1 ? a.chunk : n_sum;
     const int64_t per_thread = std::max<int64_t>(1, (chunk + a.R - 1) / a.R);
-    const int64_t by_work = std::max<int64_t>(1, 256 / per_thread);
-    const int64_t by_spread = std::max<int64_t>(1, (blocks + 255) / 256);
-    return (int)std::max<int64_t>(1, std::min<int64_t>({by_work, by_spread, 64}));
+    return q_units_per_task(blocks, kBlock * per_thread);
 }
 
 // Appends the items of net `bi` of the batch; false (nothing appended) if
@@ -1031,7 +1045,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
         it.tc = tint;
         it.prep = D.d_prep + j++;
         it.n_units = (lp.size + 255) / 256;
-        it.units_per_task = 16;
+        it.units_per_task = (int32_t)q_units_per_task(it.n_units, 256 * (1 + (int64_t)lp.scales.size()));
         voff[lp.value] = Q.take(lp.size * es);
         prod[lp.value] = Q.add(it, {-1, -1, voff[lp.value], -1});
     }
@@ -1086,7 +1100,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
                 it.unary = 1;
                 it.s = pack_args(pk);
                 it.n_units = (pk.n + kBlock - 1) / kBlock;
-                it.units_per_task = q_step_blocks_per_task(it.s, 1, it.n_units);
+                it.units_per_task = (int32_t)q_step_blocks_per_task(it.s, 1, it.n_units);
                 Opd r;
                 r.off = o[2] = Q.take(pk.n * pes);
                 r.t = tp;
@@ -1125,7 +1139,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
                 ksum.dep0 = g;
                 ksum.flags = out_flags;
                 ksum.n_units = (total + 255) / 256;
-                ksum.units_per_task = 16;
+                ksum.units_per_task = (int32_t)q_units_per_task(ksum.n_units, 256 * (int64_t)ks);
                 last = Q.add(ksum, {part_off, -1, coff, -1});
             } else {
                 it.flags = out_flags;
@@ -1163,7 +1177,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
                 o[3] = Q.take(s.n_out * s.split_global * 16);
             }
             it.n_units = (s.n_out * a.R * a.split + kBlock - 1) / kBlock;
-            it.units_per_task = q_step_blocks_per_task(a, s.n_sum, it.n_units);
+            it.units_per_task = (int32_t)q_step_blocks_per_task(a, s.n_sum, it.n_units);
             if (a.split > 1) {
                 const int g = Q.add(it, o);
                 kern::QItem fin = q_item(kern::QI_FINISH, bi, n);
@@ -1173,7 +1187,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
                 fin.dep0 = g;
                 fin.flags = out_flags;
                 fin.n_units = (s.n_out + 3) / 4;
-                fin.units_per_task = 16;
+                fin.units_per_task = (int32_t)q_units_per_task(fin.n_units, 4 * (int64_t)a.split);
                 last = Q.add(fin, {-1, -1, coff, o[3]});
             } else {
                 it.flags = out_flags;
@@ -1187,20 +1201,58 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
         Q.items.resize(first);
         Q.off.resize(first);
         Q.level.resize(first);
+        Q.sub.resize(first);
         throw Error{HTN_E_STATE, "queue: the last kernel step does not write the output"};
     }
     return true;
 }
 
-// Orders the items by dependency level (a task's producers all come
-// earlier), cuts them into tasks, allocates the workspace and uploads.
-static void queue_upload(htn_batch *b, QBuild &Q) {
+// A net run step by step joins the work queue by default when its kernel
+// steps are small (mean below kQueueMeanStepMults multiplications): a
+// launch per step would then cost about as much as the step.  Nets of few
+// large steps keep one launch per step, which spreads each step over the
+// whole device (the queue keeps a net on one XCD).
+static constexpr double kQueueMeanStepMults = 524288.0;
+static bool queue_by_default(const Net &n) {
+    const size_t k = n.plan.kernel_steps.size();
+    return k > 0 && n.plan.mults / (double)k < kQueueMeanStepMults;
+}
+
+// Hardware ids of the device's XCDs (a probe launch at first use per
+// device; {0} if the probe finds none).
+static std::vector<int> device_xccs(int dev) {
+    static std::mutex mu;
+    static std::unordered_map<int, std::vector<int>> known;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(dev);
+    if (it != known.end()) return it->second;
+    uint32_t *d = dalloc<uint32_t>(1);
+    const uint32_t mask = kern::queue_xcc_mask(d);
+    dfree(d);
+    std::vector<int> ids;
+    for (int x = 0; x < kern::QC_MAX_SUB; ++x)
+        if (mask & (1u << x)) ids.push_back(x);
+    if (ids.empty()) ids.push_back(0);
+    known[dev] = ids;
+    return ids;
+}
+
+// Orders the items by sub-queue, then dependency level (a task's producers
+// all come earlier in its sub-queue), cuts them into tasks, allocates the
+// workspace and uploads.
+static void queue_upload(htn_batch *b, QBuild &Q, const std::vector<int> &sub_xcc) {
     htn_batch::Queue &q = b->q;
     const int ni = (int)Q.items.size();
+    const int n_sub = (int)sub_xcc.size();
     std::vector<int> order(ni), pos(ni);
     for (int i = 0; i < ni; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return Q.level[x] < Q.level[y]; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return Q.sub[x] != Q.sub[y] ? Q.sub[x] < Q.sub[y] : Q.level[x] < Q.level[y];
+    });
     for (int i = 0; i < ni; ++i) pos[order[i]] = i;
+    std::vector<int32_t> qinfo(kern::kQInfoWords, -1);
+    for (int k = 0; k < n_sub; ++k) qinfo[sub_xcc[k]] = k;
+    for (int k = 0; k <= n_sub; ++k) qinfo[kern::QC_MAX_SUB + k] = 0;
     q.d_ws = Q.ws > 0 ? dalloc_bytes((size_t)Q.ws) : nullptr;
     unsigned char *ws = (unsigned char *)q.d_ws;
     std::vector<kern::QItem> items(ni);
@@ -1228,7 +1280,15 @@ static void queue_upload(htn_batch *b, QBuild &Q) {
         init[i] = (int32_t)nt;
         for (int64_t t = 0; t < nt; ++t) tasks.push_back(kern::QTask{i, (int32_t)t});
         items[i] = it;
+        if (it.dep0 >= 0 && Q.sub[order[it.dep0]] != Q.sub[order[i]]) throw Error{HTN_E_STATE, "queue: dependency across sub-queues"};
+        if (it.dep1 >= 0 && Q.sub[order[it.dep1]] != Q.sub[order[i]]) throw Error{HTN_E_STATE, "queue: dependency across sub-queues"};
+        qinfo[kern::QC_MAX_SUB + Q.sub[order[i]] + 1] = (int32_t)tasks.size();
     }
+    for (int k = 1; k <= n_sub; ++k)  // sub-queues without items
+        qinfo[kern::QC_MAX_SUB + k] = std::max(qinfo[kern::QC_MAX_SUB + k], qinfo[kern::QC_MAX_SUB + k - 1]);
+    q.n_sub = n_sub;
+    q.d_qinfo = dalloc<int32_t>(kern::kQInfoWords);
+    HIP_TRY(hipMemcpy(q.d_qinfo, qinfo.data(), kern::kQInfoWords * 4, hipMemcpyHostToDevice));
     q.n_items = ni;
     q.n_tasks = (int)tasks.size();
     q.gk = Q.gk;
@@ -1247,7 +1307,9 @@ static void queue_upload(htn_batch *b, QBuild &Q) {
     int dev = 0, cus = 256;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    q.n_blocks = (int)std::min<int64_t>(q.n_tasks, (int64_t)kern::queue_blocks_per_cu(q.gk, q.lds) * cus);
+    // every XCD must get workgroups: the whole resident capacity (workgroups
+    // are spread over the XCDs; those without a task leave at once)
+    q.n_blocks = std::max(kern::queue_blocks_per_cu(q.gk, q.lds) * cus, 2 * kern::QC_MAX_SUB);
 }
 
 htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) {
@@ -1329,20 +1391,27 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
                 b->side_of.push_back(q);
                 load[q] += nets[i]->plan.mults;
             }
-            // the work queue takes every step-by-step net it can
+            // the work queue takes every step-by-step net it can, each net
+            // on the least loaded XCD (heaviest first)
             QBuild Q;
+            const std::vector<int> xccs = device_xccs(dev);
+            std::vector<double> xload(xccs.size(), 0.0);
             b->in_queue.assign(b->step_nets.size(), 0);
             for (size_t k = 0; k < b->step_nets.size(); ++k) {
                 Net &net = *nets[b->step_nets[k]];
-                if (net.queue_mode != 2 && queue_net(Q, net, b->step_nets[k])) {
+                if (net.queue_mode == 2 || (net.queue_mode == 0 && !queue_by_default(net))) continue;
+                Q.cur_sub = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+                if (queue_net(Q, net, b->step_nets[k])) {
                     b->in_queue[k] = 1;
                     ++b->q.n_nets;
+                    xload[Q.cur_sub] += net.plan.mults;
                 }
             }
             if (!Q.items.empty()) {
-                queue_upload(b, Q);
+                queue_upload(b, Q, xccs);
                 if (!b->groups.empty()) {
                     HIP_TRY(hipStreamCreateWithFlags(&b->q.stream, hipStreamNonBlocking));
+                    HIP_TRY(hipEventCreateWithFlags(&b->q.ev_fork, hipEventDisableTiming));
                     HIP_TRY(hipEventCreateWithFlags(&b->q.ev_join, hipEventDisableTiming));
                 }
             }
@@ -1411,29 +1480,33 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto &g = b->groups[gi];
-        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute, gi == 0 && prep_stamps ? run_start : nullptr,
-                                   st));
+        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_max, g.compute,
+                                   gi == 0 && prep_stamps ? run_start : nullptr, st));
     }
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     if (!b->sides.empty()) {
         HIP_TRY(hipEventRecord(b->ev_fork, st));
         for (hipStream_t q : b->sides) HIP_TRY(hipStreamWaitEvent(q, b->ev_fork, 0));
     }
+    if (use_queue && !queue_alone) {
+        HIP_TRY(hipEventRecord(b->q.ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(b->q.stream, b->q.ev_fork, 0));
+    }
     for (auto &g : b->groups)
         HIP_TRY(kern::launch_fused(b->d_desc, g.d_order, b->d_outs, b->d_stamps, nullptr, b->d_phase, b->max_phases,
                                    (int)g.idx.size(), g.lds, g.compute, g.fm, g.threads, st));
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
+    // the queue goes after the fused launch: launched first, its resident
+    // workgroups would hold every CU while the fused nets wait
     if (use_queue) {
         const htn_batch::Queue &q = b->q;
-        hipStream_t qs = queue_alone ? st : q.stream;
-        if (!queue_alone) HIP_TRY(hipStreamWaitEvent(qs, b->ev_fork, 0));
-        HIP_TRY(kern::launch_queue(q.d_items, q.d_tasks, q.n_tasks, q.d_init, q.d_counters, q.n_items, q.d_ctrl,
-                                   b->d_outs, b->d_stamps, queue_alone ? run_start : nullptr, q.gk, q.lds,
-                                   q.n_blocks, qs));
-        if (!queue_alone) {
-            HIP_TRY(hipEventRecord(q.ev_join, qs));
-            HIP_TRY(hipStreamWaitEvent(st, q.ev_join, 0));
-        }
+        HIP_TRY(kern::launch_queue(q.d_items, q.d_tasks, q.d_qinfo, q.n_sub, q.d_init, q.d_counters, q.n_items,
+                                   q.d_ctrl, b->d_outs, b->d_stamps, queue_alone ? run_start : nullptr, q.gk, q.lds,
+                                   q.n_blocks, queue_alone ? st : q.stream));
+    }
+    if (use_queue && !queue_alone) {
+        HIP_TRY(hipEventRecord(b->q.ev_join, b->q.stream));
+        HIP_TRY(hipStreamWaitEvent(st, b->q.ev_join, 0));
     }
     for (size_t k = 0; k < b->step_nets.size(); ++k) {
         if (use_queue && b->in_queue[k]) continue;

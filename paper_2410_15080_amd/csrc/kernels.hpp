@@ -157,8 +157,18 @@ struct QItem {
 struct QTask {
     int32_t item, task;
 };
-// Control words of a queue: next task, error flag, exited workgroups.
-enum { QC_NEXT = 0, QC_ERR = 1, QC_EXITED = 2, QC_WORDS = 4 };
+// Control words of a queue: error flag, exited workgroups, then the next
+// task of each sub-queue.  ctrl[QC_ERR]: 1 a task gave up waiting for a
+// dependency, 2 a sub-queue was left with tasks nobody took.
+enum { QC_ERR = 0, QC_EXITED = 1, QC_NEXT = 2, QC_MAX_SUB = 16, QC_WORDS = QC_NEXT + QC_MAX_SUB };
+// qinfo: [xcc] sub-queue of the workgroups on XCD xcc (-1: none), for
+// xcc < QC_MAX_SUB; then QC_MAX_SUB + 1 task offsets (sub-queue k holds
+// tasks [qinfo[QC_MAX_SUB + k], qinfo[QC_MAX_SUB + k + 1])).
+constexpr int kQInfoWords = 2 * QC_MAX_SUB + 1;
+// Bit x set: some workgroup of a wide probe launch (4096 workgroups) ran on
+// XCD x (hardware XCC id, x < QC_MAX_SUB).  d_word: one device word of
+// scratch.  0 on failure.
+uint32_t queue_xcc_mask(uint32_t *d_word);
 // GEMM kind of a queue kernel for packed inputs of dtype tin and results of
 // dtype tout (1..5; -1: no such product), its dynamic LDS bytes, and the
 // resident workgroups per compute unit of the queue kernel of kind gk
@@ -166,17 +176,16 @@ enum { QC_NEXT = 0, QC_ERR = 1, QC_EXITED = 2, QC_WORDS = 4 };
 int queue_gemm_kind(int tin, int tout);
 int queue_gemm_lds(int gk);
 int queue_blocks_per_cu(int gk, int lds_bytes);
-// Runs the queue in one launch of n_blocks workgroups.  counters[i] must
-// hold items[i].n_tasks and ctrl[QC_NEXT], ctrl[QC_EXITED] zero at launch;
-// the last workgroup to finish restores them from init, so the next launch
-// starts clean.  ctrl[QC_ERR] is set to 1 if a task gave up waiting for a
-// dependency (it never does on a queue listed in dependency order).
+// Runs the queue in one launch of n_blocks workgroups; each takes tasks from
+// the sub-queue of the XCD it runs on.  counters[i] must hold
+// items[i].n_tasks and the ctrl words after QC_ERR zero at launch; the
+// last workgroup to finish restores them, so the next launch starts clean.
 // stamps (optional): [2 net] start, [2 net + 1] end of each network, device
 // clock; run_start (optional): clock at the start of the launch.  gk: the
 // GEMM kind of every GEMM item (0 if there are none).
-hipError_t launch_queue(const QItem *items, const QTask *tasks, int n_tasks, const int32_t *init, int32_t *counters,
-                        int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps, int64_t *run_start, int gk,
-                        int lds_bytes, int n_blocks, hipStream_t st);
+hipError_t launch_queue(const QItem *items, const QTask *tasks, const int32_t *qinfo, int n_sub, const int32_t *init,
+                        int32_t *counters, int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps,
+                        int64_t *run_start, int gk, int lds_bytes, int n_blocks, hipStream_t st);
 
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.

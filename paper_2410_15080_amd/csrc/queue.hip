@@ -4,18 +4,24 @@
 //
 // Every input materialisation, every block of a table-driven step, every
 // second pass of a split sum, every output tile of a matrix-core product
-// and every block of a split-K sum is a task.  The tasks are listed in
-// dependency order (a task's producers come earlier in the list) and the
-// resident workgroups of one launch take them in list order from an atomic
-// counter.  A task first waits until the counters of the items it reads
-// show all their tasks done, then runs, publishes its results with a
-// device-scope release and counts itself done.  Since tasks are taken in
-// list order, the earliest unfinished task never waits on an unfinished
-// task, so the queue always drains.  Every wait is bounded as well: a bound
-// that would only trip on an inconsistent queue sets an error flag and the
-// task goes on, so the launch always ends.  The last workgroup to leave
-// restores the counters, so the next launch (or graph replay) starts clean
-// without a memset.
+// and every block of a split-K sum is a task.  Each network belongs to one
+// XCD: its tasks form part of that XCD's sub-queue, listed in dependency
+// order (a task's producers come earlier), and only workgroups running on
+// that XCD (read from the hardware XCC id) take them, in list order, from
+// the sub-queue's atomic counter.  A task first waits until the counters
+// of the items it reads show all their tasks done, then runs, and is
+// counted done once every wave's stores have completed.  Producer and
+// consumer thus always share one L2 (the XCD's), which is coherent for its
+// CUs: a task needs no L2 write-back or invalidation, only an L1
+// invalidation before reading what other CUs wrote.
+//
+// Since tasks are taken in list order, the earliest unfinished task of a
+// sub-queue never waits on an unfinished task, so every sub-queue drains.
+// Every wait is bounded as well: a bound that would only trip on an
+// inconsistent queue sets an error flag and the task goes on, so the
+// launch always ends.  The last workgroup to leave checks that every
+// sub-queue was drained and restores the counters, so the next launch (or
+// graph replay) starts clean without a memset.
 //
 // The task bodies are the per-step kernels' own (step_dev.hpp,
 // mfma_dev.hpp), so a network gives the same result bit for bit through
@@ -41,8 +47,13 @@ constexpr int kQThreads = 256;
 // inconsistent queue still ends promptly.
 constexpr int64_t kQWaitTicks = 50000000;
 
-__device__ __forceinline__ int q_load_acquire(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int q_load_relaxed(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Hardware id of the XCD the calling wave runs on (HW_REG_XCC_ID).
+__device__ __forceinline__ int q_xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20) & 15u);
 }
 
 template <typename TA, typename TB, typename TC, typename ACC, bool U, bool CMP>
@@ -166,100 +177,120 @@ __device__ void q_gemm(const QItem &it, void *C, int64_t u0, int64_t u1, unsigne
 }
 
 template <int GK>
-__global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(GK ? 2 : 1))) void k_queue(const QItem *__restrict__ items, const QTask *__restrict__ tasks,
-                                                     int n_tasks, const int32_t *__restrict__ init,
-                                                     int32_t *__restrict__ counters, int n_items,
-                                                     int32_t *__restrict__ ctrl, void *const *__restrict__ outs,
-                                                     int64_t *__restrict__ stamps, int64_t *__restrict__ run_start) {
+__global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(GK ? 2 : 1))) void k_queue(
+    const QItem *__restrict__ items, const QTask *__restrict__ tasks, const int32_t *__restrict__ qinfo, int n_sub,
+    const int32_t *__restrict__ init, int32_t *__restrict__ counters, int n_items, int32_t *__restrict__ ctrl,
+    void *const *__restrict__ outs, int64_t *__restrict__ stamps, int64_t *__restrict__ run_start) {
     extern __shared__ __align__(16) unsigned char q_lds[];
     __shared__ int task_s, last_s;
-    // Thread 0 counts the previous task done and takes the next task in one
-    // block at the top of the loop, so that every path back to the loop
-    // head runs through the same barriers: were the two thread-0 blocks
-    // apart, the compiler could thread the lanes that skip them straight
-    // back to the head and repeat a task on them.
-    int prev = -1;  // the previous task's item (uniform)
-    for (;;) {
-        if (threadIdx.x == 0) {
-            if (prev >= 0) {
-                const int left =
-                    __hip_atomic_fetch_add(counters + prev, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                const QItem &pi = items[prev];
-                if (stamps && (pi.flags & QF_LAST) && left == 1) stamps[2 * pi.net + 1] = (int64_t)wall_clock64();
-            }
-            task_s = atomicAdd(ctrl + QC_NEXT, 1);
-        }
-        __syncthreads();
-        // uniform, and known to be: the loop exit must not look divergent
-        const int t = __builtin_amdgcn_readfirstlane(task_s);
-        if (t >= n_tasks) break;
-        const QTask tk = tasks[t];
-        const QItem &it = items[tk.item];
-        if (threadIdx.x == 0) {
-            if (t == 0 && run_start) *run_start = (int64_t)wall_clock64();
-            for (int d = 0; d < 2; ++d) {
-                const int dep = d == 0 ? it.dep0 : it.dep1;
-                if (dep < 0 || __hip_atomic_load(ctrl + QC_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
-                const int64_t t0 = (int64_t)wall_clock64();
-                while (q_load_acquire(counters + dep) > 0) {
-                    if ((int64_t)wall_clock64() - t0 > kQWaitTicks) {
-                        atomicExch(ctrl + QC_ERR, 1);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+    const int sub = qinfo[q_xcc_id()];  // uniform: every wave of a workgroup runs on one XCD
+    if (sub >= 0) {
+        const int q_beg = qinfo[QC_MAX_SUB + sub], q_len = qinfo[QC_MAX_SUB + sub + 1] - q_beg;
+        // Thread 0 counts the previous task done and takes the next task in
+        // one block at the top of the loop, so that every path back to the
+        // loop head runs through the same barriers: were the two thread-0
+        // blocks apart, the compiler could thread the lanes that skip them
+        // straight back to the head and repeat a task on them.
+        int prev = -1;  // the previous task's item (uniform)
+        for (;;) {
+            if (threadIdx.x == 0) {
+                if (prev >= 0) {
+                    const int left =
+                        __hip_atomic_fetch_add(counters + prev, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const QItem &pi = items[prev];
+                    if (stamps && (pi.flags & QF_LAST) && left == 1)
+                        stamps[2 * pi.net + 1] = (int64_t)wall_clock64();
                 }
+                task_s = atomicAdd(ctrl + QC_NEXT + sub, 1);
             }
-            if (stamps && (it.flags & QF_FIRST) && tk.task == 0) stamps[2 * it.net] = (int64_t)wall_clock64();
+            __syncthreads();
+            // uniform, and known to be: the loop exit must not look divergent
+            const int t = __builtin_amdgcn_readfirstlane(task_s);
+            if (t >= q_len) break;
+            const QTask tk = tasks[q_beg + t];
+            const QItem &it = items[tk.item];
+            if (threadIdx.x == 0) {
+                if (sub == 0 && t == 0 && run_start) *run_start = (int64_t)wall_clock64();
+                for (int d = 0; d < 2; ++d) {
+                    const int dep = d == 0 ? it.dep0 : it.dep1;
+                    if (dep < 0 || q_load_relaxed(ctrl + QC_ERR)) continue;
+                    const int64_t t0 = (int64_t)wall_clock64();
+                    while (q_load_relaxed(counters + dep) > 0) {
+                        if ((int64_t)wall_clock64() - t0 > kQWaitTicks) {
+                            atomicExch(ctrl + QC_ERR, 1);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                // the producers ran on this XCD and their stores are in its
+                // L2: drop this CU's L1 lines before the workgroup reads
+                asm volatile("buffer_inv sc0" ::: "memory");
+                if (stamps && (it.flags & QF_FIRST) && tk.task == 0) stamps[2 * it.net] = (int64_t)wall_clock64();
+            }
+            __syncthreads();  // also: every thread has read task_s before thread 0 writes it again
+            void *C = (it.flags & QF_OUT) ? outs[it.net] : it.C;
+            const int64_t u0 = (int64_t)tk.task * it.units_per_task;
+            const int64_t u1 = min(it.n_units, u0 + it.units_per_task);
+            switch (it.kind) {
+                case QI_LOAD:
+                    q_load(it, C, u0, u1);
+                    break;
+                case QI_STEP:
+                    q_step(it, C, u0, u1);
+                    break;
+                case QI_FINISH:
+                    q_finish(it, C, u0, u1);
+                    break;
+                case QI_GEMM:
+                    if constexpr (GK != 0) q_gemm<GK>(it, C, u0, u1, q_lds);
+                    break;
+                default:
+                    if (it.tc == 0)
+                        q_ksum_t<double>(it, C, u0, u1);
+                    else
+                        q_ksum_t<float>(it, C, u0, u1);
+                    break;
+            }
+            // every wave waits until its stores have reached the L2 (a
+            // workgroup-scope fence does not wait: the waves share one CU);
+            // thread 0 then counts the task done at the top of the loop
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            prev = __builtin_amdgcn_readfirstlane(tk.item);
         }
-        __syncthreads();  // also: every thread has read task_s before thread 0 writes it again
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        void *C = (it.flags & QF_OUT) ? outs[it.net] : it.C;
-        const int64_t u0 = (int64_t)tk.task * it.units_per_task;
-        const int64_t u1 = min(it.n_units, u0 + it.units_per_task);
-        switch (it.kind) {
-            case QI_LOAD:
-                q_load(it, C, u0, u1);
-                break;
-            case QI_STEP:
-                q_step(it, C, u0, u1);
-                break;
-            case QI_FINISH:
-                q_finish(it, C, u0, u1);
-                break;
-            case QI_GEMM:
-                if constexpr (GK != 0) q_gemm<GK>(it, C, u0, u1, q_lds);
-                break;
-            default:
-                if (it.tc == 0)
-                    q_ksum_t<double>(it, C, u0, u1);
-                else
-                    q_ksum_t<float>(it, C, u0, u1);
-                break;
-        }
-        // publish this task's results; thread 0 counts it done at the top
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        prev = __builtin_amdgcn_readfirstlane(tk.item);
     }
-    // The last workgroup out restores the counters for the next launch: by
-    // then every other workgroup has stopped touching them.
+    // The last workgroup out checks that every sub-queue was drained and
+    // restores the counters for the next launch: by then every other
+    // workgroup has stopped touching them.  (The last task's count was made
+    // at the top of the final pass of the loop.)
     if (threadIdx.x == 0)
         last_s = __hip_atomic_fetch_add(ctrl + QC_EXITED, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
                  (int)gridDim.x - 1;
     __syncthreads();
     if (__builtin_amdgcn_readfirstlane(last_s)) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (int i = threadIdx.x; i < n_items; i += kQThreads) counters[i] = init[i];
         if (threadIdx.x == 0) {
-            ctrl[QC_NEXT] = 0;
+            for (int k = 0; k < n_sub; ++k) {
+                if (q_load_relaxed(ctrl + QC_NEXT + k) < qinfo[QC_MAX_SUB + k + 1] - qinfo[QC_MAX_SUB + k])
+                    atomicExch(ctrl + QC_ERR, 2);
+                ctrl[QC_NEXT + k] = 0;
+            }
             ctrl[QC_EXITED] = 0;
         }
     }
 }
 
+// One wave per workgroup records the XCD it runs on.
+__global__ void k_xcc_probe(uint32_t *mask) {
+    if (threadIdx.x == 0) atomicOr(mask, 1u << q_xcc_id());
+}
+
 template <int GK>
-hipError_t go_queue(const QItem *items, const QTask *tasks, int n_tasks, const int32_t *init, int32_t *counters,
-                    int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps, int64_t *run_start, int lds_bytes,
-                    int n_blocks, hipStream_t st) {
+hipError_t go_queue(const QItem *items, const QTask *tasks, const int32_t *qinfo, int n_sub, const int32_t *init,
+                    int32_t *counters, int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps,
+                    int64_t *run_start, int lds_bytes, int n_blocks, hipStream_t st) {
     static int configured = -1;
     if (lds_bytes > configured) {
         hipError_t e =
@@ -270,8 +301,8 @@ hipError_t go_queue(const QItem *items, const QTask *tasks, int n_tasks, const i
         }
         configured = lds_bytes;
     }
-    hipLaunchKernelGGL((k_queue<GK>), dim3((unsigned)n_blocks), dim3(kQThreads), lds_bytes, st, items, tasks,
-                       n_tasks, init, counters, n_items, ctrl, outs, stamps, run_start);
+    hipLaunchKernelGGL((k_queue<GK>), dim3((unsigned)n_blocks), dim3(kQThreads), lds_bytes, st, items, tasks, qinfo,
+                       n_sub, init, counters, n_items, ctrl, outs, stamps, run_start);
     return hipGetLastError();
 }
 
@@ -317,11 +348,11 @@ int queue_blocks_per_cu(int gk, int lds_bytes) {
     }
 }
 
-hipError_t launch_queue(const QItem *items, const QTask *tasks, int n_tasks, const int32_t *init, int32_t *counters,
-                        int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps, int64_t *run_start, int gk,
-                        int lds_bytes, int n_blocks, hipStream_t st) {
-    if (n_tasks <= 0 || n_blocks <= 0) return hipErrorInvalidValue;
-#define HTN_GO(G) go_queue<G>(items, tasks, n_tasks, init, counters, n_items, ctrl, outs, stamps, run_start, lds_bytes, n_blocks, st)
+hipError_t launch_queue(const QItem *items, const QTask *tasks, const int32_t *qinfo, int n_sub, const int32_t *init,
+                        int32_t *counters, int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps,
+                        int64_t *run_start, int gk, int lds_bytes, int n_blocks, hipStream_t st) {
+    if (n_sub < 1 || n_sub > QC_MAX_SUB || n_blocks <= 0) return hipErrorInvalidValue;
+#define HTN_GO(G) go_queue<G>(items, tasks, qinfo, n_sub, init, counters, n_items, ctrl, outs, stamps, run_start, lds_bytes, n_blocks, st)
     switch (gk) {
         case 0: return HTN_GO(0);
         case 1: return HTN_GO(1);
@@ -332,6 +363,20 @@ hipError_t launch_queue(const QItem *items, const QTask *tasks, int n_tasks, con
         default: return hipErrorInvalidValue;
     }
 #undef HTN_GO
+}
+
+uint32_t queue_xcc_mask(uint32_t *d_word) {
+    if (hipMemset(d_word, 0, sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    uint32_t h = 0;
+    hipLaunchKernelGGL(k_xcc_probe, dim3(4096), dim3(64), 0, 0, d_word);
+    if (hipGetLastError() != hipSuccess || hipMemcpy(&h, d_word, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return h;
 }
 
 }  // namespace kern
