@@ -456,6 +456,42 @@ __device__ __forceinline__ void copy_chunks(const g_uint4 *src, u32x4 *dst, int 
     }
 }
 
+// Copies the chunks [from, ...) of a phase's copy ops [ops, ops_end) (their
+// chunks numbered consecutively in op order) with kFlatLoads independent
+// loads in flight per thread: the phase then waits about one memory
+// latency for all of them, not one per op.
+constexpr int kFlatLoads = 8;
+template <int BLK>
+__device__ __forceinline__ void copy_ops_flat(const int32_t *ops, const int32_t *ops_end, int from,
+                                              const int32_t *image, const unsigned char *ws, u32x4 *lds4) {
+    if (ops == ops_end) return;
+    const int32_t *r = ops;
+    CopyOp cur = decode_copy(r, image, ws);
+    int cur_start = 0;
+    for (int base = from;; base += kFlatLoads * BLK) {
+        u32x4 v[kFlatLoads];
+        int dst[kFlatLoads];
+#pragma unroll
+        for (int u = 0; u < kFlatLoads; ++u) {
+            const int c = base + (int)threadIdx.x + u * BLK;
+            while (r != ops_end && c >= cur_start + cur.n) {  // this thread's chunks only grow
+                cur_start += cur.n;
+                r += 5;
+                if (r != ops_end) cur = decode_copy(r, image, ws);
+            }
+            dst[u] = -1;
+            if (r != ops_end) {
+                v[u] = cur.src[c - cur_start];
+                dst[u] = cur.dst + (c - cur_start);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatLoads; ++u)
+            if (dst[u] >= 0) lds4[dst[u]] = v[u];
+        if (r == ops_end) break;
+    }
+}
+
 // The fused kernel.  A workgroup copies its network's program into LDS and
 // interprets it: COPY moves tables or materialised inputs into LDS,
 // STEP / TSTEP contract two values, SYNC ends a phase.
@@ -606,18 +642,10 @@ __device__ __forceinline__ void fused_body(const FusedDesc &d, const int net, vo
         if (dst1 >= 0) lds4[dst1] = stg1;
         if (dst2 >= 0) lds4[dst2] = stg2;
         if (dst3 >= 0) lds4[dst3] = stg3;
-        if (tot > kPrefetch * BLK || copies_end != staged_end) {
-            // rare: re-read the copy ops (their decoded form is not kept
-            // live across the step) and copy the chunks beyond the staged
-            // ones, then any copy op past the fourth
-            int start = 0;
-            for (const int32_t *r = copies0; r != copies_end; r += 5) {
-                const CopyOp c = decode_copy(r, gimg, (const unsigned char *)d.scratch);
-                const int skip = r < staged_end ? max(0, kPrefetch * BLK - start) : 0;
-                if (skip < c.n) copy_chunks<BLK>(c.src + skip, lds4 + c.dst + skip, c.n - skip);
-                start += c.n;
-            }
-        }
+        // then every chunk beyond the staged ones, all loads in flight
+        if (tot > kPrefetch * BLK || copies_end != staged_end)
+            copy_ops_flat<BLK>(copies0, copies_end, min(tot, kPrefetch * BLK), gimg, (const unsigned char *)d.scratch,
+                               lds4);
         p = steps_end;
     }
     if (stamps && threadIdx.x == 0) {

@@ -97,8 +97,8 @@ def run_program(w, prog, n_loads, elem_bytes=8, threads=None):
     and every copy to stay inside its slot or value."""
     prog = np.asarray(prog, dtype=np.int64)
     n_words, lds_bytes, _, slot0, slot_words, red_byte, tab_base, ld_base = (int(x) for x in prog[:8])
-    assert slot0 >= 8 and slot0 % 4 == 0 and slot_words % 4 == 0
-    assert red_byte >= 4 * (slot0 + 2 * slot_words)
+    assert slot0 >= 8 and slot0 % 4 == 0 and slot_words % 4 == 0 and slot_words > 0
+    assert red_byte >= 4 * slot0 and red_byte % 4 == 0
     lo_elem = (red_byte + 256 + elem_bytes - 1) // elem_bytes
     hi_elem = lds_bytes // elem_bytes
     lds = np.full(lds_bytes // elem_bytes + 4, np.nan)
@@ -131,8 +131,10 @@ def run_program(w, prog, n_loads, elem_bytes=8, threads=None):
             v *= ins[sct[q]][sc[q]]
         ws[dst:dst + size] = v
         p += 7 + 2 * ns + rk * (4 + ns)
-    # tables live in the image as int32 words; LDS slots as separate arrays
-    slots = {}
+    # tables live in the image as int32 words; the LDS table region
+    # [slot0, red_byte / 4) in words, unwritten words marked
+    unset = -(1 << 40)
+    tabmem = np.full(red_byte // 4 - slot0, unset, dtype=np.int64)
     result = None
     epc = 16 // elem_bytes  # elements per 16-byte chunk
 
@@ -158,9 +160,10 @@ def run_program(w, prog, n_loads, elem_bytes=8, threads=None):
             kind, src, n, dst = (int(x) for x in prog[p + 1:p + 5])
             if kind == 0:
                 words = prog[tab_base + 4 * src:tab_base + 4 * (src + n)]
-                slot_idx = (4 * dst - slot0) // slot_words
-                assert 4 * dst == slot0 + slot_idx * slot_words and slot_idx in (0, 1) and 4 * n <= slot_words
-                slots[slot_idx] = words.copy()
+                assert words.size == 4 * n
+                w0_ = 4 * dst - slot0
+                assert 0 <= w0_ and w0_ + 4 * n <= tabmem.size, (dst, n, slot0, red_byte)
+                tabmem[w0_:w0_ + 4 * n] = words
             else:
                 d0 = dst * 16 // elem_bytes
                 at(d0, n * epc)
@@ -208,7 +211,11 @@ def run_program(w, prog, n_loads, elem_bytes=8, threads=None):
         if threads is not None:
             assert R <= 64 or (R == threads and nw == threads // 64), (R, nw, threads)
         ranges.append((w0, nw, R > 64))
-        tab = slots[slot].reshape(-1, 2)
+        t0 = slot * slot_words
+        assert 0 <= t0 <= tabmem.size and t0 % 2 == 0
+        tab = tabmem[t0:tabmem.size - (tabmem.size - t0) % 2].reshape(-1, 2)
+        for t_, n_ in ((t_ohi, n_ohi), (t_olo, n_olo), (t_shi, n_shi), (t_slo, n_slo)):
+            assert 0 <= t_ and t_ + n_ <= tab.shape[0] and (tab[t_:t_ + n_] != unset).all(), (t_, n_)
         oa = _two_level(tab, t_ohi, t_olo, n_olo, n_ohi * n_olo, 0)
         sa = _two_level(tab, t_shi, t_slo, n_slo, n_shi * n_slo, 0)
         aa, ao = at(la, int((oa[:, None] + sa[None, :]).max()) + 1)
