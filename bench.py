@@ -94,11 +94,11 @@ def parse():
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 797.3125 x 2048 B, WRITE_SIZE 213.5 x 1024 B
-    "k_fused_grid": {"read_bytes": 38_496_896, "write_bytes": 218_624, "sources": "af6e1d77f20c0f03",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 717.3 x 2048 B, WRITE_SIZE 178.4 x 1024 B
+    "k_fused_grid": {"read_bytes": 38_333_030, "write_bytes": 182_682, "sources": "8580a9f90c2f7855",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
-    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 476 x 2048 B, WRITE_SIZE 15 552.6 x 1024 B
-    "k_truncate_qpd8": {"read_bytes": 27_598_848, "write_bytes": 15_925_862, "sources": "c89d2a641b3a6971",
+    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 478.7 x 2048 B, WRITE_SIZE 15 552.9 x 1024 B
+    "k_truncate_qpd8": {"read_bytes": 27_604_378, "write_bytes": 15_926_170, "sources": "70341a0b57e0d2b7",
                         "files": ["paper_2410_15080_amd/csrc/qpd.hip", "paper_2410_15080_amd/csrc/api.hip",
                                   "paper_2410_15080_amd/csrc/kernels.hpp"],
                         "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
