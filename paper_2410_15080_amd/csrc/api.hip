@@ -1110,7 +1110,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
             const Opd pa = pack(A, s.pack_a), pb = pack(B, s.pack_b);
             int ks = s.ksplit, kper = 0;
             kern::gemm_ksplit((int)s.gk, ks, kper);
-            const int wi = (gk == 2 || gk == 4) ? 2 : 4;
+            const int rows = kern::queue_tile_rows();
             kern::QItem it = q_item(kern::QI_GEMM, bi, n);
             std::array<int64_t, 4> o{-1, -1, -1, -1};
             set_ab(it, o, pa, pb);
@@ -1124,7 +1124,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
             it.kchunk = 64;
             it.ksplit = ks;
             it.kper = kper;
-            it.tiles_m = (int)((s.gm + 32 * wi - 1) / (32 * wi));
+            it.tiles_m = (int)((s.gm + rows - 1) / rows);
             it.tiles_n = (int)((s.gn + 127) / 128);
             it.n_units = (int64_t)it.tiles_m * it.tiles_n * it.batch * ks;
             const int64_t total = s.gb * s.gm * s.gn;

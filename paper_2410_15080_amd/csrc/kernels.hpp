@@ -175,6 +175,7 @@ uint32_t queue_xcc_mask(uint32_t *d_word);
 // (0: no GEMM items).
 int queue_gemm_kind(int tin, int tout);
 int queue_gemm_lds(int gk);
+int queue_tile_rows();  // output rows of a queue GEMM tile (columns: 128)
 int queue_blocks_per_cu(int gk, int lds_bytes);
 // Runs the queue in one launch of n_blocks workgroups; each takes tasks from
 // the sub-queue of the XCD it runs on.  counters[i] must hold

@@ -114,13 +114,17 @@ struct TileLoader {
 
 // One output tile of C[b][m][n] = sum_k A[b][m][k] B[b][n][k]: tile index t
 // as in the GEMM kernel ((b * ksplit + kz) * tiles_m + tm) * tiles_n + tn.
-// lds: 16-byte aligned, gemm_lds_bytes<T, WI>() bytes.
-template <typename T, int WI>
+// lds: 16-byte aligned, gemm_lds_bytes<T, WI, NBUF>() bytes.  NBUF = 2:
+// the next K slice is staged into the other LDS buffer while the current
+// one is multiplied; NBUF = 1: one buffer (half the LDS), the next slice
+// waits in registers until the current one is consumed.  Neither the tile
+// shape (WI) nor the buffering changes any output's K order.
+template <typename T, int WI, int NBUF = 2>
 __host__ __device__ constexpr int gemm_lds_bytes() {
-    return 2 * (32 * WI + GBN) * (MfmaOp<T>::BK + MfmaOp<T>::PAD) * (int)sizeof(T);
+    return NBUF * (32 * WI + GBN) * (MfmaOp<T>::BK + MfmaOp<T>::PAD) * (int)sizeof(T);
 }
 
-template <typename T, typename TOUT, bool COMBINE64, int WI>
+template <typename T, typename TOUT, bool COMBINE64, int WI, int NBUF = 2>
 __device__ void gemm_tile(const T *__restrict__ A0, const T *__restrict__ B0, TOUT *__restrict__ C0, int M, int N,
                           int K, int kchunk, int ksplit, int kper, int batch, int tiles_m, int tiles_n, int t,
                           unsigned char *lds) {
@@ -128,8 +132,8 @@ __device__ void gemm_tile(const T *__restrict__ A0, const T *__restrict__ B0, TO
     constexpr int BK = Op::BK;
     constexpr int LD = BK + Op::PAD;
     constexpr int TBM = 32 * WI;
-    T *const As = (T *)lds;                  // two buffers of TBM x LD
-    T *const Bs = (T *)lds + 2 * TBM * LD;   // two buffers of GBN x LD
+    T *const As = (T *)lds;                     // NBUF buffers of TBM x LD
+    T *const Bs = (T *)lds + NBUF * TBM * LD;   // NBUF buffers of GBN x LD
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * (16 * WI), wn = (wave & 1) * 64;
     const int lr = lane & 15, lk = (lane >> 4) * Op::KPL;
@@ -165,7 +169,7 @@ __device__ void gemm_tile(const T *__restrict__ A0, const T *__restrict__ B0, TO
     __syncthreads();
     int since = 0;
     for (int kt = 0; kt < nk; ++kt) {
-        const int cb = kt & 1;
+        const int cb = NBUF == 2 ? (kt & 1) : 0;
         if (kt + 1 < nk) {
             la.load(A, M, K, kend, m0, kbeg + (kt + 1) * BK);
             lb.load(B, N, K, kend, n0, kbeg + (kt + 1) * BK);
@@ -199,9 +203,17 @@ __device__ void gemm_tile(const T *__restrict__ A0, const T *__restrict__ B0, TO
                 since = 0;
             }
         }
-        if (kt + 1 < nk) {
-            la.store(As + (cb ^ 1) * (TBM * LD));
-            lb.store(Bs + (cb ^ 1) * (GBN * LD));
+        if constexpr (NBUF == 2) {
+            if (kt + 1 < nk) {
+                la.store(As + (cb ^ 1) * (TBM * LD));
+                lb.store(Bs + (cb ^ 1) * (GBN * LD));
+            }
+        } else {
+            __syncthreads();  // every wave is done with the buffer
+            if (kt + 1 < nk) {
+                la.store(As);
+                lb.store(Bs);
+            }
         }
         __syncthreads();
     }

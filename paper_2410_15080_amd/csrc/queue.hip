@@ -159,18 +159,22 @@ __device__ void q_ksum_t(const QItem &it, void *C, int64_t u0, int64_t u1) {
 
 // GEMM items of one (input, output) dtype pair per queue kernel (GK 1..5:
 // f64->f64, f32->f64, f32->f32, bf16->f64, bf16->f32; 0: none), so that
-// each variant's registers are those of one tile shape.
+// each variant's registers are those of one tile shape.  Tiles of 64 x 128
+// with one LDS buffer (about 26 KB): small enough for a queue workgroup to
+// share a CU with a fused-kernel workgroup (up to 96 KB), so the queue
+// runs beside the fused launch instead of after it.
+constexpr int kQTileWI = 2;
 template <int GK>
 __device__ void q_gemm(const QItem &it, void *C, int64_t u0, int64_t u1, unsigned char *lds) {
     for (int64_t t = u0; t < u1; ++t) {
-#define HTN_TILE(T, TOUT, C64, WI)                                                                              \
-    gemm_tile<T, TOUT, C64, WI>((const T *)it.A, (const T *)it.B, (TOUT *)C, it.M, it.N, it.K, it.kchunk,      \
+#define HTN_TILE(T, TOUT, C64)                                                                                  \
+    gemm_tile<T, TOUT, C64, kQTileWI, 1>((const T *)it.A, (const T *)it.B, (TOUT *)C, it.M, it.N, it.K, it.kchunk,      \
                                 it.ksplit, it.kper, it.batch, it.tiles_m, it.tiles_n, (int)t, lds)
-        if constexpr (GK == 1) HTN_TILE(double, double, false, 4);
-        if constexpr (GK == 2) HTN_TILE(float, double, true, 2);
-        if constexpr (GK == 3) HTN_TILE(float, float, false, 4);
-        if constexpr (GK == 4) HTN_TILE(bf16_t, double, true, 2);
-        if constexpr (GK == 5) HTN_TILE(bf16_t, float, false, 4);
+        if constexpr (GK == 1) HTN_TILE(double, double, false);
+        if constexpr (GK == 2) HTN_TILE(float, double, true);
+        if constexpr (GK == 3) HTN_TILE(float, float, false);
+        if constexpr (GK == 4) HTN_TILE(bf16_t, double, true);
+        if constexpr (GK == 5) HTN_TILE(bf16_t, float, false);
 #undef HTN_TILE
         __syncthreads();  // the tile's LDS is free before the next one is staged
     }
@@ -327,14 +331,14 @@ int queue_gemm_kind(int tin, int tout) {
 
 int queue_gemm_lds(int gk) {
     switch (gk) {
-        case 1: return gemm_lds_bytes<double, 4>();
-        case 2: return gemm_lds_bytes<float, 2>();
-        case 3: return gemm_lds_bytes<float, 4>();
-        case 4: return gemm_lds_bytes<bf16_t, 2>();
-        case 5: return gemm_lds_bytes<bf16_t, 4>();
+        case 1: return gemm_lds_bytes<double, kQTileWI, 1>();
+        case 2: case 3: return gemm_lds_bytes<float, kQTileWI, 1>();
+        case 4: case 5: return gemm_lds_bytes<bf16_t, kQTileWI, 1>();
         default: return 0;
     }
 }
+
+int queue_tile_rows() { return 32 * kQTileWI; }
 
 int queue_blocks_per_cu(int gk, int lds_bytes) {
     switch (gk) {
