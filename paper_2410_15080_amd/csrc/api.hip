@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <limits>
 #include <mutex>
@@ -69,6 +70,8 @@ struct DeviceState {
     bool fprep_in_kernel = false;  // the fused workgroup materialises its inputs
     int plan_uploaded = -1;
     int64_t uploads = 0;  // input and plan uploads so far (a batch holds the addresses of one)
+    std::vector<kern::FoldDesc> folds;  // per fold chain of the plan (per-step executor)
+    int32_t *d_fold_tab = nullptr;      // their index tables
     struct SliceRun *slices = nullptr;  // a sliced net's slice networks (built at first use)
 };
 }  // namespace htn
@@ -274,6 +277,7 @@ static void release_device(Net &n) {
     dfree(D.d_prep);
     dfree(D.d_fdesc);
     dfree(D.d_fprep);
+    dfree(D.d_fold_tab);
     delete n.dev;
     n.dev = nullptr;
 }
@@ -380,6 +384,89 @@ static void upload_plan(Net &n) {
     if (!prep.empty()) {
         D.d_prep = dalloc<kern::PrepDesc>(prep.size());
         HIP_TRY(hipMemcpy(D.d_prep, prep.data(), prep.size() * sizeof(kern::PrepDesc), hipMemcpyHostToDevice));
+    }
+    D.folds.clear();
+    dfree(D.d_fold_tab);
+    D.d_fold_tab = nullptr;
+    std::vector<int32_t> ftab;
+    for (const auto &ch : P.chains) {
+        const FoldLayout F = fold_layout(n, P, ch);
+        if (!F.ok) throw Error{HTN_E_STATE, "fold chain without a layout"};
+        kern::FoldDesc fd;
+        std::memset(&fd, 0, sizeof(fd));
+        // index tables: offsets of every in-tile index at the source and
+        // the destination, and per stage each output's first input term
+        // and new digit (digits over the in-tile axes, last fastest)
+        auto offsets = [&](const std::vector<int> &ext, const std::vector<int64_t> &str) {
+            int64_t size = 1;
+            for (int e : ext) size *= e;
+            for (int64_t a = 0; a < size; ++a) {
+                int64_t r = a, off = 0;
+                for (int j = (int)ext.size() - 1; j >= 0; --j) {
+                    off += (r % ext[j]) * str[j];
+                    r /= ext[j];
+                }
+                if (off > INT32_MAX) throw Error{HTN_E_UNSUPPORTED, "fold chain offset beyond 32 bits"};
+                ftab.push_back((int32_t)off);
+            }
+            return (int32_t)size;
+        };
+        fd.t_src = (int32_t)ftab.size();
+        offsets(F.ext0, F.s_src);
+        fd.t_dst = (int32_t)ftab.size();
+        fd.d_final = offsets(F.ext1, F.s_dst);
+        std::vector<int> ext = F.ext0;
+        for (size_t st = 0; st < F.fold_ax.size(); ++st) {
+            const int ax = F.fold_ax[st], din = ext[ax], dout = F.fold_ext[st];
+            int64_t inner = 1, size = 1;
+            for (size_t j = ax + 1; j < ext.size(); ++j) inner *= ext[j];
+            for (int e : ext) size *= e;
+            const int64_t Dn = size / din * dout;
+            fd.d_in_ax[st] = din;
+            fd.d_out[st] = dout;
+            fd.inner[st] = (int32_t)inner;
+            fd.t_base[st] = (int32_t)ftab.size();
+            for (int64_t a = 0; a < Dn; ++a) {
+                const int64_t hi = a / (dout * inner), rem = a % (dout * inner);
+                ftab.push_back((int32_t)(hi * din * inner + rem % inner));
+            }
+            fd.t_mid[st] = (int32_t)ftab.size();
+            for (int64_t a = 0; a < Dn; ++a) ftab.push_back((int32_t)((a % (dout * inner)) / inner));
+            ext[ax] = dout;
+        }
+        fd.lg_tf = 0;
+        while ((1 << fd.lg_tf) < F.tf) ++fd.lg_tf;
+        fd.n_ax = (int32_t)F.ext0.size();
+        fd.n_outer = (int32_t)F.o_ext.size();
+        fd.n_stage = (int32_t)F.fold_ax.size();
+        fd.tf = F.tf;
+        fd.d_max = F.d_max;
+        fd.lds_bytes = (int32_t)F.lds_bytes;
+        for (int j = 0; j < fd.n_ax; ++j) {
+            fd.ext0[j] = F.ext0[j];
+            fd.ext1[j] = F.ext1[j];
+            fd.s_src[j] = F.s_src[j];
+            fd.s_dst[j] = F.s_dst[j];
+        }
+        for (int j = 0; j < fd.n_stage; ++j) {
+            fd.fold_ax[j] = F.fold_ax[j];
+            fd.fold_ext[j] = F.fold_ext[j];
+            fd.m_in[j] = (int32_t)F.m_in[j];
+            fd.m_out[j] = (int32_t)F.m_out[j];
+            fd.m[j] = D.in[F.m_tensor[j]];
+        }
+        for (int j = 0; j < fd.n_outer; ++j) {
+            fd.o_ext[j] = F.o_ext[j];
+            fd.o_src[j] = F.o_src[j];
+            fd.o_dst[j] = F.o_dst[j];
+        }
+        fd.n_outer_total = F.n_outer;
+        D.folds.push_back(fd);
+    }
+    if (!ftab.empty()) {
+        D.d_fold_tab = dalloc<int32_t>(ftab.size());
+        HIP_TRY(hipMemcpy(D.d_fold_tab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice));
+        for (auto &fd : D.folds) fd.tab = D.d_fold_tab;
     }
     D.fprep.clear();
     D.fprep_max = 0;
@@ -508,6 +595,7 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
         if (ticks && q >= 0 && q < max_ticks) HIP_TRY(kern::launch_stamp(ticks + q, st));
         ++q;
         const StepPlan &s = P.steps[k];
+        if (s.chain >= 0 && s.chain_pos > 0) continue;  // ran with its chain's first step
         auto operand = [&](int id, const void *&ptr, int &t) {
             if (id < 0) {
                 ptr = nullptr;
@@ -535,6 +623,18 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
         } else {
             C = ws + P.ws_off[s.c];
             tc = s.out_bf16 ? (int)HTN_BF16 : tint;
+        }
+        if (s.chain >= 0) {
+            // the whole fold chain: source X in, the chain's last result out
+            const auto &ch = P.chains[s.chain];
+            const StepPlan &last = P.steps[ch.back()];
+            const int x = P.values[s.a].size >= P.values[s.b].size ? s.a : s.b;
+            const void *X = x == s.a ? A : B;
+            const int tx = x == s.a ? ta : tb;
+            void *Y = ws + P.ws_off[last.c];
+            const int ty = last.out_bf16 ? (int)HTN_BF16 : tint;
+            HIP_TRY(kern::launch_fold(X, tx, tin, tint, Y, ty, D.folds[s.chain], st));
+            continue;
         }
         if (s.mfma) {
             run_mfma_step(n, s, A, ta, B, tb, C, tc, ws, st);

@@ -76,6 +76,10 @@ struct StepPlan {
     // step; steps of one phase are independent and run side by side.
     int f_w0 = 0, f_nw = 1;
     // Fused-program facts (features of the learned cost model).
+    // Fold chains (per-step executor): a large tensor contracted with small
+    // matrices one mode at a time; the chain's steps run as one launch at
+    // its first step (chain: index in Plan::chains, chain_pos: position)
+    int chain = -1, chain_pos = -1;
     int f_phase = -1;           // phase of the fused kernel that runs the step
     int f_spill = 0;            // bit 0: A, bit 1: B, bit 2: C outside LDS
     int64_t f_copy_chunks = 0;  // 16-byte chunks copied while the step runs
@@ -125,6 +129,8 @@ struct Plan {
     // kernel_steps) that run side by side in one phase, in phase order
     std::vector<std::vector<int>> fused_phases;
     std::vector<LoadPlan> loads;     // inputs needing scaling (by first use)
+    // fold chains: step indices in chain order (see StepPlan::chain)
+    std::vector<std::vector<int>> chains;
     std::vector<int32_t> tables;     // flat (x, y) pairs
     int final_value = -1;
     double mults = 0.0;
@@ -201,6 +207,25 @@ inline htn_dtype inter_dtype(htn_dtype compute) { return compute == HTN_F64 ? HT
 inline htn_dtype out_dtype(const Net &n) {
     return n.final_sum == HTN_SUM_PLAIN ? inter_dtype(n.compute) : HTN_F64;
 }
+
+// Host layout of a fold chain (see Plan::chains): in-tile axes (first
+// slowest; every folded axis, plus carried axes while the tile stays
+// small), outer axes (first slowest), one stage per chain step.
+struct FoldLayout {
+    bool ok = false;
+    int x = -1, y = -1;                 // source value (X) and result value
+    std::vector<int> ext0, ext1;        // in-tile extents at X / at the result
+    std::vector<int64_t> s_src, s_dst;  // in-tile strides in X / in the result
+    std::vector<int> fold_ax, fold_ext; // per stage: in-tile axis, its new extent
+    std::vector<int> m_tensor;          // per stage: the matrix's original tensor id
+    std::vector<int64_t> m_in, m_out;   // per stage: matrix strides of the old / new index
+    std::vector<int> o_ext;             // outer extents
+    std::vector<int64_t> o_src, o_dst;  // outer strides
+    int64_t n_outer = 1;
+    int d_max = 1, tf = 1;
+    int64_t lds_bytes = 0;
+};
+FoldLayout fold_layout(const Net &n, const Plan &P, const std::vector<int> &chain);
 
 // planner.cpp
 struct Error {

@@ -146,6 +146,137 @@ __global__ void k_stamp(int64_t *dst) {
     if (threadIdx.x == 0) *dst = (int64_t)wall_clock64();
 }
 
+// ------------------------------------------------------------------ k_fold
+
+// A tile is worked through in dependent passes (load, one per fold,
+// store): 1024 threads per workgroup shorten each pass (narrower tiles with
+// more workgroups per CU measured slower).
+constexpr int kFoldBlk = 1024;
+
+// One workgroup per tf outer indices; LDS holds two [d_max][tf + 1]
+// buffers (the +1 keeps the destination-order reads off one bank) and the
+// outer offsets of its tf indices.  Every per-element index comes from the
+// descriptor's tables: no integer division in the element loops.
+template <typename TS, typename TM, typename TI, typename TO>
+__global__ __launch_bounds__(kFoldBlk) void k_fold(const TS *__restrict__ src, TO *__restrict__ dst, const FoldDesc fd) {
+    extern __shared__ __align__(16) unsigned char fold_lds[];
+    const int tf = fd.tf, ld = tf + 1, lg = fd.lg_tf;
+    __shared__ int64_t o_src[64], o_dst[64];
+    TI *bin = (TI *)fold_lds;
+    TI *bout = bin + (int64_t)fd.d_max * ld;
+    // XCD-aware tile order: workgroups are dealt to the eight XCDs in turn,
+    // so the workgroups of one XCD take a contiguous range of tiles and
+    // neighbouring tiles (which share source cache lines) share its L2
+    const int64_t n_tiles = (fd.n_outer_total + tf - 1) / tf;
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tile >= n_tiles) return;  // whole workgroup: before any barrier
+    const int64_t f0 = tile * tf;
+    if (threadIdx.x < tf) {
+        int64_t f = f0 + threadIdx.x, os = 0, od = 0;
+        if (f < fd.n_outer_total) {
+            for (int j = fd.n_outer - 1; j >= 0; --j) {
+                const int64_t q = f / fd.o_ext[j], d = f - q * fd.o_ext[j];
+                os += d * fd.o_src[j];
+                od += d * fd.o_dst[j];
+                f = q;
+            }
+        } else {
+            os = od = -1;
+        }
+        o_src[threadIdx.x] = os;
+        o_dst[threadIdx.x] = od;
+    }
+    __syncthreads();
+    const int32_t *tsrc = fd.tab + fd.t_src;
+    int D = 1;
+    for (int j = 0; j < fd.n_ax; ++j) D *= fd.ext0[j];
+    // stage the source: outer index fastest across threads (coalesced along
+    // the source's fastest outer axis); kFoldLoads loads in flight per
+    // thread (each a table read, then the source read it addresses)
+    constexpr int kFoldLoads = 8;
+    for (int e0 = threadIdx.x; e0 < (D << lg); e0 += kFoldBlk * kFoldLoads) {
+        TI v[kFoldLoads];
+        int dl[kFoldLoads];
+#pragma unroll
+        for (int u = 0; u < kFoldLoads; ++u) {
+            const int e = e0 + u * kFoldBlk;
+            dl[u] = -1;
+            if (e < (D << lg)) {
+                const int a = e >> lg, fl = e & (tf - 1);
+                const int64_t os = o_src[fl];
+                dl[u] = a * ld + fl;
+                v[u] = os >= 0 ? Ld<TI, TS>::get(src + os + tsrc[a]) : TI(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFoldLoads; ++u)
+            if (dl[u] >= 0) bin[dl[u]] = v[u];
+    }
+    __syncthreads();
+    for (int st = 0; st < fd.n_stage; ++st) {
+        const int din = fd.d_in_ax[st], inner = fd.inner[st];
+        const int Dn = D / din * fd.d_out[st];
+        const int32_t *tb = fd.tab + fd.t_base[st], *tm = fd.tab + fd.t_mid[st];
+        const TM *M = (const TM *)fd.m[st];
+        const int mi = fd.m_in[st], mo = fd.m_out[st];
+#pragma unroll 4
+        for (int e = threadIdx.x; e < (Dn << lg); e += kFoldBlk) {
+            const int a = e >> lg, fl = e & (tf - 1);
+            const TI *x = bin + tb[a] * ld + fl;
+            const TM *m = M + tm[a] * mo;
+            TI acc = 0;
+            for (int k = 0; k < din; ++k) acc += x[k * inner * ld] * Ld<TI, TM>::get(m + k * mi);
+            bout[a * ld + fl] = acc;
+        }
+        __syncthreads();
+        TI *t = bin;
+        bin = bout;
+        bout = t;
+        D = Dn;
+    }
+    // write: in-tile index fastest across threads (contiguous in the
+    // destination's fastest in-tile axes)
+    const int32_t *tdst = fd.tab + fd.t_dst;
+    for (int e = threadIdx.x; e < D * tf; e += kFoldBlk) {
+        const int fl = e / D, a = e - fl * D;
+        if (o_dst[fl] >= 0) dst[o_dst[fl] + tdst[a]] = st_cvt<TO>(bin[a * ld + fl]);
+    }
+}
+
+template <typename TS, typename TM, typename TI, typename TO>
+static hipError_t go_fold(const void *src, void *dst, const FoldDesc &fd, hipStream_t st) {
+    static int configured = -1;
+    if (fd.lds_bytes > configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_fold<TS, TM, TI, TO>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, fd.lds_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        configured = fd.lds_bytes;
+    }
+    const int64_t blocks = 8 * (((fd.n_outer_total + fd.tf - 1) / fd.tf + 7) / 8);
+    hipLaunchKernelGGL((k_fold<TS, TM, TI, TO>), dim3((unsigned)blocks), dim3(kFoldBlk), fd.lds_bytes, st,
+                       (const TS *)src, (TO *)dst, fd);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const void *src, int ts, int tm, int ti, void *dst, int to, const FoldDesc &fd,
+                       hipStream_t st) {
+    if (fd.n_outer_total <= 0 || fd.tf < 1 || fd.tf > 64 || (1 << fd.lg_tf) != fd.tf || !fd.tab)
+        return hipErrorInvalidValue;
+    if (ts == 0 && tm == 0 && ti == 0 && to == 0) return go_fold<double, double, double, double>(src, dst, fd, st);
+    if (ts == 1 && tm == 1 && ti == 1 && to == 1) return go_fold<float, float, float, float>(src, dst, fd, st);
+    if (tm == 2 && ti == 1) {
+        if (ts == 2 && to == 2) return go_fold<bf16_t, bf16_t, float, bf16_t>(src, dst, fd, st);
+        if (ts == 2 && to == 1) return go_fold<bf16_t, bf16_t, float, float>(src, dst, fd, st);
+        if (ts == 1 && to == 2) return go_fold<float, bf16_t, float, bf16_t>(src, dst, fd, st);
+        if (ts == 1 && to == 1) return go_fold<float, bf16_t, float, float>(src, dst, fd, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------- k_slice_sum
 
 // out[e] = sum over slices k (in order) of parts[k * n + e], accumulated in

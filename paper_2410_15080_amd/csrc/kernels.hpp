@@ -188,6 +188,39 @@ hipError_t launch_queue(const QItem *items, const QTask *tasks, const int32_t *q
                         int32_t *counters, int n_items, int32_t *ctrl, void *const *outs, int64_t *stamps,
                         int64_t *run_start, int gk, int lds_bytes, int n_blocks, hipStream_t st);
 
+// Fold chain: a value X contracted with small matrices one mode at a time.
+// X's labels split into in-tile axes (every folded axis, plus carried axes
+// while the tile stays small; first slowest) and outer axes (first
+// slowest).  A workgroup takes tf consecutive outer indices, stages X's
+// in-tile sub-tensor for each in LDS, applies the folds in order (stage i
+// contracts in-tile axis fold_ax[i] with matrix m[i]: row = the axis's
+// current index, column = its new index, strides m_in / m_out), and writes
+// the result in the destination's layout.
+constexpr int kFoldAxes = 8, kFoldOuter = 4, kFoldStages = 8;
+struct FoldDesc {
+    int32_t n_ax, n_outer, n_stage, tf, d_max, lds_bytes;
+    int32_t lg_tf;                 // tf = 2^lg_tf
+    // index tables (built on the host): tab + t_src: source offset of each
+    // in-tile index; tab + t_dst: destination offset of each final in-tile
+    // index; tab + t_base[i], tab + t_mid[i]: for stage i and each output
+    // index, the tile index of its first input term and its new digit
+    const int32_t *tab;
+    int32_t t_src, t_dst, d_final;
+    int32_t t_base[kFoldStages], t_mid[kFoldStages], d_in_ax[kFoldStages], inner[kFoldStages], d_out[kFoldStages];
+    int32_t ext0[kFoldAxes], ext1[kFoldAxes];  // in-tile extents at the source / destination
+    int64_t s_src[kFoldAxes], s_dst[kFoldAxes];
+    int32_t fold_ax[kFoldStages], fold_ext[kFoldStages];  // axis and its new extent, per stage
+    int32_t m_in[kFoldStages], m_out[kFoldStages];
+    const void *m[kFoldStages];
+    int32_t o_ext[kFoldOuter];
+    int64_t o_src[kFoldOuter], o_dst[kFoldOuter];
+    int64_t n_outer_total;
+};
+// ts: source dtype, tm: matrix dtype, ti: arithmetic (0 double, 1 float),
+// to: destination dtype.
+hipError_t launch_fold(const void *src, int ts, int tm, int ti, void *dst, int to, const FoldDesc &fd,
+                       hipStream_t st);
+
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.
 hipError_t launch_slice_sum(const void *parts, int n_slices, int64_t n, void *out, int tout, bool comp,

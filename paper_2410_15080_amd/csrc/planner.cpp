@@ -493,6 +493,120 @@ static void classify_mfma(const Net &n, StepPlan &s, const std::vector<int> &al,
     s.sum_labels = gk;
 }
 
+FoldLayout fold_layout(const Net &n, const Plan &P, const std::vector<int> &chain) {
+    constexpr int kAx = 8, kOuter = 4, kStages = 8;
+    constexpr int64_t kTileMax = 1024, kLdsMax = 81920;
+    FoldLayout F;
+    if (chain.empty() || (int)chain.size() > kStages) return F;
+    auto row_major = [&](const std::vector<int> &labels) {
+        std::vector<int64_t> st(labels.size(), 1);
+        for (int k = (int)labels.size() - 2; k >= 0; --k) st[k] = st[k + 1] * n.dims[labels[k + 1]];
+        return st;
+    };
+    // the chain's source: the head's larger operand; its labels are the axes
+    const StepPlan &h = P.steps[chain[0]];
+    if (h.a < 0 || h.b < 0) return F;
+    F.x = P.values[h.a].size >= P.values[h.b].size ? h.a : h.b;
+    const std::vector<int> &xl = P.values[F.x].labels;
+    const std::vector<int64_t> xs = row_major(xl);
+    std::vector<int> cur = xl;
+    std::vector<char> folded(xl.size(), 0);
+    int prev = F.x;
+    for (int k : chain) {
+        const StepPlan &s = P.steps[k];
+        const int m = s.a == prev ? s.b : (s.b == prev ? s.a : -1);
+        if (m < 0 || s.sum_labels.size() != 1) return F;
+        const Value &M = P.values[m];
+        if (!M.input || M.labels.size() != 2) return F;
+        const int l = s.sum_labels[0];
+        const int lp = M.labels[0] == l ? M.labels[1] : M.labels[0];
+        int ax = -1;
+        for (size_t j = 0; j < cur.size(); ++j)
+            if (cur[j] == l) ax = (int)j;
+        if (ax < 0) return F;
+        // the matrix is read raw: strides of its original tensor
+        const std::vector<int> &ml = n.labels[M.base];
+        const std::vector<int64_t> ms = row_major(ml);
+        if (ml.size() != 2) return F;
+        F.fold_ax.push_back(ax);
+        F.fold_ext.push_back((int)n.dims[lp]);
+        F.m_tensor.push_back(M.base);
+        F.m_in.push_back(ml[0] == l ? ms[0] : ms[1]);
+        F.m_out.push_back(ml[0] == l ? ms[1] : ms[0]);
+        cur[ax] = lp;
+        folded[ax] = 1;
+        prev = s.c;
+    }
+    F.y = prev;
+    const std::vector<int> &yl = P.values[F.y].labels;
+    const std::vector<int64_t> ys = row_major(yl);
+    if (yl.size() != xl.size()) return F;
+    std::vector<int64_t> dst_of(xl.size(), -1);
+    for (size_t j = 0; j < xl.size(); ++j)
+        for (size_t q = 0; q < yl.size(); ++q)
+            if (yl[q] == cur[j]) dst_of[j] = ys[q];
+    for (int64_t d : dst_of)
+        if (d < 0) return F;
+    // largest in-tile size over the stages for the current in-tile axes
+    std::vector<char> tile(xl.size(), 1);
+    auto d_max = [&]() {
+        std::vector<int64_t> e(xl.size());
+        for (size_t j = 0; j < xl.size(); ++j) e[j] = n.dims[xl[j]];
+        auto size = [&]() {
+            int64_t p = 1;
+            for (size_t j = 0; j < xl.size(); ++j)
+                if (tile[j]) p *= e[j];
+            return p;
+        };
+        int64_t mx = size();
+        for (size_t st = 0; st < F.fold_ax.size(); ++st) {
+            e[F.fold_ax[st]] = F.fold_ext[st];
+            mx = std::max(mx, size());
+        }
+        return mx;
+    };
+    // move the largest carried axes out of the tile until it is small
+    while (d_max() > kTileMax) {
+        int best = -1;
+        for (size_t j = 0; j < xl.size(); ++j)
+            if (tile[j] && !folded[j] && (best < 0 || n.dims[xl[j]] > n.dims[xl[best]])) best = (int)j;
+        if (best < 0) return F;
+        tile[best] = 0;
+    }
+    // in-tile axes by falling destination stride (stores run along the
+    // fastest), outer axes by falling source stride (loads run along it)
+    std::vector<int> in_ax, out_ax;
+    for (size_t j = 0; j < xl.size(); ++j) (tile[j] ? in_ax : out_ax).push_back((int)j);
+    std::stable_sort(in_ax.begin(), in_ax.end(), [&](int p, int q) { return dst_of[p] > dst_of[q]; });
+    std::stable_sort(out_ax.begin(), out_ax.end(), [&](int p, int q) { return xs[p] > xs[q]; });
+    if ((int)in_ax.size() > kAx || (int)out_ax.size() > kOuter) return F;
+    std::vector<int> pos(xl.size(), -1);
+    for (size_t q = 0; q < in_ax.size(); ++q) pos[in_ax[q]] = (int)q;
+    for (size_t q = 0; q < in_ax.size(); ++q) {
+        const int j = in_ax[q];
+        F.ext0.push_back((int)n.dims[xl[j]]);
+        F.ext1.push_back((int)n.dims[cur[j]]);
+        F.s_src.push_back(xs[j]);
+        F.s_dst.push_back(dst_of[j]);
+    }
+    for (int &a : F.fold_ax) a = pos[a];
+    for (int j : out_ax) {
+        F.o_ext.push_back((int)n.dims[xl[j]]);
+        F.o_src.push_back(xs[j]);
+        F.o_dst.push_back(dst_of[j]);
+        F.n_outer *= n.dims[xl[j]];
+    }
+    F.d_max = (int)d_max();
+    const int64_t es = dtype_size(inter_dtype(n.compute));
+    // 16 outer indices per tile: 128-byte runs of an FP64 source axis
+    F.tf = 16;
+    while (F.tf > 1 && 2 * (int64_t)F.d_max * (F.tf + 1) * es > kLdsMax) F.tf /= 2;
+    while (F.tf > 1 && F.tf / 2 >= F.n_outer) F.tf /= 2;
+    F.lds_bytes = 2 * (int64_t)F.d_max * (F.tf + 1) * es;
+    F.ok = F.lds_bytes <= kLdsMax;
+    return F;
+}
+
 void build_plan(Net &n) {
     const int N = n.n_t;
     const int L = (int)n.dims.size();
@@ -1008,6 +1122,67 @@ void build_plan(Net &n) {
         }
     }
 
+    // Fold chains for the per-step executor: a step contracting a large
+    // value X (>= kFoldMinSize elements) with a small input matrix M (read
+    // raw from its original tensor, so M may carry no folded scales)
+    // over one label l of X, M's other label l' taking l's place, is a
+    // fold; a fold whose X is the result of another fold continues that
+    // one's chain.  A chain runs as one launch at its first step (its
+    // intermediate results are never stored), so that each large tensor is
+    // read and written once instead of once per matrix.
+    P.chains.clear();
+    {
+        constexpr int64_t kFoldMinSize = 65536, kFoldMaxMatrix = 4096, kFoldMaxExtent = 64;
+        auto fold_big = [&](const StepPlan &s) -> int {  // X's SSA id, or -1
+            if (s.mfma || s.b < 0 || s.final_step || s.split_global > 1 || s.sum_labels.size() != 1) return -1;
+            for (int pick = 0; pick < 2; ++pick) {
+                const int m = pick ? s.a : s.b, x = pick ? s.b : s.a;
+                const Value &M = P.values[m], &X = P.values[x];
+                if (!M.input || !M.scales.empty() || M.labels.size() != 2 ||
+                    M.size > kFoldMaxMatrix || X.size < kFoldMinSize)
+                    continue;
+                const int l = s.sum_labels[0];
+                const int lp = M.labels[0] == l ? M.labels[1] : (M.labels[1] == l ? M.labels[0] : -1);
+                if (lp < 0 || !contains(X.labels, l) || contains(X.labels, lp)) continue;
+                if (n.dims[l] > kFoldMaxExtent || n.dims[lp] > kFoldMaxExtent) continue;
+                std::vector<int> want;
+                for (int y : X.labels) want.push_back(y == l ? lp : y);
+                std::vector<int> got = s.c_labels;
+                std::sort(want.begin(), want.end());
+                std::sort(got.begin(), got.end());
+                if (want == got) return x;
+            }
+            return -1;
+        };
+        std::vector<int> big(P.steps.size(), -1);
+        for (int k : P.kernel_steps) big[k] = fold_big(P.steps[k]);
+        for (int k : P.kernel_steps) {
+            if (big[k] < 0) continue;
+            const int pr = P.values[big[k]].producer;
+            if (!P.values[big[k]].input && pr >= 0 && big[pr] >= 0 && P.steps[pr].chain >= 0) {
+                StepPlan &s = P.steps[k];
+                s.chain = P.steps[pr].chain;
+                s.chain_pos = (int)P.chains[s.chain].size();
+                P.chains[s.chain].push_back(k);
+            } else {
+                P.steps[k].chain = (int)P.chains.size();
+                P.steps[k].chain_pos = 0;
+                P.chains.push_back({k});
+            }
+        }
+        // chains the fold kernel cannot take run step by step
+        std::vector<std::vector<int>> kept;
+        for (auto &ch : P.chains) {
+            const bool ok = fold_layout(n, P, ch).ok;
+            for (int k : ch) {
+                P.steps[k].chain = ok ? (int)kept.size() : -1;
+                if (!ok) P.steps[k].chain_pos = -1;
+            }
+            if (ok) kept.push_back(ch);
+        }
+        P.chains = std::move(kept);
+    }
+
     // Per-step executor workspace: scaled inputs are written up front by
     // one launch; each kernel step then allocates its result and releases
     // its operands.
@@ -1020,6 +1195,18 @@ void build_plan(Net &n) {
         const int64_t pes = n.compute == HTN_BF16 ? 2 : es;  // packed operand element size
         for (int k : P.kernel_steps) {
             StepPlan &s = P.steps[k];
+            if (s.chain >= 0) {
+                // a fold chain writes its last result at its first step;
+                // its other results are never stored
+                const auto &ch = P.chains[s.chain];
+                if (s.chain_pos == 0) {
+                    const StepPlan &last = P.steps[ch.back()];
+                    P.ws_off[last.c] = ff.alloc(P.values[last.c].size * es, 256);
+                }
+                for (int id : {s.a, s.b})
+                    if (id >= 0 && P.ws_off[id] >= 0 && (s.chain_pos == 0 || P.values[id].input)) ff.release(P.ws_off[id]);
+                continue;
+            }
             if (!s.final_step) P.ws_off[s.c] = ff.alloc(P.values[s.c].size * es, 256);
             if (s.mfma) {
                 s.ws_pa = s.pack_a.identity ? -1 : ff.alloc(s.pack_a.n * pes, 256);
@@ -1451,6 +1638,50 @@ void plan_net(Net &n) {
     n.plan_version++;
 }
 
+// Fold chains with their kernel layouts (see FoldLayout), as JSON.
+static std::string chains_json(const Net &n) {
+    std::ostringstream o;
+    auto arr = [&](const char *name, const auto &v) {
+        o << "\"" << name << "\":[";
+        for (size_t k = 0; k < v.size(); ++k) o << (k ? "," : "") << v[k];
+        o << "]";
+    };
+    o << "[";
+    for (size_t c = 0; c < n.plan.chains.size(); ++c) {
+        const FoldLayout F = fold_layout(n, n.plan, n.plan.chains[c]);
+        o << (c ? "," : "") << "{";
+        arr("steps", n.plan.chains[c]);
+        o << ",\"x\":" << F.x << ",\"y\":" << F.y << ",\"tf\":" << F.tf << ",\"d_max\":" << F.d_max
+          << ",\"n_outer\":" << F.n_outer << ",";
+        arr("ext0", F.ext0);
+        o << ",";
+        arr("ext1", F.ext1);
+        o << ",";
+        arr("s_src", F.s_src);
+        o << ",";
+        arr("s_dst", F.s_dst);
+        o << ",";
+        arr("fold_ax", F.fold_ax);
+        o << ",";
+        arr("fold_ext", F.fold_ext);
+        o << ",";
+        arr("m_tensor", F.m_tensor);
+        o << ",";
+        arr("m_in", F.m_in);
+        o << ",";
+        arr("m_out", F.m_out);
+        o << ",";
+        arr("o_ext", F.o_ext);
+        o << ",";
+        arr("o_src", F.o_src);
+        o << ",";
+        arr("o_dst", F.o_dst);
+        o << "}";
+    }
+    o << "]";
+    return o.str();
+}
+
 std::string plan_json(const Net &n) {
     const Plan &P = n.plan;
     std::ostringstream o;
@@ -1464,6 +1695,7 @@ std::string plan_json(const Net &n) {
       << ",\"fused_lds_only\":" << (P.fused_lds_only ? "true" : "false") << ",\"fused_lds_bytes\":" << P.fused_lds_bytes
       << ",\"fused_scratch_bytes\":" << P.fused_scratch_bytes << ",\"ws_bytes\":" << P.ws_bytes
       << ",\"final_value\":" << P.final_value << ",\"n_table_entries\":" << P.tables.size() / 2
+      << ",\"chains\":" << chains_json(n)
       << ",\"steps\":[";
     for (size_t k = 0; k < P.steps.size(); ++k) {
         const StepPlan &s = P.steps[k];
@@ -1478,7 +1710,7 @@ std::string plan_json(const Net &n) {
         o << ",\"mults\":" << s.mults << ",\"absorbed\":" << (s.absorbed ? "true" : "false")
           << ",\"final\":" << (s.final_step ? "true" : "false") << ",\"synthetic\":" << (s.synthetic ? "true" : "false")
           << ",\"n_out\":" << s.n_out << ",\"n_sum\":" << s.n_sum << ",\"r_fused\":" << s.r_fused
-          << ",\"r_global\":" << s.r_global << ",\"split\":" << s.split_global << ",\"ksplit\":" << s.ksplit << ",\"f_phase\":" << s.f_phase << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
+          << ",\"r_global\":" << s.r_global << ",\"split\":" << s.split_global << ",\"ksplit\":" << s.ksplit << ",\"chain\":" << s.chain << ",\"chain_pos\":" << s.chain_pos << ",\"f_phase\":" << s.f_phase << ",\"geom\":[" << s.n_ohi << "," << s.n_olo << "," << s.n_shi << ","
           << s.n_slo << "," << s.t_ohi << "," << s.t_olo << "," << s.t_shi << "," << s.t_slo << "],\"pack_a\":["
           << s.pack_a.n_ohi << "," << s.pack_a.n_olo << "," << s.pack_a.t_ohi << "," << s.pack_a.t_olo << "],\"pack_b\":["
           << s.pack_b.n_ohi << "," << s.pack_b.n_olo << "," << s.pack_b.t_ohi << "," << s.pack_b.t_olo
