@@ -625,15 +625,30 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
             tc = s.out_bf16 ? (int)HTN_BF16 : tint;
         }
         if (s.chain >= 0) {
-            // the whole fold chain: source X in, the chain's last result out
-            const auto &ch = P.chains[s.chain];
-            const StepPlan &last = P.steps[ch.back()];
-            const int x = P.values[s.a].size >= P.values[s.b].size ? s.a : s.b;
-            const void *X = x == s.a ? A : B;
-            const int tx = x == s.a ? ta : tb;
-            void *Y = ws + P.ws_off[last.c];
-            const int ty = last.out_bf16 ? (int)HTN_BF16 : tint;
-            HIP_TRY(kern::launch_fold(X, tx, tin, tint, Y, ty, D.folds[s.chain], st));
+            // whole fold chains (source X in, each chain's last result out):
+            // the chains of the group this step leads, side by side
+            if (P.chain_lead[s.chain] != s.chain) continue;  // launched with its group
+            std::vector<kern::FoldJob> jobs;
+            std::vector<std::pair<int, int>> types;  // (X dtype, result dtype) per job
+            for (int c = 0; c < (int)P.chains.size(); ++c) {
+                if (P.chain_lead[c] != s.chain) continue;
+                const StepPlan &h = P.steps[P.chains[c][0]];
+                const StepPlan &last = P.steps[P.chains[c].back()];
+                const int x = P.values[h.a].size >= P.values[h.b].size ? h.a : h.b;
+                const void *X;
+                int tx;
+                operand(x, X, tx);
+                jobs.push_back({X, ws + P.ws_off[last.c], &D.folds[c]});
+                types.push_back({tx, last.out_bf16 ? (int)HTN_BF16 : tint});
+            }
+            // one launch per run of equal types
+            for (size_t j0 = 0; j0 < jobs.size();) {
+                size_t j1 = j0 + 1;
+                while (j1 < jobs.size() && types[j1] == types[j0]) ++j1;
+                HIP_TRY(kern::launch_folds(jobs.data() + j0, (int)(j1 - j0), types[j0].first, tin, tint,
+                                           types[j0].second, st));
+                j0 = j1;
+            }
             continue;
         }
         if (s.mfma) {

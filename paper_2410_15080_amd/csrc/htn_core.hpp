@@ -131,6 +131,12 @@ struct Plan {
     std::vector<LoadPlan> loads;     // inputs needing scaling (by first use)
     // fold chains: step indices in chain order (see StepPlan::chain)
     std::vector<std::vector<int>> chains;
+    // per chain, the chain at whose first step it is launched: itself, or
+    // an earlier chain of its group (chains whose first steps follow one
+    // another in the step order, with only steps of the group's chains in
+    // between, and whose large tensor is a network input: independent of
+    // each other, so one launch runs them side by side)
+    std::vector<int> chain_lead;
     std::vector<int32_t> tables;     // flat (x, y) pairs
     int final_value = -1;
     double mults = 0.0;

@@ -14,6 +14,7 @@
 //           coefficient scaling) into their workspaces.
 //  The fused whole-network kernel lives in fused.hpp / fused_b*.hip.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "kern_common.hpp"
@@ -157,9 +158,17 @@ constexpr int kFoldBlk = 1024;
 // buffers (the +1 keeps the destination-order reads off one bank) and the
 // outer offsets of its tf indices.  Every per-element index comes from the
 // descriptor's tables: no integer division in the element loops.
+// Several independent chains may share a launch (FoldBatch): each takes
+// its own range of workgroups, so their tiles run side by side.
 template <typename TS, typename TM, typename TI, typename TO>
-__global__ __launch_bounds__(kFoldBlk) void k_fold(const TS *__restrict__ src, TO *__restrict__ dst, const FoldDesc fd) {
+__global__ __launch_bounds__(kFoldBlk) void k_fold(const FoldBatch fb) {
     extern __shared__ __align__(16) unsigned char fold_lds[];
+    static_assert(kFoldBatch == 2, "the chain of a workgroup is picked from two");
+    const int c = (fb.n > 1 && (int)blockIdx.x >= fb.blk0[1]) ? 1 : 0;
+    const FoldDesc &fd = c ? fb.fd[1] : fb.fd[0];
+    const TS *__restrict__ src = (const TS *)(c ? fb.src[1] : fb.src[0]);
+    TO *__restrict__ dst = (TO *)(c ? fb.dst[1] : fb.dst[0]);
+    const int blk = (int)blockIdx.x - fb.blk0[c];
     const int tf = fd.tf, ld = tf + 1, lg = fd.lg_tf;
     __shared__ int64_t o_src[64], o_dst[64];
     TI *bin = (TI *)fold_lds;
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(kFoldBlk) void k_fold(const TS *__restrict__ src, T
     // neighbouring tiles (which share source cache lines) share its L2
     const int64_t n_tiles = (fd.n_outer_total + tf - 1) / tf;
     const int64_t per_xcd = (n_tiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t tile = (int64_t)(blk % 8) * per_xcd + blk / 8;
     if (tile >= n_tiles) return;  // whole workgroup: before any barrier
     const int64_t f0 = tile * tf;
     if (threadIdx.x < tf) {
@@ -245,34 +254,60 @@ __global__ __launch_bounds__(kFoldBlk) void k_fold(const TS *__restrict__ src, T
 }
 
 template <typename TS, typename TM, typename TI, typename TO>
-static hipError_t go_fold(const void *src, void *dst, const FoldDesc &fd, hipStream_t st) {
+static hipError_t go_fold(const FoldBatch &fb, int lds_bytes, hipStream_t st) {
     static int configured = -1;
-    if (fd.lds_bytes > configured) {
+    if (lds_bytes > configured) {
         hipError_t e = hipFuncSetAttribute((const void *)k_fold<TS, TM, TI, TO>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, fd.lds_bytes);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return e;
         }
-        configured = fd.lds_bytes;
+        configured = lds_bytes;
     }
-    const int64_t blocks = 8 * (((fd.n_outer_total + fd.tf - 1) / fd.tf + 7) / 8);
-    hipLaunchKernelGGL((k_fold<TS, TM, TI, TO>), dim3((unsigned)blocks), dim3(kFoldBlk), fd.lds_bytes, st,
-                       (const TS *)src, (TO *)dst, fd);
+    hipLaunchKernelGGL((k_fold<TS, TM, TI, TO>), dim3((unsigned)fb.blk0[fb.n]), dim3(kFoldBlk), lds_bytes, st, fb);
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const void *src, int ts, int tm, int ti, void *dst, int to, const FoldDesc &fd,
-                       hipStream_t st) {
-    if (fd.n_outer_total <= 0 || fd.tf < 1 || fd.tf > 64 || (1 << fd.lg_tf) != fd.tf || !fd.tab)
-        return hipErrorInvalidValue;
-    if (ts == 0 && tm == 0 && ti == 0 && to == 0) return go_fold<double, double, double, double>(src, dst, fd, st);
-    if (ts == 1 && tm == 1 && ti == 1 && to == 1) return go_fold<float, float, float, float>(src, dst, fd, st);
+template <typename TS, typename TM, typename TI, typename TO>
+static hipError_t go_folds(const FoldJob *jobs, int n, hipStream_t st) {
+    static_assert(sizeof(FoldBatch) <= 2048, "fold launch arguments");
+    for (int j0 = 0; j0 < n; j0 += kFoldBatch) {
+        FoldBatch fb;
+        fb.n = std::min(kFoldBatch, n - j0);
+        fb.blk0[0] = 0;
+        int lds = 0;
+        for (int c = 0; c < fb.n; ++c) {
+            const FoldDesc &fd = *jobs[j0 + c].fd;
+            fb.fd[c] = fd;
+            fb.src[c] = jobs[j0 + c].src;
+            fb.dst[c] = jobs[j0 + c].dst;
+            const int64_t blocks = 8 * (((fd.n_outer_total + fd.tf - 1) / fd.tf + 7) / 8);
+            if (fb.blk0[c] + blocks > INT32_MAX) return hipErrorInvalidValue;
+            fb.blk0[c + 1] = fb.blk0[c] + (int32_t)blocks;
+            lds = std::max(lds, fd.lds_bytes);
+        }
+        for (int c = fb.n; c < kFoldBatch; ++c) fb.blk0[c + 1] = fb.blk0[c];
+        hipError_t e = go_fold<TS, TM, TI, TO>(fb, lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_folds(const FoldJob *jobs, int n, int ts, int tm, int ti, int to, hipStream_t st) {
+    if (n < 1 || !jobs) return hipErrorInvalidValue;
+    for (int j = 0; j < n; ++j) {
+        const FoldDesc *fd = jobs[j].fd;
+        if (!fd || fd->n_outer_total <= 0 || fd->tf < 1 || fd->tf > 64 || (1 << fd->lg_tf) != fd->tf || !fd->tab)
+            return hipErrorInvalidValue;
+    }
+    if (ts == 0 && tm == 0 && ti == 0 && to == 0) return go_folds<double, double, double, double>(jobs, n, st);
+    if (ts == 1 && tm == 1 && ti == 1 && to == 1) return go_folds<float, float, float, float>(jobs, n, st);
     if (tm == 2 && ti == 1) {
-        if (ts == 2 && to == 2) return go_fold<bf16_t, bf16_t, float, bf16_t>(src, dst, fd, st);
-        if (ts == 2 && to == 1) return go_fold<bf16_t, bf16_t, float, float>(src, dst, fd, st);
-        if (ts == 1 && to == 2) return go_fold<float, bf16_t, float, bf16_t>(src, dst, fd, st);
-        if (ts == 1 && to == 1) return go_fold<float, bf16_t, float, float>(src, dst, fd, st);
+        if (ts == 2 && to == 2) return go_folds<bf16_t, bf16_t, float, bf16_t>(jobs, n, st);
+        if (ts == 2 && to == 1) return go_folds<bf16_t, bf16_t, float, float>(jobs, n, st);
+        if (ts == 1 && to == 2) return go_folds<float, bf16_t, float, bf16_t>(jobs, n, st);
+        if (ts == 1 && to == 1) return go_folds<float, bf16_t, float, float>(jobs, n, st);
     }
     return hipErrorInvalidValue;
 }

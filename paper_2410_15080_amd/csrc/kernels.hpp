@@ -216,10 +216,25 @@ struct FoldDesc {
     int64_t o_src[kFoldOuter], o_dst[kFoldOuter];
     int64_t n_outer_total;
 };
-// ts: source dtype, tm: matrix dtype, ti: arithmetic (0 double, 1 float),
-// to: destination dtype.
-hipError_t launch_fold(const void *src, int ts, int tm, int ti, void *dst, int to, const FoldDesc &fd,
-                       hipStream_t st);
+// Chains of one launch: the workgroups of chain c are [blk0[c], blk0[c+1])
+// (multiples of 8, so every chain keeps the XCD-aware tile order).
+constexpr int kFoldBatch = 2;
+struct FoldBatch {
+    FoldDesc fd[kFoldBatch];
+    const void *src[kFoldBatch];
+    void *dst[kFoldBatch];
+    int32_t blk0[kFoldBatch + 1];
+    int32_t n;
+};
+struct FoldJob {
+    const void *src;
+    void *dst;
+    const FoldDesc *fd;
+};
+// n independent chains of the same types, side by side in as few launches
+// as possible (kFoldBatch per launch).  ts: source dtype, tm: matrix dtype,
+// ti: arithmetic (0 double, 1 float), to: destination dtype.
+hipError_t launch_folds(const FoldJob *jobs, int n, int ts, int tm, int ti, int to, hipStream_t st);
 
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.

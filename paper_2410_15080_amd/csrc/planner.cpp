@@ -1181,6 +1181,26 @@ void build_plan(Net &n) {
             if (ok) kept.push_back(ch);
         }
         P.chains = std::move(kept);
+        // groups of chains launched together (Plan::chain_lead): a chain
+        // whose large tensor is a network input joins the open group when
+        // every step since the group's first is a step of its chains
+        P.chain_lead.assign(P.chains.size(), -1);
+        int open = -1;
+        for (int k : P.kernel_steps) {
+            const StepPlan &s = P.steps[k];
+            if (s.chain >= 0 && s.chain_pos > 0 && open >= 0 && P.chain_lead[s.chain] == open) continue;
+            if (s.chain >= 0 && s.chain_pos == 0) {
+                const int x = P.values[s.a].size >= P.values[s.b].size ? s.a : s.b;
+                if (open >= 0 && P.values[x].input) {
+                    P.chain_lead[s.chain] = open;
+                } else {
+                    P.chain_lead[s.chain] = s.chain;
+                    open = s.chain;
+                }
+                continue;
+            }
+            open = -1;
+        }
     }
 
     // Per-step executor workspace: scaled inputs are written up front by
@@ -1196,15 +1216,27 @@ void build_plan(Net &n) {
         for (int k : P.kernel_steps) {
             StepPlan &s = P.steps[k];
             if (s.chain >= 0) {
-                // a fold chain writes its last result at its first step;
-                // its other results are never stored
-                const auto &ch = P.chains[s.chain];
-                if (s.chain_pos == 0) {
-                    const StepPlan &last = P.steps[ch.back()];
-                    P.ws_off[last.c] = ff.alloc(P.values[last.c].size * es, 256);
+                // a group of fold chains writes the last result of each
+                // chain at the group's first step (every result allocated
+                // before any operand of the group is released: the chains
+                // run side by side); their other results are never stored
+                if (s.chain_pos == 0 && P.chain_lead[s.chain] == s.chain) {
+                    std::vector<int> group;
+                    for (int c = 0; c < (int)P.chains.size(); ++c)
+                        if (P.chain_lead[c] == s.chain) group.push_back(c);
+                    for (int c : group) {
+                        const StepPlan &last = P.steps[P.chains[c].back()];
+                        P.ws_off[last.c] = ff.alloc(P.values[last.c].size * es, 256);
+                    }
+                    for (int c : group) {
+                        const StepPlan &h = P.steps[P.chains[c][0]];
+                        for (int id : {h.a, h.b})
+                            if (id >= 0 && P.ws_off[id] >= 0) ff.release(P.ws_off[id]);
+                    }
+                } else if (s.chain_pos > 0) {
+                    for (int id : {s.a, s.b})
+                        if (id >= 0 && P.ws_off[id] >= 0 && P.values[id].input) ff.release(P.ws_off[id]);
                 }
-                for (int id : {s.a, s.b})
-                    if (id >= 0 && P.ws_off[id] >= 0 && (s.chain_pos == 0 || P.values[id].input)) ff.release(P.ws_off[id]);
                 continue;
             }
             if (!s.final_step) P.ws_off[s.c] = ff.alloc(P.values[s.c].size * es, 256);
@@ -1651,6 +1683,7 @@ static std::string chains_json(const Net &n) {
         const FoldLayout F = fold_layout(n, n.plan, n.plan.chains[c]);
         o << (c ? "," : "") << "{";
         arr("steps", n.plan.chains[c]);
+        o << ",\"lead\":" << n.plan.chain_lead[c] << ",\"ws_x\":" << n.plan.ws_off[F.x] << ",\"ws_y\":" << n.plan.ws_off[F.y];
         o << ",\"x\":" << F.x << ",\"y\":" << F.y << ",\"tf\":" << F.tf << ",\"d_max\":" << F.d_max
           << ",\"n_outer\":" << F.n_outer << ",";
         arr("ext0", F.ext0);

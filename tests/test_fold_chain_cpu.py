@@ -129,8 +129,24 @@ def test_fold_chain_layout_replays_to_the_contraction(idx):
         chains = plan["chains"]
         if idx < 2:  # every c_w fold is in a chain, one chain per QT
             assert len(chains) == 2 and sum(len(c["steps"]) for c in chains) == len(w.tensors) - 2
+            # both chains fold network inputs: one group, launched together
+            assert [c["lead"] for c in chains] == [0, 0]
         else:
             assert [len(c["steps"]) for c in chains] == [3]
+        # the chains of a group run side by side: their results and the
+        # workspace copies of their sources occupy disjoint bytes
+        es = 8 if compute == htn.HTN_F64 else 4
+        for lead in {c["lead"] for c in chains}:
+            spans = []
+            for c in chains:
+                if c["lead"] != lead:
+                    continue
+                for key, vid in (("ws_y", c["y"]), ("ws_x", c["x"])):
+                    if c[key] >= 0:
+                        size = int(np.prod([w.dims[l] for l in plan["values"][vid]["labels"]]))
+                        spans.append((c[key], c[key] + size * es))
+            spans.sort()
+            assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:])), spans
         for c in chains:
             assert plan["values"][c["x"]]["input"]
             x_data = _value_data(w, plan, c["x"])
