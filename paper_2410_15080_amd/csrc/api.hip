@@ -629,7 +629,7 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
             // the chains of the group this step leads, side by side
             if (P.chain_lead[s.chain] != s.chain) continue;  // launched with its group
             std::vector<kern::FoldJob> jobs;
-            std::vector<std::pair<int, int>> types;  // (X dtype, result dtype) per job
+            std::vector<int> types;  // result dtype per job
             for (int c = 0; c < (int)P.chains.size(); ++c) {
                 if (P.chain_lead[c] != s.chain) continue;
                 const StepPlan &h = P.steps[P.chains[c][0]];
@@ -638,15 +638,14 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
                 const void *X;
                 int tx;
                 operand(x, X, tx);
-                jobs.push_back({X, ws + P.ws_off[last.c], &D.folds[c]});
-                types.push_back({tx, last.out_bf16 ? (int)HTN_BF16 : tint});
+                jobs.push_back({X, tx, ws + P.ws_off[last.c], &D.folds[c]});
+                types.push_back(last.out_bf16 ? (int)HTN_BF16 : tint);
             }
-            // one launch per run of equal types
+            // one launch per run of equal result types
             for (size_t j0 = 0; j0 < jobs.size();) {
                 size_t j1 = j0 + 1;
                 while (j1 < jobs.size() && types[j1] == types[j0]) ++j1;
-                HIP_TRY(kern::launch_folds(jobs.data() + j0, (int)(j1 - j0), types[j0].first, tin, tint,
-                                           types[j0].second, st));
+                HIP_TRY(kern::launch_folds(jobs.data() + j0, (int)(j1 - j0), tin, tint, types[j0], st));
                 j0 = j1;
             }
             continue;

@@ -159,14 +159,15 @@ constexpr int kFoldBlk = 1024;
 // outer offsets of its tf indices.  Every per-element index comes from the
 // descriptor's tables: no integer division in the element loops.
 // Several independent chains may share a launch (FoldBatch): each takes
-// its own range of workgroups, so their tiles run side by side.
-template <typename TS, typename TM, typename TI, typename TO>
+// its own range of workgroups, so their tiles run side by side.  The
+// source of the first chain has type TS0, that of the second TS1.
+template <typename TS0, typename TS1, typename TM, typename TI, typename TO>
 __global__ __launch_bounds__(kFoldBlk) void k_fold(const FoldBatch fb) {
     extern __shared__ __align__(16) unsigned char fold_lds[];
     static_assert(kFoldBatch == 2, "the chain of a workgroup is picked from two");
     const int c = (fb.n > 1 && (int)blockIdx.x >= fb.blk0[1]) ? 1 : 0;
     const FoldDesc &fd = c ? fb.fd[1] : fb.fd[0];
-    const TS *__restrict__ src = (const TS *)(c ? fb.src[1] : fb.src[0]);
+    const void *const srcv = c ? fb.src[1] : fb.src[0];
     TO *__restrict__ dst = (TO *)(c ? fb.dst[1] : fb.dst[0]);
     const int blk = (int)blockIdx.x - fb.blk0[c];
     const int tf = fd.tf, ld = tf + 1, lg = fd.lg_tf;
@@ -204,24 +205,32 @@ __global__ __launch_bounds__(kFoldBlk) void k_fold(const FoldBatch fb) {
     // the source's fastest outer axis); kFoldLoads loads in flight per
     // thread (each a table read, then the source read it addresses)
     constexpr int kFoldLoads = 8;
-    for (int e0 = threadIdx.x; e0 < (D << lg); e0 += kFoldBlk * kFoldLoads) {
-        TI v[kFoldLoads];
-        int dl[kFoldLoads];
+    auto stage = [&](auto tag) {
+        typedef decltype(tag) TS;
+        const TS *__restrict__ src = (const TS *)srcv;
+        for (int e0 = threadIdx.x; e0 < (D << lg); e0 += kFoldBlk * kFoldLoads) {
+            TI v[kFoldLoads];
+            int dl[kFoldLoads];
 #pragma unroll
-        for (int u = 0; u < kFoldLoads; ++u) {
-            const int e = e0 + u * kFoldBlk;
-            dl[u] = -1;
-            if (e < (D << lg)) {
-                const int a = e >> lg, fl = e & (tf - 1);
-                const int64_t os = o_src[fl];
-                dl[u] = a * ld + fl;
-                v[u] = os >= 0 ? Ld<TI, TS>::get(src + os + tsrc[a]) : TI(0);
+            for (int u = 0; u < kFoldLoads; ++u) {
+                const int e = e0 + u * kFoldBlk;
+                dl[u] = -1;
+                if (e < (D << lg)) {
+                    const int a = e >> lg, fl = e & (tf - 1);
+                    const int64_t os = o_src[fl];
+                    dl[u] = a * ld + fl;
+                    v[u] = os >= 0 ? Ld<TI, TS>::get(src + os + tsrc[a]) : TI(0);
+                }
             }
-        }
 #pragma unroll
-        for (int u = 0; u < kFoldLoads; ++u)
-            if (dl[u] >= 0) bin[dl[u]] = v[u];
-    }
+            for (int u = 0; u < kFoldLoads; ++u)
+                if (dl[u] >= 0) bin[dl[u]] = v[u];
+        }
+    };
+    if (c == 0)  // workgroup-uniform
+        stage(TS0{});
+    else
+        stage(TS1{});
     __syncthreads();
     for (int st = 0; st < fd.n_stage; ++st) {
         const int din = fd.d_in_ax[st], inner = fd.inner[st];
@@ -253,11 +262,11 @@ __global__ __launch_bounds__(kFoldBlk) void k_fold(const FoldBatch fb) {
     }
 }
 
-template <typename TS, typename TM, typename TI, typename TO>
+template <typename TS0, typename TS1, typename TM, typename TI, typename TO>
 static hipError_t go_fold(const FoldBatch &fb, int lds_bytes, hipStream_t st) {
     static int configured = -1;
     if (lds_bytes > configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_fold<TS, TM, TI, TO>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_fold<TS0, TS1, TM, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -265,12 +274,24 @@ static hipError_t go_fold(const FoldBatch &fb, int lds_bytes, hipStream_t st) {
         }
         configured = lds_bytes;
     }
-    hipLaunchKernelGGL((k_fold<TS, TM, TI, TO>), dim3((unsigned)fb.blk0[fb.n]), dim3(kFoldBlk), lds_bytes, st, fb);
+    hipLaunchKernelGGL((k_fold<TS0, TS1, TM, TI, TO>), dim3((unsigned)fb.blk0[fb.n]), dim3(kFoldBlk), lds_bytes,
+                       st, fb);
     return hipGetLastError();
 }
 
-template <typename TS, typename TM, typename TI, typename TO>
-static hipError_t go_folds(const FoldJob *jobs, int n, hipStream_t st) {
+// BF16 arithmetic paths: each chain's source is FP32 or BF16
+template <typename TO>
+static hipError_t go_fold_bf(const FoldBatch &fb, int lds, int ts0, int ts1, hipStream_t st) {
+    if (ts0 == 2 && ts1 == 2) return go_fold<bf16_t, bf16_t, bf16_t, float, TO>(fb, lds, st);
+    if (ts0 == 2 && ts1 == 1) return go_fold<bf16_t, float, bf16_t, float, TO>(fb, lds, st);
+    if (ts0 == 1 && ts1 == 2) return go_fold<float, bf16_t, bf16_t, float, TO>(fb, lds, st);
+    if (ts0 == 1 && ts1 == 1) return go_fold<float, float, bf16_t, float, TO>(fb, lds, st);
+    return hipErrorInvalidValue;
+}
+
+// tm, ti, to: matrix, arithmetic and destination types (0 double, 1 float,
+// 2 bf16); every job's source type is jobs[j].ts
+static hipError_t go_folds(const FoldJob *jobs, int n, int tm, int ti, int to, hipStream_t st) {
     static_assert(sizeof(FoldBatch) <= 2048, "fold launch arguments");
     for (int j0 = 0; j0 < n; j0 += kFoldBatch) {
         FoldBatch fb;
@@ -288,28 +309,29 @@ static hipError_t go_folds(const FoldJob *jobs, int n, hipStream_t st) {
             lds = std::max(lds, fd.lds_bytes);
         }
         for (int c = fb.n; c < kFoldBatch; ++c) fb.blk0[c + 1] = fb.blk0[c];
-        hipError_t e = go_fold<TS, TM, TI, TO>(fb, lds, st);
+        const int ts0 = jobs[j0].ts, ts1 = fb.n > 1 ? jobs[j0 + 1].ts : ts0;
+        hipError_t e = hipErrorInvalidValue;
+        if (tm == 0 && ti == 0 && to == 0 && ts0 == 0 && ts1 == 0)
+            e = go_fold<double, double, double, double, double>(fb, lds, st);
+        else if (tm == 1 && ti == 1 && to == 1 && ts0 == 1 && ts1 == 1)
+            e = go_fold<float, float, float, float, float>(fb, lds, st);
+        else if (tm == 2 && ti == 1 && to == 2)
+            e = go_fold_bf<bf16_t>(fb, lds, ts0, ts1, st);
+        else if (tm == 2 && ti == 1 && to == 1)
+            e = go_fold_bf<float>(fb, lds, ts0, ts1, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_folds(const FoldJob *jobs, int n, int ts, int tm, int ti, int to, hipStream_t st) {
+hipError_t launch_folds(const FoldJob *jobs, int n, int tm, int ti, int to, hipStream_t st) {
     if (n < 1 || !jobs) return hipErrorInvalidValue;
     for (int j = 0; j < n; ++j) {
         const FoldDesc *fd = jobs[j].fd;
         if (!fd || fd->n_outer_total <= 0 || fd->tf < 1 || fd->tf > 64 || (1 << fd->lg_tf) != fd->tf || !fd->tab)
             return hipErrorInvalidValue;
     }
-    if (ts == 0 && tm == 0 && ti == 0 && to == 0) return go_folds<double, double, double, double>(jobs, n, st);
-    if (ts == 1 && tm == 1 && ti == 1 && to == 1) return go_folds<float, float, float, float>(jobs, n, st);
-    if (tm == 2 && ti == 1) {
-        if (ts == 2 && to == 2) return go_folds<bf16_t, bf16_t, float, bf16_t>(jobs, n, st);
-        if (ts == 2 && to == 1) return go_folds<bf16_t, bf16_t, float, float>(jobs, n, st);
-        if (ts == 1 && to == 2) return go_folds<float, bf16_t, float, bf16_t>(jobs, n, st);
-        if (ts == 1 && to == 1) return go_folds<float, bf16_t, float, float>(jobs, n, st);
-    }
-    return hipErrorInvalidValue;
+    return go_folds(jobs, n, tm, ti, to, st);
 }
 
 // ------------------------------------------------------------- k_slice_sum

@@ -228,13 +228,14 @@ struct FoldBatch {
 };
 struct FoldJob {
     const void *src;
+    int ts;  // source dtype
     void *dst;
     const FoldDesc *fd;
 };
-// n independent chains of the same types, side by side in as few launches
-// as possible (kFoldBatch per launch).  ts: source dtype, tm: matrix dtype,
-// ti: arithmetic (0 double, 1 float), to: destination dtype.
-hipError_t launch_folds(const FoldJob *jobs, int n, int ts, int tm, int ti, int to, hipStream_t st);
+// n independent chains, side by side in as few launches as possible
+// (kFoldBatch per launch).  tm: matrix dtype, ti: arithmetic (0 double,
+// 1 float), to: destination dtype of every chain.
+hipError_t launch_folds(const FoldJob *jobs, int n, int tm, int ti, int to, hipStream_t st);
 
 // Sum of the slices of a sliced network: out[e] = sum_k parts[k * n + e]
 // in FP64 (compensated when comp), k in order; tout 0 f64, 1 f32.
