@@ -155,6 +155,17 @@ static constexpr int kSideStreams = 3;
 // resident workgroup slot).
 static constexpr double kStragglerFloor = 1048576.0;
 static constexpr double kStragglerFactor = 4.0;
+// Resident fused workgroups per CU for a net's launch shape: the fused
+// kernel keeps at most two waves per SIMD (eight per CU), and a CU's
+// kLdsPerCu bytes of LDS bound the workgroups by their dynamic LDS.
+static constexpr int kLdsPerCu = 160 * 1024;
+static int fused_slots_per_cu(int threads, int64_t lds_bytes) {
+    const int by_waves = std::max(1, 8 / std::max(1, threads / 64));
+    const int by_lds = lds_bytes > 0 ? (int)std::max<int64_t>(1, kLdsPerCu / lds_bytes) : by_waves;
+    return std::min(by_waves, by_lds);
+}
+static bool queue_by_default(const Net &n);
+static std::vector<int> device_xccs(int dev);
 
 // ------------------------------------------------------------- helpers
 
@@ -1437,14 +1448,36 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
         for (int i = 0; i < n; ++i)
             if (!nets[i]) throw Error{HTN_E_ARG, "nets[" + std::to_string(i) + "] is NULL"};
         // straggler threshold from the work of the fused-eligible nets and
-        // the workgroup slots of the device
+        // the resident workgroup slots of their launch shape
         double fused_total = 0.0;
+        int slots_per_cu = 8;
         for (int i = 0; i < n; ++i)
-            if (use_fused_in_batch(*nets[i])) fused_total += nets[i]->plan.mults;
+            if (use_fused_in_batch(*nets[i])) {
+                fused_total += nets[i]->plan.mults;
+                slots_per_cu = std::min(slots_per_cu,
+                                        fused_slots_per_cu(nets[i]->fused_threads, nets[i]->plan.fused_lds_bytes));
+            }
         int dev = 0, cus = 256;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const double straggler = std::max(kStragglerFloor, kStragglerFactor * fused_total / (2.0 * cus));
+        double straggler = std::max(kStragglerFloor, kStragglerFactor * fused_total / ((double)slots_per_cu * cus));
+        {
+            // the work queue gives each net one XCD: fused-eligible nets
+            // that would go to it beyond one per XCD (they would wait behind
+            // another net there) stay in the fused launch, the lightest first
+            std::vector<double> over;
+            for (int i = 0; i < n; ++i) {
+                const Net &net = *nets[i];
+                if (net.queue_mode == 0 && use_fused_in_batch(net) && net.plan.mults > straggler &&
+                    queue_by_default(net))
+                    over.push_back(net.plan.mults);
+            }
+            const size_t n_xcd = over.empty() ? 0 : device_xccs(dev).size();
+            if (over.size() > n_xcd) {
+                std::sort(over.begin(), over.end(), std::greater<double>());
+                straggler = std::max(straggler, over[n_xcd]);
+            }
+        }
         for (int i = 0; i < n; ++i) {
             Net &net = *nets[i];
             if (net.n_slices > 1)
