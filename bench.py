@@ -93,15 +93,23 @@ def parse():
 # on a plain copy (profiles/ holds the summaries and commands).  Each record
 # carries a digest of the sources that shape the kernel and its plans; when
 # they change the record no longer applies and traffic is reported as null.
+MARGINAL_TRAFFIC_FILES = ["paper_2410_15080_amd/csrc/" + f for f in (
+    "mfma.hip", "mfma_dev.hpp", "kernels.hip", "kernels.hpp", "step_dev.hpp", "kern_common.hpp", "planner.cpp", "api.hip")]
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 717.3 x 2048 B, WRITE_SIZE 178.4 x 1024 B
-    "k_fused_grid": {"read_bytes": 38_333_030, "write_bytes": 182_682, "sources": "8580a9f90c2f7855",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 716.3 x 2047.2 B, WRITE_SIZE 181.7 x 1024 B
+    "k_fused_grid": {"read_bytes": 38_315_781, "write_bytes": 186_061, "sources": "daab8134708a909f",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
-    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 478.7 x 2048 B, WRITE_SIZE 15 552.9 x 1024 B
-    "k_truncate_qpd8": {"read_bytes": 27_604_378, "write_bytes": 15_926_170, "sources": "70341a0b57e0d2b7",
+    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 478.8 x 2047.2 B, WRITE_SIZE 15 553.2 x 1024 B
+    "k_truncate_qpd8": {"read_bytes": 27_593_635, "write_bytes": 15_926_477, "sources": "d8268a84a6f5211f",
                         "files": ["paper_2410_15080_amd/csrc/qpd.hip", "paper_2410_15080_amd/csrc/api.hip",
                                   "paper_2410_15080_amd/csrc/kernels.hpp"],
                         "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
+    # profiles/k_gemm_marginal4096_f64_f32_bf16.md: one contraction's kernels
+    # (k_prep, k_fold, k_gemm), FETCH_SIZE x 2047.2 B and WRITE_SIZE x 1024 B summed
+    "marginal_bf16": {"read_bytes": 27_860_998, "write_bytes": 142_695_834, "sources": "2564113eb183ca3c",
+                      "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
+    "marginal_f64": {"read_bytes": 107_722_409, "write_bytes": 159_395_328, "sources": "2564113eb183ca3c",
+                     "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
                    "paper_2410_15080_amd/csrc/fused_b256.hip", "paper_2410_15080_amd/csrc/planner.cpp"]
@@ -750,7 +758,8 @@ def bench_marginal(args):
         # the whole contraction (coefficient fold, packs and the GEMM) timed as
         # one: the GEMM's flops over the inputs read once and the FP64
         # result written once
-        "roofline": roofline(mf * 1e9, in_bytes + out_bytes, kern_ms * 1e-3, peak, "mfma", traffic=None,
+        "roofline": roofline(mf * 1e9, in_bytes + out_bytes, kern_ms * 1e-3, peak, "mfma",
+                             traffic=measured_traffic("marginal_" + name) if name != "f32" else None,
                              kernel="whole contraction: fold + pack + k_gemm", kernel_ms=round(kern_ms, 4)),
         "cpu_baseline": cpu,
     }
