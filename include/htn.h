@@ -341,10 +341,8 @@ void htn_batch_destroy(htn_batch_t batch);
  * Step features (row of HTN_MODEL_FEATURES floats; "lg" = log2(v) / 8):
  *   0 lg(1 + multiplications)  1 lg(outputs)  2 lg(summed terms per output)
  *   3 lg(size of operand A)    4 lg(size of operand B; 1 if unary)
- *   5-7 lg(M), lg(N), lg(K) of a register-tiled step or of a per-step
- *       GEMM (0 otherwise)
- *   8 lg(outputs per thread of a VALU-tiled step; batch of a per-step
- *       GEMM)   9 lg(lanes per output)
+ *   5-7 lg(M), lg(N), lg(K) of a register-tiled step (0 otherwise)
+ *   8 lg(outputs per thread of a VALU-tiled step)   9 lg(lanes per output)
  *   10 tiled step  11 one lane per output  12 several lanes per output
  *   13 whole workgroup per output  14 matrix cores (GEMM step or
  *   matrix-core tiled step)  15 unary step

@@ -54,13 +54,6 @@ void step_features(const Net &n, std::vector<float> &rows) {
             f[6] = lg((double)s.tN);
             f[7] = lg((double)s.tK);
             f[8] = lg((double)std::max(1, s.TM * s.TN));
-        } else if (mfma) {
-            // a per-step GEMM: its shape (a narrow side pads the 128-wide
-            // tile, a long K is split), in the slots of the tile shape
-            f[5] = lg((double)s.gm);
-            f[6] = lg((double)s.gn);
-            f[7] = lg((double)s.gk);
-            f[8] = lg((double)std::max<int64_t>(1, s.gb));
         }
         const int R = fused ? s.r_fused : s.r_global;
         if (!tile && !mfma) f[9] = lg((double)R);

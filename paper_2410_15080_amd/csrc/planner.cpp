@@ -446,13 +446,6 @@ static void choose_tile(StepPlan &s, int threads) {
 // result is laid out [batch][M][N]; for the final step the output labels
 // must already be in that grouped order.
 constexpr double kMfmaMinMults = 4194304.0;
-// A product with one side of only 16-63 rows still goes to the matrix cores
-// when it is this large and its K this long: the padded 128-wide tile then
-// wastes most of the instruction's work, but the alternative, one output
-// per lane group gathering K products through offset tables, is slower by
-// far more.
-constexpr double kMfmaNarrowMinMults = 8388608.0;
-constexpr int64_t kMfmaNarrowMinK = 256;
 
 static void classify_mfma(const Net &n, StepPlan &s, const std::vector<int> &al, const std::vector<int> &bl,
                           const std::vector<int> &kept, const std::vector<int> &sums, bool last) {
@@ -471,8 +464,7 @@ static void classify_mfma(const Net &n, StepPlan &s, const std::vector<int> &al,
     for (int l : bl)
         if (kept_has(l) && !contains(al, l)) gn.push_back(l);
     const int64_t M = (int64_t)prod_dims(n, gm), N = (int64_t)prod_dims(n, gn), K = (int64_t)prod_dims(n, gk);
-    const bool narrow = std::min(M, N) >= 16 && K >= kMfmaNarrowMinK && s.mults >= kMfmaNarrowMinMults;
-    if (!narrow && (M < 64 || N < 64 || K < 8)) return;
+    if (M < 64 || N < 64 || K < 8) return;
     if (last) {
         // output order must read batch..., M..., N...
         const auto &o = n.out_labels;
