@@ -192,3 +192,30 @@ def test_changed_net_invalidates_the_batch():
     with pytest.raises(htn.HtnError):
         htn.htn_batch_run(b, htn.pointer_array([out]), torch.cuda.current_stream())
     htn.htn_batch_destroy(b)
+
+
+def test_queue_takes_at_most_one_fused_eligible_network_per_xcd():
+    """Networks that would join the work queue beyond one per XCD stay in
+    the fused launch (each queued network has one XCD to itself); the batch
+    still gives every network the value of its per-step launches."""
+    ws = [configs.ring_of_rings(s) for s in range(24)]
+    nets = [create(w) for w in ws]  # queue option left at auto
+    outs = [htn.new_output(n) for n in nets]
+    b, r = _run_batch(nets, outs)
+    n_q, _, err = htn.htn_batch_queue_info(b)
+    assert err == 0
+    # 24 networks above the straggler bound of a 24-network batch, all
+    # queue-eligible: at most one per XCD (an MI355X has eight)
+    assert 1 <= n_q <= 8
+    stepped = [create(w, exec_mode=htn.HTN_EXEC_STEPS) for w in ws]
+    for n in stepped:
+        htn.htn_set_option(n, htn.HTN_OPT_QUEUE, 2)
+    so = [htn.new_output(n) for n in stepped]
+    bs, rs = _run_batch(stepped, so)
+    for i, w in enumerate(ws[:4]):
+        hi, lo = oracle.ve_contract(w.tensors, w.labels, w.dims, w.out_labels)
+        ref = float(hi) + float(lo)
+        assert abs(float(r[0][i][0]) - ref) <= 1e-10 * abs(ref), i
+        assert abs(float(rs[0][i][0]) - ref) <= 1e-10 * abs(ref), i
+    htn.htn_batch_destroy(b)
+    htn.htn_batch_destroy(bs)
