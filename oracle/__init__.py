@@ -56,7 +56,7 @@ def _load():
     dp = ctypes.POINTER(ctypes.c_double)
     dpp = ctypes.POINTER(dp)
     lib.oracle_naive.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, i64p, dpp,
-                                 ctypes.c_int, i32p, dp, i64p]
+                                 ctypes.c_int, i32p, dp, i64p, i64p]
     lib.oracle_naive.restype = ctypes.c_int
     lib.oracle_ve.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, i64p, dpp,
                               ctypes.c_int, i32p, ctypes.c_int, dp, dp]
@@ -91,20 +91,28 @@ def _p(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def naive_contract(tensors, labels, dims, out_labels=()):
-    """Naive knitting sum; returns (result array shaped by out_labels, n_terms)."""
+def naive_contract_counted(tensors, labels, dims, out_labels=()):
+    """Naive knitting sum (Sec. 2.1, Eq. knitting); returns (result array
+    shaped by out_labels, n_terms, multiplications the loop performed)."""
     lib = _load()
     (arrs, ranks, flat, d, outl, ptrs), n_o = _marshal(tensors, labels, dims, out_labels)
     out = np.zeros(n_o, dtype=np.float64)
     nterms = ctypes.c_int64(0)
+    nmults = ctypes.c_int64(0)
     st = lib.oracle_naive(len(arrs), _p(ranks, ctypes.c_int32), _p(flat, ctypes.c_int32),
                           len(dims), _p(d, ctypes.c_int64), ptrs, len(out_labels),
                           _p(outl, ctypes.c_int32), _p(out, ctypes.c_double),
-                          ctypes.byref(nterms))
+                          ctypes.byref(nterms), ctypes.byref(nmults))
     if st != 0:
         raise ValueError(f"oracle_naive failed with status {st}")
     shape = tuple(dims[l] for l in out_labels)
-    return out.reshape(shape), int(nterms.value)
+    return out.reshape(shape), int(nterms.value), int(nmults.value)
+
+
+def naive_contract(tensors, labels, dims, out_labels=()):
+    """Naive knitting sum; returns (result array shaped by out_labels, n_terms)."""
+    out, n_terms, _ = naive_contract_counted(tensors, labels, dims, out_labels)
+    return out, n_terms
 
 
 def ve_contract(tensors, labels, dims, out_labels=(), mode="dd"):

@@ -133,11 +133,15 @@ static int check_net(int n_t, const int *ranks, const int *labels, int n_labels,
  * out[o] (o over out_labels, row-major) =
  *     sum over assignments of summed labels of  prod_i data[i][entry].
  * Summed labels = labels carried by some tensor and not in out_labels.
- * n_terms (optional) receives the number of (output, summed) assignments.
+ * n_terms (optional) receives the number of (output, summed) assignments;
+ * n_mults (optional) the multiplications the loop performed, counted as
+ * they are made (each term is the product of its n_t factors: n_t - 1
+ * multiplications, the |C| (s + n_g - 1) of Sec. 2.1 for s QTs and n_g
+ * coefficient tensors).
  */
 int oracle_naive(int n_t, const int *ranks, const int *labels, int n_labels,
                  const int64_t *dims, const double *const *data, int n_out,
-                 const int *out_labels, double *out, int64_t *n_terms) {
+                 const int *out_labels, double *out, int64_t *n_terms, int64_t *n_mults) {
     int st = check_net(n_t, ranks, labels, n_labels, dims, n_out, out_labels);
     if (st) return st;
     if (!data || !out) return OR_EARG;
@@ -169,13 +173,16 @@ int oracle_naive(int n_t, const int *ranks, const int *labels, int n_labels,
     /* Parallelise over fixed chunks of the summed space so the result does
      * not depend on the thread count. */
     const int64_t n_chunks = n_s < 64 ? n_s : 64;
+    int64_t mults = 0;
     for (int64_t o = 0; o < n_o; ++o) {
         neum *part = calloc((size_t)n_chunks, sizeof(neum));
-        if (!part) { st = OR_ENOMEM; break; }
+        int64_t *part_mults = calloc((size_t)n_chunks, sizeof(int64_t));
+        if (!part || !part_mults) { free(part); free(part_mults); st = OR_ENOMEM; break; }
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t ch = 0; ch < n_chunks; ++ch) {
             int64_t *idx = malloc(sizeof(int64_t) * ((size_t)n_labels + 1));
             int64_t s0 = n_s * ch / n_chunks, s1 = n_s * (ch + 1) / n_chunks;
+            int64_t cnt = 0;
             neum acc = {0.0, 0.0};
             /* output label digits */
             int64_t r = o;
@@ -191,20 +198,28 @@ int oracle_naive(int n_t, const int *ranks, const int *labels, int n_labels,
                     idx[l] = q % dims[l];
                     q /= dims[l];
                 }
-                double prod = 1.0;
+                double prod = 0.0;
                 for (int i = 0; i < n_t; ++i) {
                     int64_t e = 0;
                     for (int a = 0; a < ranks[i]; ++a) {
                         int l = labels[toff[i] + a];
                         e = e * dims[l] + idx[l];
                     }
-                    prod *= data[i][e];
+                    if (i == 0) {
+                        prod = data[i][e];
+                    } else {
+                        prod *= data[i][e];
+                        ++cnt;
+                    }
                 }
                 neum_add(&acc, prod);
             }
             part[ch] = acc;
+            part_mults[ch] = cnt;
             free(idx);
         }
+        for (int64_t ch = 0; ch < n_chunks; ++ch) mults += part_mults[ch];
+        free(part_mults);
         neum tot = {0.0, 0.0};
         for (int64_t ch = 0; ch < n_chunks; ++ch) {
             neum_add(&tot, part[ch].s);
@@ -213,6 +228,7 @@ int oracle_naive(int n_t, const int *ranks, const int *labels, int n_labels,
         out[o] = tot.s + tot.c;
         free(part);
     }
+    if (n_mults) *n_mults = mults;
     free(is_out); free(used); free(sum_labels); free(toff);
     return st;
 }

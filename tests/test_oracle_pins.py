@@ -336,6 +336,22 @@ def test_worked_example_costs():
     n_c = nv["gate_terms"] ** nv["n_gate_cuts"] * nv["wire_terms"] ** nv["n_wire_cuts"]
     assert n_c == nv["expected_C"]
     assert oracle.naive_pp_cost(n_c, nv["s"], nv["n_g"]) == nv["expected_cost"]
+    # the naive oracle on the worked example as Eq. knitting sums it: one
+    # summed index per cut over its QPD terms (the four gate cuts' 6, the
+    # wire cut's 8; the h-TN above carries the wire cut as a 4 x 4 tensor
+    # instead), random entries; it visits |C| terms and performs
+    # |C| (s + n_g - 1) multiplications, counted by its own loop
+    g1, g2, g3, g4, w = range(5)
+    dims = [nv["gate_terms"]] * 4 + [nv["wire_terms"]]
+    labels = [[g1, g2], [w, g1, g2], [w, g3, g4], [g3, g4], [g1], [g2], [g3], [g4], [w]]
+    assert len(labels) == nv["s"] + nv["n_g"]
+    rng = np.random.default_rng(5)
+    ts = [rng.uniform(-1, 1, size=[dims[l] for l in ls]) for ls in labels]
+    val, n_terms, n_mults = oracle.naive_contract_counted(ts, labels, dims, [])
+    assert n_terms == nv["expected_C"]
+    assert n_mults == nv["expected_cost"]
+    hi, lo = oracle.ve_contract(ts, labels, dims, [])
+    assert abs(float(val) - (float(hi) + float(lo))) <= 1e-12 * (1 + abs(float(hi)))
 
 
 def test_slices_sum_to_the_network():
