@@ -142,6 +142,18 @@ __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ ent
         fprep_words<T, TIN, LaneWords>(p, en.ws, en.e0, lane);
 }
 
+// Entries of rank <= 4 with at most 4 scales only: the short unrolled
+// form alone (about half the registers of k_fprep, which also holds the
+// longer forms).
+template <typename T, typename TIN>
+__global__ __launch_bounds__(64) void k_fprep_small(const FPrepEntry *__restrict__ entries, int64_t *stamp) {
+    const int lane = threadIdx.x;
+    if (stamp && blockIdx.x == 0 && lane == 0) *stamp = (int64_t)wall_clock64();
+    const FPrepEntry en = entries[blockIdx.x];
+    const LaneWords p(en.desc, en.n_words, lane);
+    fprep_words<T, TIN, LaneWords, 4, 4>(p, en.ws, en.e0, lane);
+}
+
 // Device clock read into *dst (one thread).
 __global__ void k_stamp(int64_t *dst) {
     if (threadIdx.x == 0) *dst = (int64_t)wall_clock64();
@@ -372,17 +384,27 @@ hipError_t launch_stamp(int64_t *dst, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
-                        hipStream_t st) {
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int n_small, int max_size, int compute,
+                        int64_t *stamp, hipStream_t st) {
     (void)max_size;
     if (n_entries <= 0) return hipSuccess;
+    if (n_small < 0 || n_small > n_entries || compute < 0 || compute > 2) return hipErrorInvalidValue;
     dim3 grid(n_entries);
-    if (compute == 0)
-        hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries, stamp);
-    else if (compute == 1)
-        hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries, stamp);
-    else
-        hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
+    if (n_small == n_entries) {
+        if (compute == 0)
+            hipLaunchKernelGGL((k_fprep_small<double, double>), grid, dim3(64), 0, st, entries, stamp);
+        else if (compute == 1)
+            hipLaunchKernelGGL((k_fprep_small<float, float>), grid, dim3(64), 0, st, entries, stamp);
+        else
+            hipLaunchKernelGGL((k_fprep_small<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
+    } else {
+        if (compute == 0)
+            hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries, stamp);
+        else if (compute == 1)
+            hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries, stamp);
+        else
+            hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
+    }
     return hipGetLastError();
 }
 

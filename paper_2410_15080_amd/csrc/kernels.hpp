@@ -101,8 +101,13 @@ constexpr int kFPrepDescMax = 215;
 // Elements per FPrepEntry chunk (one wave each).
 constexpr int kFPrepChunk = 4096;
 // stamp (may be null): the device clock at the start of the first workgroup
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int max_size, int compute, int64_t *stamp,
-                        hipStream_t st);
+// entries[0, n_small) have rank <= 4 and at most 4 CT scales.  When every
+// entry does, the launch uses a kernel of that form only, whose waves need
+// about half the registers (more of them resident per SIMD); otherwise one
+// launch of the general kernel takes them all (two launches back to back
+// measured slower than one).
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int n_small, int max_size, int compute,
+                        int64_t *stamp, hipStream_t st);
 
 // QT evaluator (qteval.hip): statevector instances, one workgroup each.
 constexpr int kSvMaxQubits = 24;
