@@ -65,8 +65,8 @@ struct DeviceState {
     int n_prep = 0, prep_max = 0;
     kern::FusedDesc *d_fdesc = nullptr;
     kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of the fused path
-    std::vector<kern::FPrepEntry> fprep;  // entries of the short form first
-    int fprep_small = 0;                  // how many of them (see launch_fprep)
+    std::vector<kern::FPrepEntry> fprep;
+    int fprep_form = 0;  // the longest load form among them (kern::fprep_form)
     int fprep_max = 0;
     bool fprep_in_kernel = false;  // the fused workgroup materialises its inputs
     int plan_uploaded = -1;
@@ -101,7 +101,7 @@ struct htn_batch {
         std::vector<int> idx;  // net indices, heaviest first
         int32_t *d_order = nullptr;
         kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of every net
-        int n_fprep = 0, n_fprep_small = 0, fprep_max = 0;
+        int n_fprep = 0, fprep_form = 0, fprep_max = 0;
     };
     std::vector<htn_net *> nets;
     std::vector<int> versions;
@@ -482,21 +482,17 @@ static void upload_plan(Net &n) {
     }
     D.fprep.clear();
     D.fprep_max = 0;
-    D.fprep_small = 0;
-    for (int pass = 0; pass < 2; ++pass)  // loads of the short form first
-        for (const LoadPlan &lp : P.loads) {
-            if (lp.desc_word < 0 || lp.desc_word + 7 > (int64_t)P.program.size()) continue;  // no fused image
-            const int32_t rk = P.program[lp.desc_word + 5], ns = P.program[lp.desc_word + 6];
-            const int32_t words = 7 + 2 * ns + rk * (4 + ns);
-            if (words > kern::kFPrepDescMax) throw Error{HTN_E_UNSUPPORTED, "load descriptor too long"};
-            const bool small = rk <= 4 && ns <= 4;
-            if (small != (pass == 0)) continue;
-            for (int64_t e0 = 0; e0 < lp.size; e0 += kern::kFPrepChunk) {
-                D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws, (int32_t)e0, words});
-                if (small) ++D.fprep_small;
-            }
-            D.fprep_max = std::max<int>(D.fprep_max, (int)lp.size);
-        }
+    D.fprep_form = 0;
+    for (const LoadPlan &lp : P.loads) {
+        if (lp.desc_word < 0 || lp.desc_word + 7 > (int64_t)P.program.size()) continue;  // no fused image
+        const int32_t rk = P.program[lp.desc_word + 5], ns = P.program[lp.desc_word + 6];
+        const int32_t words = 7 + 2 * ns + rk * (4 + ns);
+        if (words > kern::kFPrepDescMax) throw Error{HTN_E_UNSUPPORTED, "load descriptor too long"};
+        for (int64_t e0 = 0; e0 < lp.size; e0 += kern::kFPrepChunk)
+            D.fprep.push_back(kern::FPrepEntry{D.d_prog + lp.desc_word, D.d_ws, (int32_t)e0, words});
+        D.fprep_max = std::max<int>(D.fprep_max, (int)lp.size);
+        D.fprep_form = std::max(D.fprep_form, kern::fprep_form(rk, ns));
+    }
     dfree(D.d_fprep);
     D.d_fprep = nullptr;
     if (!D.fprep.empty()) {
@@ -553,7 +549,7 @@ static bool use_fused(const Net &n) {
 
 static void run_fused_single(Net &n, void *out, hipStream_t st) {
     if (!n.dev->fprep_in_kernel)
-        HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_small, n.dev->fprep_max,
+        HIP_TRY(kern::launch_fprep(n.dev->d_fprep, (int)n.dev->fprep.size(), n.dev->fprep_form, n.dev->fprep_max,
                                    (int)n.compute, nullptr, st));
     HIP_TRY(kern::launch_fused(n.dev->d_fdesc, nullptr, nullptr, nullptr, out, nullptr, 0, 1,
                                (int)n.plan.fused_lds_bytes, (int)n.compute, final_mode(n), n.fused_threads, st));
@@ -1518,16 +1514,12 @@ htn_status htn_batch_create(htn_batch_t *out, int32_t n, const htn_net_t *nets) 
                              [&](int x, int y) { return nets[x]->plan.mults > nets[y]->plan.mults; });
             g.d_order = dalloc<int32_t>(g.idx.size());
             HIP_TRY(hipMemcpy(g.d_order, g.idx.data(), g.idx.size() * 4, hipMemcpyHostToDevice));
-            std::vector<kern::FPrepEntry> fp;  // every net's short-form entries first
+            std::vector<kern::FPrepEntry> fp;
             for (int i : g.idx) {
                 const DeviceState &D = *nets[i]->dev;
-                fp.insert(fp.end(), D.fprep.begin(), D.fprep.begin() + D.fprep_small);
+                fp.insert(fp.end(), D.fprep.begin(), D.fprep.end());
                 g.fprep_max = std::max(g.fprep_max, D.fprep_max);
-            }
-            g.n_fprep_small = (int)fp.size();
-            for (int i : g.idx) {
-                const DeviceState &D = *nets[i]->dev;
-                fp.insert(fp.end(), D.fprep.begin() + D.fprep_small, D.fprep.end());
+                g.fprep_form = std::max(g.fprep_form, D.fprep_form);
             }
             g.n_fprep = (int)fp.size();
             if (!fp.empty()) {
@@ -1639,7 +1631,7 @@ static void batch_enqueue(htn_batch *b, void *const *outs, hipStream_t st, bool 
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto &g = b->groups[gi];
-        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.n_fprep_small, g.fprep_max, g.compute,
+        HIP_TRY(kern::launch_fprep(g.d_fprep, g.n_fprep, g.fprep_form, g.fprep_max, g.compute,
                                    gi == 0 && prep_stamps ? run_start : nullptr, st));
     }
     if (events) HIP_TRY(hipEventRecord(next_event(b), st));

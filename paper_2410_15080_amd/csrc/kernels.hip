@@ -142,9 +142,8 @@ __global__ __launch_bounds__(64) void k_fprep(const FPrepEntry *__restrict__ ent
         fprep_words<T, TIN, LaneWords>(p, en.ws, en.e0, lane);
 }
 
-// Entries of rank <= 4 with at most 4 scales only: the short unrolled
-// form alone (about half the registers of k_fprep, which also holds the
-// longer forms).
+// Entries of rank <= 4 with at most 4 scales only (form 0): the short
+// unrolled form alone (descriptors of at most 47 words).
 template <typename T, typename TIN>
 __global__ __launch_bounds__(64) void k_fprep_small(const FPrepEntry *__restrict__ entries, int64_t *stamp) {
     const int lane = threadIdx.x;
@@ -152,6 +151,25 @@ __global__ __launch_bounds__(64) void k_fprep_small(const FPrepEntry *__restrict
     const FPrepEntry en = entries[blockIdx.x];
     const LaneWords p(en.desc, en.n_words, lane);
     fprep_words<T, TIN, LaneWords, 4, 4>(p, en.ws, en.e0, lane);
+}
+
+// Entries of rank <= 6 with at most 6 scales (form 1); descriptors of more
+// than 64 words (up to 79) are read through the constant address space.
+template <typename T, typename TIN>
+__global__ __launch_bounds__(64) void k_fprep_mid(const FPrepEntry *__restrict__ entries, int64_t *stamp) {
+    const int lane = threadIdx.x;
+    if (stamp && blockIdx.x == 0 && lane == 0) *stamp = (int64_t)wall_clock64();
+    const FPrepEntry en = entries[blockIdx.x];
+    if (en.n_words > 64) {
+        fprep_words<T, TIN, ConstWords, 6, 6>(ConstWords{(const c_int32 *)en.desc}, en.ws, en.e0, lane);
+        return;
+    }
+    const LaneWords p(en.desc, en.n_words, lane);
+    const int rk = p(5), ns = p(6);
+    if (rk <= 4 && ns <= 4)
+        fprep_words<T, TIN, LaneWords, 4, 4>(p, en.ws, en.e0, lane);
+    else
+        fprep_words<T, TIN, LaneWords, 6, 6>(p, en.ws, en.e0, lane);
 }
 
 // Device clock read into *dst (one thread).
@@ -384,27 +402,28 @@ hipError_t launch_stamp(int64_t *dst, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int n_small, int max_size, int compute,
+template <typename T, typename TIN>
+static void go_fprep(const FPrepEntry *entries, int n_entries, int form, int64_t *stamp, hipStream_t st) {
+    const dim3 grid(n_entries);
+    if (form == 0)
+        hipLaunchKernelGGL((k_fprep_small<T, TIN>), grid, dim3(64), 0, st, entries, stamp);
+    else if (form == 1)
+        hipLaunchKernelGGL((k_fprep_mid<T, TIN>), grid, dim3(64), 0, st, entries, stamp);
+    else
+        hipLaunchKernelGGL((k_fprep<T, TIN>), grid, dim3(64), 0, st, entries, stamp);
+}
+
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int form, int max_size, int compute,
                         int64_t *stamp, hipStream_t st) {
     (void)max_size;
     if (n_entries <= 0) return hipSuccess;
-    if (n_small < 0 || n_small > n_entries || compute < 0 || compute > 2) return hipErrorInvalidValue;
-    dim3 grid(n_entries);
-    if (n_small == n_entries) {
-        if (compute == 0)
-            hipLaunchKernelGGL((k_fprep_small<double, double>), grid, dim3(64), 0, st, entries, stamp);
-        else if (compute == 1)
-            hipLaunchKernelGGL((k_fprep_small<float, float>), grid, dim3(64), 0, st, entries, stamp);
-        else
-            hipLaunchKernelGGL((k_fprep_small<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
-    } else {
-        if (compute == 0)
-            hipLaunchKernelGGL((k_fprep<double, double>), grid, dim3(64), 0, st, entries, stamp);
-        else if (compute == 1)
-            hipLaunchKernelGGL((k_fprep<float, float>), grid, dim3(64), 0, st, entries, stamp);
-        else
-            hipLaunchKernelGGL((k_fprep<float, bf16_t>), grid, dim3(64), 0, st, entries, stamp);
-    }
+    if (form < 0 || form > 2 || compute < 0 || compute > 2) return hipErrorInvalidValue;
+    if (compute == 0)
+        go_fprep<double, double>(entries, n_entries, form, stamp, st);
+    else if (compute == 1)
+        go_fprep<float, float>(entries, n_entries, form, stamp, st);
+    else
+        go_fprep<float, bf16_t>(entries, n_entries, form, stamp, st);
     return hipGetLastError();
 }
 

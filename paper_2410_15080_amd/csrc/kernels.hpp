@@ -101,13 +101,19 @@ constexpr int kFPrepDescMax = 215;
 // Elements per FPrepEntry chunk (one wave each).
 constexpr int kFPrepChunk = 4096;
 // stamp (may be null): the device clock at the start of the first workgroup
-// entries[0, n_small) have rank <= 4 and at most 4 CT scales.  When every
-// entry does, the launch uses a kernel of that form only, whose waves need
-// about half the registers (more of them resident per SIMD); otherwise one
-// launch of the general kernel takes them all (two launches back to back
-// measured slower than one).
-hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int n_small, int max_size, int compute,
+// form: the longest load form among the entries (fprep_form): 0 when every
+// entry has rank <= 4 and at most 4 CT scales, 1 when rank <= 6 and at most
+// 6 scales, 2 otherwise.  Each form has a kernel of its own, unrolled to its
+// bounds only: the shorter forms need fewer registers (50, 69, 88), so
+// more waves stay resident per SIMD (8, 7, 5).
+hipError_t launch_fprep(const FPrepEntry *entries, int n_entries, int form, int max_size, int compute,
                         int64_t *stamp, hipStream_t st);
+// The form (as above) of one load: rank and number of CT scales.
+inline int fprep_form(int rank, int n_scales) {
+    if (rank <= 4 && n_scales <= 4) return 0;
+    if (rank <= 6 && n_scales <= 6) return 1;
+    return 2;
+}
 
 // QT evaluator (qteval.hip): statevector instances, one workgroup each.
 constexpr int kSvMaxQubits = 24;
