@@ -99,16 +99,16 @@ TRAFFIC = {
     # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 716.3 x 2047.2 B, WRITE_SIZE 181.7 x 1024 B
     "k_fused_grid": {"read_bytes": 38_315_781, "write_bytes": 186_061, "sources": "daab8134708a909f",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
-    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 479.3 x 2047.2 B, WRITE_SIZE 15 552.8 x 1024 B
-    "k_truncate_qpd8": {"read_bytes": 27_594_743, "write_bytes": 15_926_067, "sources": "11e2d366fd0df080",
+    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 479.3 x 2047.2 B, WRITE_SIZE 15 554.1 x 1024 B
+    "k_truncate_qpd8": {"read_bytes": 27_594_743, "write_bytes": 15_927_398, "sources": "1842a05c0f4c968e",
                         "files": ["paper_2410_15080_amd/csrc/qpd.hip", "paper_2410_15080_amd/csrc/api.hip",
                                   "paper_2410_15080_amd/csrc/kernels.hpp"],
                         "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
     # profiles/k_gemm_marginal4096_f64_f32_bf16.md: one contraction's kernels
     # (k_prep, k_fold, k_gemm), FETCH_SIZE x 2047.2 B and WRITE_SIZE x 1024 B summed
-    "marginal_bf16": {"read_bytes": 27_875_004, "write_bytes": 142_715_290, "sources": "771a24a9d8e66698",
+    "marginal_bf16": {"read_bytes": 27_868_453, "write_bytes": 142_725_222, "sources": "d307b70e642532bd",
                       "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
-    "marginal_f64": {"read_bytes": 107_742_595, "write_bytes": 159_392_563, "sources": "771a24a9d8e66698",
+    "marginal_f64": {"read_bytes": 107_766_343, "write_bytes": 159_386_522, "sources": "d307b70e642532bd",
                      "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",
