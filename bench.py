@@ -96,19 +96,19 @@ def parse():
 MARGINAL_TRAFFIC_FILES = ["paper_2410_15080_amd/csrc/" + f for f in (
     "mfma.hip", "mfma_dev.hpp", "kernels.hip", "kernels.hpp", "step_dev.hpp", "kern_common.hpp", "planner.cpp", "api.hip")]
 TRAFFIC = {
-    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 716.3 x 2047.2 B, WRITE_SIZE 181.7 x 1024 B
-    "k_fused_grid": {"read_bytes": 38_315_781, "write_bytes": 186_061, "sources": "daab8134708a909f",
+    # profiles/k_fused_grid4x4_batch1024_f64.md: FETCH_SIZE 18 716.2 x 2047.2 B, WRITE_SIZE 181.1 x 1024 B
+    "k_fused_grid": {"read_bytes": 38_315_694, "write_bytes": 185_446, "sources": "b23f60e326e35d2a",
                      "profile": "profiles/k_fused_grid4x4_batch1024_f64.md"},
-    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 479.3 x 2047.2 B, WRITE_SIZE 15 554.1 x 1024 B
-    "k_truncate_qpd8": {"read_bytes": 27_594_743, "write_bytes": 15_927_398, "sources": "1842a05c0f4c968e",
+    # profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md: FETCH_SIZE 13 479.3 x 2047.2 B, WRITE_SIZE 15 553.6 x 1024 B
+    "k_truncate_qpd8": {"read_bytes": 27_594_743, "write_bytes": 15_926_886, "sources": "e5762072f8252300",
                         "files": ["paper_2410_15080_amd/csrc/qpd.hip", "paper_2410_15080_amd/csrc/api.hip",
                                   "paper_2410_15080_amd/csrc/kernels.hpp"],
                         "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
     # profiles/k_gemm_marginal4096_f64_f32_bf16.md: one contraction's kernels
-    # (k_prep, k_fold, k_gemm), FETCH_SIZE x 2047.2 B and WRITE_SIZE x 1024 B summed
-    "marginal_bf16": {"read_bytes": 27_868_453, "write_bytes": 142_725_222, "sources": "d307b70e642532bd",
+    # (k_fold, k_gemm), FETCH_SIZE x 2047.2 B and WRITE_SIZE x 1024 B summed
+    "marginal_bf16": {"read_bytes": 23_593_912, "write_bytes": 138_507_059, "sources": "144e13fb655b7476",
                       "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
-    "marginal_f64": {"read_bytes": 107_766_343, "write_bytes": 159_386_522, "sources": "d307b70e642532bd",
+    "marginal_f64": {"read_bytes": 99_675_627, "write_bytes": 151_019_008, "sources": "144e13fb655b7476",
                      "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",

@@ -61,8 +61,13 @@ struct DeviceState {
     int2 *d_tab = nullptr;
     void *d_ws = nullptr;
     int64_t ws_cap = 0;
+    // materialisations of the loads that need a copy: first those the
+    // per-step executor runs (n_prep_steps; the rest are fold-chain sources
+    // it reads in place), then the others; prep_index[k]: the entry of the
+    // k-th such load in plan order (the work queue runs them all)
     kern::PrepDesc *d_prep = nullptr;
-    int n_prep = 0, prep_max = 0;
+    int n_prep = 0, n_prep_steps = 0, prep_max = 0;
+    std::vector<int> prep_index;
     kern::FusedDesc *d_fdesc = nullptr;
     kern::FPrepEntry *d_fprep = nullptr;  // input materialisation of the fused path
     std::vector<kern::FPrepEntry> fprep;
@@ -369,12 +374,27 @@ static void upload_plan(Net &n) {
     }
     std::vector<kern::PrepDesc> prep;
     int pmax = 0;
-    for (const LoadPlan &lp : P.loads) {
-        if (!lp.needs_copy()) continue;
+    D.prep_index.clear();
+    std::vector<int> order;  // needs_copy loads: per-step ones first
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t k = 0; k < P.loads.size(); ++k) {
+            const LoadPlan &lp = P.loads[k];
+            if (lp.needs_copy() && (P.ws_off[lp.value] >= 0) == (pass == 0)) order.push_back((int)k);
+        }
+    {
+        std::vector<int> slot(P.loads.size(), -1);
+        for (size_t i = 0; i < order.size(); ++i) slot[order[i]] = (int)i;
+        for (size_t k = 0; k < P.loads.size(); ++k)
+            if (P.loads[k].needs_copy()) D.prep_index.push_back(slot[k]);
+    }
+    D.n_prep_steps = 0;
+    for (int k : order) {
+        const LoadPlan &lp = P.loads[k];
         kern::PrepDesc q;
         std::memset(&q, 0, sizeof(q));
         q.src = D.in[lp.base];
-        q.dst_off = P.ws_off[lp.value];
+        q.dst_off = P.ws_off[lp.value];  // -1: not run by the per-step executor
+        if (q.dst_off >= 0) ++D.n_prep_steps;
         q.size = (int32_t)lp.size;
         q.ns = (int32_t)lp.scales.size();
         for (int k = 0; k < q.ns; ++k) {
@@ -603,7 +623,8 @@ static void run_steps(Net &n, void *out, hipStream_t st, int64_t *ticks = nullpt
     const Plan &P = n.plan;
     unsigned char *ws = (unsigned char *)(ws_base ? ws_base : D.d_ws);
     const int tin = (int)input_dtype(n.compute), tint = (int)inter_dtype(n.compute);
-    if (D.n_prep) HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep, D.prep_max, tin, tint, D.d_tab, ws, st));
+    if (D.n_prep_steps)
+        HIP_TRY(kern::launch_prep(D.d_prep, D.n_prep_steps, D.prep_max, tin, tint, D.d_tab, ws, st));
     int q = -1;
     for (int k : P.kernel_steps) {
         if (ticks && q >= 0 && q < max_ticks) HIP_TRY(kern::launch_stamp(ticks + q, st));
@@ -1171,7 +1192,7 @@ static bool queue_net(QBuild &Q, Net &n, int bi) {
         kern::QItem it = q_item(kern::QI_LOAD, bi, n);
         it.ta = tin;
         it.tc = tint;
-        it.prep = D.d_prep + j++;
+        it.prep = D.d_prep + D.prep_index[j++];
         it.n_units = (lp.size + 255) / 256;
         it.units_per_task = (int32_t)q_units_per_task(it.n_units, 256 * (1 + (int64_t)lp.scales.size()));
         voff[lp.value] = Q.take(lp.size * es);

@@ -137,6 +137,8 @@ struct Plan {
     // between, and whose large tensor is a network input: independent of
     // each other, so one launch runs them side by side)
     std::vector<int> chain_lead;
+    // per chain, whether its large tensor is read in place (FoldLayout::x_raw)
+    std::vector<char> chain_x_raw;
     std::vector<int32_t> tables;     // flat (x, y) pairs
     int final_value = -1;
     double mults = 0.0;
@@ -220,6 +222,9 @@ inline htn_dtype out_dtype(const Net &n) {
 struct FoldLayout {
     bool ok = false;
     int x = -1, y = -1;                 // source value (X) and result value
+    // X is a network input with no folded scales: read in place from its
+    // original tensor (no materialised copy)
+    bool x_raw = false;
     std::vector<int> ext0, ext1;        // in-tile extents at X / at the result
     std::vector<int64_t> s_src, s_dst;  // in-tile strides in X / in the result
     std::vector<int> fold_ax, fold_ext; // per stage: in-tile axis, its new extent

@@ -508,7 +508,29 @@ FoldLayout fold_layout(const Net &n, const Plan &P, const std::vector<int> &chai
     if (h.a < 0 || h.b < 0) return F;
     F.x = P.values[h.a].size >= P.values[h.b].size ? h.a : h.b;
     const std::vector<int> &xl = P.values[F.x].labels;
-    const std::vector<int64_t> xs = row_major(xl);
+    std::vector<int64_t> xs = row_major(xl);
+    {
+        // an input without folded scales is read in place: the strides of
+        // its original tensor (labels it has beyond X's have extent 1)
+        const Value &XV = P.values[F.x];
+        if (XV.input && XV.scales.empty() && XV.base >= 0) {
+            const std::vector<int> &bl = n.labels[XV.base];
+            const std::vector<int64_t> bs = row_major(bl);
+            std::vector<int64_t> raw(xl.size(), -1);
+            bool ok = true;
+            for (size_t j = 0; j < xl.size(); ++j) {
+                for (size_t q = 0; q < bl.size(); ++q)
+                    if (bl[q] == xl[j]) raw[j] = bs[q];
+                if (raw[j] < 0) ok = false;
+            }
+            for (int l : bl)
+                if (!contains(xl, l) && n.dims[l] != 1) ok = false;
+            if (ok) {
+                xs = raw;
+                F.x_raw = true;
+            }
+        }
+    }
     std::vector<int> cur = xl;
     std::vector<char> folded(xl.size(), 0);
     int prev = F.x;
@@ -1184,6 +1206,8 @@ void build_plan(Net &n) {
         // groups of chains launched together (Plan::chain_lead): a chain
         // whose large tensor is a network input joins the open group when
         // every step since the group's first is a step of its chains
+        P.chain_x_raw.assign(P.chains.size(), 0);
+        for (size_t c = 0; c < P.chains.size(); ++c) P.chain_x_raw[c] = fold_layout(n, P, P.chains[c]).x_raw ? 1 : 0;
         P.chain_lead.assign(P.chains.size(), -1);
         int open = -1;
         for (int k : P.kernel_steps) {
@@ -1210,8 +1234,22 @@ void build_plan(Net &n) {
         const int64_t es = dtype_size(inter_dtype(n.compute));
         FirstFit ff;
         P.ws_off.assign(P.values.size(), -1);
+        // (inputs a fold chain reads in place get no copy here: its large
+        // tensor when unscaled, and its matrices, always read raw; the
+        // queue and the fused kernel keep their own copies)
+        std::vector<char> in_place(P.values.size(), 0);
+        for (size_t c = 0; c < P.chains.size(); ++c) {
+            const StepPlan &h = P.steps[P.chains[c][0]];
+            int prev = P.values[h.a].size >= P.values[h.b].size ? h.a : h.b;
+            if (P.chain_x_raw[c]) in_place[prev] = 1;
+            for (int k : P.chains[c]) {
+                const StepPlan &s = P.steps[k];
+                in_place[s.a == prev ? s.b : s.a] = 1;  // the matrix (an input)
+                prev = s.c;
+            }
+        }
         for (auto &lp : P.loads)
-            if (lp.needs_copy()) P.ws_off[lp.value] = ff.alloc(lp.size * es, 256);
+            if (lp.needs_copy() && !in_place[lp.value]) P.ws_off[lp.value] = ff.alloc(lp.size * es, 256);
         const int64_t pes = n.compute == HTN_BF16 ? 2 : es;  // packed operand element size
         for (int k : P.kernel_steps) {
             StepPlan &s = P.steps[k];
@@ -1683,7 +1721,7 @@ static std::string chains_json(const Net &n) {
         const FoldLayout F = fold_layout(n, n.plan, n.plan.chains[c]);
         o << (c ? "," : "") << "{";
         arr("steps", n.plan.chains[c]);
-        o << ",\"lead\":" << n.plan.chain_lead[c] << ",\"ws_x\":" << n.plan.ws_off[F.x] << ",\"ws_y\":" << n.plan.ws_off[F.y];
+        o << ",\"lead\":" << n.plan.chain_lead[c] << ",\"x_raw\":" << (F.x_raw ? 1 : 0) << ",\"ws_x\":" << n.plan.ws_off[F.x] << ",\"ws_y\":" << n.plan.ws_off[F.y];
         o << ",\"x\":" << F.x << ",\"y\":" << F.y << ",\"tf\":" << F.tf << ",\"d_max\":" << F.d_max
           << ",\"n_outer\":" << F.n_outer << ",";
         arr("ext0", F.ext0);

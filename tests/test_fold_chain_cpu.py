@@ -149,7 +149,11 @@ def test_fold_chain_layout_replays_to_the_contraction(idx):
             assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:])), spans
         for c in chains:
             assert plan["values"][c["x"]]["input"]
-            x_data = _value_data(w, plan, c["x"])
+            # an unscaled input is read in place (its original tensor's
+            # strides, no workspace copy); otherwise its planned copy
+            base = plan["values"][c["x"]]["base"]
+            assert c["x_raw"] == 1 and c["ws_x"] == -1
+            x_data = np.asarray(w.tensors[base], dtype=np.float64).ravel()
             mats = [np.asarray(w.tensors[t], dtype=np.float64).ravel() for t in c["m_tensor"]]
             y_size = int(np.prod([w.dims[l] for l in plan["values"][c["y"]]["labels"]]))
             got = _replay(c, x_data, mats, y_size)
