@@ -106,9 +106,9 @@ TRAFFIC = {
                         "profile": "profiles/k_truncate_grid4x4_qpd8_batch1024_f64.md"},
     # profiles/k_gemm_marginal4096_f64_f32_bf16.md: one contraction's kernels
     # (k_fold, k_gemm), FETCH_SIZE x 2047.2 B and WRITE_SIZE x 1024 B summed
-    "marginal_bf16": {"read_bytes": 23_593_912, "write_bytes": 138_507_059, "sources": "144e13fb655b7476",
+    "marginal_bf16": {"read_bytes": 23_626_944, "write_bytes": 138_531_328, "sources": "fc6d7fa7bfcade02",
                       "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
-    "marginal_f64": {"read_bytes": 99_675_627, "write_bytes": 151_019_008, "sources": "144e13fb655b7476",
+    "marginal_f64": {"read_bytes": 99_749_016, "write_bytes": 151_014_810, "sources": "fc6d7fa7bfcade02",
                      "files": MARGINAL_TRAFFIC_FILES, "profile": "profiles/k_gemm_marginal4096_f64_f32_bf16.md"},
 }
 TRAFFIC_SOURCES = ["paper_2410_15080_amd/csrc/fused.hpp", "paper_2410_15080_amd/csrc/kern_common.hpp",

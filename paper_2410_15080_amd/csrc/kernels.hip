@@ -183,6 +183,8 @@ __global__ void k_stamp(int64_t *dst) {
 // store): 1024 threads per workgroup shorten each pass (narrower tiles with
 // more workgroups per CU measured slower).
 constexpr int kFoldBlk = 1024;
+// matrices of at most this many entries are staged in LDS for their fold
+constexpr int kFoldStagedM = 256;
 
 // One workgroup per tf outer indices; LDS holds two [d_max][tf + 1]
 // buffers (the +1 keeps the destination-order reads off one bank) and the
@@ -262,19 +264,37 @@ __global__ __launch_bounds__(kFoldBlk) void k_fold(const FoldBatch fb) {
     else
         stage(TS1{});
     __syncthreads();
+    __shared__ TI m_s[kFoldStagedM];
     for (int st = 0; st < fd.n_stage; ++st) {
-        const int din = fd.d_in_ax[st], inner = fd.inner[st];
-        const int Dn = D / din * fd.d_out[st];
+        const int din = fd.d_in_ax[st], inner = fd.inner[st], dout = fd.d_out[st];
+        const int Dn = D / din * dout;
         const int32_t *tb = fd.tab + fd.t_base[st], *tm = fd.tab + fd.t_mid[st];
         const TM *M = (const TM *)fd.m[st];
         const int mi = fd.m_in[st], mo = fd.m_out[st];
+        // a small matrix is staged in LDS as [old digit][new digit], so the
+        // sums read no global memory; the terms are added in the same order
+        const bool staged = din * dout <= kFoldStagedM;  // workgroup-uniform
+        if (staged) {
+            for (int q = threadIdx.x; q < din * dout; q += kFoldBlk) {
+                const int k = q / dout, o = q - k * dout;
+                m_s[q] = Ld<TI, TM>::get(M + (int64_t)k * mi + (int64_t)o * mo);
+            }
+            __syncthreads();
+        }
 #pragma unroll 4
         for (int e = threadIdx.x; e < (Dn << lg); e += kFoldBlk) {
             const int a = e >> lg, fl = e & (tf - 1);
             const TI *x = bin + tb[a] * ld + fl;
-            const TM *m = M + tm[a] * mo;
+            const int mid = tm[a];
             TI acc = 0;
-            for (int k = 0; k < din; ++k) acc += x[k * inner * ld] * Ld<TI, TM>::get(m + k * mi);
+            if (staged) {
+                const TI *ms = m_s + mid;
+#pragma unroll 4
+                for (int k = 0; k < din; ++k) acc += x[k * inner * ld] * ms[k * dout];
+            } else {
+                const TM *m = M + mid * mo;
+                for (int k = 0; k < din; ++k) acc += x[k * inner * ld] * Ld<TI, TM>::get(m + k * mi);
+            }
             bout[a * ld + fl] = acc;
         }
         __syncthreads();
